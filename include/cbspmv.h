@@ -1,0 +1,219 @@
+/*
+ * cbspmv.h -- C ABI of the CB-SpMV library for AMD Instinct MI355X (gfx950).
+ *
+ * The library converts a CSR matrix into the two-level tile structure of
+ * CB-SpMV (Cong et al., ICS '25) and multiplies it with dense vectors on the
+ * GPU:
+ *   - uniform 16 x 16 sub-blocks ("tiles") located by a high-level COO of
+ *     tiles: blk_row_idx, blk_col_idx, nnz_per_blk, vp_per_blk, type_per_blk
+ *     (Section 3.1);
+ *   - every tile's packed 4+4-bit coordinates, padding and values stored side
+ *     by side in one byte buffer and found through its virtual pointer
+ *     (Section 3.2);
+ *   - block-aware column aggregation, chosen by the th0 rule, and per-tile
+ *     COO / CSR / Dense format selection by th1 / th2 (Section 3.3);
+ *   - inter-thread-block load balance (Section 3.4, Algorithm 2), plus a
+ *     panel-contiguous nnz-balanced split that keeps every 16-row panel in
+ *     one work unit where it can;
+ *   - y = alpha * A * x + beta * y (Section 3.5 kernels, Algorithms 3 and 4)
+ *     and the k-right-hand-side form Y = alpha * A * X + beta * Y.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a cb_status_t.  Out-parameters are written only on
+ *     CB_SUCCESS.  No exception or abort crosses the ABI.  A thread-local
+ *     message for the last failure is available from cb_last_error().
+ *   - "stream" is a hipStream_t passed as void*; NULL is the null stream.
+ *   - Host arrays given to cb_create / cb_create_host are read during the call
+ *     and copied; the caller may free them on return.
+ *   - A handle owns all device memory of one converted matrix; cb_destroy
+ *     releases it.  After creation a handle is read-only, so several streams
+ *     may use it at once; the caller must synchronise those streams before
+ *     cb_destroy.
+ *   - Vectors x, y, X, Y are caller-owned DEVICE pointers.  cb_spmv and
+ *     cb_spmm never allocate and never synchronise: they only enqueue work on
+ *     the stream, so they may be captured in a HIP graph.
+ *   - Index limits: 0 <= m, n < 2^31 and 0 <= nnz < 2^31.
+ */
+#ifndef CBSPMV_H
+#define CBSPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cb_matrix_s *cb_matrix_t;
+
+typedef enum {
+    CB_SUCCESS = 0,
+    CB_ERROR_INVALID_VALUE = 1,   /* bad argument or non-canonical CSR */
+    CB_ERROR_OUT_OF_MEMORY = 2,   /* host or device allocation failed */
+    CB_ERROR_HIP = 3,             /* a HIP runtime call or kernel launch failed */
+    CB_ERROR_NOT_SUPPORTED = 4,   /* valid request this build cannot serve */
+    CB_ERROR_INTERNAL = 5
+} cb_status_t;
+
+/* Storage precision of the matrix values (the paper evaluates FP64,
+ * Section 4.2).  F64: x and y are double, FP64 arithmetic.  F32 / BF16:
+ * values rounded to nearest-even straight from the FP64 input at creation,
+ * x and y are float, products and sums in FP32. */
+typedef enum { CB_VALUE_F64 = 0, CB_VALUE_F32 = 1, CB_VALUE_BF16 = 2 } cb_value_t;
+
+/* Tile formats (Section 3.3.2). */
+typedef enum { CB_FMT_COO = 0, CB_FMT_CSR = 1, CB_FMT_DENSE = 2 } cb_format_t;
+
+/* How tiles are grouped into the units of work the kernel hands to one
+ * wavefront.
+ *   CB_LB_NONE:       natural order (panel, then column), fixed groups of
+ *                     quantum_tiles tiles -- the structure without load
+ *                     balance.
+ *   CB_LB_PAPER:      Algorithm 2 (Section 3.4): tiles sorted by nnz, each
+ *                     given to the least-loaded group of quantum_tiles tiles
+ *                     (min-heap), metadata permuted into group order.
+ *   CB_LB_CONTIGUOUS: natural order cut into ranges of about wave_nnz
+ *                     non-zeros at panel boundaries; only panels heavier than
+ *                     twice that are split.  The default: a panel inside one
+ *                     range is written to y once, with no atomics. */
+typedef enum { CB_LB_NONE = 0, CB_LB_PAPER = 1, CB_LB_CONTIGUOUS = 2 } cb_lb_t;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(cb_options_t): set by cb_options_default */
+    int32_t value_type;     /* cb_value_t, default CB_VALUE_F64 */
+    int32_t col_agg;        /* -1: th0 rule of Section 3.3.1 (default); 0: off; 1: on */
+    int32_t th1;            /* COO below th1 non-zeros (default 32, Section 3.3.2) */
+    int32_t th2;            /* Dense above th2 non-zeros (default 128, Section 3.3.2) */
+    int32_t quantum_tiles;  /* tiles per group for CB_LB_NONE / CB_LB_PAPER (default 8, Algorithm 2) */
+    int32_t lb_mode;        /* cb_lb_t, default CB_LB_CONTIGUOUS */
+    int32_t host_threads;   /* converter threads; 0 = all hardware threads */
+    double th0;             /* super-sparse share that turns aggregation on (default 0.15) */
+    int64_t wave_nnz;       /* target non-zeros per wavefront work range; 0 = automatic */
+    int64_t reserved[6];
+} cb_options_t;
+
+typedef struct {
+    uint32_t struct_size;   /* caller sets sizeof(cb_info_t) before the call */
+    int32_t value_type;
+    int64_t m, n, nnz;
+    int64_t npanels;        /* ceil(m / 16) */
+    int64_t ntiles;
+    int64_t tiles_coo, tiles_csr, tiles_dense;
+    int32_t col_agg;        /* 1 when column aggregation was applied */
+    int32_t lb_mode;
+    double super_sparse_share;  /* share of tiles with < 32 non-zeros on the plain 16 x 16 partition */
+    int64_t plain_tiles;    /* tiles of the plain partition (before aggregation) */
+    int64_t payload_bytes;  /* packed tile data (mtx_data) */
+    int64_t meta_bytes;     /* high-level arrays: 4+4+4+8+1 bytes per tile */
+    int64_t restore_bytes;  /* restore_cols + cols_offset (0 without aggregation) */
+    int64_t sched_bytes;    /* work-range pointers, panel flags, pre-pass panel list */
+    int64_t nquanta;        /* groups of Algorithm 2 (or the contiguous ranges) */
+    int64_t nwaves;         /* wavefront work ranges launched per SpMV */
+    int64_t shared_panels;  /* panels whose tiles span more than one work range */
+    int64_t prepass_panels; /* panels written by the y <- beta*y pre-pass (shared or empty) */
+    int64_t quantum_nnz_max;
+    double quantum_nnz_mean, quantum_nnz_std;
+    int64_t wave_nnz_max;
+    double wave_nnz_mean, wave_nnz_std;
+    int64_t spmv_bytes;     /* algorithmic HBM bytes of one cb_spmv with beta == 0:
+                               structure + x once + y once */
+    int64_t device_bytes;   /* device memory owned by the handle */
+    double convert_seconds; /* host conversion time */
+    int32_t on_device;      /* 1 for cb_create handles, 0 for cb_create_host */
+    int32_t reserved0;
+    int64_t reserved[8];
+} cb_info_t;
+
+/* Host buffers receiving the structure in kernel order (ntiles entries for the
+ * tile arrays).  Any pointer may be NULL to skip that array.  Sizes come from
+ * cb_get_info: payload_bytes, nquanta + 1, nwaves + 1, npanels (+ 1 for
+ * cols_offset), restore_bytes / 4 - npanels - 1 entries of restore_cols when
+ * aggregation is applied, prepass_panels. */
+typedef struct {
+    int32_t *tile_row;       /* blk_row_idx: 16-row panel of each tile */
+    int32_t *tile_col;       /* blk_col_idx: 16-column block, or aggregated chunk */
+    int32_t *tile_nnz;       /* nnz_per_blk */
+    int64_t *tile_vp;        /* vp_per_blk: byte offset of the tile in payload */
+    uint8_t *tile_type;      /* type_per_blk: cb_format_t */
+    int32_t *tile_ori;       /* index of the tile in natural (panel, column) order */
+    uint8_t *payload;        /* mtx_data */
+    int32_t *restore_cols;   /* aggregated column -> original column */
+    int32_t *cols_offset;    /* start of each panel's restore_cols, npanels + 1 */
+    int32_t *quantum_ptr;    /* tile range of each group, nquanta + 1 */
+    int32_t *wave_ptr;       /* tile range of each wavefront work range, nwaves + 1 */
+    uint8_t *panel_shared;   /* 1 if the panel's tiles span more than one work range */
+    int32_t *prepass_list;   /* panels written by the pre-pass */
+} cb_structure_t;
+
+/* Fill *opt with the defaults above (the paper's thresholds). */
+cb_status_t cb_options_default(cb_options_t *opt);
+
+/* Convert the CSR matrix (HOST arrays: row_ptr[m+1] int64, col_idx[nnz]
+ * int32, values[nnz] double) into the CB structure (Section 3, Fig. 7 order:
+ * partition, aggregation decision, column aggregation, format selection,
+ * packing, load balance) and copy it to the current HIP device with one
+ * transfer on `stream` (the call waits for that copy).  The CSR must be
+ * canonical: row_ptr[0] = 0, non-decreasing, row_ptr[m] = nnz, 0 <= col < n,
+ * columns strictly increasing within a row.  Explicit zeros, signed zeros,
+ * NaN and Inf values are legal and stored.  opt may be NULL (defaults).
+ * Errors: CB_ERROR_INVALID_VALUE for bad input, CB_ERROR_OUT_OF_MEMORY,
+ * CB_ERROR_HIP. */
+cb_status_t cb_create(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                      const int32_t *col_idx, const double *values, const cb_options_t *opt, void *stream);
+
+/* The same conversion without touching any GPU: the handle keeps the
+ * structure in host memory for inspection (cb_get_info, cb_export_csr,
+ * cb_export_structure).  cb_spmv / cb_spmm on it return
+ * CB_ERROR_NOT_SUPPORTED. */
+cb_status_t cb_create_host(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col_idx, const double *values, const cb_options_t *opt);
+
+/* y = alpha * A * x + beta * y over the CB structure (Section 3.5,
+ * Algorithms 3 and 4).  x: n device elements, y: m device elements, double
+ * for CB_VALUE_F64 and float otherwise (alpha and beta are then applied in
+ * FP32).  beta == 0 means y is only written (NaN in y does not propagate).
+ * Summation order differs from a sequential loop (results are within rounding
+ * of the exact product).  x and y must not overlap.  Errors:
+ * CB_ERROR_INVALID_VALUE (NULL handle or vectors), CB_ERROR_NOT_SUPPORTED
+ * (host-only handle), CB_ERROR_HIP (launch failure). */
+cb_status_t cb_spmv(cb_matrix_t A, double alpha, const void *x, double beta, void *y, void *stream);
+
+/* Y = alpha * A * X + beta * Y for k right-hand sides.  X is n x k and Y is
+ * m x k, both row-major device arrays with leading dimensions ldx >= k and
+ * ldy >= k (elements).  Element type as for cb_spmv.  k == 1 is cb_spmv.
+ * Dense tiles use the matrix cores (MFMA) when k >= 8 and the values are
+ * FP64.  Errors as for cb_spmv, plus CB_ERROR_INVALID_VALUE for k < 1 or
+ * ld < k. */
+cb_status_t cb_spmm(cb_matrix_t A, int32_t k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
+                    int64_t ldy, void *stream);
+
+/* Release the handle and its device memory.  cb_destroy(NULL) is a no-op. */
+cb_status_t cb_destroy(cb_matrix_t A);
+
+/* Rebuild CSR from the stored structure (for a device handle, from the
+ * device copy) into HOST buffers: row_ptr[m+1], col_idx[nnz] and values[nnz]
+ * in the storage type (double, float, or the 16-bit bf16 pattern).  For FP64
+ * storage the result equals the cb_create input bit for bit. */
+cb_status_t cb_export_csr(cb_matrix_t A, int64_t *row_ptr, int32_t *col_idx, void *values);
+
+/* Sizes, counts and statistics of the structure.  info->struct_size must be
+ * set by the caller. */
+cb_status_t cb_get_info(cb_matrix_t A, cb_info_t *info);
+
+/* Copy the structure into the caller's host buffers (see cb_structure_t). */
+cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *out);
+
+/* Device-to-device copy of `bytes` bytes with the library's streaming copy
+ * kernel (16-byte loads and stores), used to measure the achievable HBM
+ * bandwidth of the device.  src and dst must be 16-byte aligned device
+ * pointers and must not overlap; bytes must be a multiple of 16. */
+cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
+/* Message for the last non-success status returned on this thread. */
+const char *cb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBSPMV_H */

@@ -1,0 +1,296 @@
+"""Python binding of libcbspmv (ctypes).
+
+Argument marshalling only: every step of the conversion and of the products
+runs in the native library (host converter in C++, products in the HIP
+kernels).  Functions carry the C ABI's names.  Vectors are torch tensors on
+the GPU (or raw device pointers as ints); torch is used for device memory and
+streams only.  Importing this module fails loudly when the library has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbspmv.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "cbspmv.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2605_18515_amd.build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CB_SUCCESS, CB_ERROR_INVALID_VALUE, CB_ERROR_OUT_OF_MEMORY, CB_ERROR_HIP, CB_ERROR_NOT_SUPPORTED, \
+    CB_ERROR_INTERNAL = range(6)
+CB_VALUE_F64, CB_VALUE_F32, CB_VALUE_BF16 = range(3)
+CB_FMT_COO, CB_FMT_CSR, CB_FMT_DENSE = range(3)
+CB_LB_NONE, CB_LB_PAPER, CB_LB_CONTIGUOUS = range(3)
+VALUE_TYPES = {"f64": CB_VALUE_F64, "f32": CB_VALUE_F32, "bf16": CB_VALUE_BF16}
+LB_MODES = {"none": CB_LB_NONE, "paper": CB_LB_PAPER, "contiguous": CB_LB_CONTIGUOUS}
+
+_i32, _i64, _u32, _dbl, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+
+
+class CbOptions(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
+                ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
+                ("wave_nnz", _i64), ("reserved", _i64 * 6)]
+
+
+class CbInfo(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("value_type", _i32), ("m", _i64), ("n", _i64), ("nnz", _i64),
+                ("npanels", _i64), ("ntiles", _i64), ("tiles_coo", _i64), ("tiles_csr", _i64),
+                ("tiles_dense", _i64), ("col_agg", _i32), ("lb_mode", _i32), ("super_sparse_share", _dbl),
+                ("plain_tiles", _i64), ("payload_bytes", _i64), ("meta_bytes", _i64), ("restore_bytes", _i64),
+                ("sched_bytes", _i64), ("nquanta", _i64), ("nwaves", _i64), ("shared_panels", _i64),
+                ("prepass_panels", _i64), ("quantum_nnz_max", _i64), ("quantum_nnz_mean", _dbl),
+                ("quantum_nnz_std", _dbl), ("wave_nnz_max", _i64), ("wave_nnz_mean", _dbl), ("wave_nnz_std", _dbl),
+                ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
+                ("reserved0", _i32), ("reserved", _i64 * 8)]
+
+
+class CbStructure(ctypes.Structure):
+    _fields_ = [(n, _p) for n in ("tile_row", "tile_col", "tile_nnz", "tile_vp", "tile_type", "tile_ori", "payload",
+                                  "restore_cols", "cols_offset", "quantum_ptr", "wave_ptr", "panel_shared",
+                                  "prepass_list")]
+
+
+_lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
+_lib.cb_create.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions), _p]
+_lib.cb_create_host.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions)]
+_lib.cb_spmv.argtypes = [_p, _dbl, _p, _dbl, _p, _p]
+_lib.cb_spmm.argtypes = [_p, _i32, _dbl, _p, _i64, _dbl, _p, _i64, _p]
+_lib.cb_destroy.argtypes = [_p]
+_lib.cb_export_csr.argtypes = [_p, _p, _p, _p]
+_lib.cb_get_info.argtypes = [_p, ctypes.POINTER(CbInfo)]
+_lib.cb_export_structure.argtypes = [_p, ctypes.POINTER(CbStructure)]
+_lib.cb_copy_probe.argtypes = [_p, _p, _i64, _p]
+_lib.cb_last_error.argtypes = []
+_lib.cb_last_error.restype = ctypes.c_char_p
+for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
+           "cb_get_info", "cb_export_structure", "cb_copy_probe"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class CbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cbspmv status {status}: {msg}")
+        self.status = status
+
+
+def cb_last_error() -> str:
+    return (_lib.cb_last_error() or b"").decode()
+
+
+def _check(st: int) -> None:
+    if st != CB_SUCCESS:
+        raise CbError(st, cb_last_error())
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/cbspmv.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:cb_status_t|const char \*)\s*(cb_\w+)\s*\(", text, re.M)))
+
+
+def library_handle() -> ctypes.CDLL:
+    return _lib
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream  # torch.cuda.Stream
+
+
+def _dev_ptr(t, dtype_name: str | None = None, numel: int | None = None):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("vectors must live on the GPU")
+    if dtype_name is not None and str(t.dtype) != dtype_name:
+        raise ValueError(f"expected {dtype_name}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor has {t.numel()} elements, {numel} needed")
+    return t.data_ptr()
+
+
+def cb_options_default(**overrides) -> CbOptions:
+    o = CbOptions()
+    _check(_lib.cb_options_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if k == "value_type" and isinstance(v, str):
+            v = VALUE_TYPES[v]
+        if k == "lb_mode" and isinstance(v, str):
+            v = LB_MODES[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _csr_args(row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(values, dtype=np.float64)
+    return rp, ci, va
+
+
+def cb_create(m, n, nnz, row_ptr, col_idx, values, opt: CbOptions | None = None, stream=None) -> int:
+    rp, ci, va = _csr_args(row_ptr, col_idx, values)
+    h = _p()
+    _check(_lib.cb_create(ctypes.byref(h), m, n, nnz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                          ctypes.byref(opt) if opt is not None else None, _stream_ptr(stream)))
+    return h.value
+
+
+def cb_create_host(m, n, nnz, row_ptr, col_idx, values, opt: CbOptions | None = None) -> int:
+    rp, ci, va = _csr_args(row_ptr, col_idx, values)
+    h = _p()
+    _check(_lib.cb_create_host(ctypes.byref(h), m, n, nnz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                               ctypes.byref(opt) if opt is not None else None))
+    return h.value
+
+
+def cb_destroy(A: int) -> None:
+    _check(_lib.cb_destroy(A))
+
+
+def cb_spmv(A: int, alpha: float, x, beta: float, y, stream=None) -> None:
+    _check(_lib.cb_spmv(A, float(alpha), _dev_ptr(x), float(beta), _dev_ptr(y), _stream_ptr(stream)))
+
+
+def cb_spmm(A: int, k: int, alpha: float, X, ldx: int, beta: float, Y, ldy: int, stream=None) -> None:
+    _check(_lib.cb_spmm(A, int(k), float(alpha), _dev_ptr(X), int(ldx), float(beta), _dev_ptr(Y), int(ldy),
+                        _stream_ptr(stream)))
+
+
+def cb_get_info(A: int) -> dict:
+    info = CbInfo()
+    info.struct_size = ctypes.sizeof(CbInfo)
+    _check(_lib.cb_get_info(A, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in CbInfo._fields_ if not name.startswith("reserved")}
+
+
+_VDT = {CB_VALUE_F64: np.float64, CB_VALUE_F32: np.float32, CB_VALUE_BF16: np.uint16}
+
+
+def cb_export_csr(A: int):
+    """(row_ptr int64, col_idx int32, values) with values in the storage type
+    (float64, float32, or uint16 bf16 bit patterns)."""
+    info = cb_get_info(A)
+    m, nnz = info["m"], info["nnz"]
+    rp = np.empty(m + 1, np.int64)
+    ci = np.empty(max(nnz, 1), np.int32)
+    va = np.empty(max(nnz, 1), _VDT[info["value_type"]])
+    _check(_lib.cb_export_csr(A, rp.ctypes.data, ci.ctypes.data, va.ctypes.data))
+    return rp, ci[:nnz], va[:nnz]
+
+
+def cb_export_structure(A: int) -> dict:
+    info = cb_get_info(A)
+    NT, P = info["ntiles"], info["npanels"]
+    nrest = (info["restore_bytes"] // 4 - (P + 1)) if info["col_agg"] else 0
+    arrs = {
+        "tile_row": np.empty(NT, np.int32), "tile_col": np.empty(NT, np.int32), "tile_nnz": np.empty(NT, np.int32),
+        "tile_vp": np.empty(NT, np.int64), "tile_type": np.empty(NT, np.uint8), "tile_ori": np.empty(NT, np.int32),
+        "payload": np.empty(info["payload_bytes"], np.uint8), "restore_cols": np.empty(nrest, np.int32),
+        "cols_offset": np.empty(P + 1 if info["col_agg"] else 0, np.int32),
+        "quantum_ptr": np.empty(info["nquanta"] + 1, np.int32), "wave_ptr": np.empty(info["nwaves"] + 1, np.int32),
+        "panel_shared": np.empty(P, np.uint8), "prepass_list": np.empty(info["prepass_panels"], np.int32),
+    }
+    s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
+    _check(_lib.cb_export_structure(A, ctypes.byref(s)))
+    return arrs
+
+
+def cb_copy_probe(src, dst, nbytes: int, stream=None) -> None:
+    _check(_lib.cb_copy_probe(_dev_ptr(src), _dev_ptr(dst), int(nbytes), _stream_ptr(stream)))
+
+
+class CbMatrix:
+    """Owning wrapper of a cb_matrix_t handle."""
+
+    def __init__(self, handle: int, vtype: int):
+        self.handle = handle
+        self.vtype = vtype
+        self._info = None
+
+    @classmethod
+    def from_csr(cls, csr, device: bool = True, stream=None, **opts) -> "CbMatrix":
+        o = cb_options_default(**opts)
+        if device:
+            h = cb_create(csr.m, csr.n, csr.nnz, csr.row_ptr, csr.col_idx, csr.values, o, stream)
+        else:
+            h = cb_create_host(csr.m, csr.n, csr.nnz, csr.row_ptr, csr.col_idx, csr.values, o)
+        return cls(h, o.value_type)
+
+    @property
+    def info(self) -> dict:
+        if self._info is None:
+            self._info = cb_get_info(self.handle)
+        return self._info
+
+    @property
+    def vector_dtype(self) -> str:
+        return "torch.float64" if self.vtype == CB_VALUE_F64 else "torch.float32"
+
+    def spmv(self, x, y, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        inf = self.info
+        _dev_ptr(x, self.vector_dtype, inf["n"]) if inf["n"] else None
+        _dev_ptr(y, self.vector_dtype, inf["m"]) if inf["m"] else None
+        cb_spmv(self.handle, alpha, x, beta, y, stream)
+        return y
+
+    def spmm(self, X, Y, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+            raise ValueError("X (n x k) and Y (m x k) must be 2-D with the same k")
+        if X.stride(1) != 1 or Y.stride(1) != 1:
+            raise ValueError("X and Y must be row-major")
+        inf = self.info
+        if X.shape[0] != inf["n"] or Y.shape[0] != inf["m"]:
+            raise ValueError("shape mismatch")
+        _dev_ptr(X, self.vector_dtype)
+        _dev_ptr(Y, self.vector_dtype)
+        k = X.shape[1]
+        cb_spmm(self.handle, k, alpha, X, max(X.stride(0), k), beta, Y, max(Y.stride(0), k), stream)
+        return Y
+
+    def export_csr(self):
+        return cb_export_csr(self.handle)
+
+    def structure(self) -> dict:
+        return cb_export_structure(self.handle)
+
+    def close(self):
+        if self.handle:
+            cb_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,35 @@
+// Device view of a converted matrix and the kernel launchers (internal to libcbspmv).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cbd {
+
+// Pointers into the handle's single device allocation.  The tile arrays are in
+// kernel order: wavefront w processes tiles [wave_ptr[w], wave_ptr[w+1]).
+struct DevView {
+    const int32_t *tile_row;      // 16-row panel of the tile
+    const int32_t *tile_col;      // column block, or aggregated chunk
+    const int32_t *tile_nnz;
+    const int64_t *tile_vp;       // byte offset of the tile's packed region
+    const uint8_t *tile_type;     // 0 COO, 1 CSR, 2 Dense
+    const uint8_t *payload;
+    const int32_t *restore_cols;  // aggregated -> original column (col_agg only)
+    const int32_t *cols_offset;   // npanels + 1 (col_agg only)
+    const int32_t *wave_ptr;      // nwaves + 1
+    const uint8_t *panel_shared;  // npanels
+    const int32_t *prepass_list;  // nprepass
+    int64_t m, n;
+    int32_t nwaves, npanels, nprepass, col_agg;
+};
+
+// vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float)
+hipError_t launch_spmv(const DevView &d, int vtype, double alpha, const void *x, double beta, void *y,
+                       hipStream_t stream);
+hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const void *X, int64_t ldx, double beta,
+                       void *Y, int64_t ldy, hipStream_t stream);
+hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream);
+
+}  // namespace cbd

@@ -1,0 +1,56 @@
+// Host-side CB structure and converter interface (internal to libcbspmv).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cbspmv.h"
+
+namespace cbh {
+
+constexpr int kBlk = 16;          // Section 3.1: 16 x 16 sub-blocks
+constexpr int kSuperSparse = 32;  // Section 3.3.1: fewer than 32 non-zeros
+constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte boundary
+constexpr int kDenseMaskBytes = 32;
+constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
+
+struct HostStructure {
+    int64_t m = 0, n = 0, nnz = 0;
+    int vtype = CB_VALUE_F64;
+    int vsize = 8;
+    int col_agg = 0;
+    double share = 0.0;
+    int64_t plain_tiles = 0;
+    int lb_mode = CB_LB_CONTIGUOUS;
+    int quantum_tiles = 8;
+    int64_t npanels = 0, ntiles = 0;
+    // kernel order (after load balance)
+    std::vector<int32_t> tile_row, tile_col, tile_nnz, tile_ori;
+    std::vector<int64_t> tile_vp;
+    std::vector<uint8_t> tile_type;
+    std::vector<uint8_t> payload;
+    std::vector<int32_t> restore_cols, cols_offset;
+    std::vector<int32_t> quantum_ptr, wave_ptr;
+    std::vector<uint8_t> panel_shared;
+    std::vector<int32_t> prepass_list;
+    // counts kept when the big arrays move to the device
+    int64_t payload_bytes = 0, nrestore = 0, nquanta = 0, nwaves = 0, nprepass = 0, nshared = 0;
+    int64_t tiles_fmt[3] = {0, 0, 0};
+    int64_t quantum_nnz_max = 0, wave_nnz_max = 0;
+    double quantum_nnz_mean = 0, quantum_nnz_std = 0, wave_nnz_mean = 0, wave_nnz_std = 0;
+    double convert_seconds = 0.0;
+};
+
+int padding(int64_t index_bytes, int vsize);
+int64_t region_bytes(int fmt, int64_t nnz, int vsize);
+uint32_t f32_bits_rne(double v);
+uint16_t bf16_bits_rne(double v);
+
+cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err);
+cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_idx, void *values, std::string &err);
+void fill_info(const HostStructure &s, cb_info_t &info);
+int64_t spmv_bytes(const HostStructure &s);
+
+}  // namespace cbh

@@ -1,0 +1,650 @@
+// Host converter: CSR -> CB structure (Section 3, Fig. 7 order), CB -> CSR
+// export and structure statistics.  Plain C++17, no HIP.
+#include <sched.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <numeric>
+#include <queue>
+#include <thread>
+
+#include "cb_host.h"
+
+namespace cbh {
+
+namespace {
+
+int default_threads() {
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+        int c = CPU_COUNT(&set);
+        if (c > 0) return c;
+    }
+    unsigned h = std::thread::hardware_concurrency();
+    return h ? (int)h : 1;
+}
+
+// Runs fn(begin, end) over [0, n) in chunks of `grain`, handed out dynamically.
+template <class F>
+bool parallel_dynamic(int nthreads, int64_t n, int64_t grain, F &&fn, std::string &err) {
+    if (n <= 0) return true;
+    std::atomic<int64_t> next{0};
+    std::atomic<bool> failed{false};
+    std::mutex mu;
+    auto worker = [&]() {
+        try {
+            for (;;) {
+                if (failed.load(std::memory_order_relaxed)) return;
+                int64_t b = next.fetch_add(grain);
+                if (b >= n) return;
+                fn(b, std::min(n, b + grain));
+            }
+        } catch (const std::bad_alloc &) {
+            std::lock_guard<std::mutex> g(mu);
+            failed = true;
+            err = "host allocation failed during conversion";
+        } catch (const std::exception &e) {
+            std::lock_guard<std::mutex> g(mu);
+            failed = true;
+            err = e.what();
+        }
+    };
+    int T = (int)std::max<int64_t>(1, std::min<int64_t>(nthreads, (n + grain - 1) / grain));
+    std::vector<std::thread> th;
+    for (int i = 1; i < T; ++i) th.emplace_back(worker);
+    worker();
+    for (auto &t : th) t.join();
+    return !failed.load();
+}
+
+struct Entry {
+    uint64_t key;  // chunk << 8 | local_row << 4 | local_col
+    int64_t idx;   // position in the CSR arrays
+};
+
+inline int select_format(int64_t nnz, int th1, int th2) {
+    if (nnz < th1) return CB_FMT_COO;  // Section 3.3.2
+    if (nnz > th2) return CB_FMT_DENSE;
+    return CB_FMT_CSR;
+}
+
+inline void store_value(uint8_t *dst, double v, int vtype) {
+    if (vtype == CB_VALUE_F64) {
+        std::memcpy(dst, &v, 8);
+    } else if (vtype == CB_VALUE_F32) {
+        uint32_t b = f32_bits_rne(v);
+        std::memcpy(dst, &b, 4);
+    } else {
+        uint16_t b = bf16_bits_rne(v);
+        std::memcpy(dst, &b, 2);
+    }
+}
+
+struct PanelCounts {
+    int64_t tiles = 0, bytes = 0, cols = 0, fmt[3] = {0, 0, 0};
+};
+
+// Groups the entries of one 16-row panel into tiles.  With aggregation the
+// panel's distinct columns (ascending) are its aggregated columns and chunk c
+// holds aggregated columns [16c, 16c + 16) (Section 3.3.1); without it chunk
+// = column / 16.  Entries end up row-major inside each tile.
+class PanelBuilder {
+  public:
+    PanelBuilder(const int64_t *rp, const int32_t *ci, int64_t m) : rp_(rp), ci_(ci), m_(m) {}
+
+    void build(int64_t p, bool agg) {
+        const int64_t r0 = p * kBlk, r1 = std::min(m_, r0 + kBlk);
+        const int64_t e0 = rp_[r0], e1 = rp_[r1];
+        cols_.clear();
+        ent_.clear();
+        if (agg) {
+            cols_.assign(ci_ + e0, ci_ + e1);
+            std::sort(cols_.begin(), cols_.end());
+            cols_.erase(std::unique(cols_.begin(), cols_.end()), cols_.end());
+        }
+        ent_.reserve((size_t)(e1 - e0));
+        for (int64_t r = r0; r < r1; ++r) {
+            const uint64_t lr = (uint64_t)(r - r0);
+            for (int64_t t = rp_[r]; t < rp_[r + 1]; ++t) {
+                uint64_t a;
+                if (agg)
+                    a = (uint64_t)(std::lower_bound(cols_.begin(), cols_.end(), ci_[t]) - cols_.begin());
+                else
+                    a = (uint64_t)ci_[t];
+                ent_.push_back({((a >> 4) << 8) | (lr << 4) | (a & 15u), t});
+            }
+        }
+        std::sort(ent_.begin(), ent_.end(), [](const Entry &x, const Entry &y) { return x.key < y.key; });
+    }
+
+    const std::vector<int32_t> &cols() const { return cols_; }
+    const std::vector<Entry> &entries() const { return ent_; }
+
+  private:
+    const int64_t *rp_;
+    const int32_t *ci_;
+    int64_t m_;
+    std::vector<int32_t> cols_;
+    std::vector<Entry> ent_;
+};
+
+template <class F>
+void for_each_tile(const std::vector<Entry> &ent, F &&f) {
+    size_t b = 0;
+    while (b < ent.size()) {
+        size_t e = b + 1;
+        const uint64_t chunk = ent[b].key >> 8;
+        while (e < ent.size() && (ent[e].key >> 8) == chunk) ++e;
+        f((int64_t)chunk, b, e);
+        b = e;
+    }
+}
+
+void moments(const std::vector<int64_t> &v, int64_t &mx, double &mean, double &sd) {
+    mx = 0;
+    mean = sd = 0.0;
+    if (v.empty()) return;
+    long double s = 0, s2 = 0;
+    for (int64_t x : v) {
+        mx = std::max(mx, x);
+        s += x;
+    }
+    mean = (double)(s / v.size());
+    for (int64_t x : v) s2 += ((long double)x - mean) * ((long double)x - mean);
+    sd = std::sqrt((double)(s2 / v.size()));
+}
+
+}  // namespace
+
+int padding(int64_t index_bytes, int vsize) {
+    // Algorithm 3: (nnz * size(Idx)) mod size(Val), complemented when non-zero
+    const int r = (int)(index_bytes % vsize);
+    return r ? vsize - r : 0;
+}
+
+int64_t region_bytes(int fmt, int64_t nnz, int vsize) {
+    int64_t b;
+    if (fmt == CB_FMT_COO)
+        b = nnz + padding(nnz, vsize) + nnz * vsize;
+    else if (fmt == CB_FMT_CSR)
+        b = kBlk + nnz + padding(kBlk + nnz, vsize) + nnz * vsize;
+    else
+        b = (int64_t)kBlk * kBlk * vsize + kDenseMaskBytes;
+    return (b + kTileAlign - 1) / kTileAlign * kTileAlign;
+}
+
+uint32_t f32_bits_rne(double v) {
+    // the FP64 -> FP32 conversion of the host FPU in its default
+    // round-to-nearest-even mode; NaN payloads keep their top bits, quiet
+    const float f = (float)v;
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    return b;
+}
+
+uint16_t bf16_bits_rne(double v) {
+    // Round-to-odd to FP32 followed by round-to-nearest-even to BF16 equals a
+    // single RNE rounding from FP64 (Boldo and Melquiond, "Emulation of FMA
+    // and correctly rounded sums: proved algorithms using rounding to odd",
+    // IEEE TC 2008): FP32 keeps 16 more significand bits than BF16.
+    if (std::isnan(v)) return (uint16_t)((f32_bits_rne(v) >> 16) | 0x0040u);
+    const float f = (float)v;
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    if (std::isfinite(f) && (double)f != v) {
+        if (std::fabs((double)f) > std::fabs(v)) b -= 1u;  // step back to the truncated value
+        b |= 1u;                                           // sticky bit: round to odd
+    }
+    if ((b & 0x7F800000u) == 0x7F800000u) return (uint16_t)(b >> 16);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t kLim = (int64_t)1 << 31;
+    if (m < 0 || n < 0 || nnz < 0) { err = "negative size"; return CB_ERROR_INVALID_VALUE; }
+    if (m >= kLim || n >= kLim || nnz >= kLim) { err = "m, n and nnz must be below 2^31"; return CB_ERROR_INVALID_VALUE; }
+    if (!row_ptr && !(m == 0 && nnz == 0)) { err = "row_ptr is NULL"; return CB_ERROR_INVALID_VALUE; }
+    if (nnz > 0 && (!col_idx || !values)) { err = "col_idx or values is NULL"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.value_type < 0 || opt.value_type > 2) { err = "value_type out of range"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.col_agg < -1 || opt.col_agg > 1) { err = "col_agg must be -1, 0 or 1"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.th1 < 0 || opt.th2 < 0) { err = "th1 and th2 must be non-negative"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.quantum_tiles < 1 || opt.quantum_tiles > (1 << 20)) { err = "quantum_tiles out of range"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.lb_mode < 0 || opt.lb_mode > 2) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
+    if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
+    const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
+
+    // ---- validation: canonical CSR ------------------------------------------
+    if (m == 0 && nnz != 0) { err = "nnz must be 0 when m == 0"; return CB_ERROR_INVALID_VALUE; }
+    if (row_ptr) {
+        if (row_ptr[0] != 0) { err = "row_ptr[0] must be 0"; return CB_ERROR_INVALID_VALUE; }
+        if (row_ptr[m] != nnz) { err = "row_ptr[m] must equal nnz"; return CB_ERROR_INVALID_VALUE; }
+        for (int64_t i = 0; i < m; ++i)
+            if (row_ptr[i + 1] < row_ptr[i]) {
+                err = "row_ptr decreases at row " + std::to_string(i);
+                return CB_ERROR_INVALID_VALUE;
+            }
+    }
+    std::atomic<int64_t> bad_row{INT64_MAX};
+    std::string perr;
+    if (!parallel_dynamic(nth, m, 4096, [&](int64_t b, int64_t e) {
+            for (int64_t i = b; i < e; ++i) {
+                for (int64_t t = row_ptr[i]; t < row_ptr[i + 1]; ++t) {
+                    const int32_t c = col_idx[t];
+                    if (c < 0 || c >= n || (t > row_ptr[i] && c <= col_idx[t - 1])) {
+                        int64_t cur = bad_row.load();
+                        while (i < cur && !bad_row.compare_exchange_weak(cur, i)) {}
+                        break;
+                    }
+                }
+            }
+        }, perr)) { err = perr; return CB_ERROR_OUT_OF_MEMORY; }
+    if (bad_row.load() != INT64_MAX) {
+        err = "row " + std::to_string(bad_row.load()) +
+              ": column indices must lie in [0, n) and increase strictly within a row";
+        return CB_ERROR_INVALID_VALUE;
+    }
+
+    HostStructure s;
+    s.m = m;
+    s.n = n;
+    s.nnz = nnz;
+    s.vtype = opt.value_type;
+    s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
+    s.lb_mode = opt.lb_mode;
+    s.quantum_tiles = opt.quantum_tiles;
+    const int64_t P = (m + kBlk - 1) / kBlk;
+    s.npanels = P;
+
+    try {
+        // ---- Section 3.1 + 3.3.1: plain partition census, th0 decision ------
+        std::vector<int64_t> plain_cnt(P, 0), super_cnt(P, 0);
+        if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
+                std::vector<int32_t> cb;
+                for (int64_t p = b; p < e; ++p) {
+                    const int64_t r0 = p * kBlk, r1 = std::min(m, r0 + kBlk);
+                    cb.clear();
+                    for (int64_t t = row_ptr[r0]; t < row_ptr[r1]; ++t) cb.push_back(col_idx[t] >> 4);
+                    std::sort(cb.begin(), cb.end());
+                    size_t i = 0;
+                    while (i < cb.size()) {
+                        size_t j = i;
+                        while (j < cb.size() && cb[j] == cb[i]) ++j;
+                        plain_cnt[p] += 1;
+                        if (j - i < (size_t)kSuperSparse) super_cnt[p] += 1;
+                        i = j;
+                    }
+                }
+            }, err)) return CB_ERROR_OUT_OF_MEMORY;
+        const int64_t plain = std::accumulate(plain_cnt.begin(), plain_cnt.end(), (int64_t)0);
+        const int64_t super = std::accumulate(super_cnt.begin(), super_cnt.end(), (int64_t)0);
+        s.plain_tiles = plain;
+        s.share = plain ? (double)super / (double)plain : 0.0;
+        bool agg;
+        if (opt.col_agg == 0) agg = false;
+        else if (opt.col_agg == 1) agg = true;
+        else agg = s.share >= opt.th0;  // aggregation skipped when the super-sparse share is low
+        s.col_agg = agg ? 1 : 0;
+
+        // ---- pass A: tiles, bytes and aggregated columns per panel ----------
+        std::vector<PanelCounts> pc(P);
+        if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
+                PanelBuilder pb(row_ptr, col_idx, m);
+                for (int64_t p = b; p < e; ++p) {
+                    pb.build(p, agg);
+                    PanelCounts c;
+                    c.cols = agg ? (int64_t)pb.cols().size() : 0;
+                    for_each_tile(pb.entries(), [&](int64_t, size_t lo, size_t hi) {
+                        const int fmt = select_format((int64_t)(hi - lo), opt.th1, opt.th2);
+                        c.tiles += 1;
+                        c.fmt[fmt] += 1;
+                        c.bytes += region_bytes(fmt, (int64_t)(hi - lo), s.vsize);
+                    });
+                    pc[p] = c;
+                }
+            }, err)) return CB_ERROR_OUT_OF_MEMORY;
+
+        std::vector<int64_t> tile_base(P + 1, 0), byte_base(P + 1, 0), col_base(P + 1, 0);
+        for (int64_t p = 0; p < P; ++p) {
+            tile_base[p + 1] = tile_base[p] + pc[p].tiles;
+            byte_base[p + 1] = byte_base[p] + pc[p].bytes;
+            col_base[p + 1] = col_base[p] + pc[p].cols;
+            for (int f = 0; f < 3; ++f) s.tiles_fmt[f] += pc[p].fmt[f];
+        }
+        const int64_t NT = tile_base[P];
+        s.ntiles = NT;
+        if (NT >= kLim || col_base[P] >= kLim) { err = "structure too large"; return CB_ERROR_NOT_SUPPORTED; }
+
+        // natural-order arrays and the packed payload (Section 3.2)
+        std::vector<int32_t> nrow(NT), ncol(NT), nnzv(NT);
+        std::vector<int64_t> nvp(NT);
+        std::vector<uint8_t> ntype(NT);
+        s.payload.assign((size_t)byte_base[P], 0);
+        if (agg) {
+            s.restore_cols.resize((size_t)col_base[P]);
+            s.cols_offset.resize((size_t)P + 1);
+            for (int64_t p = 0; p <= P; ++p) s.cols_offset[p] = (int32_t)col_base[p];
+        }
+
+        // ---- pass B: write tiles --------------------------------------------
+        const int vs = s.vsize, vt = s.vtype;
+        if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
+                PanelBuilder pb(row_ptr, col_idx, m);
+                for (int64_t p = b; p < e; ++p) {
+                    pb.build(p, agg);
+                    if (agg) std::copy(pb.cols().begin(), pb.cols().end(), s.restore_cols.begin() + col_base[p]);
+                    int64_t ti = tile_base[p], off = byte_base[p];
+                    const auto &ent = pb.entries();
+                    for_each_tile(ent, [&](int64_t chunk, size_t lo, size_t hi) {
+                        const int64_t nz = (int64_t)(hi - lo);
+                        const int fmt = select_format(nz, opt.th1, opt.th2);
+                        nrow[ti] = (int32_t)p;
+                        ncol[ti] = (int32_t)chunk;
+                        nnzv[ti] = (int32_t)nz;
+                        nvp[ti] = off;
+                        ntype[ti] = (uint8_t)fmt;
+                        uint8_t *base = s.payload.data() + off;
+                        if (fmt == CB_FMT_DENSE) {
+                            uint8_t *mask = base + (int64_t)kBlk * kBlk * vs;
+                            for (size_t q = lo; q < hi; ++q) {
+                                const int slot = (int)(ent[q].key & 0xFFu);  // (lr << 4 | lc) = lr*16 + lc
+                                store_value(base + (int64_t)slot * vs, values[ent[q].idx], vt);
+                                mask[slot >> 3] |= (uint8_t)(1u << (slot & 7));
+                            }
+                        } else {
+                            uint8_t *codes = base;
+                            int64_t hdr = 0;
+                            if (fmt == CB_FMT_CSR) {
+                                hdr = kBlk;
+                                codes = base + kBlk;
+                                // one-byte row starts: entries before row r
+                                int cnt[kBlk + 1] = {0};
+                                for (size_t q = lo; q < hi; ++q) cnt[((ent[q].key >> 4) & 15u) + 1] += 1;
+                                for (int r = 0; r < kBlk; ++r) {
+                                    cnt[r + 1] += cnt[r];
+                                    base[r] = (uint8_t)cnt[r];
+                                }
+                            }
+                            uint8_t *vals = codes + nz + padding(hdr + nz, vs);
+                            for (size_t q = lo; q < hi; ++q) {
+                                const uint32_t lr = (uint32_t)((ent[q].key >> 4) & 15u), lc = (uint32_t)(ent[q].key & 15u);
+                                codes[q - lo] = (uint8_t)((lc << 4) | lr);  // Algorithm 3: row = b & 15, col = b >> 4
+                                store_value(vals + (int64_t)(q - lo) * vs, values[ent[q].idx], vt);
+                            }
+                        }
+                        off += region_bytes(fmt, nz, vs);
+                        ++ti;
+                    });
+                }
+            }, err)) return CB_ERROR_OUT_OF_MEMORY;
+
+        // ---- Section 3.4: grouping into work units ---------------------------
+        const int W = opt.quantum_tiles;
+        std::vector<int32_t> order(NT);
+        std::vector<int32_t> qptr;
+        if (opt.lb_mode == CB_LB_PAPER) {
+            // Algorithm 2: descending nnz (stable), min-heap of (load, tb_id), W slots per block
+            std::vector<int32_t> byn(NT);
+            std::iota(byn.begin(), byn.end(), 0);
+            std::stable_sort(byn.begin(), byn.end(), [&](int32_t a, int32_t b) { return nnzv[a] > nnzv[b]; });
+            const int64_t T = (NT + W - 1) / W;
+            struct Slot {
+                int64_t load;
+                int64_t tb;
+                int32_t warps;
+            };
+            auto cmp = [](const Slot &a, const Slot &b) { return a.load != b.load ? a.load > b.load : a.tb > b.tb; };
+            std::priority_queue<Slot, std::vector<Slot>, decltype(cmp)> pq(cmp);
+            for (int64_t tb = 0; tb < T; ++tb) pq.push({0, tb, 0});
+            std::vector<int32_t> slot((size_t)(T * W), -1);
+            for (int64_t i = 0; i < NT; ++i) {
+                Slot top = pq.top();
+                pq.pop();
+                const int32_t blk = byn[i];
+                slot[(size_t)(top.tb * W + top.warps)] = blk;  // end = tb_id * W + warps
+                top.load += nnzv[blk];
+                top.warps += 1;
+                if (top.warps < W) pq.push(top);
+            }
+            // sort by end = keep slot order, dropping the empty slots but not the group boundaries
+            qptr.assign((size_t)T + 1, 0);
+            int64_t k = 0;
+            for (int64_t tb = 0; tb < T; ++tb) {
+                for (int w = 0; w < W; ++w) {
+                    const int32_t blk = slot[(size_t)(tb * W + w)];
+                    if (blk >= 0) order[k++] = blk;
+                }
+                qptr[tb + 1] = (int32_t)k;
+            }
+        } else {
+            std::iota(order.begin(), order.end(), 0);
+            if (opt.lb_mode == CB_LB_NONE) {
+                const int64_t T = (NT + W - 1) / W;
+                qptr.assign((size_t)T + 1, 0);
+                for (int64_t tb = 0; tb <= T; ++tb) qptr[tb] = (int32_t)std::min<int64_t>(NT, tb * W);
+            }
+        }
+
+        // target work per wavefront range, in non-zero equivalents
+        const int64_t total_w = nnz + (int64_t)kTileCost * NT;
+        int64_t target = opt.wave_nnz;
+        if (target == 0) target = std::min<int64_t>(4096, std::max<int64_t>(64, (total_w + 16383) / 16384));
+        auto tw = [&](int32_t i) { return (int64_t)nnzv[i] + kTileCost; };
+
+        std::vector<int32_t> wptr;
+        if (opt.lb_mode == CB_LB_CONTIGUOUS) {
+            // natural order cut at panel boundaries; a panel heavier than twice
+            // the target is cut at tile boundaries into pieces of about the target
+            wptr.push_back(0);
+            int64_t cur = 0;
+            for (int64_t p = 0; p < P; ++p) {
+                const int64_t b = tile_base[p], e = tile_base[p + 1];
+                if (b == e) continue;
+                int64_t wp = 0;
+                for (int64_t i = b; i < e; ++i) wp += tw((int32_t)i);
+                if (wp > 2 * target) {
+                    if (cur > 0) { wptr.push_back((int32_t)b); cur = 0; }
+                    const int64_t pieces = (wp + target - 1) / target;
+                    const int64_t piece_w = (wp + pieces - 1) / pieces;
+                    int64_t acc = 0;
+                    for (int64_t i = b; i < e; ++i) {
+                        acc += tw((int32_t)i);
+                        if (acc >= piece_w && i + 1 < e) { wptr.push_back((int32_t)(i + 1)); acc = 0; }
+                    }
+                    wptr.push_back((int32_t)e);
+                    cur = 0;
+                } else {
+                    if (cur > 0 && cur + wp > target) { wptr.push_back((int32_t)b); cur = 0; }
+                    cur += wp;
+                }
+            }
+            if (wptr.back() != (int32_t)NT) wptr.push_back((int32_t)NT);
+            if (NT == 0) wptr.assign(1, 0);
+            qptr = wptr;
+        } else {
+            const int64_t T = (int64_t)qptr.size() - 1;
+            const double mean_q = T > 0 ? (double)total_w / (double)T : 1.0;
+            const int64_t G = std::max<int64_t>(1, (int64_t)std::llround((double)target / std::max(1.0, mean_q)));
+            for (int64_t q = 0; q < T; q += G) wptr.push_back(qptr[q]);
+            wptr.push_back((int32_t)NT);
+            if (NT == 0) wptr.assign(1, 0);
+        }
+
+        // ---- kernel-order arrays --------------------------------------------
+        s.tile_row.resize(NT);
+        s.tile_col.resize(NT);
+        s.tile_nnz.resize(NT);
+        s.tile_vp.resize(NT);
+        s.tile_type.resize(NT);
+        s.tile_ori = order;
+        for (int64_t i = 0; i < NT; ++i) {
+            const int32_t o = order[i];
+            s.tile_row[i] = nrow[o];
+            s.tile_col[i] = ncol[o];
+            s.tile_nnz[i] = nnzv[o];
+            s.tile_vp[i] = nvp[o];
+            s.tile_type[i] = ntype[o];
+        }
+        s.quantum_ptr = qptr;
+        s.wave_ptr = wptr;
+
+        // a panel is owned when its tiles form one run inside one work range;
+        // otherwise it is shared (atomics after a y <- beta*y pre-pass); empty
+        // panels are written by the pre-pass alone
+        std::vector<int32_t> runs(P, 0);
+        const int64_t NW = (int64_t)wptr.size() - 1;
+        for (int64_t w = 0; w < NW; ++w)
+            for (int64_t i = wptr[w]; i < wptr[w + 1]; ++i)
+                if (i == wptr[w] || s.tile_row[i] != s.tile_row[i - 1]) runs[s.tile_row[i]] += 1;
+        s.panel_shared.assign(P, 0);
+        for (int64_t p = 0; p < P; ++p) {
+            if (runs[p] > 1) { s.panel_shared[p] = 1; s.nshared += 1; }
+            if (runs[p] != 1) s.prepass_list.push_back((int32_t)p);
+        }
+
+        // ---- statistics -------------------------------------------------------
+        std::vector<int64_t> qn, wn;
+        for (size_t q = 0; q + 1 < qptr.size(); ++q) {
+            int64_t a = 0;
+            for (int32_t i = qptr[q]; i < qptr[q + 1]; ++i) a += s.tile_nnz[i];
+            qn.push_back(a);
+        }
+        for (int64_t w = 0; w < NW; ++w) {
+            int64_t a = 0;
+            for (int32_t i = wptr[w]; i < wptr[w + 1]; ++i) a += s.tile_nnz[i];
+            wn.push_back(a);
+        }
+        moments(qn, s.quantum_nnz_max, s.quantum_nnz_mean, s.quantum_nnz_std);
+        moments(wn, s.wave_nnz_max, s.wave_nnz_mean, s.wave_nnz_std);
+        s.payload_bytes = (int64_t)s.payload.size();
+        s.nrestore = (int64_t)s.restore_cols.size();
+        s.nquanta = (int64_t)qptr.size() - 1;
+        s.nwaves = NW;
+        s.nprepass = (int64_t)s.prepass_list.size();
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed during conversion";
+        return CB_ERROR_OUT_OF_MEMORY;
+    }
+    s.convert_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    out = std::move(s);
+    return CB_SUCCESS;
+}
+
+cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_idx, void *values, std::string &err) {
+    if (!row_ptr || (s.nnz > 0 && (!col_idx || !values))) {
+        err = "NULL output buffer";
+        return CB_ERROR_INVALID_VALUE;
+    }
+    const int vs = s.vsize;
+    try {
+        // decode every tile into (row, col, value bits); tiles may come in any order
+        std::vector<int64_t> cnt((size_t)s.m + 1, 0);
+        auto visit = [&](auto &&emit) {
+            for (int64_t i = 0; i < s.ntiles; ++i) {
+                const int64_t p = s.tile_row[i], c = s.tile_col[i], nz = s.tile_nnz[i];
+                const int fmt = s.tile_type[i];
+                const uint8_t *base = s.payload.data() + s.tile_vp[i];
+                auto orig_col = [&](int lc) -> int64_t {
+                    if (s.col_agg) return s.restore_cols[(size_t)(s.cols_offset[p] + 16 * c + lc)];
+                    return 16 * c + lc;
+                };
+                if (fmt == CB_FMT_DENSE) {
+                    const uint8_t *mask = base + (int64_t)kBlk * kBlk * vs;
+                    for (int e = 0; e < kBlk * kBlk; ++e)
+                        if ((mask[e >> 3] >> (e & 7)) & 1) emit(16 * p + (e >> 4), orig_col(e & 15), base + (int64_t)e * vs);
+                } else {
+                    const int64_t hdr = fmt == CB_FMT_CSR ? kBlk : 0;
+                    const uint8_t *codes = base + hdr;
+                    const uint8_t *vals = codes + nz + padding(hdr + nz, vs);
+                    for (int64_t q = 0; q < nz; ++q)
+                        emit(16 * p + (codes[q] & 15), orig_col(codes[q] >> 4), vals + q * vs);
+                }
+            }
+        };
+        int64_t total = 0;
+        bool bad = false;
+        visit([&](int64_t r, int64_t, const uint8_t *) {
+            if (r < 0 || r >= s.m) { bad = true; return; }
+            cnt[(size_t)r + 1] += 1;
+            ++total;
+        });
+        if (bad || total != s.nnz) {
+            err = "stored structure is inconsistent";
+            return CB_ERROR_INTERNAL;
+        }
+        for (int64_t r = 0; r < s.m; ++r) cnt[r + 1] += cnt[r];
+        std::vector<int64_t> cur(cnt.begin(), cnt.end() - 1);
+        std::vector<std::pair<int32_t, uint64_t>> tmp((size_t)s.nnz);
+        visit([&](int64_t r, int64_t col, const uint8_t *v) {
+            uint64_t bits = 0;
+            std::memcpy(&bits, v, vs);
+            tmp[(size_t)cur[r]++] = {(int32_t)col, bits};
+        });
+        for (int64_t r = 0; r < s.m; ++r) {
+            std::sort(tmp.begin() + cnt[r], tmp.begin() + cnt[r + 1],
+                      [](const auto &a, const auto &b) { return a.first < b.first; });
+            row_ptr[r] = cnt[r];
+        }
+        if (s.m >= 0) row_ptr[s.m] = s.nnz;
+        uint8_t *vout = (uint8_t *)values;
+        for (int64_t t = 0; t < s.nnz; ++t) {
+            col_idx[t] = tmp[(size_t)t].first;
+            std::memcpy(vout + t * vs, &tmp[(size_t)t].second, vs);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed during export";
+        return CB_ERROR_OUT_OF_MEMORY;
+    }
+    return CB_SUCCESS;
+}
+
+int64_t spmv_bytes(const HostStructure &s) {
+    const int64_t xe = s.vtype == CB_VALUE_F64 ? 8 : 4;
+    int64_t b = s.payload_bytes + 21 * s.ntiles;  // payload + high-level arrays (4+4+4+8+1 per tile)
+    if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1);
+    b += 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;  // work ranges, panel flags, pre-pass list
+    b += xe * s.n + xe * s.m;                              // x read once, y written once
+    return b;
+}
+
+void fill_info(const HostStructure &s, cb_info_t &info) {
+    info.value_type = s.vtype;
+    info.m = s.m;
+    info.n = s.n;
+    info.nnz = s.nnz;
+    info.npanels = s.npanels;
+    info.ntiles = s.ntiles;
+    info.tiles_coo = s.tiles_fmt[0];
+    info.tiles_csr = s.tiles_fmt[1];
+    info.tiles_dense = s.tiles_fmt[2];
+    info.col_agg = s.col_agg;
+    info.lb_mode = s.lb_mode;
+    info.super_sparse_share = s.share;
+    info.plain_tiles = s.plain_tiles;
+    info.payload_bytes = s.payload_bytes;
+    info.meta_bytes = 21 * s.ntiles;
+    info.restore_bytes = s.col_agg ? 4 * s.nrestore + 4 * (s.npanels + 1) : 0;
+    info.sched_bytes = 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;
+    info.nquanta = s.nquanta;
+    info.nwaves = s.nwaves;
+    info.shared_panels = s.nshared;
+    info.prepass_panels = s.nprepass;
+    info.quantum_nnz_max = s.quantum_nnz_max;
+    info.quantum_nnz_mean = s.quantum_nnz_mean;
+    info.quantum_nnz_std = s.quantum_nnz_std;
+    info.wave_nnz_max = s.wave_nnz_max;
+    info.wave_nnz_mean = s.wave_nnz_mean;
+    info.wave_nnz_std = s.wave_nnz_std;
+    info.spmv_bytes = spmv_bytes(s);
+    info.convert_seconds = s.convert_seconds;
+}
+
+}  // namespace cbh

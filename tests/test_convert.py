@@ -1,0 +1,325 @@
+"""Host-side checks of the library (no GPU): the C ABI loads and exports every
+declared symbol; the C++ converter reproduces the conversion oracle bit for bit
+(tiles, formats, aggregation arrays, packed bytes, Algorithm 2 groups); CSR
+round trips are exact; malformed input is rejected with a status."""
+import ctypes
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from oracle import cb_model as cm
+from paper_2605_18515_amd import matgen
+
+cb = pytest.importorskip("paper_2605_18515_amd.cbspmv", reason="libcbspmv.so not built")
+
+VT = {"f64": cb.CB_VALUE_F64, "f32": cb.CB_VALUE_F32, "bf16": cb.CB_VALUE_BF16}
+ROUNDER = {"f64": None, "f32": oracle.round_f32_bits, "bf16": oracle.round_bf16_bits}
+
+
+def test_every_declared_symbol_is_exported():
+    names = cb.header_functions()
+    assert len(names) >= 11
+    lib = cb.library_handle()
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    for required in ("cb_create", "cb_spmv", "cb_spmm", "cb_destroy"):
+        assert required in names
+
+
+def test_struct_sizes_match_header():
+    o = cb.cb_options_default()
+    assert o.struct_size == ctypes.sizeof(cb.CbOptions)
+    assert o.th1 == 32 and o.th2 == 128 and abs(o.th0 - 0.15) == 0 and o.quantum_tiles == 8 and o.col_agg == -1
+    A = matgen.identity(5)
+    h = cb.cb_create_host(5, 5, 5, A.row_ptr, A.col_idx, A.values)
+    assert cb.cb_get_info(h)["struct_size"] == ctypes.sizeof(cb.CbInfo)
+    cb.cb_destroy(h)
+
+
+def host_matrix(A, **opts):
+    return cb.CbMatrix.from_csr(A, device=False, **opts)
+
+
+def check_against_model(A, vtype="f64", col_agg=-1, th1=32, th2=128, lb="contiguous", W=8, th0=0.15):
+    M = host_matrix(A, value_type=vtype, col_agg=col_agg, th1=th1, th2=th2, lb_mode=lb, quantum_tiles=W, th0=th0)
+    info, s = M.info, M.structure()
+    model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=col_agg, th0=th0, th1=th1, th2=th2)
+    NT = len(model.tiles)
+    assert info["ntiles"] == NT
+    assert info["col_agg"] == int(model.col_agg)
+    assert info["super_sparse_share"] == model.share
+    assert [info["tiles_coo"], info["tiles_csr"], info["tiles_dense"]] == \
+        [sum(t.fmt == f for t in model.tiles) for f in (cm.COO, cm.CSR, cm.DENSE)]
+    assert info["meta_bytes"] == 21 * NT
+    # natural order view of the kernel-order arrays
+    ori = s["tile_ori"]
+    assert sorted(ori.tolist()) == list(range(NT))
+    nat = np.empty(NT, np.int64)
+    nat[ori] = np.arange(NT)
+    vps, total = cm.layout(model, vtype)
+    assert info["payload_bytes"] == total
+    for i, t in enumerate(model.tiles):
+        j = nat[i]
+        assert (s["tile_row"][j], s["tile_col"][j], s["tile_nnz"][j], s["tile_type"][j], s["tile_vp"][j]) == \
+            (t.panel, t.tcol, t.nnz, t.fmt, vps[i]), i
+    assert bytes(s["payload"]) == cm.pack(model, A.values, vtype, ROUNDER[vtype])
+    if model.col_agg:
+        assert np.array_equal(s["restore_cols"], model.restore_cols)
+        assert np.array_equal(s["cols_offset"], model.cols_offset)
+    # grouping
+    if lb == "paper":
+        end, order, T = cm.lb_paper([t.nnz for t in model.tiles], W)
+        assert ori.tolist() == order
+        qp = s["quantum_ptr"]
+        assert len(qp) == T + 1 and qp[0] == 0 and qp[-1] == NT
+        for b in range(T):
+            assert all(end[ori[k]] // W == b for k in range(qp[b], qp[b + 1]))
+    elif lb == "none":
+        assert ori.tolist() == list(range(NT))
+        assert s["quantum_ptr"].tolist() == [min(NT, b * W) for b in range((NT + W - 1) // W + 1)]
+    else:
+        assert ori.tolist() == list(range(NT))
+    wp = s["wave_ptr"]
+    assert wp[0] == 0 and wp[-1] == NT and (NT == 0 or np.all(np.diff(wp) > 0))
+    # panel ownership: one run inside one work range
+    runs = np.zeros(info["npanels"], int)
+    for w in range(len(wp) - 1):
+        for k in range(wp[w], wp[w + 1]):
+            if k == wp[w] or s["tile_row"][k] != s["tile_row"][k - 1]:
+                runs[s["tile_row"][k]] += 1
+    assert np.array_equal(s["panel_shared"], (runs > 1).astype(np.uint8))
+    assert s["prepass_list"].tolist() == np.nonzero(runs != 1)[0].tolist()
+    M.close()
+    return info, s, model
+
+
+MATS = {
+    "lap64": lambda: matgen.laplacian_2d(64),
+    "lap13": lambda: matgen.laplacian_2d(13),
+    "block4": lambda: matgen.block_3d(4, seed=3),
+    "poisson6": lambda: matgen.poisson_3d(6),
+    "power": lambda: matgen.power_law(3000, seed=5, max_len=2000, window=200),
+    "rect": lambda: matgen.random_csr(77, 203, 0.08, 4),
+    "dense_mix": lambda: matgen.from_dense(
+        np.where(np.random.default_rng(1).random((70, 90)) < np.repeat([0.95, 0.4, 0.05], [32, 20, 18])[:, None],
+                 np.random.default_rng(2).uniform(-1, 1, (70, 90)), 0.0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("col_agg", [-1, 0, 1])
+def test_converter_matches_model(name, col_agg):
+    check_against_model(MATS[name](), col_agg=col_agg)
+
+
+@pytest.mark.parametrize("vtype", ["f32", "bf16"])
+@pytest.mark.parametrize("name", ["dense_mix", "power"])
+def test_converter_matches_model_low_precision(vtype, name):
+    check_against_model(MATS[name](), vtype=vtype, col_agg=1, th1=20, th2=60)
+
+
+@pytest.mark.parametrize("lb", ["paper", "none"])
+@pytest.mark.parametrize("W", [1, 3, 8])
+@pytest.mark.parametrize("name", ["dense_mix", "power", "lap13"])
+def test_grouping_modes_match_model(name, lb, W):
+    check_against_model(MATS[name](), lb=lb, W=W)
+
+
+def test_thresholds_reach_every_format():
+    info, _, _ = check_against_model(MATS["dense_mix"](), col_agg=0, th1=20, th2=60)
+    assert info["tiles_coo"] and info["tiles_csr"] and info["tiles_dense"]
+
+
+@pytest.mark.parametrize("nz", [0, 1, 2, 15, 16, 31, 32, 33, 64, 127, 128, 129, 200, 255, 256])
+def test_single_tile_sweep(nz):
+    A = matgen.single_tile(nz, seed=nz)
+    info, s, model = check_against_model(A, col_agg=0)
+    if nz:
+        assert s["tile_type"][0] == cm.select_format(nz)
+    rp, ci, va = host_matrix(A).export_csr()
+    assert np.array_equal(rp, A.row_ptr) and np.array_equal(ci, A.col_idx)
+    assert np.array_equal(va.view(np.uint64), A.values.view(np.uint64))
+
+
+def roundtrip(A, vtype="f64", **opts):
+    M = host_matrix(A, value_type=vtype, **opts)
+    rp, ci, va = M.export_csr()
+    assert np.array_equal(rp, A.row_ptr)
+    assert np.array_equal(ci, A.col_idx)
+    if vtype == "f64":
+        assert np.array_equal(va.view(np.uint64), A.values.view(np.uint64))
+    elif vtype == "f32":
+        assert np.array_equal(va.view(np.uint32), oracle.round_f32_bits(A.values))
+    else:
+        assert np.array_equal(va, oracle.round_bf16_bits(A.values))
+    M.close()
+
+
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_round_trip(name, vtype):
+    for agg in (0, 1):
+        for lb in ("contiguous", "paper"):
+            roundtrip(MATS[name](), vtype, col_agg=agg, th1=20, th2=60, lb_mode=lb)
+
+
+def test_round_trip_special_values():
+    rng = np.random.default_rng(7)
+    D = np.zeros((40, 40))
+    keep = rng.random((40, 40)) < 0.6
+    D[keep] = rng.choice([0.0, -0.0, np.nan, np.inf, -np.inf, 1e-310, -5e-324, 1.5, 3.4e38, 1e300], keep.sum())
+    A = matgen.from_dense(D, keep_zeros_mask=keep)
+    assert A.nnz == keep.sum()
+    for vt in ("f64", "f32", "bf16"):
+        for th2 in (128, 5):  # th2 = 5 forces Dense tiles, whose zero fill must not swallow stored zeros
+            roundtrip(A, vt, col_agg=0, th1=2, th2=th2)
+            roundtrip(A, vt, col_agg=1, th1=2, th2=th2)
+
+
+def test_empty_shapes():
+    for m, n in [(0, 0), (0, 7), (7, 0), (33, 17)]:
+        A = matgen.Csr(m, n, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+        M = host_matrix(A)
+        inf = M.info
+        assert inf["ntiles"] == 0 and inf["npanels"] == (m + 15) // 16
+        assert inf["prepass_panels"] == inf["npanels"]  # every (empty) panel is written by the pre-pass
+        rp, ci, va = M.export_csr()
+        assert np.array_equal(rp, A.row_ptr) and ci.size == 0
+        M.close()
+
+
+def test_empty_rows_and_panels():
+    D = np.zeros((100, 60))
+    D[3, 5] = 1.0
+    D[70, 59] = 2.0
+    D[99, 0] = 3.0
+    A = matgen.from_dense(D)
+    info, s, _ = check_against_model(A)
+    assert set(s["prepass_list"].tolist()) == {1, 2, 3, 5}
+    roundtrip(A)
+
+
+def test_wide_rows_split_contiguous():
+    # one row with 5000 entries: its panel is heavier than twice the range target and is split
+    A = matgen.power_law(600, seed=9, max_len=600, window=100)
+    rp = np.array([0, 5000] + [5000] * 15, np.int64)
+    B = matgen.Csr(16, 6000, rp, np.arange(0, 6000, 6000 / 5000).astype(np.int32)[:5000], np.ones(5000))
+    info, s, _ = check_against_model(B, col_agg=0)
+    assert info["nwaves"] > 1 and info["shared_panels"] == 1 and s["prepass_list"].tolist() == [0]
+    M = host_matrix(B, col_agg=0, wave_nnz=256)
+    assert M.info["nwaves"] >= 5000 // 256
+    check_against_model(A)
+
+
+def test_contiguous_ranges_are_balanced():
+    A = matgen.block_3d(8, seed=1)
+    M = host_matrix(A, wave_nnz=2000)
+    inf, s = M.info, M.structure()
+    w = np.array([s["tile_nnz"][s["wave_ptr"][i]:s["wave_ptr"][i + 1]].sum() for i in range(inf["nwaves"])])
+    assert w.max() <= 2000 + 8 * 100 and inf["shared_panels"] == 0
+    assert inf["wave_nnz_max"] == w.max()
+
+
+def test_storage_model_matches_paper_widths():
+    A = matgen.random_csr(200, 230, 0.03, 8)
+    M = host_matrix(A, col_agg=0, th1=1000, th2=1000)
+    inf, s = M.info, M.structure()
+    assert inf["tiles_coo"] == inf["ntiles"]
+    pads = sum(cm.padding(int(z), 8) for z in s["tile_nnz"])
+    raw = 9 * A.nnz + pads
+    align = sum((-cm.tile_region_bytes(cm.COO, int(z), "f64")) % 16 for z in s["tile_nnz"])
+    assert inf["payload_bytes"] == raw + align
+    assert inf["meta_bytes"] + 9 * A.nnz == cm.bytes_model_cb(inf["ntiles"], A.nnz)
+
+
+def _status(fn, *a):
+    try:
+        fn(*a)
+    except cb.CbError as e:
+        return e.status, str(e)
+    return 0, ""
+
+
+@pytest.mark.parametrize("case", ["rp0", "rpm", "decreasing", "col_range", "col_neg", "unsorted", "duplicate",
+                                  "neg_m", "null_cols", "huge"])
+def test_malformed_csr_is_rejected(case):
+    rp = np.array([0, 2, 3, 5], np.int64)
+    ci = np.array([0, 2, 1, 0, 3], np.int32)
+    va = np.ones(5)
+    m, n, nnz = 3, 4, 5
+    if case == "rp0":
+        rp = rp.copy(); rp[0] = 1
+    elif case == "rpm":
+        nnz = 4
+    elif case == "decreasing":
+        rp = np.array([0, 3, 2, 5], np.int64)
+    elif case == "col_range":
+        ci = ci.copy(); ci[4] = 4
+    elif case == "col_neg":
+        ci = ci.copy(); ci[2] = -1
+    elif case == "unsorted":
+        ci = np.array([2, 0, 1, 0, 3], np.int32)
+    elif case == "duplicate":
+        ci = np.array([0, 0, 1, 0, 3], np.int32)
+    elif case == "neg_m":
+        m = -1
+    elif case == "huge":
+        n = 1 << 31
+    if case == "null_cols":
+        h = ctypes.c_void_p()
+        st = cb.library_handle().cb_create_host(ctypes.byref(h), 3, 4, 5, rp.ctypes.data, None, va.ctypes.data, None)
+        assert st == cb.CB_ERROR_INVALID_VALUE and "NULL" in cb.cb_last_error()
+        return
+    st, msg = _status(cb.cb_create_host, m, n, nnz, rp, ci, va)
+    assert st == cb.CB_ERROR_INVALID_VALUE, (case, st, msg)
+    assert msg
+
+
+def test_bad_options_are_rejected():
+    A = matgen.identity(20)
+    for k, v in [("value_type", 3), ("col_agg", 2), ("th1", -1), ("quantum_tiles", 0), ("lb_mode", 7),
+                 ("wave_nnz", -5), ("th0", float("nan"))]:
+        o = cb.cb_options_default()
+        setattr(o, k, v)
+        st, _ = _status(cb.cb_create_host, 20, 20, 20, A.row_ptr, A.col_idx, A.values, o)
+        assert st == cb.CB_ERROR_INVALID_VALUE, k
+    o = cb.cb_options_default()
+    o.struct_size = 12
+    assert _status(cb.cb_create_host, 20, 20, 20, A.row_ptr, A.col_idx, A.values, o)[0] == cb.CB_ERROR_INVALID_VALUE
+
+
+def test_host_handle_cannot_multiply():
+    A = matgen.identity(20)
+    h = cb.cb_create_host(20, 20, 20, A.row_ptr, A.col_idx, A.values)
+    st = cb.library_handle().cb_spmv(h, 1.0, 16, 0.0, 32, None)
+    assert st == cb.CB_ERROR_NOT_SUPPORTED
+    st = cb.library_handle().cb_spmm(h, 0, 1.0, 16, 1, 0.0, 32, 1, None)
+    assert st in (cb.CB_ERROR_NOT_SUPPORTED, cb.CB_ERROR_INVALID_VALUE)
+    cb.cb_destroy(h)
+    assert cb.library_handle().cb_destroy(None) == cb.CB_SUCCESS
+    assert cb.library_handle().cb_spmv(None, 1.0, 16, 0.0, 32, None) == cb.CB_ERROR_INVALID_VALUE
+
+
+def test_copy_probe_validates_arguments():
+    lib = cb.library_handle()
+    assert lib.cb_copy_probe(16, 4096, 17, None) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_copy_probe(16, 32, 64, None) == cb.CB_ERROR_INVALID_VALUE  # overlap
+    assert lib.cb_copy_probe(None, 32, 64, None) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_copy_probe(16, 32, 0, None) == cb.CB_SUCCESS
+
+
+@settings(max_examples=40, deadline=None)
+@given(m=st.integers(0, 60), n=st.integers(0, 60), dens=st.floats(0, 1), seed=st.integers(0, 10 ** 6),
+       vtype=st.sampled_from(["f64", "f32", "bf16"]), agg=st.sampled_from([-1, 0, 1]),
+       th=st.sampled_from([(32, 128), (4, 40), (1, 1)]), lb=st.sampled_from(["contiguous", "paper", "none"]))
+def test_random_round_trip(m, n, dens, seed, vtype, agg, th, lb):
+    rng = np.random.default_rng(seed)
+    D = np.where(rng.random((m, n)) < dens,
+                 rng.choice([0.0, -0.0, np.nan, np.inf, 1.0, -2.5, 1e-40, 7e38], (m, n)) * 1.0, 0.0)
+    keep = rng.random((m, n)) < dens
+    A = matgen.from_dense(D, keep_zeros_mask=keep)
+    roundtrip(A, vtype, col_agg=agg, th1=th[0], th2=th[1], lb_mode=lb, wave_nnz=int(rng.integers(0, 300)))
+    if m * n <= 900 and vtype == "f64":
+        check_against_model(A, col_agg=agg, th1=th[0], th2=th[1], lb=lb)
