@@ -59,12 +59,16 @@ void oracle_spmv_coo_comp(int64_t m, int64_t nnz, const int32_t *row, const int3
         const int32_t i = row[t];
         const double p = val[t] * x[col[t]];
         const double sum = s[i] + p;
-        if (fabs(s[i]) >= fabs(p)) c[i] += (s[i] - sum) + p;
-        else                       c[i] += (p - sum) + s[i];
+        /* the compensation is defined for finite partial sums only; once a sum
+         * is Inf or NaN the result is the plain IEEE sum */
+        if (isfinite(sum)) {
+            if (fabs(s[i]) >= fabs(p)) c[i] += (s[i] - sum) + p;
+            else                       c[i] += (p - sum) + s[i];
+        }
         s[i] = sum;
     }
     for (int64_t i = 0; i < m; ++i) {
-        double r = alpha * (s[i] + c[i]);
+        double r = alpha * (isfinite(s[i]) ? s[i] + c[i] : s[i]);
         if (beta != 0.0) r += beta * y0[i];
         y[i] = r;
     }
@@ -103,14 +107,17 @@ void oracle_spmm_coo(int64_t m, int64_t nnz, int32_t k, const int32_t *row, cons
             double *si = &s[i * k + j];
             if (!comp) { *si += p; continue; }
             const double sum = *si + p;
-            if (fabs(*si) >= fabs(p)) c[i * k + j] += (*si - sum) + p;
-            else                      c[i * k + j] += (p - sum) + *si;
+            if (isfinite(sum)) {
+                if (fabs(*si) >= fabs(p)) c[i * k + j] += (*si - sum) + p;
+                else                      c[i * k + j] += (p - sum) + *si;
+            }
             *si = sum;
         }
     }
     for (int64_t i = 0; i < m; ++i)
         for (int32_t j = 0; j < k; ++j) {
-            double r = alpha * (s[i * k + j] + c[i * k + j]);
+            const double sij = s[i * k + j];
+            double r = alpha * (isfinite(sij) ? sij + c[i * k + j] : sij);
             if (beta != 0.0) r += beta * Y0[i * ldy + j];
             Y[i * ldy + j] = r;
         }

@@ -249,3 +249,24 @@ def test_scaled_error_rules():
     assert oracle.scaled_error(y, yref, scl, 1e-12)[1] == 1
     y = yref.copy(); y[5] = np.nan
     assert oracle.scaled_error(y, yref, scl, 1e-12)[1] == 1
+
+
+def test_compensated_sum_with_non_finite_terms():
+    """An Inf or NaN product makes the row the plain IEEE sum: +Inf stays +Inf,
+    Inf - Inf and NaN give NaN, whatever the summation variant."""
+    D = np.array([[1.0, np.inf, 2.0, 0.0],
+                  [1.0, np.inf, -np.inf, 0.0],
+                  [np.nan, 1.0, 0.0, 0.0],
+                  [1e308, 1e308, 0.0, 0.0],
+                  [3.0, -1.0, 0.0, 1.0]])
+    keep = np.ones_like(D, dtype=bool)
+    A = matgen.from_dense(D, keep_zeros_mask=keep)
+    x = np.array([1.0, 2.0, 3.0, 4.0])
+    with np.errstate(invalid="ignore", over="ignore"):
+        ref = D @ x
+    for comp in (False, True):
+        y = oracle.spmv(A, x, comp=comp)
+        assert np.array_equal(np.isnan(y), np.isnan(ref))
+        assert np.array_equal(y[~np.isnan(y)], ref[~np.isnan(ref)])
+        Y = oracle.spmm(A, np.stack([x, 2 * x], axis=1), comp=comp)
+        assert np.array_equal(np.isnan(Y[:, 0]), np.isnan(ref)) and Y[0, 0] == np.inf and Y[3, 1] == np.inf
