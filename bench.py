@@ -29,6 +29,27 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_f64_block3d.json")
 
 
+WORKLOADS = {
+    "block3d": "FP64 y=A*x, 3D block matrix {side}^3 grid x 3 dof (7-point, dense 3x3 blocks, diag +10)",
+    "powerlaw": "FP64 y=A*x, power-law rows: n=4,000,000, Zipf(2.1) lengths in [1,1e5] scaled to mean 16, "
+                "70% of columns within +-2048 of the diagonal",
+    "poisson": "FP64 y=A*x, 3D 7-point Poisson operator on a 192^3 grid",
+    "laplacian": "FP64 y=A*x, 2D 5-point Laplacian on a 64x64 grid",
+}
+
+
+def make_matrix(name: str, side: int):
+    from paper_2605_18515_amd import matgen
+
+    if name == "block3d":
+        return matgen.block_3d(side, 3, 10.0, seed=1)
+    if name == "powerlaw":
+        return matgen.power_law(4_000_000, seed=2)
+    if name == "poisson":
+        return matgen.poisson_3d(192)
+    return matgen.laplacian_2d(64)
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -49,6 +70,32 @@ def measured_traffic():
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def time_graph(fn, steps: int, warmup: int, replays: int = 5):
+    """Capture `steps` calls in one HIP graph (torch's capture stream) and time
+    its replays: per-launch time without host launch overhead."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(steps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(replays):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall / (steps * replays), e0.elapsed_time(e1) / 1e3 / (steps * replays)
 
 
 def time_calls(fn, steps: int, warmup: int):
@@ -75,6 +122,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--side", type=int, default=100, help="grid side of the 3D block matrix")
+    ap.add_argument("--workload", default="block3d", choices=list(WORKLOADS),
+                    help="matrix: block3d (default, 100^3 x 3 dof), powerlaw (n = 4M, Zipf 2.1 rows, mean 16), "
+                         "poisson (7-point, 192^3), laplacian (5-point, 64 x 64)")
     ap.add_argument("--lb", default="contiguous", choices=["contiguous", "paper", "none"])
     ap.add_argument("--col-agg", type=int, default=-1)
     ap.add_argument("--wave-nnz", type=int, default=0)
@@ -82,6 +132,10 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--graph", action="store_true",
+                    help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -97,10 +151,18 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_only:
+        nbytes = args.copy_only << 20
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        w_s, k_s = time_calls(lambda: cb.cb_copy_probe(src, dst, nbytes), args.steps, args.warmup)
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": args.steps + args.warmup,
+                          "GBs": 2 * nbytes / k_s / 1e9}), flush=True)
+        return 0
     t = time.perf_counter()
-    A = matgen.block_3d(args.side, 3, 10.0, seed=1)
+    A = make_matrix(args.workload, args.side)
     x = matgen.vector(A.n, 1)
-    log(f"generated 3D block matrix n={A.n} nnz={A.nnz} in {time.perf_counter() - t:.1f}s")
+    log(f"generated {args.workload} matrix n={A.n} nnz={A.nnz} in {time.perf_counter() - t:.1f}s")
 
     t = time.perf_counter()
     M = cb.CbMatrix.from_csr(A, lb_mode=args.lb, col_agg=args.col_agg, wave_nnz=args.wave_nnz)
@@ -113,7 +175,7 @@ def main() -> int:
     xd = torch.from_numpy(x).to(dev)
     yd = torch.empty(A.m, dtype=torch.float64, device=dev)
     step = lambda: M.spmv(xd, yd)  # noqa: E731
-    wall_s, kern_s = time_calls(step, args.steps, args.warmup)
+    wall_s, kern_s = (time_graph if args.graph else time_calls)(step, args.steps, args.warmup)
     gflops = 2.0 * A.nnz / wall_s / 1e9
     achieved = info["spmv_bytes"] / kern_s / 1e9
     log(f"FP64 SpMV: {wall_s * 1e6:.1f} us/step wall, {kern_s * 1e6:.1f} us kernel, {gflops:.1f} GFLOP/s, "
@@ -198,8 +260,8 @@ def main() -> int:
                 break
         el = time.perf_counter() - t0
         cpu = {"value": 2.0 * A.nnz * reps / el / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full 3D block matrix ({A.nnz} nnz), {reps} plain FP64 COO-loop SpMVs in {el:.1f}s "
-                         f"on one host core"}
+               "sample": f"the full {args.workload} matrix ({A.nnz} nnz), {reps} plain FP64 COO-loop SpMVs in "
+                         f"{el:.1f}s on one host core"}
         log(f"cpu oracle: {cpu['value']:.3f} GFLOP/s")
 
     traffic = measured_traffic()
@@ -216,8 +278,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FP64 y=A*x, 3D block matrix {args.side}^3 grid x 3 dof (7-point, dense 3x3 "
-                               f"blocks, diag +10)", "n": A.n, "nnz": A.nnz, "lb_mode": args.lb,
+        "config": {"workload": WORKLOADS[args.workload].format(side=args.side), "n": A.n, "nnz": A.nnz,
+                   "lb_mode": args.lb, "timing": "hip graph replay" if args.graph else "stream launches",
                    "col_agg": info["col_agg"], "value_storage": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -105,7 +105,8 @@ typedef struct {
     int64_t plain_tiles;    /* tiles of the plain partition (before aggregation) */
     int64_t payload_bytes;  /* packed tile data (mtx_data) */
     int64_t meta_bytes;     /* high-level arrays: 4+4+4+8+1 bytes per tile */
-    int64_t restore_bytes;  /* restore_cols + cols_offset (0 without aggregation) */
+    int64_t restore_bytes;  /* restore_cols + cols_offset + a 4-byte restore index per tile
+                               (0 without aggregation) */
     int64_t sched_bytes;    /* work-range pointers, panel flags, pre-pass panel list */
     int64_t nquanta;        /* groups of Algorithm 2 (or the contiguous ranges) */
     int64_t nwaves;         /* wavefront work ranges launched per SpMV */
@@ -127,8 +128,9 @@ typedef struct {
 /* Host buffers receiving the structure in kernel order (ntiles entries for the
  * tile arrays).  Any pointer may be NULL to skip that array.  Sizes come from
  * cb_get_info: payload_bytes, nquanta + 1, nwaves + 1, npanels (+ 1 for
- * cols_offset), restore_bytes / 4 - npanels - 1 entries of restore_cols when
- * aggregation is applied, prepass_panels. */
+ * cols_offset), restore_bytes / 4 - npanels - 1 - ntiles entries of restore_cols
+ * when aggregation is applied, prepass_panels, ntiles for tile_xoff (aggregation
+ * only). */
 typedef struct {
     int32_t *tile_row;       /* blk_row_idx: 16-row panel of each tile */
     int32_t *tile_col;       /* blk_col_idx: 16-column block, or aggregated chunk */
@@ -143,6 +145,7 @@ typedef struct {
     int32_t *wave_ptr;       /* tile range of each wavefront work range, nwaves + 1 */
     uint8_t *panel_shared;   /* 1 if the panel's tiles span more than one work range */
     int32_t *prepass_list;   /* panels written by the pre-pass */
+    int32_t *tile_xoff;      /* aggregation only: cols_offset[tile_row] + 16 * tile_col, kernel order */
 } cb_structure_t;
 
 /* Fill *opt with the defaults above (the paper's thresholds). */

@@ -57,7 +57,7 @@ class CbInfo(ctypes.Structure):
 class CbStructure(ctypes.Structure):
     _fields_ = [(n, _p) for n in ("tile_row", "tile_col", "tile_nnz", "tile_vp", "tile_type", "tile_ori", "payload",
                                   "restore_cols", "cols_offset", "quantum_ptr", "wave_ptr", "panel_shared",
-                                  "prepass_list")]
+                                  "prepass_list", "tile_xoff")]
 
 
 _lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
@@ -206,7 +206,7 @@ def cb_export_csr(A: int):
 def cb_export_structure(A: int) -> dict:
     info = cb_get_info(A)
     NT, P = info["ntiles"], info["npanels"]
-    nrest = (info["restore_bytes"] // 4 - (P + 1)) if info["col_agg"] else 0
+    nrest = (info["restore_bytes"] // 4 - (P + 1) - NT) if info["col_agg"] else 0
     arrs = {
         "tile_row": np.empty(NT, np.int32), "tile_col": np.empty(NT, np.int32), "tile_nnz": np.empty(NT, np.int32),
         "tile_vp": np.empty(NT, np.int64), "tile_type": np.empty(NT, np.uint8), "tile_ori": np.empty(NT, np.int32),
@@ -214,6 +214,7 @@ def cb_export_structure(A: int) -> dict:
         "cols_offset": np.empty(P + 1 if info["col_agg"] else 0, np.int32),
         "quantum_ptr": np.empty(info["nquanta"] + 1, np.int32), "wave_ptr": np.empty(info["nwaves"] + 1, np.int32),
         "panel_shared": np.empty(P, np.uint8), "prepass_list": np.empty(info["prepass_panels"], np.int32),
+        "tile_xoff": np.empty(NT if info["col_agg"] else 0, np.int32),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
     _check(_lib.cb_export_structure(A, ctypes.byref(s)))

@@ -26,7 +26,7 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 
 // byte offsets of every array inside the single device allocation
 struct Layout {
-    size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, payload, restore_cols, cols_offset, wave_ptr,
+    size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
         quantum_ptr, panel_shared, prepass_list, total;
 };
 
@@ -47,8 +47,10 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.tile_vp = put(8 * NT);
     L.tile_type = put(NT);
     L.tile_ori = put(4 * NT);
-    L.payload = put((size_t)s.payload_bytes);
-    L.restore_cols = put(4 * (size_t)s.nrestore);
+    L.tile_xoff = put(s.col_agg ? 4 * NT : 0);
+    // the streaming kernel reads whole 1 KB chunks past the last tile and the last restore entry
+    L.payload = put((size_t)s.payload_bytes + cbh::kStreamPad);
+    L.restore_cols = put(4 * (size_t)s.nrestore + cbh::kStreamPad);
     L.cols_offset = put(s.col_agg ? 4 * ((size_t)s.npanels + 1) : 0);
     L.wave_ptr = put(4 * ((size_t)s.nwaves + 1));
     L.quantum_ptr = put(4 * ((size_t)s.nquanta + 1));
@@ -128,6 +130,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.tile_vp, s.tile_vp);
         put_array(stage, L.tile_type, s.tile_type);
         put_array(stage, L.tile_ori, s.tile_ori);
+        put_array(stage, L.tile_xoff, s.tile_xoff);
         put_array(stage, L.payload, s.payload);
         put_array(stage, L.restore_cols, s.restore_cols);
         put_array(stage, L.cols_offset, s.cols_offset);
@@ -151,6 +154,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.tile_nnz = dptr<int32_t>(A, L.tile_nnz);
     v.tile_vp = dptr<int64_t>(A, L.tile_vp);
     v.tile_type = dptr<uint8_t>(A, L.tile_type);
+    v.tile_xoff = dptr<int32_t>(A, L.tile_xoff);
     v.payload = dptr<uint8_t>(A, L.payload);
     v.restore_cols = dptr<int32_t>(A, L.restore_cols);
     v.cols_offset = dptr<int32_t>(A, L.cols_offset);
@@ -163,11 +167,13 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.npanels = (int32_t)s.npanels;
     v.nprepass = (int32_t)s.nprepass;
     v.col_agg = s.col_agg;
+    v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
     // the device copy is the structure from now on
     std::vector<int32_t>().swap(s.tile_row);
     std::vector<int32_t>().swap(s.tile_col);
     std::vector<int32_t>().swap(s.tile_nnz);
     std::vector<int32_t>().swap(s.tile_ori);
+    std::vector<int32_t>().swap(s.tile_xoff);
     std::vector<int64_t>().swap(s.tile_vp);
     std::vector<uint8_t>().swap(s.tile_type);
     std::vector<uint8_t>().swap(s.payload);
@@ -206,6 +212,7 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.tile_vp, NT, tmp.tile_vp)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.tile_type, NT, tmp.tile_type)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.tile_ori, NT, tmp.tile_ori)) != CB_SUCCESS) return st;
+    if ((st = fetch(A, L.tile_xoff, A->h.col_agg ? NT : 0, tmp.tile_xoff)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.payload, (size_t)A->h.payload_bytes, tmp.payload)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.restore_cols, (size_t)A->h.nrestore, tmp.restore_cols)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.cols_offset, A->h.col_agg ? (size_t)A->h.npanels + 1 : 0, tmp.cols_offset)) != CB_SUCCESS)
@@ -348,6 +355,7 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *o) {
     cp(o->tile_vp, s->tile_vp);
     cp(o->tile_type, s->tile_type);
     cp(o->tile_ori, s->tile_ori);
+    cp(o->tile_xoff, s->tile_xoff);
     cp(o->payload, s->payload);
     cp(o->restore_cols, s->restore_cols);
     cp(o->cols_offset, s->cols_offset);

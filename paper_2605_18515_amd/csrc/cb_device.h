@@ -15,6 +15,7 @@ struct DevView {
     const int32_t *tile_nnz;
     const int64_t *tile_vp;       // byte offset of the tile's packed region
     const uint8_t *tile_type;     // 0 COO, 1 CSR, 2 Dense
+    const int32_t *tile_xoff;     // col_agg only: restore_cols index of the tile's first column
     const uint8_t *payload;
     const int32_t *restore_cols;  // aggregated -> original column (col_agg only)
     const int32_t *cols_offset;   // npanels + 1 (col_agg only)
@@ -23,6 +24,7 @@ struct DevView {
     const int32_t *prepass_list;  // nprepass
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
+    int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
 };
 
 // vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float)

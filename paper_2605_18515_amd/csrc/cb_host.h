@@ -14,6 +14,7 @@ constexpr int kSuperSparse = 32;  // Section 3.3.1: fewer than 32 non-zeros
 constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte boundary
 constexpr int kDenseMaskBytes = 32;
 constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
+constexpr int kStreamPad = 2048;  // device bytes after payload and restore_cols read by the streaming kernel
 
 struct HostStructure {
     int64_t m = 0, n = 0, nnz = 0;
@@ -27,6 +28,7 @@ struct HostStructure {
     int64_t npanels = 0, ntiles = 0;
     // kernel order (after load balance)
     std::vector<int32_t> tile_row, tile_col, tile_nnz, tile_ori;
+    std::vector<int32_t> tile_xoff;  // aggregation only: cols_offset[row] + 16 * col (restore_cols index of the tile)
     std::vector<int64_t> tile_vp;
     std::vector<uint8_t> tile_type;
     std::vector<uint8_t> payload;

@@ -493,6 +493,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             s.tile_vp[i] = nvp[o];
             s.tile_type[i] = ntype[o];
         }
+        if (agg) {
+            s.tile_xoff.resize(NT);
+            for (int64_t i = 0; i < NT; ++i) s.tile_xoff[i] = s.cols_offset[s.tile_row[i]] + 16 * s.tile_col[i];
+        }
         s.quantum_ptr = qptr;
         s.wave_ptr = wptr;
 
@@ -609,7 +613,7 @@ cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_id
 int64_t spmv_bytes(const HostStructure &s) {
     const int64_t xe = s.vtype == CB_VALUE_F64 ? 8 : 4;
     int64_t b = s.payload_bytes + 21 * s.ntiles;  // payload + high-level arrays (4+4+4+8+1 per tile)
-    if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1);
+    if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1) + 4 * s.ntiles;  // + per-tile restore index
     b += 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;  // work ranges, panel flags, pre-pass list
     b += xe * s.n + xe * s.m;                              // x read once, y written once
     return b;
@@ -631,7 +635,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.plain_tiles = s.plain_tiles;
     info.payload_bytes = s.payload_bytes;
     info.meta_bytes = 21 * s.ntiles;
-    info.restore_bytes = s.col_agg ? 4 * s.nrestore + 4 * (s.npanels + 1) : 0;
+    info.restore_bytes = s.col_agg ? 4 * s.nrestore + 4 * (s.npanels + 1) + 4 * s.ntiles : 0;
     info.sched_bytes = 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;
     info.nquanta = s.nquanta;
     info.nwaves = s.nwaves;

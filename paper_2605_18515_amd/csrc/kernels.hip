@@ -80,6 +80,50 @@ __device__ __forceinline__ A quad_sum(A v) {
     return v;
 }
 
+// DPP move with `old` returned where the source lane lies outside the 16-lane row
+template <int CTRL>
+__device__ __forceinline__ int dpp_or(int v, int old) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_or(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_or(double v, double old) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <class A>
+__device__ __forceinline__ void lds_add(A *p, A v);
+
+// Adds each lane's product into acc[key] where the keys of consecutive lanes are
+// non-decreasing (a tile's entries in row-major order).  A segmented inclusive
+// scan inside every 16-lane DPP row (row_shr 1, 2, 4, 8) leaves each run's sum
+// in its last lane; those lanes add into the accumulator, so a row meets at most
+// one add per DPP row.  Lanes outside the tile carry a key no other lane has.
+template <class A>
+__device__ __forceinline__ void segmented_row_add(A val, int key, bool valid, A *acc) {
+    int kp;
+    A vp;
+    kp = dpp_or<0x111>(key, -1);
+    vp = dpp_or<0x111>(val, A(0));
+    if (kp == key) val += vp;
+    kp = dpp_or<0x112>(key, -1);
+    vp = dpp_or<0x112>(val, A(0));
+    if (kp == key) val += vp;
+    kp = dpp_or<0x114>(key, -1);
+    vp = dpp_or<0x114>(val, A(0));
+    if (kp == key) val += vp;
+    kp = dpp_or<0x118>(key, -1);
+    vp = dpp_or<0x118>(val, A(0));
+    if (kp == key) val += vp;
+    const int kn = dpp_or<0x101>(key, -2);  // row_shl:1, the next lane's key
+    if (valid && kn != key) lds_add(&acc[key], val);
+}
+
 template <class A>
 __device__ __forceinline__ void lds_add(A *p, A v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -177,8 +221,288 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
     if (cur >= 0) flush(cur);
 }
 
-// k right-hand sides: KC columns of X per launch slice (blockIdx.y), 64 / KC
-// entries in flight per wavefront pass, one lane per (entry, column).
+// ---- streaming SpMV over natural-order structures --------------------------
+//
+// When the kernel order equals the packing order (contiguous or no load
+// balance), a wavefront's tiles occupy one contiguous byte range of the
+// payload and one contiguous range of restore_cols.  The wavefront walks its
+// range in batches of at most 16 tiles and 3 KB.  At the start of step b the
+// loads issued during step b-1 have landed: the payload chunks and restore
+// entries of batch b and the metadata of batch b+1.  Step b then
+//   1. moves them into LDS (payload ring, restore area, 16-byte metadata
+//      records of batch b+1) and finds where batch b+1 ends (a ballot),
+//   2. gathers the x values of batch b's tiles (16 columns each),
+//   3. issues the loads of batch b+1's payload and restore entries and of
+//      batch b+2's metadata,
+//   4. stores the gathered x in LDS -- the only wait inside a step, which
+//      leaves the step-3 loads in flight -- and
+//   5. multiplies batch b's tiles out of LDS.
+// Loads are issued on every path (addresses clamped into the arrays) so the
+// number of loads between a load and its use never depends on the path.
+
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+using i32x4 = int __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 1024;          // one wave-wide load: 64 lanes x 16 bytes
+constexpr int kPRing = 4 * kChunk;    // payload ring per wavefront
+constexpr int kPMask = kPRing - 1;
+constexpr int kBatchBytes = 3 * kChunk;  // a batch spans at most 4 chunks of the ring
+constexpr int kBatchTiles = 16;
+constexpr int kRArea = 512;           // restore_cols entries staged per batch (two loads per lane)
+
+// packed region size of a tile (16-byte aligned), as laid out by the converter
+template <int VS>
+__device__ __forceinline__ int region_dev(int ty, int nz) {
+    int b;
+    if (ty == 0)
+        b = nz + pad_bytes(nz, VS) + nz * VS;
+    else if (ty == 1)
+        b = 16 + nz + pad_bytes(16 + nz, VS) + nz * VS;
+    else
+        b = 256 * VS + 32;
+    return (b + 15) & ~15;
+}
+
+// metadata of up to 17 consecutive tiles, lane i holding tile s + i (clamped to the range)
+struct MetaRegs {
+    int row, xo, nz, ty, vplo;
+};
+
+template <int VT, bool AGG, bool DPPRED>
+__global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
+                                                                     typename Val<VT>::A beta,
+                                                                     const typename Val<VT>::A *__restrict__ x,
+                                                                     typename Val<VT>::A *__restrict__ y) {
+    using A = typename Val<VT>::A;
+    constexpr int VS = Val<VT>::kSize;
+    __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
+    __shared__ __align__(16) int32_t rarea_all[kWavesPerBlock][AGG ? kRArea : 4];
+    __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
+    __shared__ __align__(16) i32x4 meta_all[kWavesPerBlock][2][kBatchTiles];
+    __shared__ A acc_all[kWavesPerBlock][16];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
+    if (w >= d.nwaves) return;
+    uint8_t *pring = pring_all[wid];
+    int32_t *rarea = rarea_all[wid];
+    A *xarea = xarea_all[wid];
+    A *acc = acc_all[wid];
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    const int64_t B0 = d.tile_vp[t0];
+    const int b0lo = (int)B0;
+    const int nchunk = (int)((d.tile_vp[t1 - 1] + region_dev<VS>(d.tile_type[t1 - 1], d.tile_nnz[t1 - 1]) - B0 +
+                              kChunk - 1) / kChunk);
+    const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + B0) + lane;
+    const int *vp_lo = reinterpret_cast<const int *>(d.tile_vp);  // low words of the 64-bit virtual pointers
+    // only the first and the last panel of a natural-order range can be shared with another range
+    const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
+    const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
+
+    auto mload = [&](int s, MetaRegs &M) {
+        const int t = min(s + lane, t1 - 1);
+        M.row = d.tile_row[t];
+        M.xo = AGG ? d.tile_xoff[t] : d.tile_col[t];
+        M.nz = d.tile_nnz[t];
+        M.ty = d.tile_type[t];
+        M.vplo = vp_lo[2 * (size_t)t];
+    };
+    // first tile past s that is past t1, 16 tiles on, or would end the batch more than kBatchBytes after s
+    auto batch_end = [&](int s, const MetaRegs &M, int &end_rel) {
+        const int rel = M.vplo - b0lo;
+        const int e = rel + region_dev<VS>(M.ty, M.nz);
+        const int rs = __builtin_amdgcn_readfirstlane(rel);
+        const bool c = lane >= 1 && (s + lane >= t1 || lane >= kBatchTiles || e - rs > kBatchBytes);
+        const int n = (int)__builtin_ctzll(__ballot(c));
+        end_rel = __builtin_amdgcn_readlane(e, n - 1);
+        return s + n;
+    };
+
+    u32x4 P0, P1, P2, P3;
+    i32x4 R0 = {0, 0, 0, 0}, R1 = {0, 0, 0, 0};
+    int chi = 0;           // payload chunks whose loads have been issued
+    int pfirst = 0, pcnt = 0;
+    int rbase = 0;
+    // payload chunks of the batch [rs, re) not loaded yet, clamped to the batch's last chunk,
+    // and restore entries from the batch's first tile
+    auto issue_batch = [&](int rs, int re, int xo_first) {
+        const int lastc = min((re - 1) >> 10, nchunk - 1);
+        const int firstc = max(chi, rs >> 10);
+        pfirst = firstc;
+        pcnt = max(0, lastc - firstc + 1);
+        const int c0 = min(firstc, lastc);
+        P0 = pstream[(size_t)min(c0 + 0, lastc) * kWave];
+        P1 = pstream[(size_t)min(c0 + 1, lastc) * kWave];
+        P2 = pstream[(size_t)min(c0 + 2, lastc) * kWave];
+        P3 = pstream[(size_t)min(c0 + 3, lastc) * kWave];
+        chi = max(chi, lastc + 1);
+        if (AGG) {
+            rbase = xo_first & ~3;
+            const i32x4 *rp = reinterpret_cast<const i32x4 *>(d.restore_cols + rbase) + lane;
+            R0 = rp[0];
+            R1 = rp[kWave];
+        }
+    };
+
+    if (lane < 16) acc[lane] = A(0);
+    int cur = -1;
+    auto flush = [&](int p) {
+        if (lane < 16) {
+            const int64_t row = 16 * (int64_t)p + lane;
+            const A v = acc[lane];
+            acc[lane] = A(0);
+            if (row < d.m) {
+                if ((p == p_first && sh_first) || (p == p_last && sh_last)) {
+                    global_add(&y[row], alpha * v);
+                } else {
+                    A r = alpha * v;
+                    if (beta != A(0)) r += beta * y[row];
+                    y[row] = r;
+                }
+            }
+        }
+    };
+    auto rv = [&](int off) { return Val<VT>::load(pring + (off & kPMask), 0); };
+    // metadata record of tile i of a batch: (row, rel, xo, nz | ty << 16)
+    auto put_meta = [&](i32x4 *dst, const MetaRegs &M) {
+        if (lane < kBatchTiles) dst[lane] = i32x4{M.row, M.vplo - b0lo, M.xo, M.nz | (M.ty << 16)};
+    };
+
+    if (lane < 2 * kBatchTiles) (&meta_all[wid][0][0])[lane] = i32x4{0, 0, 0, 0};
+    // prologue: metadata of batch 0, its extent, its loads and batch 1's metadata
+    MetaRegs M;
+    mload(t0, M);
+    int s = t0, end_rel;
+    int e = batch_end(s, M, end_rel);
+    put_meta(meta_all[wid][0], M);
+    issue_batch(__builtin_amdgcn_readfirstlane(M.vplo - b0lo), end_rel, __builtin_amdgcn_readfirstlane(M.xo));
+    mload(e, M);
+    int buf = 0;
+    while (s < t1) {
+        // 1. batch b's payload and restore entries, batch b+1's metadata into LDS
+        {
+            const int pf = pfirst, pc = pcnt;
+            u32x4 *ring4 = reinterpret_cast<u32x4 *>(pring);
+            if (pc > 0) ring4[((pf + 0) & 3) * kWave + lane] = P0;
+            if (pc > 1) ring4[((pf + 1) & 3) * kWave + lane] = P1;
+            if (pc > 2) ring4[((pf + 2) & 3) * kWave + lane] = P2;
+            if (pc > 3) ring4[((pf + 3) & 3) * kWave + lane] = P3;
+            if (AGG) {
+                i32x4 *ra4 = reinterpret_cast<i32x4 *>(rarea);
+                ra4[lane] = R0;
+                ra4[kWave + lane] = R1;
+            }
+        }
+        const int rb = rbase;
+        const i32x4 *meta = meta_all[wid][buf];
+        put_meta(meta_all[wid][buf ^ 1], M);
+        const int s2 = e;
+        int end2;
+        const int e2 = batch_end(s2, M, end2);
+        const int rs2 = __builtin_amdgcn_readfirstlane(M.vplo - b0lo);
+        const int xo2 = __builtin_amdgcn_readfirstlane(M.xo);
+        // 2. x of batch b: lane (gj, glc) takes column glc of tile 4g + gj
+        const int gj = lane >> 4, glc = lane & 15;
+        A xg[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int i = 4 * g + gj;
+            const int xo = meta[i].z;
+            // slots past the batch hold an older batch's record; clamp so every load stays in x
+            int col;
+            if (AGG) {
+                const int64_t ra = (int64_t)xo + glc - rb;
+                col = rarea[ra < 0 ? 0 : (ra >= kRArea ? kRArea - 1 : (int)ra)];
+            } else {
+                const int64_t c = 16 * (int64_t)xo + glc;
+                col = (c >= 0 && c < d.n) ? (int)c : 0;
+            }
+            xg[g] = x[col];
+        }
+        // 3. batch b+1's payload and restore loads, batch b+2's metadata
+        issue_batch(rs2, end2, xo2);
+        mload(e2, M);
+        // 4. gathered x into LDS (slots of tiles past the batch are never read)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) xarea[(4 * g + gj) * 16 + glc] = xg[g];
+        // 5. batch b's tiles
+        for (int u = s; u < e; ++u) {
+            const i32x4 rec = meta[u - s];
+            const int row = __builtin_amdgcn_readfirstlane(rec.x);
+            const int rel = __builtin_amdgcn_readfirstlane(rec.y);
+            const int nt = __builtin_amdgcn_readfirstlane(rec.w);
+            const int nz = nt & 0xFFFF, ty = nt >> 16;
+            if (row != cur) {
+                if (cur >= 0) flush(cur);
+                cur = row;
+            }
+            const A *xs = xarea + (u - s) * 16;
+            if (ty != 2) {
+                // COO (Algorithm 3) and CSR tiles: one lane per entry on the shared codes
+                const int hdr = ty == 1 ? 16 : 0;
+                const int coff = rel + hdr, voff = rel + hdr + nz + pad_bytes(hdr + nz, VS);
+                for (int q0 = 0; q0 < nz; q0 += kWave) {
+                    const int q = q0 + lane;
+                    const bool valid = q < nz;
+                    const uint32_t code = pring[(coff + min(q, nz - 1)) & kPMask];
+                    const A prod = valid ? rv(voff + q * VS) * xs[code >> 4] : A(0);
+                    if (DPPRED)
+                        segmented_row_add(prod, valid ? (int)(code & 15) : 16 + lane, valid, acc);
+                    else if (valid)
+                        lds_add(&acc[code & 15], prod);
+                }
+            } else {
+                const uint32_t bits = (pring[(rel + 256 * VS + 2 * (lane >> 2) + ((lane & 3) >> 1)) & kPMask] >>
+                                       ((lane & 1) * 4)) & 0xFu;
+                const int r4 = lane >> 2, q4 = lane & 3;
+                const int vo = rel + (r4 * 16 + 4 * q4) * VS;
+                A sum = A(0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((bits >> j) & 1u) sum += rv(vo + j * VS) * xs[4 * q4 + j];
+                sum = quad_sum(sum);
+                if (q4 == 0) acc[r4] += sum;
+            }
+        }
+        s = s2;
+        e = e2;
+        buf ^= 1;
+    }
+    if (cur >= 0) flush(cur);
+}
+
+// ---- k right-hand sides ---------------------------------------------------
+//
+// Y = alpha*A*X + beta*Y with X (n x k) and Y (m x k) row-major.  A launch
+// slice (blockIdx.y) covers KC columns of X.  A wavefront walks its tiles as
+// spmv_kernel does; lane (r, q) owns row r of the current panel and KC/4
+// consecutive columns, in registers.  Per tile the X rows of the tile's 16
+// columns are staged in LDS; each lane walks the entries of its row (row
+// starts from the CSR header, or counted with ballots for COO tiles) and
+// updates its KC/4 accumulators.  Dense tiles are multiplied on the matrix
+// cores: the 16x16 tile times the 16 x KC block of X as 16x16x4 MFMA steps
+// (FP64 values: v_mfma_f64_16x16x4_f64; FP32/BF16 values: v_mfma_f32_16x16x4_f32),
+// unless one of the staged X values is Inf or NaN, where the zero fill of the
+// tile would contribute 0*Inf; those tiles take the entry-by-entry path.
+
+template <class A>
+struct Mfma;
+// Operands of both shapes: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].  The
+// accumulator differs: element v of lane l is D[4v + l/16][l % 16] for FP64 and
+// D[4(l/16) + v][l % 16] for FP32 (checked on gfx950 with one-hot operands).
+template <>
+struct Mfma<double> {
+    using C = double __attribute__((ext_vector_type(4)));
+    __device__ static C step(double a, double b, C c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+    using C = float __attribute__((ext_vector_type(4)));
+    __device__ static C step(float a, float b, C c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
 template <int VT, int KC>
 __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename Val<VT>::A alpha,
                                                               typename Val<VT>::A beta,
@@ -187,9 +511,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
                                                               int k) {
     using A = typename Val<VT>::A;
     constexpr int VS = Val<VT>::kSize;
-    constexpr int S = kWave / KC;
+    constexpr int NJ = KC / 4;  // columns per lane
     __shared__ A xs_all[kWavesPerBlock][16 * KC];
-    __shared__ A acc_all[kWavesPerBlock][16 * KC];
+    __shared__ A cs_all[kWavesPerBlock][KC >= 16 ? 16 * KC : 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
@@ -197,29 +521,33 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
     const int j0 = blockIdx.y * KC;
     const int kc = min(KC, k - j0);
     A *xs = xs_all[wid];
-    A *acc = acc_all[wid];
+    A *cs = cs_all[wid];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
-    for (int i = lane; i < 16 * KC; i += kWave) acc[i] = A(0);
-    const int slot = lane / KC, jj = lane % KC;
+    const int r4 = lane >> 2, q4 = lane & 3, jb = q4 * NJ;
+    A acc[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) acc[i] = A(0);
 
     auto flush = [&](int p) {
-        const bool shared = d.panel_shared[p] != 0;
-        for (int i = lane; i < 16 * KC; i += kWave) {
-            const int r = i / KC, j = i % KC;
-            const int64_t row = 16 * (int64_t)p + r;
-            const A v = acc[i];
-            acc[i] = A(0);
-            if (row < d.m && j < kc) {
-                A *yp = Y + row * ldy + j0 + j;
-                if (shared) {
-                    global_add(yp, alpha * v);
-                } else {
-                    A out = alpha * v;
-                    if (beta != A(0)) out += beta * *yp;
-                    *yp = out;
+        const int64_t row = 16 * (int64_t)p + r4;
+        if (row < d.m) {
+            const bool shared = d.panel_shared[p] != 0;
+            A *yp = Y + row * ldy + j0 + jb;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                if (jb + i < kc) {
+                    if (shared) {
+                        global_add(&yp[i], alpha * acc[i]);
+                    } else {
+                        A out = alpha * acc[i];
+                        if (beta != A(0)) out += beta * yp[i];
+                        yp[i] = out;
+                    }
                 }
             }
         }
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) acc[i] = A(0);
     };
 
     int cur = -1;
@@ -233,33 +561,81 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
             if (cur >= 0) flush(cur);
             cur = p;
         }
-        for (int i = lane; i < 16 * KC; i += kWave) {
-            const int lc = i / KC, j = i % KC;
+        // X rows of the tile's 16 columns: lane (r4, q4) stages column r4, KC/4 entries
+        int col = -1;
+        if (d.col_agg) {
+            const int a = d.cols_offset[p] + 16 * c + r4;
+            if (a < d.cols_offset[p + 1]) col = d.restore_cols[a];
+        } else {
+            const int64_t cc = 16 * (int64_t)c + r4;
+            if (cc < d.n) col = (int)cc;
+        }
+        bool finite = true;
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
             A xv = A(0);
-            if (j < kc) {
-                if (d.col_agg) {
-                    const int a = d.cols_offset[p] + 16 * c + lc;
-                    if (a < d.cols_offset[p + 1]) xv = X[(int64_t)d.restore_cols[a] * ldx + j0 + j];
-                } else {
-                    const int64_t col = 16 * (int64_t)c + lc;
-                    if (col < d.n) xv = X[col * ldx + j0 + j];
-                }
+            if (col >= 0 && jb + i < kc) xv = X[(int64_t)col * ldx + j0 + jb + i];
+            finite = finite && __builtin_isfinite(xv);
+            xs[r4 * KC + jb + i] = xv;
+        }
+        if (ty == 2 && KC >= 16 && __ballot(!finite) == 0) {
+            // dense tile on the matrix cores: C(16 x 16 block ob) = sum_kb D[:, 4kb:4kb+4] X[4kb:4kb+4, block]
+            const int li = lane & 15, lk = lane >> 4;
+            A a[4];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) a[kb] = Val<VT>::load(base, li * 16 + 4 * kb + lk);
+#pragma unroll
+            for (int ob = 0; ob < KC / 16; ++ob) {
+                typename Mfma<A>::C cv = {A(0), A(0), A(0), A(0)};
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) cv = Mfma<A>::step(a[kb], xs[(4 * kb + lk) * KC + ob * 16 + li], cv);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cs[Mfma<A>::row(lane, v) * KC + ob * 16 + li] = cv[v];
             }
-            xs[i] = xv;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += cs[r4 * KC + jb + i];
+            continue;
         }
         if (ty == 2) {
+            // entry by entry over the occupancy bitmap of row r4
             const uint8_t *mask = base + 256 * VS;
-            for (int e = slot; e < 256; e += S)
-                if (((mask[e >> 3] >> (e & 7)) & 1u) && jj < kc)
-                    lds_add(&acc[(e >> 4) * KC + jj], Val<VT>::load(base, e) * xs[(e & 15) * KC + jj]);
-        } else {
-            const int hdr = ty == 1 ? 16 : 0;
-            const uint8_t *codes = base + hdr;
-            const uint8_t *vals = codes + nz + pad_bytes(hdr + nz, VS);
-            for (int e = slot; e < nz; e += S) {
-                const uint32_t code = codes[e];
-                if (jj < kc) lds_add(&acc[(code & 15) * KC + jj], Val<VT>::load(vals, e) * xs[(code >> 4) * KC + jj]);
+            const uint32_t bits = (uint32_t)mask[2 * r4] | ((uint32_t)mask[2 * r4 + 1] << 8);
+            for (int cc = 0; cc < 16; ++cc) {
+                if ((bits >> cc) & 1u) {
+                    const A v = Val<VT>::load(base, r4 * 16 + cc);
+#pragma unroll
+                    for (int i = 0; i < NJ; ++i) acc[i] += v * xs[cc * KC + jb + i];
+                }
             }
+            continue;
+        }
+        const int hdr = ty == 1 ? 16 : 0;
+        const uint8_t *codes = base + hdr;
+        const uint8_t *vals = codes + nz + pad_bytes(hdr + nz, VS);
+        int rs, re;
+        if (ty == 1) {
+            rs = base[r4];
+            re = r4 < 15 ? (int)base[r4 + 1] : nz;
+        } else {
+            // COO: entries are row-major; row r4 spans the entries with row < r4 + 1 minus those with row < r4
+            rs = 0;
+            re = 0;
+            for (int e0 = 0; e0 < nz; e0 += kWave) {
+                const int e = e0 + lane;
+                const int row_e = e < nz ? (int)(codes[e] & 15) : 16;
+#pragma unroll
+                for (int r = 1; r <= 16; ++r) {
+                    const int cnt = __popcll(__ballot(row_e < r));
+                    if (r == r4) rs += cnt;
+                    if (r == r4 + 1) re += cnt;
+                }
+            }
+        }
+        for (int e = rs; e < re; ++e) {
+            const A v = Val<VT>::load(vals, e);
+            const int lc = codes[e] >> 4;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) acc[i] += v * xs[lc * KC + jb + i];
         }
     }
     if (cur >= 0) flush(cur);
@@ -311,8 +687,16 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     if (e != hipSuccess) return e;
     if (d.nwaves <= 0) return hipSuccess;
     const int nb = (d.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-    hipLaunchKernelGGL(spmv_kernel<VT>, dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha, (A)beta, (const A *)x,
-                       (A *)y);
+    constexpr bool kDpp = VT != 0;  // FP32 LDS atomics with conflicting lanes are slow; FP64 ones are not
+    if (d.natural_order && d.col_agg)
+        hipLaunchKernelGGL((spmv_stream_kernel<VT, true, kDpp>), dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha,
+                           (A)beta, (const A *)x, (A *)y);
+    else if (d.natural_order)
+        hipLaunchKernelGGL((spmv_stream_kernel<VT, false, kDpp>), dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha,
+                           (A)beta, (const A *)x, (A *)y);
+    else
+        hipLaunchKernelGGL(spmv_kernel<VT>, dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha, (A)beta,
+                           (const A *)x, (A *)y);
     return hipGetLastError();
 }
 
@@ -333,8 +717,6 @@ hipError_t spmm_kc(const DevView &d, int k, double alpha, const void *X, int64_t
 template <int VT>
 hipError_t spmm_vt(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                    int64_t ldy, hipStream_t s) {
-    if (k <= 1) return spmm_kc<VT, 1>(d, k, alpha, X, ldx, beta, Y, ldy, s);
-    if (k <= 2) return spmm_kc<VT, 2>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 4) return spmm_kc<VT, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 8) return spmm_kc<VT, 8>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 16) return spmm_kc<VT, 16>(d, k, alpha, X, ldx, beta, Y, ldy, s);

@@ -68,6 +68,9 @@ def check_against_model(A, vtype="f64", col_agg=-1, th1=32, th2=128, lb="contigu
     if model.col_agg:
         assert np.array_equal(s["restore_cols"], model.restore_cols)
         assert np.array_equal(s["cols_offset"], model.cols_offset)
+        assert np.array_equal(s["tile_xoff"], s["cols_offset"][s["tile_row"]] + 16 * s["tile_col"])
+    else:
+        assert s["tile_xoff"].size == 0
     # grouping
     if lb == "paper":
         end, order, T = cm.lb_paper([t.nnz for t in model.tiles], W)

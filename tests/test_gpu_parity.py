@@ -260,3 +260,21 @@ def test_copy_probe(cb):
     cb.cb_copy_probe(src, dst, n * 8)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+@pytest.mark.parametrize("vtype", ["f64", "f32"])
+def test_spmm_dense_tiles_with_nonfinite_x(cb, vtype):
+    """Dense tiles go to the matrix cores unless the staged X rows hold Inf/NaN:
+    a zero-filled slot must not turn 0 * Inf into NaN."""
+    A = SMALL["dense_mix"]()
+    k = 16
+    X = matgen.rhs(A.n, k, 3)
+    X[5, 3] = np.inf
+    X[40, 0] = -np.inf
+    X[77, 9] = np.nan
+    Y0 = np.zeros((A.m, k))
+    for th in ((8, 40), (32, 128)):
+        Y = run_spmm(cb, A, X, 1.0, 0.0, Y0, vtype, col_agg=0, th1=th[0], th2=th[1])
+        ref = oracle.spmm(A, X, comp=True)
+        e, viol, w = oracle.scaled_error(Y, ref, oracle.spmm_scale(A, X), TOL[vtype])
+        assert viol == 0, (th, e, w)
