@@ -22,8 +22,25 @@
 namespace cbd {
 namespace {
 
+// Tuning parameters (fixed at build time; the defaults are the measured best on MI355X)
+#ifndef CB_TUNE_WAVES_PER_BLOCK
+#define CB_TUNE_WAVES_PER_BLOCK 4
+#endif
+#ifndef CB_TUNE_RING_CHUNKS
+#define CB_TUNE_RING_CHUNKS 4  // 1 KB chunks in the payload ring; a batch spans at most this many
+#endif
+#ifndef CB_TUNE_BATCH_TILES
+#define CB_TUNE_BATCH_TILES 16
+#endif
+#ifndef CB_TUNE_F64_DPP
+#define CB_TUNE_F64_DPP 0  // FP64 row sums: 0 = LDS atomics per entry, 1 = DPP segmented scan
+#endif
+#ifndef CB_TUNE_NT_LOADS
+#define CB_TUNE_NT_LOADS 0  // payload chunk loads with the nontemporal hint
+#endif
+
 constexpr int kWave = 64;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = CB_TUNE_WAVES_PER_BLOCK;
 constexpr int kBlockThreads = kWave * kWavesPerBlock;
 
 template <int VT>
@@ -53,6 +70,14 @@ struct Val<2> {
 __device__ __forceinline__ int pad_bytes(int index_bytes, int vsize) {
     const int r = index_bytes & (vsize - 1);
     return r ? vsize - r : 0;
+}
+
+// Byte of a device array at a wave-uniform index, read through the scalar cache as the
+// aligned dword that holds it (sub-arrays start on 256-byte boundaries, so the dword lies
+// inside the allocation).
+__device__ __forceinline__ int uniform_byte(const uint8_t *p, int64_t i) {
+    const uint32_t w = reinterpret_cast<const uint32_t *>(p)[i >> 2];
+    return (int)((w >> (8 * (i & 3))) & 0xFFu);
 }
 
 // Workgroup b is dispatched to XCD b % 8.  Give each XCD a contiguous range of
@@ -244,10 +269,13 @@ using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 using i32x4 = int __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = 1024;          // one wave-wide load: 64 lanes x 16 bytes
-constexpr int kPRing = 4 * kChunk;    // payload ring per wavefront
+constexpr int kRC = CB_TUNE_RING_CHUNKS;
+static_assert(kRC == 4 || kRC == 8, "ring of 4 or 8 chunks");
+constexpr int kPRing = kRC * kChunk;  // payload ring per wavefront
 constexpr int kPMask = kPRing - 1;
-constexpr int kBatchBytes = 3 * kChunk;  // a batch spans at most 4 chunks of the ring
-constexpr int kBatchTiles = 16;
+constexpr int kBatchBytes = (kRC - 1) * kChunk;  // a batch spans at most kRC chunks of the ring
+constexpr int kBatchTiles = CB_TUNE_BATCH_TILES;
+static_assert(kBatchTiles % 4 == 0 && kBatchTiles <= 60, "x gathers take four tiles per load");
 constexpr int kRArea = 512;           // restore_cols entries staged per batch (two loads per lane)
 
 // packed region size of a tile (16-byte aligned), as laid out by the converter
@@ -275,6 +303,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                                                                      typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
     constexpr int VS = Val<VT>::kSize;
+    constexpr int NG = kBatchTiles / 4;  // x gathers per batch, four tiles each
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) int32_t rarea_all[kWavesPerBlock][AGG ? kRArea : 4];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
@@ -291,13 +320,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
     const int64_t B0 = d.tile_vp[t0];
     const int b0lo = (int)B0;
-    const int nchunk = (int)((d.tile_vp[t1 - 1] + region_dev<VS>(d.tile_type[t1 - 1], d.tile_nnz[t1 - 1]) - B0 +
-                              kChunk - 1) / kChunk);
     const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + B0) + lane;
     const int *vp_lo = reinterpret_cast<const int *>(d.tile_vp);  // low words of the 64-bit virtual pointers
     // only the first and the last panel of a natural-order range can be shared with another range
     const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
     const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
+    const int gj = lane >> 4, glc = lane & 15;
 
     auto mload = [&](int s, MetaRegs &M) {
         const int t = min(s + lane, t1 - 1);
@@ -307,44 +335,90 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         M.ty = d.tile_type[t];
         M.vplo = vp_lo[2 * (size_t)t];
     };
-    // first tile past s that is past t1, 16 tiles on, or would end the batch more than kBatchBytes after s
-    auto batch_end = [&](int s, const MetaRegs &M, int &end_rel) {
+    // batch starting at tile s (metadata of tiles s.. in lanes 0..): returns the first tile past it
+    // -- past t1, 16 tiles on, or ending more than kBatchBytes after s -- and its byte range
+    auto batch_end = [&](int s, const MetaRegs &M, int &rs, int &re) {
         const int rel = M.vplo - b0lo;
         const int e = rel + region_dev<VS>(M.ty, M.nz);
-        const int rs = __builtin_amdgcn_readfirstlane(rel);
+        rs = __builtin_amdgcn_readfirstlane(rel);
         const bool c = lane >= 1 && (s + lane >= t1 || lane >= kBatchTiles || e - rs > kBatchBytes);
         const int n = (int)__builtin_ctzll(__ballot(c));
-        end_rel = __builtin_amdgcn_readlane(e, n - 1);
+        re = __builtin_amdgcn_readlane(e, n - 1);
         return s + n;
     };
+    auto put_meta = [&](i32x4 *dst, const MetaRegs &M) {
+        if (lane < kBatchTiles) dst[lane] = i32x4{M.row, M.vplo - b0lo, M.xo, M.nz | (M.ty << 16)};
+    };
 
-    u32x4 P0, P1, P2, P3;
-    i32x4 R0 = {0, 0, 0, 0}, R1 = {0, 0, 0, 0};
-    int chi = 0;           // payload chunks whose loads have been issued
-    int pfirst = 0, pcnt = 0;
-    int rbase = 0;
-    // payload chunks of the batch [rs, re) not loaded yet, clamped to the batch's last chunk,
-    // and restore entries from the batch's first tile
-    auto issue_batch = [&](int rs, int re, int xo_first) {
-        const int lastc = min((re - 1) >> 10, nchunk - 1);
+    // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued)
+    u32x4 P[kRC];
+    int chi = 0, pfirst = 0, pcnt = 0;
+    auto issue_payload = [&](int rs, int re) {
+        const int lastc = (re - 1) >> 10;
         const int firstc = max(chi, rs >> 10);
         pfirst = firstc;
         pcnt = max(0, lastc - firstc + 1);
-        const int c0 = min(firstc, lastc);
-        P0 = pstream[(size_t)min(c0 + 0, lastc) * kWave];
-        P1 = pstream[(size_t)min(c0 + 1, lastc) * kWave];
-        P2 = pstream[(size_t)min(c0 + 2, lastc) * kWave];
-        P3 = pstream[(size_t)min(c0 + 3, lastc) * kWave];
-        chi = max(chi, lastc + 1);
-        if (AGG) {
-            rbase = xo_first & ~3;
-            const i32x4 *rp = reinterpret_cast<const i32x4 *>(d.restore_cols + rbase) + lane;
-            R0 = rp[0];
-            R1 = rp[kWave];
+#pragma unroll
+        for (int i = 0; i < kRC; ++i) {
+            if (i < pcnt) {
+                const u32x4 *src = pstream + (size_t)(firstc + i) * kWave;
+                P[i] = CB_TUNE_NT_LOADS ? __builtin_nontemporal_load(src) : *src;
+            }
         }
+        chi = max(chi, lastc + 1);
+    };
+    auto put_payload = [&]() {
+        u32x4 *ring4 = reinterpret_cast<u32x4 *>(pring);
+#pragma unroll
+        for (int i = 0; i < kRC; ++i)
+            if (i < pcnt) ring4[((pfirst + i) & (kRC - 1)) * kWave + lane] = P[i];
+    };
+    // restore_cols entries of a batch: a batch's tiles use at most 16 x 16 consecutive entries, so
+    // 512 entries from its first tile's entry (rounded down to 16 bytes) always cover them
+    i32x4 R0 = {0, 0, 0, 0}, R1 = {0, 0, 0, 0};
+    int rbase = 0, rbase_cur = 0;
+    auto issue_restore = [&](int xo_first) {
+        if (!AGG) return;
+        rbase = xo_first & ~3;
+        const i32x4 *rp = reinterpret_cast<const i32x4 *>(d.restore_cols + rbase) + lane;
+        R0 = rp[0];
+        R1 = rp[kWave];
+    };
+    auto put_restore = [&]() {
+        if (!AGG) return;
+        i32x4 *ra4 = reinterpret_cast<i32x4 *>(rarea);
+        ra4[lane] = R0;
+        ra4[kWave + lane] = R1;
+        rbase_cur = rbase;
+    };
+    // x of a batch's tiles (records in meta, nt tiles): lane (gj, glc) takes column glc of tile 4g + gj
+    A XG[NG];
+    auto issue_x = [&](const i32x4 *meta, int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (4 * g < nt) {
+                const int i = 4 * g + gj;
+                const int xo = meta[i].z;
+                int col;
+                if (AGG) {
+                    const int64_t ra = (int64_t)xo + glc - rbase_cur;
+                    col = rarea[ra < 0 ? 0 : (ra >= kRArea ? kRArea - 1 : (int)ra)];
+                } else {
+                    const int64_t c = 16 * (int64_t)xo + glc;
+                    col = (c >= 0 && c < d.n) ? (int)c : 0;
+                }
+                XG[g] = x[col];
+            }
+        }
+    };
+    auto put_x = [&](int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            if (4 * g < nt) xarea[(4 * g + gj) * 16 + glc] = XG[g];
     };
 
     if (lane < 16) acc[lane] = A(0);
+    if (lane < 2 * kBatchTiles) (&meta_all[wid][0][0])[lane] = i32x4{0, 0, 0, 0};
     int cur = -1;
     auto flush = [&](int p) {
         if (lane < 16) {
@@ -363,75 +437,54 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         }
     };
     auto rv = [&](int off) { return Val<VT>::load(pring + (off & kPMask), 0); };
-    // metadata record of tile i of a batch: (row, rel, xo, nz | ty << 16)
-    auto put_meta = [&](i32x4 *dst, const MetaRegs &M) {
-        if (lane < kBatchTiles) dst[lane] = i32x4{M.row, M.vplo - b0lo, M.xo, M.nz | (M.ty << 16)};
-    };
 
-    if (lane < 2 * kBatchTiles) (&meta_all[wid][0][0])[lane] = i32x4{0, 0, 0, 0};
-    // prologue: metadata of batch 0, its extent, its loads and batch 1's metadata
+    // Pipeline state at the top of step b: the loads issued during step b-1 have
+    // landed -- P = batch b's new payload chunks, XG = batch b's x, R = batch b+1's
+    // restore entries, M = batch b+1's metadata; meta[buf] holds batch b's records.
     MetaRegs M;
+    int s = t0, rs, re;
     mload(t0, M);
-    int s = t0, end_rel;
-    int e = batch_end(s, M, end_rel);
-    put_meta(meta_all[wid][0], M);
-    issue_batch(__builtin_amdgcn_readfirstlane(M.vplo - b0lo), end_rel, __builtin_amdgcn_readfirstlane(M.xo));
-    mload(e, M);
+    int e = batch_end(s, M, rs, re);
     int buf = 0;
+    put_meta(meta_all[wid][0], M);
+    issue_payload(rs, re);
+    issue_restore(__builtin_amdgcn_readfirstlane(M.xo));
+    put_restore();  // waits: batch 0's restore entries are needed for its own x gathers
+    issue_x(meta_all[wid][0], e - s);
+    if (e < t1) {
+        issue_restore(__builtin_amdgcn_readlane(M.xo, e - s));  // batch 1 starts at tile e
+        mload(e, M);
+    }
     while (s < t1) {
-        // 1. batch b's payload and restore entries, batch b+1's metadata into LDS
-        {
-            const int pf = pfirst, pc = pcnt;
-            u32x4 *ring4 = reinterpret_cast<u32x4 *>(pring);
-            if (pc > 0) ring4[((pf + 0) & 3) * kWave + lane] = P0;
-            if (pc > 1) ring4[((pf + 1) & 3) * kWave + lane] = P1;
-            if (pc > 2) ring4[((pf + 2) & 3) * kWave + lane] = P2;
-            if (pc > 3) ring4[((pf + 3) & 3) * kWave + lane] = P3;
-            if (AGG) {
-                i32x4 *ra4 = reinterpret_cast<i32x4 *>(rarea);
-                ra4[lane] = R0;
-                ra4[kWave + lane] = R1;
-            }
-        }
-        const int rb = rbase;
-        const i32x4 *meta = meta_all[wid][buf];
-        put_meta(meta_all[wid][buf ^ 1], M);
+        const int nt = e - s;
+        // 1. step b-1's loads into LDS
+        put_payload();
+        put_x(nt);
+        const bool more = e < t1;
         const int s2 = e;
-        int end2;
-        const int e2 = batch_end(s2, M, end2);
-        const int rs2 = __builtin_amdgcn_readfirstlane(M.vplo - b0lo);
-        const int xo2 = __builtin_amdgcn_readfirstlane(M.xo);
-        // 2. x of batch b: lane (gj, glc) takes column glc of tile 4g + gj
-        const int gj = lane >> 4, glc = lane & 15;
-        A xg[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int i = 4 * g + gj;
-            const int xo = meta[i].z;
-            // slots past the batch hold an older batch's record; clamp so every load stays in x
-            int col;
-            if (AGG) {
-                const int64_t ra = (int64_t)xo + glc - rb;
-                col = rarea[ra < 0 ? 0 : (ra >= kRArea ? kRArea - 1 : (int)ra)];
-            } else {
-                const int64_t c = 16 * (int64_t)xo + glc;
-                col = (c >= 0 && c < d.n) ? (int)c : 0;
-            }
-            xg[g] = x[col];
+        int e2 = s2, rs2 = 0, re2 = 0;
+        if (more) {
+            put_meta(meta_all[wid][buf ^ 1], M);
+            put_restore();
+            e2 = batch_end(s2, M, rs2, re2);
         }
-        // 3. batch b+1's payload and restore loads, batch b+2's metadata
-        issue_batch(rs2, end2, xo2);
-        mload(e2, M);
-        // 4. gathered x into LDS (slots of tiles past the batch are never read)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) xarea[(4 * g + gj) * 16 + glc] = xg[g];
-        // 5. batch b's tiles
+        // 2. loads for batch b+1 (payload, x) and batch b+2 (restore entries, metadata)
+        if (more) {
+            issue_payload(rs2, re2);
+            issue_x(meta_all[wid][buf ^ 1], e2 - s2);
+            if (e2 < t1) {
+                issue_restore(__builtin_amdgcn_readlane(M.xo, e2 - s2));  // batch b+2 starts at tile e2
+                mload(e2, M);  // batch b+2's metadata (tiles e2..)
+            }
+        }
+        // 3. batch b's tiles
+        const i32x4 *meta = meta_all[wid][buf];
         for (int u = s; u < e; ++u) {
             const i32x4 rec = meta[u - s];
             const int row = __builtin_amdgcn_readfirstlane(rec.x);
             const int rel = __builtin_amdgcn_readfirstlane(rec.y);
-            const int nt = __builtin_amdgcn_readfirstlane(rec.w);
-            const int nz = nt & 0xFFFF, ty = nt >> 16;
+            const int ntw = __builtin_amdgcn_readfirstlane(rec.w);
+            const int nz = ntw & 0xFFFF, ty = ntw >> 16;
             if (row != cur) {
                 if (cur >= 0) flush(cur);
                 cur = row;
@@ -452,9 +505,8 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                         lds_add(&acc[code & 15], prod);
                 }
             } else {
-                const uint32_t bits = (pring[(rel + 256 * VS + 2 * (lane >> 2) + ((lane & 3) >> 1)) & kPMask] >>
-                                       ((lane & 1) * 4)) & 0xFu;
                 const int r4 = lane >> 2, q4 = lane & 3;
+                const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
                 const int vo = rel + (r4 * 16 + 4 * q4) * VS;
                 A sum = A(0);
 #pragma unroll
@@ -509,9 +561,14 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
                                                               const typename Val<VT>::A *__restrict__ X, int64_t ldx,
                                                               typename Val<VT>::A *__restrict__ Y, int64_t ldy,
                                                               int k) {
+    // One-tile software pipeline.  While tile t is multiplied out of LDS, the
+    // loads of tile t+1 (its packed region, three 1 KB wave loads, and its 16 X
+    // rows) and the restore_cols entries of tile t+2 are in flight; the scalar
+    // metadata of tile t+2 is read through the scalar cache.
     using A = typename Val<VT>::A;
     constexpr int VS = Val<VT>::kSize;
     constexpr int NJ = KC / 4;  // columns per lane
+    __shared__ __align__(16) uint8_t tbuf_all[kWavesPerBlock][3 * kChunk];
     __shared__ A xs_all[kWavesPerBlock][16 * KC];
     __shared__ A cs_all[kWavesPerBlock][KC >= 16 ? 16 * KC : 1];
     const int lane = threadIdx.x & (kWave - 1);
@@ -520,6 +577,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
     if (w >= d.nwaves) return;
     const int j0 = blockIdx.y * KC;
     const int kc = min(KC, k - j0);
+    uint8_t *tbuf = tbuf_all[wid];
     A *xs = xs_all[wid];
     A *cs = cs_all[wid];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
@@ -528,10 +586,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
 #pragma unroll
     for (int i = 0; i < NJ; ++i) acc[i] = A(0);
 
-    auto flush = [&](int p) {
+    auto flush = [&](int p, bool shared) {
         const int64_t row = 16 * (int64_t)p + r4;
         if (row < d.m) {
-            const bool shared = d.panel_shared[p] != 0;
             A *yp = Y + row * ldy + j0 + jb;
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
@@ -550,47 +607,92 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
         for (int i = 0; i < NJ; ++i) acc[i] = A(0);
     };
 
-    int cur = -1;
+    // per-tile scalar metadata
+    struct TM {
+        int row, col, nts;  // nts = nz | type << 16 | panel-shared << 24
+        int64_t vp;
+    };
+    auto meta = [&](int t) {
+        TM m;
+        const int tc = min(t, t1 - 1);
+        m.row = d.tile_row[tc];
+        m.col = d.tile_col[tc];
+        m.vp = d.tile_vp[tc];
+        // the panel flag is read two tiles ahead of its use at the panel's flush
+        m.nts = d.tile_nnz[tc] | (uniform_byte(d.tile_type, tc) << 16) | (uniform_byte(d.panel_shared, m.row) << 24);
+        return m;
+    };
+    // original column of local column r4 of a tile (restore entry read one tile ahead)
+    auto restore_entry = [&](const TM &m) {
+        if (!d.col_agg) return 0;
+        const int a = d.cols_offset[m.row] + 16 * m.col + r4;
+        return d.restore_cols[min(a, d.cols_offset[m.row + 1] - 1)];
+    };
+    auto colvalid = [&](const TM &m) {
+        if (d.col_agg) return d.cols_offset[m.row] + 16 * m.col + r4 < d.cols_offset[m.row + 1];
+        return 16 * (int64_t)m.col + r4 < d.n;
+    };
+    // loads of one tile: its packed region (chunks past the region end re-read the last one) and
+    // its X rows (lane (r4, q4): column r4, KC/4 entries; columns outside the tile read row 0)
+    u32x4 P[3];
+    A XR[NJ];
+    auto issue_tile = [&](const TM &m, int rcol, bool cv) {
+        const int last = (region_dev<VS>((m.nts >> 16) & 0xFF, m.nts & 0xFFFF) - 1) >> 10;
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(d.payload + m.vp) + lane;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P[i] = src[min(i, last) * kWave];
+        const int64_t col = d.col_agg ? rcol : 16 * (int64_t)m.col + r4;
+        const int64_t rowoff = cv ? col * ldx : 0;
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) XR[i] = X[rowoff + j0 + min(jb + i, kc - 1)];
+    };
+
+    // prologue: tile t0's loads, tile t0+1's restore entry
+    TM m_cur = meta(t0);
+    TM m_nxt = meta(t0 + 1);
+    issue_tile(m_cur, restore_entry(m_cur), colvalid(m_cur));
+    int rc_nxt = restore_entry(m_nxt);
+    int cur = -1, cur_sh = 0;
     for (int t = t0; t < t1; ++t) {
-        const int p = d.tile_row[t];
-        const int c = d.tile_col[t];
-        const int nz = d.tile_nnz[t];
-        const int ty = d.tile_type[t];
-        const uint8_t *base = d.payload + d.tile_vp[t];
-        if (p != cur) {
-            if (cur >= 0) flush(cur);
-            cur = p;
-        }
-        // X rows of the tile's 16 columns: lane (r4, q4) stages column r4, KC/4 entries
-        int col = -1;
-        if (d.col_agg) {
-            const int a = d.cols_offset[p] + 16 * c + r4;
-            if (a < d.cols_offset[p + 1]) col = d.restore_cols[a];
-        } else {
-            const int64_t cc = 16 * (int64_t)c + r4;
-            if (cc < d.n) col = (int)cc;
-        }
+        // 1. tile t's data into LDS
+        const bool cv = colvalid(m_cur);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) reinterpret_cast<u32x4 *>(tbuf)[i * kWave + lane] = P[i];
+        // columns past kc hold a clamped copy; their sums are never written back
         bool finite = true;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            A xv = A(0);
-            if (col >= 0 && jb + i < kc) xv = X[(int64_t)col * ldx + j0 + jb + i];
+            const A xv = cv ? XR[i] : A(0);
             finite = finite && __builtin_isfinite(xv);
             xs[r4 * KC + jb + i] = xv;
         }
+        // 2. tile t+1's loads and tile t+2's restore entry and metadata
+        const TM m = m_cur;
+        const TM m2 = meta(t + 2);
+        issue_tile(m_nxt, rc_nxt, colvalid(m_nxt));
+        rc_nxt = restore_entry(m2);
+        m_cur = m_nxt;
+        m_nxt = m2;
+        // 3. tile t
+        if (m.row != cur) {
+            if (cur >= 0) flush(cur, cur_sh != 0);
+            cur = m.row;
+            cur_sh = m.nts >> 24;
+        }
+        const int nz = m.nts & 0xFFFF, ty = (m.nts >> 16) & 0xFF;
         if (ty == 2 && KC >= 16 && __ballot(!finite) == 0) {
             // dense tile on the matrix cores: C(16 x 16 block ob) = sum_kb D[:, 4kb:4kb+4] X[4kb:4kb+4, block]
             const int li = lane & 15, lk = lane >> 4;
             A a[4];
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) a[kb] = Val<VT>::load(base, li * 16 + 4 * kb + lk);
+            for (int kb = 0; kb < 4; ++kb) a[kb] = Val<VT>::load(tbuf, li * 16 + 4 * kb + lk);
 #pragma unroll
             for (int ob = 0; ob < KC / 16; ++ob) {
-                typename Mfma<A>::C cv = {A(0), A(0), A(0), A(0)};
+                typename Mfma<A>::C cvec = {A(0), A(0), A(0), A(0)};
 #pragma unroll
-                for (int kb = 0; kb < 4; ++kb) cv = Mfma<A>::step(a[kb], xs[(4 * kb + lk) * KC + ob * 16 + li], cv);
+                for (int kb = 0; kb < 4; ++kb) cvec = Mfma<A>::step(a[kb], xs[(4 * kb + lk) * KC + ob * 16 + li], cvec);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) cs[Mfma<A>::row(lane, v) * KC + ob * 16 + li] = cv[v];
+                for (int v = 0; v < 4; ++v) cs[Mfma<A>::row(lane, v) * KC + ob * 16 + li] = cvec[v];
             }
 #pragma unroll
             for (int i = 0; i < NJ; ++i) acc[i] += cs[r4 * KC + jb + i];
@@ -598,11 +700,11 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
         }
         if (ty == 2) {
             // entry by entry over the occupancy bitmap of row r4
-            const uint8_t *mask = base + 256 * VS;
+            const uint8_t *mask = tbuf + 256 * VS;
             const uint32_t bits = (uint32_t)mask[2 * r4] | ((uint32_t)mask[2 * r4 + 1] << 8);
             for (int cc = 0; cc < 16; ++cc) {
                 if ((bits >> cc) & 1u) {
-                    const A v = Val<VT>::load(base, r4 * 16 + cc);
+                    const A v = Val<VT>::load(tbuf, r4 * 16 + cc);
 #pragma unroll
                     for (int i = 0; i < NJ; ++i) acc[i] += v * xs[cc * KC + jb + i];
                 }
@@ -610,12 +712,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
             continue;
         }
         const int hdr = ty == 1 ? 16 : 0;
-        const uint8_t *codes = base + hdr;
+        const uint8_t *codes = tbuf + hdr;
         const uint8_t *vals = codes + nz + pad_bytes(hdr + nz, VS);
         int rs, re;
         if (ty == 1) {
-            rs = base[r4];
-            re = r4 < 15 ? (int)base[r4 + 1] : nz;
+            rs = tbuf[r4];
+            re = r4 < 15 ? (int)tbuf[r4 + 1] : nz;
         } else {
             // COO: entries are row-major; row r4 spans the entries with row < r4 + 1 minus those with row < r4
             rs = 0;
@@ -638,7 +740,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
             for (int i = 0; i < NJ; ++i) acc[i] += v * xs[lc * KC + jb + i];
         }
     }
-    if (cur >= 0) flush(cur);
+    if (cur >= 0) flush(cur, cur_sh != 0);
 }
 
 // y <- beta * y (0 when beta == 0) on the rows of shared and empty panels
@@ -687,7 +789,8 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     if (e != hipSuccess) return e;
     if (d.nwaves <= 0) return hipSuccess;
     const int nb = (d.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-    constexpr bool kDpp = VT != 0;  // FP32 LDS atomics with conflicting lanes are slow; FP64 ones are not
+    // FP32 LDS atomics with colliding lanes are slow on gfx950; FP64 ones are not
+    constexpr bool kDpp = VT != 0 || CB_TUNE_F64_DPP;
     if (d.natural_order && d.col_agg)
         hipLaunchKernelGGL((spmv_stream_kernel<VT, true, kDpp>), dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha,
                            (A)beta, (const A *)x, (A *)y);
