@@ -124,13 +124,14 @@ __device__ __forceinline__ double dpp_or(double v, double old) {
 template <class A>
 __device__ __forceinline__ void lds_add(A *p, A v);
 
-// Adds each lane's product into acc[key] where the keys of consecutive lanes are
-// non-decreasing (a tile's entries in row-major order).  A segmented inclusive
-// scan inside every 16-lane DPP row (row_shr 1, 2, 4, 8) leaves each run's sum
-// in its last lane; those lanes add into the accumulator, so a row meets at most
-// one add per DPP row.  Lanes outside the tile carry a key no other lane has.
+// Adds each lane's product into *dst, where lanes with equal keys share dst and
+// equal keys occupy consecutive lanes (entries in (tile, row) order).  A
+// segmented inclusive scan inside every 16-lane DPP row (row_shr 1, 2, 4, 8)
+// leaves each run's sum in its last lane; only those lanes add, so an
+// accumulator meets at most one add per run.  Lanes without an entry carry a
+// key no other lane has.
 template <class A>
-__device__ __forceinline__ void segmented_row_add(A val, int key, bool valid, A *acc) {
+__device__ __forceinline__ void segmented_row_add(A val, int key, bool valid, A *dst) {
     int kp;
     A vp;
     kp = dpp_or<0x111>(key, -1);
@@ -146,7 +147,7 @@ __device__ __forceinline__ void segmented_row_add(A val, int key, bool valid, A 
     vp = dpp_or<0x118>(val, A(0));
     if (kp == key) val += vp;
     const int kn = dpp_or<0x101>(key, -2);  // row_shl:1, the next lane's key
-    if (valid && kn != key) lds_add(&acc[key], val);
+    if (valid && kn != key) lds_add(dst, val);
 }
 
 template <class A>
@@ -250,20 +251,25 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 //
 // When the kernel order equals the packing order (contiguous or no load
 // balance), a wavefront's tiles occupy one contiguous byte range of the
-// payload and one contiguous range of restore_cols.  The wavefront walks its
-// range in batches of at most 16 tiles and 3 KB.  At the start of step b the
-// loads issued during step b-1 have landed: the payload chunks and restore
-// entries of batch b and the metadata of batch b+1.  Step b then
-//   1. moves them into LDS (payload ring, restore area, 16-byte metadata
-//      records of batch b+1) and finds where batch b+1 ends (a ballot),
-//   2. gathers the x values of batch b's tiles (16 columns each),
-//   3. issues the loads of batch b+1's payload and restore entries and of
-//      batch b+2's metadata,
-//   4. stores the gathered x in LDS -- the only wait inside a step, which
-//      leaves the step-3 loads in flight -- and
-//   5. multiplies batch b's tiles out of LDS.
-// Loads are issued on every path (addresses clamped into the arrays) so the
-// number of loads between a load and its use never depends on the path.
+// payload.  The wavefront walks its range in batches of at most 16 tiles,
+// 3 KB of payload and 8 consecutive panels.  The loads of a batch are spread
+// over the three steps before the one that multiplies it, so every step waits
+// once, at its top, for loads issued one step earlier:
+//   step b-3  issues batch b's metadata (one tile per lane),
+//   step b-2  writes batch b's records to LDS, finds where it ends (a ballot)
+//             and issues the x column index of every (tile, column) lane:
+//             the restore_cols entry under column aggregation, else computed,
+//   step b-1  issues batch b's payload chunks and its x values,
+//   step b    moves both into LDS and multiplies the batch.
+// The multiply treats the COO and CSR tiles of a batch as one stream of
+// entries -- both formats store a one-byte (row, column) code per entry,
+// Algorithm 3 -- so lane i of pass p takes entry 64p+i whatever tile it is
+// in, finds its tile from the tiles' end positions, and adds value * x into
+// the LDS accumulator of its panel row.  Dense tiles (Algorithm 4) are
+// multiplied one at a time, four lanes per row.  A panel is written to y at
+// the top of the step after its last tile was multiplied (alpha*sum + beta*y,
+// y read one step ahead; a global atomic add for panels shared with another
+// wavefront, pre-scaled by a pre-pass).
 
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 using i32x4 = int __attribute__((ext_vector_type(4)));
@@ -275,8 +281,9 @@ constexpr int kPRing = kRC * kChunk;  // payload ring per wavefront
 constexpr int kPMask = kPRing - 1;
 constexpr int kBatchBytes = (kRC - 1) * kChunk;  // a batch spans at most kRC chunks of the ring
 constexpr int kBatchTiles = CB_TUNE_BATCH_TILES;
-static_assert(kBatchTiles % 4 == 0 && kBatchTiles <= 60, "x gathers take four tiles per load");
-constexpr int kRArea = 512;           // restore_cols entries staged per batch (two loads per lane)
+static_assert(kBatchTiles % 4 == 0 && kBatchTiles <= 16, "x gathers take four tiles per load; records fill one DPP row");
+constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kMaxPanels = 8;  // accumulator slots: the panels of a batch lie within this many consecutive ones
 
 // packed region size of a tile (16-byte aligned), as laid out by the converter
 template <int VS>
@@ -291,7 +298,11 @@ __device__ __forceinline__ int region_dev(int ty, int nz) {
     return (b + 15) & ~15;
 }
 
-// metadata of up to 17 consecutive tiles, lane i holding tile s + i (clamped to the range)
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// metadata of up to 17 consecutive tiles, lane i holding tile s + min(i, 16) (clamped to the range)
 struct MetaRegs {
     int row, xo, nz, ty, vplo;
 };
@@ -305,19 +316,21 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     constexpr int VS = Val<VT>::kSize;
     constexpr int NG = kBatchTiles / 4;  // x gathers per batch, four tiles each
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
-    __shared__ __align__(16) int32_t rarea_all[kWavesPerBlock][AGG ? kRArea : 4];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
-    __shared__ __align__(16) i32x4 meta_all[kWavesPerBlock][2][kBatchTiles];
-    __shared__ A acc_all[kWavesPerBlock][16];
+    // per batch (three in flight): tile records, flat tiles from index 0 and dense tiles from
+    // index kBatchTiles-1 down, then the header {first panel, panel mask, nflat | ndense << 8, entries}
+    __shared__ __align__(16) i32x4 rec_all[kWavesPerBlock][3][kBatchTiles + 1];
+    __shared__ __align__(16) A acc_all[kWavesPerBlock][kMaxPanels * 16];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
     if (w >= d.nwaves) return;
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    if (t0 >= t1) return;
     uint8_t *pring = pring_all[wid];
-    int32_t *rarea = rarea_all[wid];
     A *xarea = xarea_all[wid];
     A *acc = acc_all[wid];
-    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    i32x4 *recs = rec_all[wid][0];
     const int64_t B0 = d.tile_vp[t0];
     const int b0lo = (int)B0;
     const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + B0) + lane;
@@ -328,26 +341,55 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     const int gj = lane >> 4, glc = lane & 15;
 
     auto mload = [&](int s, MetaRegs &M) {
-        const int t = min(s + lane, t1 - 1);
+        const int t = min(s + min(lane, kBatchTiles), t1 - 1);
         M.row = d.tile_row[t];
         M.xo = AGG ? d.tile_xoff[t] : d.tile_col[t];
         M.nz = d.tile_nnz[t];
         M.ty = d.tile_type[t];
         M.vplo = vp_lo[2 * (size_t)t];
     };
-    // batch starting at tile s (metadata of tiles s.. in lanes 0..): returns the first tile past it
-    // -- past t1, 16 tiles on, or ending more than kBatchBytes after s -- and its byte range
+    // batch starting at tile s (metadata in M): returns the first tile past it -- past t1, 16
+    // tiles on, more than kBatchBytes of payload or kMaxPanels panels after s -- and its bytes
     auto batch_end = [&](int s, const MetaRegs &M, int &rs, int &re) {
         const int rel = M.vplo - b0lo;
         const int e = rel + region_dev<VS>(M.ty, M.nz);
         rs = __builtin_amdgcn_readfirstlane(rel);
-        const bool c = lane >= 1 && (s + lane >= t1 || lane >= kBatchTiles || e - rs > kBatchBytes);
+        const int row0 = __builtin_amdgcn_readfirstlane(M.row);
+        const bool c = lane >= 1 && (s + lane >= t1 || lane >= kBatchTiles || e - rs > kBatchBytes ||
+                                     M.row - row0 >= kMaxPanels);
         const int n = (int)__builtin_ctzll(__ballot(c));
         re = __builtin_amdgcn_readlane(e, n - 1);
         return s + n;
     };
-    auto put_meta = [&](i32x4 *dst, const MetaRegs &M) {
-        if (lane < kBatchTiles) dst[lane] = i32x4{M.row, M.vplo - b0lo, M.xo, M.nz | (M.ty << 16)};
+    // records of a batch of nt tiles (metadata in M); entry positions are relative to the wave's
+    // first payload byte, so entry E of a flat tile sits at ring bytes code x+E and value y+VS*E
+    auto put_meta = [&](i32x4 *rec, const MetaRegs &M, int nt) {
+        const bool in = lane < nt;
+        const int hb = M.ty == 1 ? 16 : 0;
+        const int rel = M.vplo - b0lo;
+        const int coff = rel + hb;
+        const int voff = coff + M.nz + pad_bytes(hb + M.nz, VS);
+        const bool fl = in && M.ty != 2, dn = in && M.ty == 2;
+        const uint64_t flm = __ballot(fl), dnm = __ballot(dn);
+        const int nzf = fl ? M.nz : 0;
+        int sc = nzf;  // inclusive prefix sum of the flat entries over the DPP row of lanes 0..15
+        sc += dpp_or<0x111>(sc, 0);
+        sc += dpp_or<0x112>(sc, 0);
+        sc += dpp_or<0x114>(sc, 0);
+        sc += dpp_or<0x118>(sc, 0);
+        const int es = sc - nzf;
+        const int pb = __builtin_amdgcn_readfirstlane(M.row);
+        int pm = in ? 1 << (M.row - pb) : 0;
+        pm |= dpp_or<0x111>(pm, 0);
+        pm |= dpp_or<0x112>(pm, 0);
+        pm |= dpp_or<0x114>(pm, 0);
+        pm |= dpp_or<0x118>(pm, 0);
+        const int zx = ((M.row & (kMaxPanels - 1)) << 4) | (lane << 20);  // accumulator base | x base << 16
+        if (fl) rec[lanes_below(flm)] = i32x4{coff - es, voff - VS * es, zx, es + M.nz - 1};
+        if (dn) rec[kBatchTiles - 1 - lanes_below(dnm)] = i32x4{rel, 0, zx, 0};
+        const int nfd = (int)__builtin_popcountll(flm) | ((int)__builtin_popcountll(dnm) << 8);
+        const int etot = __builtin_amdgcn_readlane(sc, 15), pmask = __builtin_amdgcn_readlane(pm, 15);
+        if (lane == 0) rec[kBatchTiles] = i32x4{pb, pmask, nfd, etot};
     };
 
     // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued)
@@ -373,43 +415,28 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         for (int i = 0; i < kRC; ++i)
             if (i < pcnt) ring4[((pfirst + i) & (kRC - 1)) * kWave + lane] = P[i];
     };
-    // restore_cols entries of a batch: a batch's tiles use at most 16 x 16 consecutive entries, so
-    // 512 entries from its first tile's entry (rounded down to 16 bytes) always cover them
-    i32x4 R0 = {0, 0, 0, 0}, R1 = {0, 0, 0, 0};
-    int rbase = 0, rbase_cur = 0;
-    auto issue_restore = [&](int xo_first) {
-        if (!AGG) return;
-        rbase = xo_first & ~3;
-        const i32x4 *rp = reinterpret_cast<const i32x4 *>(d.restore_cols + rbase) + lane;
-        R0 = rp[0];
-        R1 = rp[kWave];
-    };
-    auto put_restore = [&]() {
-        if (!AGG) return;
-        i32x4 *ra4 = reinterpret_cast<i32x4 *>(rarea);
-        ra4[lane] = R0;
-        ra4[kWave + lane] = R1;
-        rbase_cur = rbase;
-    };
-    // x of a batch's tiles (records in meta, nt tiles): lane (gj, glc) takes column glc of tile 4g + gj
-    A XG[NG];
-    auto issue_x = [&](const i32x4 *meta, int nt) {
+    // x column of lane (gj, glc) for tile 4g + gj of a batch (metadata M, nt tiles); columns past a
+    // tile's last one read a neighbour's (restore_cols is padded) or column 0, never multiplied
+    int RG[NG];
+    auto issue_cols = [&](const MetaRegs &M, int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (4 * g < nt) {
-                const int i = 4 * g + gj;
-                const int xo = meta[i].z;
-                int col;
+                const int xo = __shfl(M.xo, 4 * g + gj);
                 if (AGG) {
-                    const int64_t ra = (int64_t)xo + glc - rbase_cur;
-                    col = rarea[ra < 0 ? 0 : (ra >= kRArea ? kRArea - 1 : (int)ra)];
+                    RG[g] = d.restore_cols[xo + glc];
                 } else {
                     const int64_t c = 16 * (int64_t)xo + glc;
-                    col = (c >= 0 && c < d.n) ? (int)c : 0;
+                    RG[g] = c < d.n ? (int)c : 0;
                 }
-                XG[g] = x[col];
             }
         }
+    };
+    A XG[NG];
+    auto issue_x = [&](int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            if (4 * g < nt) XG[g] = x[RG[g]];
     };
     auto put_x = [&](int nt) {
 #pragma unroll
@@ -417,110 +444,163 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             if (4 * g < nt) xarea[(4 * g + gj) * 16 + glc] = XG[g];
     };
 
-    if (lane < 16) acc[lane] = A(0);
-    if (lane < 2 * kBatchTiles) (&meta_all[wid][0][0])[lane] = i32x4{0, 0, 0, 0};
-    int cur = -1;
-    auto flush = [&](int p) {
-        if (lane < 16) {
-            const int64_t row = 16 * (int64_t)p + lane;
-            const A v = acc[lane];
-            acc[lane] = A(0);
-            if (row < d.m) {
-                if ((p == p_first && sh_first) || (p == p_last && sh_last)) {
-                    global_add(&y[row], alpha * v);
-                } else {
-                    A r = alpha * v;
-                    if (beta != A(0)) r += beta * y[row];
-                    y[row] = r;
-                }
-            }
+    // panels finished by a batch: lane (k, r) holds row r of panel pb + k (YP[0]) and pb + 4 + k (YP[1])
+    const int fk = lane >> 4, fr = lane & 15;
+    A YP[2] = {A(0), A(0)};
+    int done_pb = 0, done_mask = 0;
+    auto is_shared = [&](int p) { return (p == p_first && sh_first) || (p == p_last && sh_last); };
+    auto issue_y = [&]() {
+        if (beta == A(0)) return;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = fk + 4 * h;
+            const int64_t row = 16 * (int64_t)(done_pb + k) + fr;
+            if (((done_mask >> k) & 1) && row < d.m && !is_shared(done_pb + k)) YP[h] = y[row];
         }
     };
-    auto rv = [&](int off) { return Val<VT>::load(pring + (off & kPMask), 0); };
-
-    // Pipeline state at the top of step b: the loads issued during step b-1 have
-    // landed -- P = batch b's new payload chunks, XG = batch b's x, R = batch b+1's
-    // restore entries, M = batch b+1's metadata; meta[buf] holds batch b's records.
-    MetaRegs M;
-    int s = t0, rs, re;
-    mload(t0, M);
-    int e = batch_end(s, M, rs, re);
-    int buf = 0;
-    put_meta(meta_all[wid][0], M);
-    issue_payload(rs, re);
-    issue_restore(__builtin_amdgcn_readfirstlane(M.xo));
-    put_restore();  // waits: batch 0's restore entries are needed for its own x gathers
-    issue_x(meta_all[wid][0], e - s);
-    if (e < t1) {
-        issue_restore(__builtin_amdgcn_readlane(M.xo, e - s));  // batch 1 starts at tile e
-        mload(e, M);
-    }
-    while (s < t1) {
-        const int nt = e - s;
-        // 1. step b-1's loads into LDS
-        put_payload();
-        put_x(nt);
-        const bool more = e < t1;
-        const int s2 = e;
-        int e2 = s2, rs2 = 0, re2 = 0;
-        if (more) {
-            put_meta(meta_all[wid][buf ^ 1], M);
-            put_restore();
-            e2 = batch_end(s2, M, rs2, re2);
-        }
-        // 2. loads for batch b+1 (payload, x) and batch b+2 (restore entries, metadata)
-        if (more) {
-            issue_payload(rs2, re2);
-            issue_x(meta_all[wid][buf ^ 1], e2 - s2);
-            if (e2 < t1) {
-                issue_restore(__builtin_amdgcn_readlane(M.xo, e2 - s2));  // batch b+2 starts at tile e2
-                mload(e2, M);  // batch b+2's metadata (tiles e2..)
-            }
-        }
-        // 3. batch b's tiles
-        const i32x4 *meta = meta_all[wid][buf];
-        for (int u = s; u < e; ++u) {
-            const i32x4 rec = meta[u - s];
-            const int row = __builtin_amdgcn_readfirstlane(rec.x);
-            const int rel = __builtin_amdgcn_readfirstlane(rec.y);
-            const int ntw = __builtin_amdgcn_readfirstlane(rec.w);
-            const int nz = ntw & 0xFFFF, ty = ntw >> 16;
-            if (row != cur) {
-                if (cur >= 0) flush(cur);
-                cur = row;
-            }
-            const A *xs = xarea + (u - s) * 16;
-            if (ty != 2) {
-                // COO (Algorithm 3) and CSR tiles: one lane per entry on the shared codes
-                const int hdr = ty == 1 ? 16 : 0;
-                const int coff = rel + hdr, voff = rel + hdr + nz + pad_bytes(hdr + nz, VS);
-                for (int q0 = 0; q0 < nz; q0 += kWave) {
-                    const int q = q0 + lane;
-                    const bool valid = q < nz;
-                    const uint32_t code = pring[(coff + min(q, nz - 1)) & kPMask];
-                    const A prod = valid ? rv(voff + q * VS) * xs[code >> 4] : A(0);
-                    if (DPPRED)
-                        segmented_row_add(prod, valid ? (int)(code & 15) : 16 + lane, valid, acc);
-                    else if (valid)
-                        lds_add(&acc[code & 15], prod);
-                }
-            } else {
-                const int r4 = lane >> 2, q4 = lane & 3;
-                const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
-                const int vo = rel + (r4 * 16 + 4 * q4) * VS;
-                A sum = A(0);
+    auto flush = [&]() {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if ((bits >> j) & 1u) sum += rv(vo + j * VS) * xs[4 * q4 + j];
-                sum = quad_sum(sum);
-                if (q4 == 0) acc[r4] += sum;
+        for (int h = 0; h < 2; ++h) {
+            const int k = fk + 4 * h;
+            if ((done_mask >> k) & 1) {
+                const int p = done_pb + k;
+                A *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
+                const A v = *a;
+                *a = A(0);
+                const int64_t row = 16 * (int64_t)p + fr;
+                if (row < d.m) {
+                    if (is_shared(p)) {
+                        global_add(&y[row], alpha * v);
+                    } else {
+                        A r = alpha * v;
+                        if (beta != A(0)) r += beta * YP[h];
+                        y[row] = r;
+                    }
+                }
             }
         }
-        s = s2;
-        e = e2;
-        buf ^= 1;
+        done_mask = 0;
+    };
+
+    auto multiply = [&](const i32x4 *rec) {
+        const i32x4 h = rec[kBatchTiles];
+        const int nfd = __builtin_amdgcn_readfirstlane(h.z), etot = __builtin_amdgcn_readfirstlane(h.w);
+        const int nflat = nfd & 0xFF, ndense = nfd >> 8;
+        // COO and CSR entries as one stream; endv: last entry of flat tile `lane`
+        const int endv = rec[min(lane, kBatchTiles - 1)].w;
+        int j = 0;  // tile holding entry e0
+        for (int e0 = 0; e0 < etot; e0 += kWave) {
+            const int E = e0 + lane;
+            int ti = j;
+            while (j < nflat) {
+                const int ej = __builtin_amdgcn_readlane(endv, j);
+                if (ej >= e0 + kWave) break;
+                ti += E > ej ? 1 : 0;
+                ++j;
+            }
+            const bool valid = E < etot;
+            const i32x4 r = rec[min(ti, nflat - 1)];
+            const uint32_t code = pring[(r.x + E) & kPMask];
+            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[(r.z >> 16) + (code >> 4)];
+            A *dst = &acc[(r.z & 0xFFFF) + (code & 15)];
+            if (DPPRED)
+                segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
+                                  dst);
+            else if (valid)
+                lds_add(dst, prod);
+        }
+        // dense tiles, four lanes per row
+        const int r4 = lane >> 2, q4 = lane & 3;
+        for (int k = 0; k < ndense; ++k) {
+            const i32x4 r = rec[kBatchTiles - 1 - k];
+            const int rel = __builtin_amdgcn_readfirstlane(r.x), zx = __builtin_amdgcn_readfirstlane(r.z);
+            const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
+            const int vo = rel + (r4 * 16 + 4 * q4) * VS;
+            const A *xs = xarea + (zx >> 16) + 4 * q4;
+            A sum = A(0);
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
+            sum = quad_sum(sum);
+            if (q4 == 0) lds_add(&acc[(zx & 0xFFFF) + r4], sum);
+        }
+    };
+
+    if (lane < kMaxPanels * 16 / 2) {
+        acc[lane] = A(0);
+        acc[lane + kMaxPanels * 16 / 2] = A(0);
     }
-    if (cur >= 0) flush(cur);
+    // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
+    // columns; batch 2's metadata.  At the top of step b the registers hold P and XG of batch b,
+    // RG of batch b+1 and M of batch b+2; LDS holds the records of batches b and b+1.
+    MetaRegs M;
+    int bufb = 0;
+    int sb = t0, rs1, re1;
+    mload(sb, M);
+    int eb = batch_end(sb, M, rs1, re1);
+    put_meta(recs, M, eb - sb);
+    issue_cols(M, eb - sb);
+    issue_payload(rs1, re1);
+    if (eb < t1) mload(eb, M);
+    issue_x(eb - sb);  // waits for batch 0's x columns
+    int e1 = eb;
+    if (eb < t1) {
+        e1 = batch_end(eb, M, rs1, re1);
+        put_meta(recs + (kBatchTiles + 1), M, e1 - eb);
+        issue_cols(M, e1 - eb);
+        if (e1 < t1) mload(e1, M);
+    }
+    while (sb < t1) {
+        const int bufn = bufb == 2 ? 0 : bufb + 1, bufnn = bufn == 2 ? 0 : bufn + 1;
+        // the one wait of a step: every load issued by the previous step has landed (loads are
+        // issued conditionally, so the compiler's own counting would wait inside step 2)
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        // 1. step b-1's loads: payload and x of batch b into LDS, the panels batch b-1 finished to y,
+        //    batch b+2's records
+        put_payload();
+        put_x(eb - sb);
+        flush();
+        const bool have1 = eb < t1, have2 = e1 < t1;
+        int e2 = e1, rs2 = 0, re2 = 0;
+        if (have2) {
+            e2 = batch_end(e1, M, rs2, re2);
+            put_meta(recs + bufnn * (kBatchTiles + 1), M, e2 - e1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // 2. loads: payload and x of batch b+1, x columns of batch b+2, metadata of batch b+3, and
+        //    y of the panels batch b finishes
+        if (have1) {
+            issue_payload(rs1, re1);
+            issue_x(e1 - eb);
+        }
+        if (have2) {
+            issue_cols(M, e2 - e1);
+            if (e2 < t1) mload(e2, M);
+        }
+        const i32x4 *rec = recs + bufb * (kBatchTiles + 1);
+        {
+            const i32x4 hb = rec[kBatchTiles];
+            done_pb = __builtin_amdgcn_readfirstlane(hb.x);
+            done_mask = __builtin_amdgcn_readfirstlane(hb.y);
+            if (have1) {
+                // the next batch continues this batch's last panel unless it starts a new one
+                const int pn = __builtin_amdgcn_readfirstlane(recs[bufn * (kBatchTiles + 1) + kBatchTiles].x);
+                const int lastk = 31 - __builtin_clz(done_mask);
+                if (done_pb + lastk == pn) done_mask &= ~(1 << lastk);
+            }
+        }
+        issue_y();
+        // 3. batch b
+        multiply(rec);
+        __builtin_amdgcn_wave_barrier();
+        sb = eb;
+        eb = e1;
+        e1 = e2;
+        rs1 = rs2;
+        re1 = re2;
+        bufb = bufn;
+    }
+    flush();
 }
 
 // ---- k right-hand sides ---------------------------------------------------
