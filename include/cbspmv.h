@@ -116,13 +116,17 @@ typedef struct {
     double quantum_nnz_mean, quantum_nnz_std;
     int64_t wave_nnz_max;
     double wave_nnz_mean, wave_nnz_std;
-    int64_t spmv_bytes;     /* algorithmic HBM bytes of one cb_spmv with beta == 0:
-                               structure + x once + y once */
+    int64_t spmv_bytes;     /* algorithmic HBM bytes of one cb_spmv with beta == 0: the structure
+                               the kernel of the handle's load-balance mode reads (payload, batch
+                               records or the high-level arrays, restore_cols, schedule) + x once
+                               + y once */
     int64_t device_bytes;   /* device memory owned by the handle */
     double convert_seconds; /* host conversion time */
     int32_t on_device;      /* 1 for cb_create handles, 0 for cb_create_host */
     int32_t reserved0;
-    int64_t reserved[8];
+    int64_t nbatches;       /* batches of the streaming kernel (0 with CB_LB_PAPER) */
+    int64_t stream_bytes;   /* its batch records: 16 bytes per batch and per tile */
+    int64_t reserved[6];
 } cb_info_t;
 
 /* Host buffers receiving the structure in kernel order (ntiles entries for the
@@ -146,6 +150,9 @@ typedef struct {
     uint8_t *panel_shared;   /* 1 if the panel's tiles span more than one work range */
     int32_t *prepass_list;   /* panels written by the pre-pass */
     int32_t *tile_xoff;      /* aggregation only: cols_offset[tile_row] + 16 * tile_col, kernel order */
+    int32_t *batch_stream;   /* streaming kernel: stream_bytes / 4 ints, a 16-byte header per batch
+                                followed by a 16-byte record per tile (CB_LB_PAPER: none) */
+    int32_t *batch_ptr;      /* first record of each work range, nwaves + 1 (CB_LB_PAPER: none) */
 } cb_structure_t;
 
 /* Fill *opt with the defaults above (the paper's thresholds). */

@@ -51,13 +51,13 @@ class CbInfo(ctypes.Structure):
                 ("prepass_panels", _i64), ("quantum_nnz_max", _i64), ("quantum_nnz_mean", _dbl),
                 ("quantum_nnz_std", _dbl), ("wave_nnz_max", _i64), ("wave_nnz_mean", _dbl), ("wave_nnz_std", _dbl),
                 ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
-                ("reserved0", _i32), ("reserved", _i64 * 8)]
+                ("reserved0", _i32), ("nbatches", _i64), ("stream_bytes", _i64), ("reserved", _i64 * 6)]
 
 
 class CbStructure(ctypes.Structure):
     _fields_ = [(n, _p) for n in ("tile_row", "tile_col", "tile_nnz", "tile_vp", "tile_type", "tile_ori", "payload",
                                   "restore_cols", "cols_offset", "quantum_ptr", "wave_ptr", "panel_shared",
-                                  "prepass_list", "tile_xoff")]
+                                  "prepass_list", "tile_xoff", "batch_stream", "batch_ptr")]
 
 
 _lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
@@ -215,6 +215,8 @@ def cb_export_structure(A: int) -> dict:
         "quantum_ptr": np.empty(info["nquanta"] + 1, np.int32), "wave_ptr": np.empty(info["nwaves"] + 1, np.int32),
         "panel_shared": np.empty(P, np.uint8), "prepass_list": np.empty(info["prepass_panels"], np.int32),
         "tile_xoff": np.empty(NT if info["col_agg"] else 0, np.int32),
+        "batch_stream": np.empty(info["stream_bytes"] // 4, np.int32),
+        "batch_ptr": np.empty(info["nwaves"] + 1 if info["lb_mode"] != CB_LB_PAPER else 0, np.int32),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
     _check(_lib.cb_export_structure(A, ctypes.byref(s)))

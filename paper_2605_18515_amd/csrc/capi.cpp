@@ -27,7 +27,7 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 // byte offsets of every array inside the single device allocation
 struct Layout {
     size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
-        quantum_ptr, panel_shared, prepass_list, total;
+        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -49,13 +49,17 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.tile_ori = put(4 * NT);
     L.tile_xoff = put(s.col_agg ? 4 * NT : 0);
     // the streaming kernel reads whole 1 KB chunks past the last tile and the last restore entry
-    L.payload = put((size_t)s.payload_bytes + cbh::kStreamPad);
-    L.restore_cols = put(4 * (size_t)s.nrestore + cbh::kStreamPad);
+    L.payload = put((size_t)s.payload_bytes + cbs::kPayloadPad);
+    L.restore_cols = put(4 * (size_t)s.nrestore + cbs::kPayloadPad);
     L.cols_offset = put(s.col_agg ? 4 * ((size_t)s.npanels + 1) : 0);
     L.wave_ptr = put(4 * ((size_t)s.nwaves + 1));
     L.quantum_ptr = put(4 * ((size_t)s.nquanta + 1));
     L.panel_shared = put((size_t)s.npanels);
     L.prepass_list = put(4 * (size_t)s.nprepass);
+    // the streaming kernel reads 17 records from the start of every batch
+    const bool stream = s.lb_mode != CB_LB_PAPER;
+    L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kRecordPad) : 0);
+    L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
     L.total = off;
     return L;
 }
@@ -138,6 +142,8 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.quantum_ptr, s.quantum_ptr);
         put_array(stage, L.panel_shared, s.panel_shared);
         put_array(stage, L.prepass_list, s.prepass_list);
+        put_array(stage, L.batch_stream, s.batch_stream);
+        put_array(stage, L.batch_ptr, s.batch_ptr);
         e = hipMalloc(&A->dbuf, L.total);
         if (e != hipSuccess) {
             A->dbuf = nullptr;
@@ -161,6 +167,8 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.wave_ptr = dptr<int32_t>(A, L.wave_ptr);
     v.panel_shared = dptr<uint8_t>(A, L.panel_shared);
     v.prepass_list = dptr<int32_t>(A, L.prepass_list);
+    v.batch_stream = dptr<int32_t>(A, L.batch_stream);
+    v.batch_ptr = dptr<int32_t>(A, L.batch_ptr);
     v.m = s.m;
     v.n = s.n;
     v.nwaves = (int32_t)s.nwaves;
@@ -183,6 +191,8 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     std::vector<int32_t>().swap(s.wave_ptr);
     std::vector<uint8_t>().swap(s.panel_shared);
     std::vector<int32_t>().swap(s.prepass_list);
+    std::vector<int32_t>().swap(s.batch_stream);
+    std::vector<int32_t>().swap(s.batch_ptr);
     A->on_device = true;
     return CB_SUCCESS;
 }
@@ -221,6 +231,10 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.quantum_ptr, (size_t)A->h.nquanta + 1, tmp.quantum_ptr)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.panel_shared, (size_t)A->h.npanels, tmp.panel_shared)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.prepass_list, (size_t)A->h.nprepass, tmp.prepass_list)) != CB_SUCCESS) return st;
+    if ((st = fetch(A, L.batch_stream, 4 * (size_t)A->h.nrecords, tmp.batch_stream)) != CB_SUCCESS) return st;
+    if ((st = fetch(A, L.batch_ptr, A->h.lb_mode != CB_LB_PAPER ? (size_t)A->h.nwaves + 1 : 0, tmp.batch_ptr)) !=
+        CB_SUCCESS)
+        return st;
     s = &tmp;
     return CB_SUCCESS;
 }
@@ -363,6 +377,8 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *o) {
     cp(o->wave_ptr, s->wave_ptr);
     cp(o->panel_shared, s->panel_shared);
     cp(o->prepass_list, s->prepass_list);
+    cp(o->batch_stream, s->batch_stream);
+    cp(o->batch_ptr, s->batch_ptr);
     return CB_SUCCESS;
 }
 

@@ -22,6 +22,8 @@ struct DevView {
     const int32_t *wave_ptr;      // nwaves + 1
     const uint8_t *panel_shared;  // npanels
     const int32_t *prepass_list;  // nprepass
+    const int32_t *batch_stream;  // natural order only: batch headers and tile records (cb_stream.h), 4 ints each
+    const int32_t *batch_ptr;     // natural order only: first record of each work range, nwaves + 1
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range

@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "cb_stream.h"
 #include "cbspmv.h"
 
 namespace cbh {
@@ -14,7 +15,6 @@ constexpr int kSuperSparse = 32;  // Section 3.3.1: fewer than 32 non-zeros
 constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte boundary
 constexpr int kDenseMaskBytes = 32;
 constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
-constexpr int kStreamPad = 2048;  // device bytes after payload and restore_cols read by the streaming kernel
 
 struct HostStructure {
     int64_t m = 0, n = 0, nnz = 0;
@@ -36,8 +36,12 @@ struct HostStructure {
     std::vector<int32_t> quantum_ptr, wave_ptr;
     std::vector<uint8_t> panel_shared;
     std::vector<int32_t> prepass_list;
+    // batch records of the streaming kernel (natural-order modes only): 4 ints per record,
+    // batch_ptr[w] = first record of work range w
+    std::vector<int32_t> batch_stream, batch_ptr;
     // counts kept when the big arrays move to the device
     int64_t payload_bytes = 0, nrestore = 0, nquanta = 0, nwaves = 0, nprepass = 0, nshared = 0;
+    int64_t nbatches = 0, nrecords = 0;
     int64_t tiles_fmt[3] = {0, 0, 0};
     int64_t quantum_nnz_max = 0, wave_nnz_max = 0;
     double quantum_nnz_mean = 0, quantum_nnz_std = 0, wave_nnz_mean = 0, wave_nnz_std = 0;

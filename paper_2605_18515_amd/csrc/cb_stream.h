@@ -1,0 +1,38 @@
+// Batch records of the streaming SpMV kernel, shared by the converter (which
+// writes them) and the kernel (which reads them).  Internal to libcbspmv.
+//
+// With the contiguous or no load balance the kernel order is the packing
+// order, so a wavefront's tiles occupy one contiguous byte range of the
+// payload.  The converter cuts every wavefront range into batches and writes,
+// per batch, one 16-byte header followed by one 16-byte record per tile:
+//
+//   header  {re, pb, nt | nflat << 8 | ndense << 16 | done << 24, etot}
+//     re     end of the batch's payload bytes, relative to the range's first
+//            payload byte (the batch starts where the previous one ended)
+//     pb     first panel of the batch
+//     nt     tiles; nflat of them COO or CSR, ndense Dense
+//     done   bit k: panel pb + k has its last tile of this range in the batch
+//     etot   COO and CSR entries of the batch (the flat entry stream)
+//   flat record (COO and CSR tiles, in order)  {cpos, vpos, end | slot << 16, xo}
+//     the tile's entries are flat entries es .. end of the batch, and flat
+//     entry E has its one-byte code at payload byte cpos + E and its value at
+//     byte vpos + size(Val) * E (relative to the range's first payload byte)
+//   dense record (Dense tiles, after the flat ones)  {rel, 0, slot << 16, xo}
+//     rel    the tile's first payload byte (relative)
+//   slot     panel & (kBatchPanels - 1): the panel's accumulator in the kernel
+//   xo       restore_cols index of the tile's first column under column
+//            aggregation (cols_offset[panel] + 16 * chunk), else its column block
+//
+// The x values of the tile in record i land in the kernel's x area at 16 * i.
+#pragma once
+
+namespace cbs {
+
+constexpr int kChunk = 1024;      // payload bytes one wavefront-wide 16-byte load covers
+constexpr int kRingChunks = 4;    // payload chunks a batch may touch (the kernel's LDS ring)
+constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
+constexpr int kBatchPanels = 8;   // consecutive panels a batch may touch (accumulator slots)
+constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream
+constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes readable past their ends
+
+}  // namespace cbs

@@ -159,6 +159,81 @@ void moments(const std::vector<int64_t> &v, int64_t &mx, double &mean, double &s
     sd = std::sqrt((double)(s2 / v.size()));
 }
 
+// Batches of the streaming kernel (format in cb_stream.h): every work range
+// is cut, in order, into runs of at most kBatchTiles tiles whose payload bytes
+// touch at most kRingChunks chunks of kChunk bytes and whose panels lie within
+// kBatchPanels consecutive ones.
+void build_stream(HostStructure &s) {
+    using namespace cbs;
+    const int vs = s.vsize;
+    const int64_t NW = s.nwaves;
+    s.batch_ptr.assign((size_t)NW + 1, 0);
+    std::vector<int32_t> &bs = s.batch_stream;
+    bs.clear();
+    int64_t nb = 0;
+    auto region = [&](int64_t t) { return region_bytes(s.tile_type[t], s.tile_nnz[t], vs); };
+    auto push = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
+        bs.push_back(a);
+        bs.push_back(b);
+        bs.push_back(c);
+        bs.push_back(d);
+    };
+    for (int64_t w = 0; w < NW; ++w) {
+        s.batch_ptr[w] = (int32_t)(bs.size() / 4);
+        const int64_t t0 = s.wave_ptr[w], t1 = s.wave_ptr[w + 1];
+        if (t0 >= t1) continue;
+        const int64_t B0 = s.tile_vp[t0];
+        int64_t b = t0;
+        while (b < t1) {
+            const int64_t rs = s.tile_vp[b] - B0;
+            int64_t e = b + 1;
+            while (e < t1 && e - b < kBatchTiles && s.tile_row[e] - s.tile_row[b] < kBatchPanels) {
+                const int64_t re_e = s.tile_vp[e] - B0 + region(e);
+                if (((re_e - 1) / kChunk) - rs / kChunk + 1 > kRingChunks) break;
+                ++e;
+            }
+            const int64_t re = s.tile_vp[e - 1] - B0 + region(e - 1);
+            const int32_t pb = s.tile_row[b];
+            uint32_t done = 0;
+            int nflat = 0, ndense = 0;
+            for (int64_t t = b; t < e; ++t) {
+                done |= 1u << (s.tile_row[t] - pb);
+                if (s.tile_type[t] == CB_FMT_DENSE) ++ndense; else ++nflat;
+            }
+            if (e < t1 && s.tile_row[e] == s.tile_row[e - 1]) done &= ~(1u << (s.tile_row[e - 1] - pb));
+            const size_t hdr = bs.size();
+            push(0, 0, 0, 0);
+            int64_t es = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int64_t t = b; t < e; ++t) {
+                    const int fmt = s.tile_type[t];
+                    if ((fmt == CB_FMT_DENSE) != (pass == 1)) continue;
+                    const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
+                    const int32_t slot = (int32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 16;
+                    const int32_t xo = s.col_agg ? s.cols_offset[s.tile_row[t]] + 16 * s.tile_col[t] : s.tile_col[t];
+                    if (fmt == CB_FMT_DENSE) {
+                        push((int32_t)rel, 0, slot, xo);
+                    } else {
+                        const int64_t hb = fmt == CB_FMT_CSR ? kBlk : 0;
+                        const int64_t voff = rel + hb + nz + padding(hb + nz, vs);
+                        push((int32_t)(rel + hb - es), (int32_t)(voff - vs * es), (int32_t)(es + nz - 1) | slot, xo);
+                        es += nz;
+                    }
+                }
+            }
+            bs[hdr] = (int32_t)re;
+            bs[hdr + 1] = pb;
+            bs[hdr + 2] = (int32_t)((e - b) | (nflat << 8) | (ndense << 16) | (done << 24));
+            bs[hdr + 3] = (int32_t)es;
+            ++nb;
+            b = e;
+        }
+    }
+    s.batch_ptr[NW] = (int32_t)(bs.size() / 4);
+    s.nbatches = nb;
+    s.nrecords = (int64_t)(bs.size() / 4);
+}
+
 }  // namespace
 
 int padding(int64_t index_bytes, int vsize) {
@@ -533,6 +608,14 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         s.nquanta = (int64_t)qptr.size() - 1;
         s.nwaves = NW;
         s.nprepass = (int64_t)s.prepass_list.size();
+        if (opt.lb_mode != CB_LB_PAPER) {
+            // the records' 32-bit fields bound what one range and the whole stream may hold
+            if (NT + (int64_t)NW + 1 > (int64_t)INT32_MAX / 2) {
+                err = "too many tiles for the streaming kernel's batch records";
+                return CB_ERROR_NOT_SUPPORTED;
+            }
+            build_stream(s);
+        }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed during conversion";
         return CB_ERROR_OUT_OF_MEMORY;
@@ -612,10 +695,20 @@ cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_id
 
 int64_t spmv_bytes(const HostStructure &s) {
     const int64_t xe = s.vtype == CB_VALUE_F64 ? 8 : 4;
-    int64_t b = s.payload_bytes + 21 * s.ntiles;  // payload + high-level arrays (4+4+4+8+1 per tile)
-    if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1) + 4 * s.ntiles;  // + per-tile restore index
-    b += 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;  // work ranges, panel flags, pre-pass list
-    b += xe * s.n + xe * s.m;                              // x read once, y written once
+    int64_t b = s.payload_bytes + xe * s.n + xe * s.m;  // payload, x read once, y written once
+    if (s.lb_mode == CB_LB_PAPER) {
+        // tile-at-a-time kernel: high-level arrays (4+4+4+8+1 per tile), restore_cols through
+        // cols_offset, work ranges, panel flags, pre-pass list
+        b += 21 * s.ntiles;
+        if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1);
+        b += 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;
+    } else {
+        // streaming kernel: batch records, restore_cols, two range pointers per range and the
+        // first tile's offset and the end panels' flags, pre-pass list
+        b += 16 * s.nrecords;
+        if (s.col_agg) b += 4 * s.nrestore;
+        b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
+    }
     return b;
 }
 
@@ -648,6 +741,8 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.wave_nnz_mean = s.wave_nnz_mean;
     info.wave_nnz_std = s.wave_nnz_std;
     info.spmv_bytes = spmv_bytes(s);
+    info.nbatches = s.nbatches;
+    info.stream_bytes = 16 * s.nrecords;
     info.convert_seconds = s.convert_seconds;
 }
 

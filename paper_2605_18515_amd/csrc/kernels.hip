@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cb_device.h"
+#include "cb_stream.h"
 
 namespace cbd {
 namespace {
@@ -25,12 +26,6 @@ namespace {
 // Tuning parameters (fixed at build time; the defaults are the measured best on MI355X)
 #ifndef CB_TUNE_WAVES_PER_BLOCK
 #define CB_TUNE_WAVES_PER_BLOCK 4
-#endif
-#ifndef CB_TUNE_RING_CHUNKS
-#define CB_TUNE_RING_CHUNKS 4  // 1 KB chunks in the payload ring; a batch spans at most this many
-#endif
-#ifndef CB_TUNE_BATCH_TILES
-#define CB_TUNE_BATCH_TILES 16
 #endif
 #ifndef CB_TUNE_F64_DPP
 #define CB_TUNE_F64_DPP 0  // FP64 row sums: 0 = LDS atomics per entry, 1 = DPP segmented scan
@@ -251,14 +246,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 //
 // When the kernel order equals the packing order (contiguous or no load
 // balance), a wavefront's tiles occupy one contiguous byte range of the
-// payload.  The wavefront walks its range in batches of at most 16 tiles,
-// 3 KB of payload and 8 consecutive panels.  The loads of a batch are spread
-// over the three steps before the one that multiplies it, so every step waits
-// once, at its top, for loads issued one step earlier:
-//   step b-3  issues batch b's metadata (one tile per lane),
-//   step b-2  writes batch b's records to LDS, finds where it ends (a ballot)
-//             and issues the x column index of every (tile, column) lane:
-//             the restore_cols entry under column aggregation, else computed,
+// payload.  The converter cuts the range into batches (at most 16 tiles whose
+// payload touches at most four 1 KB chunks and whose panels lie within eight
+// consecutive ones) and writes each batch as a header and one record per tile
+// (format in cb_stream.h): the offsets the multiply needs, precomputed once.
+// The loads of a batch are spread over the three steps before the one that
+// multiplies it, so every step waits once, at its top, for loads issued one
+// step earlier:
+//   step b-3  issues batch b's header and records (one 16-byte load per lane),
+//   step b-2  stores them in LDS and issues the x column index of every
+//             (tile, column) lane: the restore_cols entry under column
+//             aggregation, else computed,
 //   step b-1  issues batch b's payload chunks and its x values,
 //   step b    moves both into LDS and multiplies the batch.
 // The multiply treats the COO and CSR tiles of a batch as one stream of
@@ -274,38 +272,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 using i32x4 = int __attribute__((ext_vector_type(4)));
 
-constexpr int kChunk = 1024;          // one wave-wide load: 64 lanes x 16 bytes
-constexpr int kRC = CB_TUNE_RING_CHUNKS;
-static_assert(kRC == 4 || kRC == 8, "ring of 4 or 8 chunks");
+constexpr int kChunk = cbs::kChunk;
+constexpr int kRC = cbs::kRingChunks;
 constexpr int kPRing = kRC * kChunk;  // payload ring per wavefront
 constexpr int kPMask = kPRing - 1;
-constexpr int kBatchBytes = (kRC - 1) * kChunk;  // a batch spans at most kRC chunks of the ring
-constexpr int kBatchTiles = CB_TUNE_BATCH_TILES;
-static_assert(kBatchTiles % 4 == 0 && kBatchTiles <= 16, "x gathers take four tiles per load; records fill one DPP row");
+constexpr int kBatchTiles = cbs::kBatchTiles;
+constexpr int kMaxPanels = cbs::kBatchPanels;
+constexpr int kRecs = kBatchTiles + 1;  // header and records of one batch
+static_assert(kChunk == kWave * 16 && (kPRing & kPMask) == 0, "one chunk per wavefront-wide 16-byte load");
+static_assert(kBatchTiles == 16 && kBatchTiles + 1 <= kWave, "records fill one DPP row; x gathers take four tiles per load");
+static_assert(kMaxPanels * 16 <= 2 * kWave, "accumulators cleared by two stores per lane");
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
-constexpr int kMaxPanels = 8;  // accumulator slots: the panels of a batch lie within this many consecutive ones
-
-// packed region size of a tile (16-byte aligned), as laid out by the converter
-template <int VS>
-__device__ __forceinline__ int region_dev(int ty, int nz) {
-    int b;
-    if (ty == 0)
-        b = nz + pad_bytes(nz, VS) + nz * VS;
-    else if (ty == 1)
-        b = 16 + nz + pad_bytes(16 + nz, VS) + nz * VS;
-    else
-        b = 256 * VS + 32;
-    return (b + 15) & ~15;
-}
-
-__device__ __forceinline__ int lanes_below(uint64_t m) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// metadata of up to 17 consecutive tiles, lane i holding tile s + min(i, 16) (clamped to the range)
-struct MetaRegs {
-    int row, xo, nz, ty, vplo;
-};
 
 template <int VT, bool AGG, bool DPPRED>
 __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
@@ -317,93 +294,45 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     constexpr int NG = kBatchTiles / 4;  // x gathers per batch, four tiles each
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
-    // per batch (three in flight): tile records, flat tiles from index 0 and dense tiles from
-    // index kBatchTiles-1 down, then the header {first panel, panel mask, nflat | ndense << 8, entries}
-    __shared__ __align__(16) i32x4 rec_all[kWavesPerBlock][3][kBatchTiles + 1];
+    __shared__ __align__(16) i32x4 rec_all[kWavesPerBlock][3][kRecs];  // three batches in flight
     __shared__ __align__(16) A acc_all[kWavesPerBlock][kMaxPanels * 16];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
     if (w >= d.nwaves) return;
-    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
-    if (t0 >= t1) return;
+    const int o_begin = d.batch_ptr[w], o_end = d.batch_ptr[w + 1];
+    if (o_begin >= o_end) return;
     uint8_t *pring = pring_all[wid];
     A *xarea = xarea_all[wid];
     A *acc = acc_all[wid];
     i32x4 *recs = rec_all[wid][0];
-    const int64_t B0 = d.tile_vp[t0];
-    const int b0lo = (int)B0;
-    const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + B0) + lane;
-    const int *vp_lo = reinterpret_cast<const int *>(d.tile_vp);  // low words of the 64-bit virtual pointers
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + d.tile_vp[t0]) + lane;
+    const i32x4 *rstream = reinterpret_cast<const i32x4 *>(d.batch_stream);
     // only the first and the last panel of a natural-order range can be shared with another range
     const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
     const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
     const int gj = lane >> 4, glc = lane & 15;
 
-    auto mload = [&](int s, MetaRegs &M) {
-        const int t = min(s + min(lane, kBatchTiles), t1 - 1);
-        M.row = d.tile_row[t];
-        M.xo = AGG ? d.tile_xoff[t] : d.tile_col[t];
-        M.nz = d.tile_nnz[t];
-        M.ty = d.tile_type[t];
-        M.vplo = vp_lo[2 * (size_t)t];
-    };
-    // batch starting at tile s (metadata in M): returns the first tile past it -- past t1, 16
-    // tiles on, more than kBatchBytes of payload or kMaxPanels panels after s -- and its bytes
-    auto batch_end = [&](int s, const MetaRegs &M, int &rs, int &re) {
-        const int rel = M.vplo - b0lo;
-        const int e = rel + region_dev<VS>(M.ty, M.nz);
-        rs = __builtin_amdgcn_readfirstlane(rel);
-        const int row0 = __builtin_amdgcn_readfirstlane(M.row);
-        const bool c = lane >= 1 && (s + lane >= t1 || lane >= kBatchTiles || e - rs > kBatchBytes ||
-                                     M.row - row0 >= kMaxPanels);
-        const int n = (int)__builtin_ctzll(__ballot(c));
-        re = __builtin_amdgcn_readlane(e, n - 1);
-        return s + n;
-    };
-    // records of a batch of nt tiles (metadata in M); entry positions are relative to the wave's
-    // first payload byte, so entry E of a flat tile sits at ring bytes code x+E and value y+VS*E
-    auto put_meta = [&](i32x4 *rec, const MetaRegs &M, int nt) {
-        const bool in = lane < nt;
-        const int hb = M.ty == 1 ? 16 : 0;
-        const int rel = M.vplo - b0lo;
-        const int coff = rel + hb;
-        const int voff = coff + M.nz + pad_bytes(hb + M.nz, VS);
-        const bool fl = in && M.ty != 2, dn = in && M.ty == 2;
-        const uint64_t flm = __ballot(fl), dnm = __ballot(dn);
-        const int nzf = fl ? M.nz : 0;
-        int sc = nzf;  // inclusive prefix sum of the flat entries over the DPP row of lanes 0..15
-        sc += dpp_or<0x111>(sc, 0);
-        sc += dpp_or<0x112>(sc, 0);
-        sc += dpp_or<0x114>(sc, 0);
-        sc += dpp_or<0x118>(sc, 0);
-        const int es = sc - nzf;
-        const int pb = __builtin_amdgcn_readfirstlane(M.row);
-        int pm = in ? 1 << (M.row - pb) : 0;
-        pm |= dpp_or<0x111>(pm, 0);
-        pm |= dpp_or<0x112>(pm, 0);
-        pm |= dpp_or<0x114>(pm, 0);
-        pm |= dpp_or<0x118>(pm, 0);
-        const int zx = ((M.row & (kMaxPanels - 1)) << 4) | (lane << 20);  // accumulator base | x base << 16
-        if (fl) rec[lanes_below(flm)] = i32x4{coff - es, voff - VS * es, zx, es + M.nz - 1};
-        if (dn) rec[kBatchTiles - 1 - lanes_below(dnm)] = i32x4{rel, 0, zx, 0};
-        const int nfd = (int)__builtin_popcountll(flm) | ((int)__builtin_popcountll(dnm) << 8);
-        const int etot = __builtin_amdgcn_readlane(sc, 15), pmask = __builtin_amdgcn_readlane(pm, 15);
-        if (lane == 0) rec[kBatchTiles] = i32x4{pb, pmask, nfd, etot};
+    // header and records of the batch at record o: lane 0 the header, lane 1 + i record i
+    i32x4 Q;
+    auto qload = [&](int o) { Q = rstream[o + min(lane, kBatchTiles)]; };
+    auto put_recs = [&](i32x4 *rec) {
+        if (lane < kRecs) rec[lane] = Q;
     };
 
-    // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued)
+    // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued); re is the
+    // batch's end, and it starts where the previous batch ended
     u32x4 P[kRC];
     int chi = 0, pfirst = 0, pcnt = 0;
-    auto issue_payload = [&](int rs, int re) {
+    auto issue_payload = [&](int re) {
         const int lastc = (re - 1) >> 10;
-        const int firstc = max(chi, rs >> 10);
-        pfirst = firstc;
-        pcnt = max(0, lastc - firstc + 1);
+        pfirst = chi;
+        pcnt = lastc - chi + 1;
 #pragma unroll
         for (int i = 0; i < kRC; ++i) {
             if (i < pcnt) {
-                const u32x4 *src = pstream + (size_t)(firstc + i) * kWave;
+                const u32x4 *src = pstream + (size_t)(chi + i) * kWave;
                 P[i] = CB_TUNE_NT_LOADS ? __builtin_nontemporal_load(src) : *src;
             }
         }
@@ -415,19 +344,20 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         for (int i = 0; i < kRC; ++i)
             if (i < pcnt) ring4[((pfirst + i) & (kRC - 1)) * kWave + lane] = P[i];
     };
-    // x column of lane (gj, glc) for tile 4g + gj of a batch (metadata M, nt tiles); columns past a
-    // tile's last one read a neighbour's (restore_cols is padded) or column 0, never multiplied
+    // x column of lane (gj, glc) for the tile of record 4g + gj (records in Q, nt tiles); columns
+    // past a tile's last one read a neighbour's (restore_cols is padded) or column 0, never multiplied
     int RG[NG];
-    auto issue_cols = [&](const MetaRegs &M, int nt) {
+    auto issue_cols = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (4 * g < nt) {
-                const int xo = __shfl(M.xo, 4 * g + gj);
+                const int xo = __shfl(Q.w, 1 + 4 * g + gj);
+                const bool in = 4 * g + gj < nt;
                 if (AGG) {
-                    RG[g] = d.restore_cols[xo + glc];
+                    RG[g] = d.restore_cols[in ? xo + glc : 0];
                 } else {
                     const int64_t c = 16 * (int64_t)xo + glc;
-                    RG[g] = c < d.n ? (int)c : 0;
+                    RG[g] = in && c < d.n ? (int)c : 0;
                 }
             }
         }
@@ -482,12 +412,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         done_mask = 0;
     };
 
+    // multiply one batch (header rec[0], records rec[1..])
     auto multiply = [&](const i32x4 *rec) {
-        const i32x4 h = rec[kBatchTiles];
-        const int nfd = __builtin_amdgcn_readfirstlane(h.z), etot = __builtin_amdgcn_readfirstlane(h.w);
-        const int nflat = nfd & 0xFF, ndense = nfd >> 8;
+        const int hz = __builtin_amdgcn_readfirstlane(rec[0].z), etot = __builtin_amdgcn_readfirstlane(rec[0].w);
+        const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
         // COO and CSR entries as one stream; endv: last entry of flat tile `lane`
-        const int endv = rec[min(lane, kBatchTiles - 1)].w;
+        const int endv = rec[1 + min(lane, kBatchTiles - 1)].z & 0xFFFF;
         int j = 0;  // tile holding entry e0
         for (int e0 = 0; e0 < etot; e0 += kWave) {
             const int E = e0 + lane;
@@ -499,10 +429,11 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                 ++j;
             }
             const bool valid = E < etot;
-            const i32x4 r = rec[min(ti, nflat - 1)];
+            const int tf = min(ti, nflat - 1);
+            const i32x4 r = rec[1 + tf];
             const uint32_t code = pring[(r.x + E) & kPMask];
-            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[(r.z >> 16) + (code >> 4)];
-            A *dst = &acc[(r.z & 0xFFFF) + (code & 15)];
+            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[tf * 16 + (code >> 4)];
+            A *dst = &acc[((r.z >> 16) << 4) + (code & 15)];
             if (DPPRED)
                 segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
                                   dst);
@@ -512,17 +443,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
         for (int k = 0; k < ndense; ++k) {
-            const i32x4 r = rec[kBatchTiles - 1 - k];
-            const int rel = __builtin_amdgcn_readfirstlane(r.x), zx = __builtin_amdgcn_readfirstlane(r.z);
+            const i32x4 r = rec[1 + nflat + k];
+            const int rel = __builtin_amdgcn_readfirstlane(r.x), slot = __builtin_amdgcn_readfirstlane(r.z) >> 16;
             const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
             const int vo = rel + (r4 * 16 + 4 * q4) * VS;
-            const A *xs = xarea + (zx >> 16) + 4 * q4;
+            const A *xs = xarea + (nflat + k) * 16 + 4 * q4;
             A sum = A(0);
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
                 if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
             sum = quad_sum(sum);
-            if (q4 == 0) lds_add(&acc[(zx & 0xFFFF) + r4], sum);
+            if (q4 == 0) lds_add(&acc[slot * 16 + r4], sum);
         }
     };
 
@@ -531,73 +462,68 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         acc[lane + kMaxPanels * 16 / 2] = A(0);
     }
     // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
-    // columns; batch 2's metadata.  At the top of step b the registers hold P and XG of batch b,
-    // RG of batch b+1 and M of batch b+2; LDS holds the records of batches b and b+1.
-    MetaRegs M;
-    int bufb = 0;
-    int sb = t0, rs1, re1;
-    mload(sb, M);
-    int eb = batch_end(sb, M, rs1, re1);
-    put_meta(recs, M, eb - sb);
-    issue_cols(M, eb - sb);
-    issue_payload(rs1, re1);
-    if (eb < t1) mload(eb, M);
-    issue_x(eb - sb);  // waits for batch 0's x columns
-    int e1 = eb;
-    if (eb < t1) {
-        e1 = batch_end(eb, M, rs1, re1);
-        put_meta(recs + (kBatchTiles + 1), M, e1 - eb);
-        issue_cols(M, e1 - eb);
-        if (e1 < t1) mload(e1, M);
+    // columns; batch 2's records.  At the top of step b the registers hold P and XG of batch b,
+    // RG of batch b+1 and Q of batch b+2; LDS holds the records of batches b and b+1.
+    int ob = o_begin;
+    qload(ob);
+    int ntb = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
+    put_recs(recs);
+    issue_cols(ntb);
+    issue_payload(__builtin_amdgcn_readlane(Q.x, 0));
+    int o1 = ob + 1 + ntb, nt1 = 0, re1 = 0;
+    if (o1 < o_end) qload(o1);
+    issue_x(ntb);  // waits for batch 0's x columns
+    int o2 = o1;
+    if (o1 < o_end) {
+        nt1 = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
+        re1 = __builtin_amdgcn_readlane(Q.x, 0);
+        put_recs(recs + kRecs);
+        issue_cols(nt1);
+        o2 = o1 + 1 + nt1;
+        if (o2 < o_end) qload(o2);
     }
-    while (sb < t1) {
+    int bufb = 0;
+    while (ob < o_end) {
         const int bufn = bufb == 2 ? 0 : bufb + 1, bufnn = bufn == 2 ? 0 : bufn + 1;
         // the one wait of a step: every load issued by the previous step has landed (loads are
         // issued conditionally, so the compiler's own counting would wait inside step 2)
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        // 1. step b-1's loads: payload and x of batch b into LDS, the panels batch b-1 finished to y,
-        //    batch b+2's records
+        // 1. payload and x of batch b into LDS, the panels batch b-1 finished to y, batch b+2's records
         put_payload();
-        put_x(eb - sb);
+        put_x(ntb);
         flush();
-        const bool have1 = eb < t1, have2 = e1 < t1;
-        int e2 = e1, rs2 = 0, re2 = 0;
+        const bool have1 = o1 < o_end, have2 = o2 < o_end;
+        int nt2 = 0, re2 = 0, o3 = o2;
         if (have2) {
-            e2 = batch_end(e1, M, rs2, re2);
-            put_meta(recs + bufnn * (kBatchTiles + 1), M, e2 - e1);
+            nt2 = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
+            re2 = __builtin_amdgcn_readlane(Q.x, 0);
+            put_recs(recs + bufnn * kRecs);
         }
         __builtin_amdgcn_wave_barrier();
-        // 2. loads: payload and x of batch b+1, x columns of batch b+2, metadata of batch b+3, and
+        // 2. loads: payload and x of batch b+1, x columns of batch b+2, records of batch b+3, and
         //    y of the panels batch b finishes
         if (have1) {
-            issue_payload(rs1, re1);
-            issue_x(e1 - eb);
+            issue_payload(re1);
+            issue_x(nt1);
         }
         if (have2) {
-            issue_cols(M, e2 - e1);
-            if (e2 < t1) mload(e2, M);
+            issue_cols(nt2);
+            o3 = o2 + 1 + nt2;
+            if (o3 < o_end) qload(o3);
         }
-        const i32x4 *rec = recs + bufb * (kBatchTiles + 1);
-        {
-            const i32x4 hb = rec[kBatchTiles];
-            done_pb = __builtin_amdgcn_readfirstlane(hb.x);
-            done_mask = __builtin_amdgcn_readfirstlane(hb.y);
-            if (have1) {
-                // the next batch continues this batch's last panel unless it starts a new one
-                const int pn = __builtin_amdgcn_readfirstlane(recs[bufn * (kBatchTiles + 1) + kBatchTiles].x);
-                const int lastk = 31 - __builtin_clz(done_mask);
-                if (done_pb + lastk == pn) done_mask &= ~(1 << lastk);
-            }
-        }
+        const i32x4 *rec = recs + bufb * kRecs;
+        done_pb = __builtin_amdgcn_readfirstlane(rec[0].y);
+        done_mask = (int)((uint32_t)__builtin_amdgcn_readfirstlane(rec[0].z) >> 24);
         issue_y();
         // 3. batch b
         multiply(rec);
         __builtin_amdgcn_wave_barrier();
-        sb = eb;
-        eb = e1;
-        e1 = e2;
-        rs1 = rs2;
+        ob = o1;
+        ntb = nt1;
+        o1 = o2;
+        nt1 = nt2;
         re1 = re2;
+        o2 = o3;
         bufb = bufn;
     }
     flush();
@@ -616,6 +542,19 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
 // (FP64 values: v_mfma_f64_16x16x4_f64; FP32/BF16 values: v_mfma_f32_16x16x4_f32),
 // unless one of the staged X values is Inf or NaN, where the zero fill of the
 // tile would contribute 0*Inf; those tiles take the entry-by-entry path.
+
+// packed region size of a tile (16-byte aligned), as laid out by the converter
+template <int VS>
+__device__ __forceinline__ int region_dev(int ty, int nz) {
+    int b;
+    if (ty == 0)
+        b = nz + pad_bytes(nz, VS) + nz * VS;
+    else if (ty == 1)
+        b = 16 + nz + pad_bytes(16 + nz, VS) + nz * VS;
+    else
+        b = 256 * VS + 32;
+    return (b + 15) & ~15;
+}
 
 template <class A>
 struct Mfma;
