@@ -29,7 +29,10 @@
 namespace cbs {
 
 constexpr int kChunk = 1024;      // payload bytes one wavefront-wide 16-byte load covers
-constexpr int kRingChunks = 4;    // payload chunks a batch may touch (the kernel's LDS ring)
+#ifndef CB_TUNE_STREAM_RING
+#define CB_TUNE_STREAM_RING 4
+#endif
+constexpr int kRingChunks = CB_TUNE_STREAM_RING;  // payload chunks a batch may touch (the kernel's LDS ring)
 constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
 constexpr int kBatchPanels = 8;   // consecutive panels a batch may touch (accumulator slots)
 constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream

@@ -30,6 +30,9 @@ namespace {
 #ifndef CB_TUNE_F64_DPP
 #define CB_TUNE_F64_DPP 0  // FP64 row sums: 0 = LDS atomics per entry, 1 = DPP segmented scan
 #endif
+#ifndef CB_TUNE_PASS_PAIRS
+#define CB_TUNE_PASS_PAIRS 1  // flat entry passes two at a time (FP32/BF16 values)
+#endif
 #ifndef CB_TUNE_NT_LOADS
 #define CB_TUNE_NT_LOADS 0  // payload chunk loads with the nontemporal hint
 #endif
@@ -418,9 +421,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
         // COO and CSR entries as one stream; endv: last entry of flat tile `lane`
         const int endv = rec[1 + min(lane, kBatchTiles - 1)].z & 0xFFFF;
-        int j = 0;  // tile holding entry e0
-        for (int e0 = 0; e0 < etot; e0 += kWave) {
-            const int E = e0 + lane;
+        // tile of entry E in the pass starting at entry e0; j: the tile holding entry e0, advanced to
+        // the tile holding entry e0 + 64
+        auto tile_of = [&](int e0, int E, int &j) {
             int ti = j;
             while (j < nflat) {
                 const int ej = __builtin_amdgcn_readlane(endv, j);
@@ -428,17 +431,42 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                 ti += E > ej ? 1 : 0;
                 ++j;
             }
-            const bool valid = E < etot;
-            const int tf = min(ti, nflat - 1);
-            const i32x4 r = rec[1 + tf];
-            const uint32_t code = pring[(r.x + E) & kPMask];
-            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[tf * 16 + (code >> 4)];
-            A *dst = &acc[((r.z >> 16) << 4) + (code & 15)];
+            return ti;
+        };
+        auto accumulate = [&](A prod, int ti, uint32_t code, int slot, bool valid) {
+            A *dst = &acc[(slot << 4) + (code & 15)];
             if (DPPRED)
                 segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
                                   dst);
             else if (valid)
                 lds_add(dst, prod);
+        };
+        int j = 0;
+        int e0 = 0;
+        // two passes at a time, their LDS reads interleaved (each pass is a chain of three dependent
+        // reads: record, code, x); the first pass of a pair is full.  Measured faster with the DPP
+        // reduction of FP32/BF16 sums and not with FP64 LDS atomics.
+        for (; CB_TUNE_PASS_PAIRS && DPPRED && e0 + kWave < etot; e0 += 2 * kWave) {
+            const int Ea = e0 + lane, Eb = Ea + kWave;
+            const int ta = tile_of(e0, Ea, j);
+            const int tb = tile_of(e0 + kWave, Eb, j);
+            const int fa = min(ta, nflat - 1), fb = min(tb, nflat - 1);
+            const i32x4 ra = rec[1 + fa], rb = rec[1 + fb];
+            const uint32_t ca = pring[(ra.x + Ea) & kPMask], cb = pring[(rb.x + Eb) & kPMask];
+            const A va = Val<VT>::load(pring + ((ra.y + VS * Ea) & kPMask), 0);
+            const A vb = Val<VT>::load(pring + ((rb.y + VS * Eb) & kPMask), 0);
+            const A xa = xarea[fa * 16 + (ca >> 4)], xb = xarea[fb * 16 + (cb >> 4)];
+            accumulate(va * xa, ta, ca, ra.z >> 16, true);
+            accumulate(vb * xb, tb, cb, rb.z >> 16, Eb < etot);
+        }
+        for (; e0 < etot; e0 += kWave) {
+            const int E = e0 + lane;
+            const int ti = tile_of(e0, E, j);
+            const int tf = min(ti, nflat - 1);
+            const i32x4 r = rec[1 + tf];
+            const uint32_t code = pring[(r.x + E) & kPMask];
+            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[tf * 16 + (code >> 4)];
+            accumulate(prod, ti, code, r.z >> 16, E < etot);
         }
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
