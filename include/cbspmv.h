@@ -153,6 +153,8 @@ typedef struct {
     int32_t *batch_stream;   /* streaming kernel: stream_bytes / 4 ints, a 16-byte header per batch
                                 followed by a 16-byte record per tile (CB_LB_PAPER: none) */
     int32_t *batch_ptr;      /* first record of each work range, nwaves + 1 (CB_LB_PAPER: none) */
+    int32_t *tile_cols;      /* aggregation with the streaming kernel: 16 original columns per tile in
+                                kernel order, 16 * ntiles (else none) */
 } cb_structure_t;
 
 /* Fill *opt with the defaults above (the paper's thresholds). */

@@ -57,7 +57,7 @@ class CbInfo(ctypes.Structure):
 class CbStructure(ctypes.Structure):
     _fields_ = [(n, _p) for n in ("tile_row", "tile_col", "tile_nnz", "tile_vp", "tile_type", "tile_ori", "payload",
                                   "restore_cols", "cols_offset", "quantum_ptr", "wave_ptr", "panel_shared",
-                                  "prepass_list", "tile_xoff", "batch_stream", "batch_ptr")]
+                                  "prepass_list", "tile_xoff", "batch_stream", "batch_ptr", "tile_cols")]
 
 
 _lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
@@ -217,6 +217,7 @@ def cb_export_structure(A: int) -> dict:
         "tile_xoff": np.empty(NT if info["col_agg"] else 0, np.int32),
         "batch_stream": np.empty(info["stream_bytes"] // 4, np.int32),
         "batch_ptr": np.empty(info["nwaves"] + 1 if info["lb_mode"] != CB_LB_PAPER else 0, np.int32),
+        "tile_cols": np.empty(16 * NT if info["lb_mode"] != CB_LB_PAPER and info["col_agg"] else 0, np.int32),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
     _check(_lib.cb_export_structure(A, ctypes.byref(s)))

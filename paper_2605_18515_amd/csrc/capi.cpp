@@ -27,7 +27,7 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 // byte offsets of every array inside the single device allocation
 struct Layout {
     size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
-        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, total;
+        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -60,6 +60,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     const bool stream = s.lb_mode != CB_LB_PAPER;
     L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kRecordPad) : 0);
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
+    L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)cbh::kBlk * NT : 0);
     L.total = off;
     return L;
 }
@@ -144,6 +145,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.prepass_list, s.prepass_list);
         put_array(stage, L.batch_stream, s.batch_stream);
         put_array(stage, L.batch_ptr, s.batch_ptr);
+        put_array(stage, L.tile_cols, s.tile_cols);
         e = hipMalloc(&A->dbuf, L.total);
         if (e != hipSuccess) {
             A->dbuf = nullptr;
@@ -169,6 +171,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.prepass_list = dptr<int32_t>(A, L.prepass_list);
     v.batch_stream = dptr<int32_t>(A, L.batch_stream);
     v.batch_ptr = dptr<int32_t>(A, L.batch_ptr);
+    v.tile_cols = dptr<int32_t>(A, L.tile_cols);
     v.m = s.m;
     v.n = s.n;
     v.nwaves = (int32_t)s.nwaves;
@@ -193,6 +196,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     std::vector<int32_t>().swap(s.prepass_list);
     std::vector<int32_t>().swap(s.batch_stream);
     std::vector<int32_t>().swap(s.batch_ptr);
+    std::vector<int32_t>().swap(s.tile_cols);
     A->on_device = true;
     return CB_SUCCESS;
 }
@@ -234,6 +238,9 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.batch_stream, 4 * (size_t)A->h.nrecords, tmp.batch_stream)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.batch_ptr, A->h.lb_mode != CB_LB_PAPER ? (size_t)A->h.nwaves + 1 : 0, tmp.batch_ptr)) !=
         CB_SUCCESS)
+        return st;
+    if ((st = fetch(A, L.tile_cols, A->h.lb_mode != CB_LB_PAPER && A->h.col_agg ? (size_t)cbh::kBlk * NT : 0,
+                    tmp.tile_cols)) != CB_SUCCESS)
         return st;
     s = &tmp;
     return CB_SUCCESS;
@@ -379,6 +386,7 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *o) {
     cp(o->prepass_list, s->prepass_list);
     cp(o->batch_stream, s->batch_stream);
     cp(o->batch_ptr, s->batch_ptr);
+    cp(o->tile_cols, s->tile_cols);
     return CB_SUCCESS;
 }
 

@@ -39,6 +39,8 @@ struct HostStructure {
     // batch records of the streaming kernel (natural-order modes only): 4 ints per record,
     // batch_ptr[w] = first record of work range w
     std::vector<int32_t> batch_stream, batch_ptr;
+    // column aggregation with the streaming kernel: 16 original columns per tile, kernel order
+    std::vector<int32_t> tile_cols;
     // counts kept when the big arrays move to the device
     int64_t payload_bytes = 0, nrestore = 0, nquanta = 0, nwaves = 0, nprepass = 0, nshared = 0;
     int64_t nbatches = 0, nrecords = 0;

@@ -13,17 +13,22 @@
 //     nt     tiles; nflat of them COO or CSR, ndense Dense
 //     done   bit k: panel pb + k has its last tile of this range in the batch
 //     etot   COO and CSR entries of the batch (the flat entry stream)
-//   flat record (COO and CSR tiles, in order)  {cpos, vpos, end | slot << 16, xo}
+//   flat record (COO and CSR tiles, in order)  {cpos, vpos, end | slot << 16 | ti << 20, xo}
 //     the tile's entries are flat entries es .. end of the batch, and flat
 //     entry E has its one-byte code at payload byte cpos + E and its value at
 //     byte vpos + size(Val) * E (relative to the range's first payload byte)
-//   dense record (Dense tiles, after the flat ones)  {rel, 0, slot << 16, xo}
+//   dense record (Dense tiles, after the flat ones)  {rel, 0, slot << 16 | ti << 20, xo}
 //     rel    the tile's first payload byte (relative)
 //   slot     panel & (kBatchPanels - 1): the panel's accumulator in the kernel
+//   ti       the tile's position in the batch (tiles in kernel order), which is
+//            where its 16 x values land in the kernel's x area
 //   xo       restore_cols index of the tile's first column under column
 //            aggregation (cols_offset[panel] + 16 * chunk), else its column block
 //
-// The x values of the tile in record i land in the kernel's x area at 16 * i.
+// With column aggregation the converter also writes tile_cols: for every tile in
+// kernel order its 16 original columns (restore_cols[xo .. xo + 15], the columns
+// past a panel's last one replaced by that panel's first), so the x column
+// indices of a batch are one contiguous 64-byte-per-tile block.
 #pragma once
 
 namespace cbs {

@@ -209,7 +209,7 @@ void build_stream(HostStructure &s) {
                     const int fmt = s.tile_type[t];
                     if ((fmt == CB_FMT_DENSE) != (pass == 1)) continue;
                     const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
-                    const int32_t slot = (int32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 16;
+                    const int32_t slot = ((int32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 16) | (int32_t)((t - b) << 20);
                     const int32_t xo = s.col_agg ? s.cols_offset[s.tile_row[t]] + 16 * s.tile_col[t] : s.tile_col[t];
                     if (fmt == CB_FMT_DENSE) {
                         push((int32_t)rel, 0, slot, xo);
@@ -232,6 +232,16 @@ void build_stream(HostStructure &s) {
     s.batch_ptr[NW] = (int32_t)(bs.size() / 4);
     s.nbatches = nb;
     s.nrecords = (int64_t)(bs.size() / 4);
+    s.tile_cols.clear();
+    if (s.col_agg) {
+        s.tile_cols.resize((size_t)s.ntiles * kBlk);
+        for (int64_t t = 0; t < s.ntiles; ++t) {
+            const int64_t p = s.tile_row[t], base = s.cols_offset[p] + (int64_t)kBlk * s.tile_col[t];
+            const int64_t width = std::min<int64_t>(kBlk, s.cols_offset[p + 1] - base);
+            for (int c = 0; c < kBlk; ++c)
+                s.tile_cols[(size_t)(t * kBlk + c)] = s.restore_cols[(size_t)(c < width ? base + c : s.cols_offset[p])];
+        }
+    }
 }
 
 }  // namespace
@@ -703,10 +713,11 @@ int64_t spmv_bytes(const HostStructure &s) {
         if (s.col_agg) b += 4 * s.nrestore + 4 * (s.npanels + 1);
         b += 4 * (s.nwaves + 1) + s.npanels + 4 * s.nprepass;
     } else {
-        // streaming kernel: batch records, restore_cols, two range pointers per range and the
-        // first tile's offset and the end panels' flags, pre-pass list
+        // streaming kernel: batch records, 16 original columns per tile under aggregation (else one
+        // column block per tile), two range pointers per range and the first tile's offset and the end
+        // panels' flags, pre-pass list
         b += 16 * s.nrecords;
-        if (s.col_agg) b += 4 * s.nrestore;
+        b += s.col_agg ? 4 * kBlk * s.ntiles : 4 * s.ntiles;
         b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
     }
     return b;

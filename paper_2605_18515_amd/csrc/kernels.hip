@@ -257,9 +257,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 // multiplies it, so every step waits once, at its top, for loads issued one
 // step earlier:
 //   step b-3  issues batch b's header and records (one 16-byte load per lane),
-//   step b-2  stores them in LDS and issues the x column index of every
-//             (tile, column) lane: the restore_cols entry under column
-//             aggregation, else computed,
+//   step b-2  stores them in LDS and issues the loads of the batch's x column
+//             indices (under column aggregation the tiles' original columns,
+//             tile_cols, 64 contiguous bytes per tile; else the column blocks),
 //   step b-1  issues batch b's payload chunks and its x values,
 //   step b    moves both into LDS and multiplies the batch.
 // The multiply treats the COO and CSR tiles of a batch as one stream of
@@ -283,7 +283,7 @@ constexpr int kBatchTiles = cbs::kBatchTiles;
 constexpr int kMaxPanels = cbs::kBatchPanels;
 constexpr int kRecs = kBatchTiles + 1;  // header and records of one batch
 static_assert(kChunk == kWave * 16 && (kPRing & kPMask) == 0, "one chunk per wavefront-wide 16-byte load");
-static_assert(kBatchTiles == 16 && kBatchTiles + 1 <= kWave, "records fill one DPP row; x gathers take four tiles per load");
+static_assert(kBatchTiles + 1 <= kWave && kBatchTiles % 4 == 0, "a batch's records fit one load; x gathers take four tiles each");
 static_assert(kMaxPanels * 16 <= 2 * kWave, "accumulators cleared by two stores per lane");
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
 
@@ -294,7 +294,6 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                                                                      typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
     constexpr int VS = Val<VT>::kSize;
-    constexpr int NG = kBatchTiles / 4;  // x gathers per batch, four tiles each
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
     __shared__ __align__(16) i32x4 rec_all[kWavesPerBlock][3][kRecs];  // three batches in flight
@@ -347,34 +346,40 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         for (int i = 0; i < kRC; ++i)
             if (i < pcnt) ring4[((pfirst + i) & (kRC - 1)) * kWave + lane] = P[i];
     };
-    // x column of lane (gj, glc) for the tile of record 4g + gj (records in Q, nt tiles); columns
-    // past a tile's last one read a neighbour's (restore_cols is padded) or column 0, never multiplied
+    // x of a batch whose first tile is tb (nt tiles): in gather g, lane (gj, glc) takes column glc of
+    // tile tb + 4g + gj (clamped to the range), so x lands at x area entry 16 * (tile in batch) + glc.
+    // The column indices are loaded one step before the x values: under aggregation the tiles'
+    // original columns (tile_cols, 256 contiguous bytes per gather), else the tiles' column blocks.
+    // Columns past a tile's last one read a valid column of the matrix and are never multiplied.
+    constexpr int NG = kBatchTiles / 4;
     int RG[NG];
-    auto issue_cols = [&](int nt) {
+    auto issue_cols = [&](int tb, int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (4 * g < nt) {
-                const int xo = __shfl(Q.w, 1 + 4 * g + gj);
-                const bool in = 4 * g + gj < nt;
-                if (AGG) {
-                    RG[g] = d.restore_cols[in ? xo + glc : 0];
-                } else {
-                    const int64_t c = 16 * (int64_t)xo + glc;
-                    RG[g] = in && c < d.n ? (int)c : 0;
-                }
+                const int t = min(tb + 4 * g + gj, t1 - 1);
+                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + glc] : d.tile_col[t];
             }
         }
     };
     A XG[NG];
     auto issue_x = [&](int nt) {
 #pragma unroll
-        for (int g = 0; g < NG; ++g)
-            if (4 * g < nt) XG[g] = x[RG[g]];
+        for (int g = 0; g < NG; ++g) {
+            if (4 * g < nt) {
+                int col = RG[g];
+                if (!AGG) {
+                    const int64_t c = 16 * (int64_t)RG[g] + glc;
+                    col = c < d.n ? (int)c : 0;
+                }
+                XG[g] = x[col];
+            }
+        }
     };
     auto put_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (4 * g < nt) xarea[(4 * g + gj) * 16 + glc] = XG[g];
+            if (4 * g < nt) xarea[64 * g + lane] = XG[g];
     };
 
     // panels finished by a batch: lane (k, r) holds row r of panel pb + k (YP[0]) and pb + 4 + k (YP[1])
@@ -455,9 +460,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             const uint32_t ca = pring[(ra.x + Ea) & kPMask], cb = pring[(rb.x + Eb) & kPMask];
             const A va = Val<VT>::load(pring + ((ra.y + VS * Ea) & kPMask), 0);
             const A vb = Val<VT>::load(pring + ((rb.y + VS * Eb) & kPMask), 0);
-            const A xa = xarea[fa * 16 + (ca >> 4)], xb = xarea[fb * 16 + (cb >> 4)];
-            accumulate(va * xa, ta, ca, ra.z >> 16, true);
-            accumulate(vb * xb, tb, cb, rb.z >> 16, Eb < etot);
+            const A xa = xarea[((ra.z >> 20) << 4) + (ca >> 4)], xb = xarea[((rb.z >> 20) << 4) + (cb >> 4)];
+            accumulate(va * xa, ta, ca, (ra.z >> 16) & 15, true);
+            accumulate(vb * xb, tb, cb, (rb.z >> 16) & 15, Eb < etot);
         }
         for (; e0 < etot; e0 += kWave) {
             const int E = e0 + lane;
@@ -465,17 +470,18 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             const int tf = min(ti, nflat - 1);
             const i32x4 r = rec[1 + tf];
             const uint32_t code = pring[(r.x + E) & kPMask];
-            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[tf * 16 + (code >> 4)];
-            accumulate(prod, ti, code, r.z >> 16, E < etot);
+            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[((r.z >> 20) << 4) + (code >> 4)];
+            accumulate(prod, ti, code, (r.z >> 16) & 15, E < etot);
         }
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
         for (int k = 0; k < ndense; ++k) {
             const i32x4 r = rec[1 + nflat + k];
-            const int rel = __builtin_amdgcn_readfirstlane(r.x), slot = __builtin_amdgcn_readfirstlane(r.z) >> 16;
+            const int rel = __builtin_amdgcn_readfirstlane(r.x), z = __builtin_amdgcn_readfirstlane(r.z);
+            const int slot = (z >> 16) & 15;
             const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
             const int vo = rel + (r4 * 16 + 4 * q4) * VS;
-            const A *xs = xarea + (nflat + k) * 16 + 4 * q4;
+            const A *xs = xarea + ((z >> 20) << 4) + 4 * q4;
             A sum = A(0);
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
@@ -496,18 +502,20 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     qload(ob);
     int ntb = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
     put_recs(recs);
-    issue_cols(ntb);
+    issue_cols(t0, ntb);
     issue_payload(__builtin_amdgcn_readlane(Q.x, 0));
     int o1 = ob + 1 + ntb, nt1 = 0, re1 = 0;
+    const int tb1 = t0 + ntb;
     if (o1 < o_end) qload(o1);
     issue_x(ntb);  // waits for batch 0's x columns
-    int o2 = o1;
+    int o2 = o1, tb2 = tb1;
     if (o1 < o_end) {
         nt1 = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
         re1 = __builtin_amdgcn_readlane(Q.x, 0);
         put_recs(recs + kRecs);
-        issue_cols(nt1);
+        issue_cols(tb1, nt1);
         o2 = o1 + 1 + nt1;
+        tb2 = tb1 + nt1;
         if (o2 < o_end) qload(o2);
     }
     int bufb = 0;
@@ -535,7 +543,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             issue_x(nt1);
         }
         if (have2) {
-            issue_cols(nt2);
+            issue_cols(tb2, nt2);
             o3 = o2 + 1 + nt2;
             if (o3 < o_end) qload(o3);
         }
@@ -552,6 +560,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         nt1 = nt2;
         re1 = re2;
         o2 = o3;
+        tb2 += nt2;
         bufb = bufn;
     }
     flush();

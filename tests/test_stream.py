@@ -57,6 +57,7 @@ def check_stream(A, X, vtype="f64", **opts):
     M.close()
     vs = VSIZE[vtype]
     assert info["stream_bytes"] == 16 * (info["ntiles"] + info["nbatches"])
+    assert s["tile_cols"].size == (16 * info["ntiles"] if info["col_agg"] else 0)
     assert s["batch_stream"].size == info["stream_bytes"] // 4
     bp = s["batch_ptr"]
     assert bp[0] == 0 and bp[-1] == info["ntiles"] + info["nbatches"] and np.all(np.diff(bp) >= 0)
@@ -94,8 +95,8 @@ def check_stream(A, X, vtype="f64", **opts):
             es = 0
             for r, i in zip(recs, flat + dense):
                 rel = int(vp[i]) - B0
-                slot = int(r[2]) >> 16
-                assert slot == row[i] % PANELS
+                slot, ti = (int(r[2]) >> 16) & 15, int(r[2]) >> 20
+                assert slot == row[i] % PANELS and ti == i - tiles[0]
                 xo = int(r[3])
                 assert xo == (s["cols_offset"][row[i]] + 16 * col[i] if agg else col[i])
                 if ty[i] == cm.DENSE:
@@ -110,10 +111,18 @@ def check_stream(A, X, vtype="f64", **opts):
             # the entries the records point at, multiplied out
             es = 0
             for r, i in zip(recs, flat + dense):
-                panel = pb + ((int(r[2]) >> 16) - pb) % PANELS
+                panel = pb + (((int(r[2]) >> 16) & 15) - pb) % PANELS
                 assert panel == row[i]
                 xo = int(r[3])
-                orig = (lambda c: s["restore_cols"][xo + c]) if agg else (lambda c: 16 * xo + c)
+                if agg:
+                    # the tile's 16 columns the kernel gathers x through
+                    tc = s["tile_cols"][16 * i:16 * i + 16]
+                    width = min(16, s["cols_offset"][row[i] + 1] - xo)
+                    assert np.array_equal(tc[:width], s["restore_cols"][xo:xo + width])
+                    assert np.all(tc[width:] == s["restore_cols"][s["cols_offset"][row[i]]])
+                    orig = lambda c: tc[c]
+                else:
+                    orig = lambda c: 16 * xo + c
                 if ty[i] == cm.DENSE:
                     base = B0 + int(r[0])
                     for e in range(256):
@@ -190,7 +199,7 @@ def test_paper_mode_has_no_records():
     info, s = M.info, M.structure()
     M.close()
     assert info["nbatches"] == 0 and info["stream_bytes"] == 0
-    assert s["batch_stream"].size == 0 and s["batch_ptr"].size == 0
+    assert s["batch_stream"].size == 0 and s["batch_ptr"].size == 0 and s["tile_cols"].size == 0
 
 
 def test_limits_cut_batches():
