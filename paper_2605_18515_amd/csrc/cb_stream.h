@@ -13,12 +13,15 @@
 //     nt     tiles; nflat of them COO or CSR, ndense Dense
 //     done   bit k: panel pb + k has its last tile of this range in the batch
 //     etot   COO and CSR entries of the batch (the flat entry stream)
-//   flat record (COO and CSR tiles, in order)  {cpos, vpos, end | slot << 16 | ti << 20, xo}
+//   flat record (COO and CSR tiles, in order)  {pk, end, 0, xo}
 //     the tile's entries are flat entries es .. end of the batch, and flat
 //     entry E has its one-byte code at payload byte cpos + E and its value at
-//     byte vpos + size(Val) * E (relative to the range's first payload byte)
-//   dense record (Dense tiles, after the flat ones)  {rel, 0, slot << 16 | ti << 20, xo}
+//     byte vpos + size(Val) * E (relative to the range's first payload byte);
+//   dense record (Dense tiles, after the flat ones)  {pk, 0, rel, xo}
 //     rel    the tile's first payload byte (relative)
+//   pk       (cpos mod 4096) | (vpos mod 4096) << 12 | slot << 24 | ti << 27
+//            (0 positions for Dense tiles): the kernel addresses its 4 KB
+//            payload ring modulo 4096, so one 32-bit word per entry pass
 //   slot     panel & (kBatchPanels - 1): the panel's accumulator in the kernel
 //   ti       the tile's position in the batch (tiles in kernel order), which is
 //            where its 16 x values land in the kernel's x area
@@ -34,10 +37,9 @@
 namespace cbs {
 
 constexpr int kChunk = 1024;      // payload bytes one wavefront-wide 16-byte load covers
-#ifndef CB_TUNE_STREAM_RING
-#define CB_TUNE_STREAM_RING 4
-#endif
-constexpr int kRingChunks = CB_TUNE_STREAM_RING;  // payload chunks a batch may touch (the kernel's LDS ring)
+constexpr int kRingChunks = 4;    // payload chunks a batch may touch (the kernel's LDS ring)
+constexpr int kRingBits = 12;     // the ring's 4096 bytes, the width of the packed positions
+static_assert(kChunk * kRingChunks == 1 << kRingBits, "packed positions address the ring");
 constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
 constexpr int kBatchPanels = 8;   // consecutive panels a batch may touch (accumulator slots)
 constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream

@@ -209,14 +209,16 @@ void build_stream(HostStructure &s) {
                     const int fmt = s.tile_type[t];
                     if ((fmt == CB_FMT_DENSE) != (pass == 1)) continue;
                     const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
-                    const int32_t slot = ((int32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 16) | (int32_t)((t - b) << 20);
+                    const uint32_t tag = ((uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 24) | ((uint32_t)(t - b) << 27);
                     const int32_t xo = s.col_agg ? s.cols_offset[s.tile_row[t]] + 16 * s.tile_col[t] : s.tile_col[t];
                     if (fmt == CB_FMT_DENSE) {
-                        push((int32_t)rel, 0, slot, xo);
+                        push((int32_t)tag, 0, (int32_t)rel, xo);
                     } else {
                         const int64_t hb = fmt == CB_FMT_CSR ? kBlk : 0;
                         const int64_t voff = rel + hb + nz + padding(hb + nz, vs);
-                        push((int32_t)(rel + hb - es), (int32_t)(voff - vs * es), (int32_t)(es + nz - 1) | slot, xo);
+                        const uint32_t pmask = (1u << kRingBits) - 1;
+                        const uint32_t cpos = (uint32_t)(rel + hb - es) & pmask, vpos = (uint32_t)(voff - vs * es) & pmask;
+                        push((int32_t)(tag | cpos | (vpos << kRingBits)), (int32_t)(es + nz - 1), 0, xo);
                         es += nz;
                     }
                 }

@@ -420,26 +420,39 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         done_mask = 0;
     };
 
-    // multiply one batch (header rec[0], records rec[1..])
-    auto multiply = [&](const i32x4 *rec) {
-        const int hz = __builtin_amdgcn_readfirstlane(rec[0].z), etot = __builtin_amdgcn_readfirstlane(rec[0].w);
+    // multiply one batch: records rec[1..], header fields hz = nt | nflat << 8 | ndense << 16 | done << 24
+    // and etot (flat entries); positions in the packed record words are taken modulo the ring size
+    auto multiply = [&](const i32x4 *rec, int hz, int etot) {
         const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
-        // COO and CSR entries as one stream; endv: last entry of flat tile `lane`
-        const int endv = rec[1 + min(lane, kBatchTiles - 1)].z & 0xFFFF;
-        // tile of entry E in the pass starting at entry e0; j: the tile holding entry e0, advanced to
-        // the tile holding entry e0 + 64
-        auto tile_of = [&](int e0, int E, int &j) {
+        // COO and CSR entries as one stream; lane i holds flat tile i's last entry (endv) and record
+        // word (pkv), read once per batch
+        const int endv = rec[1 + min(lane, kBatchTiles - 1)].y;
+        const uint32_t pkv = (uint32_t)rec[1 + min(lane, kBatchTiles - 1)].x;
+        // tile of entry E in the pass starting at entry e0, and its record word; j: the tile holding
+        // entry e0, advanced to the tile holding entry e0 + 64
+        auto tile_of = [&](int e0, int E, int &j, uint32_t &pk) {
             int ti = j;
+            pk = __builtin_amdgcn_readlane(pkv, min(j, kBatchTiles - 1));
             while (j < nflat) {
                 const int ej = __builtin_amdgcn_readlane(endv, j);
                 if (ej >= e0 + kWave) break;
-                ti += E > ej ? 1 : 0;
+                // selects, not a branch, keep the loop uniform
+                const uint32_t pn = __builtin_amdgcn_readlane(pkv, min(j + 1, kBatchTiles - 1));
+                const bool past = E > ej;
+                ti += past ? 1 : 0;
+                pk = past ? pn : pk;
                 ++j;
             }
             return ti;
         };
-        auto accumulate = [&](A prod, int ti, uint32_t code, int slot, bool valid) {
-            A *dst = &acc[(slot << 4) + (code & 15)];
+        // one entry: code, value and x through the tile's packed record word
+        auto entry = [&](uint32_t pk, int E, uint32_t &code) {
+            code = pring[(pk + E) & kPMask];
+            return Val<VT>::load(pring + (((pk >> cbs::kRingBits) + VS * E) & kPMask), 0) *
+                   xarea[((pk >> 27) << 4) + (code >> 4)];
+        };
+        auto accumulate = [&](A prod, int ti, uint32_t code, uint32_t pk, bool valid) {
+            A *dst = &acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + (code & 15)];
             if (DPPRED)
                 segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
                                   dst);
@@ -448,46 +461,42 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         };
         int j = 0;
         int e0 = 0;
-        // two passes at a time, their LDS reads interleaved (each pass is a chain of three dependent
-        // reads: record, code, x); the first pass of a pair is full.  Measured faster with the DPP
+        // two passes at a time, their LDS reads interleaved (each pass is a chain of two dependent
+        // reads: code, then x); the first pass of a pair is full.  Measured faster with the DPP
         // reduction of FP32/BF16 sums and not with FP64 LDS atomics.
         for (; CB_TUNE_PASS_PAIRS && DPPRED && e0 + kWave < etot; e0 += 2 * kWave) {
             const int Ea = e0 + lane, Eb = Ea + kWave;
-            const int ta = tile_of(e0, Ea, j);
-            const int tb = tile_of(e0 + kWave, Eb, j);
-            const int fa = min(ta, nflat - 1), fb = min(tb, nflat - 1);
-            const i32x4 ra = rec[1 + fa], rb = rec[1 + fb];
-            const uint32_t ca = pring[(ra.x + Ea) & kPMask], cb = pring[(rb.x + Eb) & kPMask];
-            const A va = Val<VT>::load(pring + ((ra.y + VS * Ea) & kPMask), 0);
-            const A vb = Val<VT>::load(pring + ((rb.y + VS * Eb) & kPMask), 0);
-            const A xa = xarea[((ra.z >> 20) << 4) + (ca >> 4)], xb = xarea[((rb.z >> 20) << 4) + (cb >> 4)];
-            accumulate(va * xa, ta, ca, (ra.z >> 16) & 15, true);
-            accumulate(vb * xb, tb, cb, (rb.z >> 16) & 15, Eb < etot);
+            uint32_t pa, pb;
+            const int ta = tile_of(e0, Ea, j, pa);
+            const int tb = tile_of(e0 + kWave, Eb, j, pb);
+            uint32_t ca, cb;
+            const A prod_a = entry(pa, Ea, ca), prod_b = entry(pb, Eb, cb);
+            accumulate(prod_a, ta, ca, pa, true);
+            accumulate(prod_b, tb, cb, pb, Eb < etot);
         }
         for (; e0 < etot; e0 += kWave) {
             const int E = e0 + lane;
-            const int ti = tile_of(e0, E, j);
-            const int tf = min(ti, nflat - 1);
-            const i32x4 r = rec[1 + tf];
-            const uint32_t code = pring[(r.x + E) & kPMask];
-            const A prod = Val<VT>::load(pring + ((r.y + VS * E) & kPMask), 0) * xarea[((r.z >> 20) << 4) + (code >> 4)];
-            accumulate(prod, ti, code, (r.z >> 16) & 15, E < etot);
+            uint32_t pk;
+            const int ti = tile_of(e0, E, j, pk);
+            uint32_t code;
+            const A prod = entry(pk, E, code);
+            accumulate(prod, ti, code, pk, E < etot);
         }
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
         for (int k = 0; k < ndense; ++k) {
             const i32x4 r = rec[1 + nflat + k];
-            const int rel = __builtin_amdgcn_readfirstlane(r.x), z = __builtin_amdgcn_readfirstlane(r.z);
-            const int slot = (z >> 16) & 15;
+            const uint32_t pk = (uint32_t)__builtin_amdgcn_readfirstlane(r.x);
+            const int rel = __builtin_amdgcn_readfirstlane(r.z);
             const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
             const int vo = rel + (r4 * 16 + 4 * q4) * VS;
-            const A *xs = xarea + ((z >> 20) << 4) + 4 * q4;
+            const A *xs = xarea + ((pk >> 27) << 4) + 4 * q4;
             A sum = A(0);
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
                 if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
             sum = quad_sum(sum);
-            if (q4 == 0) lds_add(&acc[slot * 16 + r4], sum);
+            if (q4 == 0) lds_add(&acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + r4], sum);
         }
     };
 
@@ -498,20 +507,29 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
     // columns; batch 2's records.  At the top of step b the registers hold P and XG of batch b,
     // RG of batch b+1 and Q of batch b+2; LDS holds the records of batches b and b+1.
+    // header fields of a batch: hz (nt | nflat << 8 | ndense << 16 | done << 24), etot, first panel
+    struct Hdr {
+        int re, hz, etot, pb;
+    };
+    auto header = [&]() {
+        return Hdr{__builtin_amdgcn_readlane(Q.x, 0), __builtin_amdgcn_readlane(Q.z, 0),
+                   __builtin_amdgcn_readlane(Q.w, 0), __builtin_amdgcn_readlane(Q.y, 0)};
+    };
     int ob = o_begin;
     qload(ob);
-    int ntb = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
+    Hdr h0 = header(), h1{}, h2{};
+    int ntb = h0.hz & 0xFF;
     put_recs(recs);
     issue_cols(t0, ntb);
-    issue_payload(__builtin_amdgcn_readlane(Q.x, 0));
-    int o1 = ob + 1 + ntb, nt1 = 0, re1 = 0;
+    issue_payload(h0.re);
+    int o1 = ob + 1 + ntb, nt1 = 0;
     const int tb1 = t0 + ntb;
     if (o1 < o_end) qload(o1);
     issue_x(ntb);  // waits for batch 0's x columns
     int o2 = o1, tb2 = tb1;
     if (o1 < o_end) {
-        nt1 = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
-        re1 = __builtin_amdgcn_readlane(Q.x, 0);
+        h1 = header();
+        nt1 = h1.hz & 0xFF;
         put_recs(recs + kRecs);
         issue_cols(tb1, nt1);
         o2 = o1 + 1 + nt1;
@@ -529,17 +547,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         put_x(ntb);
         flush();
         const bool have1 = o1 < o_end, have2 = o2 < o_end;
-        int nt2 = 0, re2 = 0, o3 = o2;
+        int nt2 = 0, o3 = o2;
         if (have2) {
-            nt2 = __builtin_amdgcn_readlane(Q.z, 0) & 0xFF;
-            re2 = __builtin_amdgcn_readlane(Q.x, 0);
+            h2 = header();
+            nt2 = h2.hz & 0xFF;
             put_recs(recs + bufnn * kRecs);
         }
         __builtin_amdgcn_wave_barrier();
         // 2. loads: payload and x of batch b+1, x columns of batch b+2, records of batch b+3, and
         //    y of the panels batch b finishes
         if (have1) {
-            issue_payload(re1);
+            issue_payload(h1.re);
             issue_x(nt1);
         }
         if (have2) {
@@ -547,18 +565,18 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             o3 = o2 + 1 + nt2;
             if (o3 < o_end) qload(o3);
         }
-        const i32x4 *rec = recs + bufb * kRecs;
-        done_pb = __builtin_amdgcn_readfirstlane(rec[0].y);
-        done_mask = (int)((uint32_t)__builtin_amdgcn_readfirstlane(rec[0].z) >> 24);
+        done_pb = h0.pb;
+        done_mask = (int)((uint32_t)h0.hz >> 24);
         issue_y();
         // 3. batch b
-        multiply(rec);
+        multiply(recs + bufb * kRecs, h0.hz, h0.etot);
         __builtin_amdgcn_wave_barrier();
         ob = o1;
         ntb = nt1;
+        h0 = h1;
         o1 = o2;
         nt1 = nt2;
-        re1 = re2;
+        h1 = h2;
         o2 = o3;
         tb2 += nt2;
         bufb = bufn;

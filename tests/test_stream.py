@@ -18,6 +18,7 @@ from paper_2605_18515_amd import matgen
 cb = pytest.importorskip("paper_2605_18515_amd.cbspmv", reason="libcbspmv.so not built")
 
 CHUNK, RING, TILES, PANELS = 1024, 4, 16, 8
+RINGB = CHUNK * RING
 VSIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 
@@ -95,23 +96,32 @@ def check_stream(A, X, vtype="f64", **opts):
             es = 0
             for r, i in zip(recs, flat + dense):
                 rel = int(vp[i]) - B0
-                slot, ti = (int(r[2]) >> 16) & 15, int(r[2]) >> 20
+                pk = int(r[0]) & 0xFFFFFFFF
+                slot, ti = (pk >> 24) & 7, pk >> 27
                 assert slot == row[i] % PANELS and ti == i - tiles[0]
                 xo = int(r[3])
                 assert xo == (s["cols_offset"][row[i]] + 16 * col[i] if agg else col[i])
                 if ty[i] == cm.DENSE:
-                    assert int(r[0]) == rel and int(r[1]) == 0 and int(r[2]) & 0xFFFF == 0
+                    assert pk & 0xFFFFFF == 0 and int(r[1]) == 0 and int(r[2]) == rel
                     continue
                 hb = 16 if ty[i] == cm.CSR else 0
                 nz = int(nnz[i])
-                assert int(r[0]) + es == rel + hb
-                assert int(r[1]) + vs * es == rel + hb + nz + cm.padding(hb + nz, vs)
-                assert int(r[2]) & 0xFFFF == es + nz - 1
+                assert int(r[2]) == 0
+                # positions are kept modulo the 4 KB ring the kernel addresses
+                assert (pk & 0xFFF) == (rel + hb - es) % RINGB
+                assert ((pk >> 12) & 0xFFF) == (rel + hb + nz + cm.padding(hb + nz, vs) - vs * es) % RINGB
+                assert int(r[1]) == es + nz - 1
                 es += nz
-            # the entries the records point at, multiplied out
+            # the entries the records point at, multiplied out (through the ring positions, as the
+            # kernel addresses them: the batch's bytes lie within four consecutive 1 KB chunks)
             es = 0
+            ws = rs // CHUNK * CHUNK  # first byte of the batch's chunk window, relative to B0
+
+            def at(pos):  # payload byte held at ring position pos while this batch is multiplied
+                return B0 + ws + (pos % RINGB - ws) % RINGB
             for r, i in zip(recs, flat + dense):
-                panel = pb + (((int(r[2]) >> 16) & 15) - pb) % PANELS
+                pk = int(r[0]) & 0xFFFFFFFF
+                panel = pb + (((pk >> 24) & 7) - pb) % PANELS
                 assert panel == row[i]
                 xo = int(r[3])
                 if agg:
@@ -124,15 +134,15 @@ def check_stream(A, X, vtype="f64", **opts):
                 else:
                     orig = lambda c: 16 * xo + c
                 if ty[i] == cm.DENSE:
-                    base = B0 + int(r[0])
+                    base = B0 + int(r[2])
                     for e in range(256):
                         if (pay[base + 256 * vs + (e >> 3)] >> (e & 7)) & 1:
                             y[16 * panel + (e >> 4)] += value_at(pay, base + e * vs, vtype) * X[orig(e & 15)]
                     continue
-                end = int(r[2]) & 0xFFFF
+                end = int(r[1])
                 for E in range(es, end + 1):
-                    code = int(pay[B0 + int(r[0]) + E])
-                    v = value_at(pay, B0 + int(r[1]) + vs * E, vtype)
+                    code = int(pay[at((pk & 0xFFF) + E)])
+                    v = value_at(pay, at(((pk >> 12) & 0xFFF) + vs * E), vtype)
                     y[16 * panel + (code & 15)] += v * X[orig(code >> 4)]
                 es = end + 1
             # done panels: every panel of the range once, in the batch holding its last tile
