@@ -55,8 +55,15 @@ def log(msg: str) -> None:
 
 
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2605_18515_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the kernel source with comments and blank lines removed, so the committed
+    counters stay valid across comment edits and go stale on any code change."""
+    code = []
+    with open(os.path.join(ROOT, "paper_2605_18515_amd", "csrc", "kernels.hip")) as f:
+        for line in f:
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                code.append(line)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
 def measured_traffic():

@@ -1,20 +1,24 @@
 // HIP kernels of libcbspmv for gfx950 (CDNA4, wave64).
 //
 // Work decomposition: one wavefront owns a contiguous range of tiles in kernel
-// order (wave_ptr) and walks it tile by tile; four independent wavefronts
-// share a 256-thread workgroup.  For every tile the wavefront
-//   1. stages the 16 x values of the tile's columns in LDS (the tile's
-//      column block, or the aggregated columns through restore_cols --
-//      Section 3.5 preloads x in shared memory; with column aggregation the
-//      16 original columns are gathered once per tile instead of per entry),
-//   2. multiplies the tile's entries (Algorithm 3 for COO: one lane per
-//      entry; CSR: four lanes per row with a DPP quad reduction, the wave64
-//      form of the shuffle reduction of Section 3.5; Dense, Algorithm 4: four
-//      lanes per row, four columns each, occupancy bits honoured),
-//   3. adds the per-row sums into a 16-entry LDS accumulator for the panel.
-// When the panel changes the accumulator is written to y: a plain store of
-// alpha*sum + beta*y for panels owned by this wavefront, a global atomic add
-// for panels shared with other wavefronts (pre-scaled by a pre-pass).
+// order (wave_ptr); four independent wavefronts share a 256-thread workgroup,
+// and workgroups are remapped so that each XCD takes a contiguous eighth of the
+// ranges (neighbouring panels share x in one L2).
+//   spmv_stream_kernel  natural order (contiguous or no load balance): streams
+//                       the range's payload and the converter's batch records
+//                       through a four-stage pipeline, multiplying the COO and
+//                       CSR entries of a batch as one stream (below).
+//   spmv_kernel         Algorithm 2 order: one tile at a time -- the tile's 16
+//                       x values staged in LDS (Section 3.5; through
+//                       restore_cols under column aggregation, once per tile
+//                       instead of per entry), COO one lane per entry
+//                       (Algorithm 3), CSR and Dense four lanes per row with a
+//                       DPP quad reduction (Algorithm 4's shuffle reduction).
+//   spmm_kernel         k right-hand sides, KC columns per launch slice, Dense
+//                       tiles on the matrix cores.
+// Row sums accumulate per panel in LDS and are written to y once per panel: a
+// plain store of alpha*sum + beta*y for panels owned by the wavefront, a global
+// atomic add for panels shared with other wavefronts (pre-scaled by a pre-pass).
 #include <hip/hip_runtime.h>
 
 #include "cb_device.h"
