@@ -27,7 +27,7 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 // byte offsets of every array inside the single device allocation
 struct Layout {
     size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
-        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, total;
+        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, tile_rec, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -61,6 +61,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kRecordPad) : 0);
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)cbh::kBlk * NT : 0);
+    L.tile_rec = put(stream ? 16 * NT : 0);
     L.total = off;
     return L;
 }
@@ -146,6 +147,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.batch_stream, s.batch_stream);
         put_array(stage, L.batch_ptr, s.batch_ptr);
         put_array(stage, L.tile_cols, s.tile_cols);
+        put_array(stage, L.tile_rec, s.tile_rec);
         e = hipMalloc(&A->dbuf, L.total);
         if (e != hipSuccess) {
             A->dbuf = nullptr;
@@ -172,6 +174,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.batch_stream = dptr<int32_t>(A, L.batch_stream);
     v.batch_ptr = dptr<int32_t>(A, L.batch_ptr);
     v.tile_cols = dptr<int32_t>(A, L.tile_cols);
+    v.tile_rec = dptr<int32_t>(A, L.tile_rec);
     v.m = s.m;
     v.n = s.n;
     v.nwaves = (int32_t)s.nwaves;
@@ -197,6 +200,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     std::vector<int32_t>().swap(s.batch_stream);
     std::vector<int32_t>().swap(s.batch_ptr);
     std::vector<int32_t>().swap(s.tile_cols);
+    std::vector<int32_t>().swap(s.tile_rec);
     A->on_device = true;
     return CB_SUCCESS;
 }

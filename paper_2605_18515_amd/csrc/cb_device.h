@@ -25,6 +25,7 @@ struct DevView {
     const int32_t *batch_stream;  // natural order only: batch headers and tile records (cb_stream.h), 4 ints each
     const int32_t *batch_ptr;     // natural order only: first record of each work range, nwaves + 1
     const int32_t *tile_cols;     // natural order with col_agg: 16 original columns per tile
+    const int32_t *tile_rec;      // natural order: {vp low, vp high | type << 16 | (nnz - 1) << 18, panel, column block}
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range

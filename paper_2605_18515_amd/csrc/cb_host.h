@@ -41,6 +41,9 @@ struct HostStructure {
     std::vector<int32_t> batch_stream, batch_ptr;
     // column aggregation with the streaming kernel: 16 original columns per tile, kernel order
     std::vector<int32_t> tile_cols;
+    // natural-order modes: one 16-byte record per tile for the k-right-hand-side kernel
+    // {vp low word, vp high 16 bits | type << 16 | (nnz - 1) << 18, panel, column block}
+    std::vector<int32_t> tile_rec;
     // counts kept when the big arrays move to the device
     int64_t payload_bytes = 0, nrestore = 0, nquanta = 0, nwaves = 0, nprepass = 0, nshared = 0;
     int64_t nbatches = 0, nrecords = 0;

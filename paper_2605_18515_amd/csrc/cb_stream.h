@@ -30,8 +30,10 @@
 //
 // With column aggregation the converter also writes tile_cols: for every tile in
 // kernel order its 16 original columns (restore_cols[xo .. xo + 15], the columns
-// past a panel's last one replaced by that panel's first), so the x column
-// indices of a batch are one contiguous 64-byte-per-tile block.
+// past a panel's last one replaced by that panel's first), local column c at
+// position (c mod 4) * 4 + c / 4 of the tile's 16, so the x column indices of a
+// batch are one contiguous 64-byte-per-tile block and the four columns q, q + 4,
+// q + 8, q + 12 of one matrix-core operand lane are adjacent.
 #pragma once
 
 namespace cbs {

@@ -234,14 +234,26 @@ void build_stream(HostStructure &s) {
     s.batch_ptr[NW] = (int32_t)(bs.size() / 4);
     s.nbatches = nb;
     s.nrecords = (int64_t)(bs.size() / 4);
+    s.tile_rec.resize((size_t)s.ntiles * 4);
+    for (int64_t t = 0; t < s.ntiles; ++t) {
+        const uint64_t vp = (uint64_t)s.tile_vp[t];
+        s.tile_rec[(size_t)(4 * t)] = (int32_t)(uint32_t)vp;
+        s.tile_rec[(size_t)(4 * t + 1)] =
+            (int32_t)((uint32_t)((vp >> 32) & 0xFFFFu) | ((uint32_t)s.tile_type[t] << 16) | ((uint32_t)(s.tile_nnz[t] - 1) << 18));
+        s.tile_rec[(size_t)(4 * t + 2)] = s.tile_row[t];
+        s.tile_rec[(size_t)(4 * t + 3)] = s.tile_col[t];
+    }
     s.tile_cols.clear();
     if (s.col_agg) {
         s.tile_cols.resize((size_t)s.ntiles * kBlk);
         for (int64_t t = 0; t < s.ntiles; ++t) {
             const int64_t p = s.tile_row[t], base = s.cols_offset[p] + (int64_t)kBlk * s.tile_col[t];
             const int64_t width = std::min<int64_t>(kBlk, s.cols_offset[p + 1] - base);
+            // column c at position (c mod 4) * 4 + c / 4: a lane of a matrix-core operand that needs
+            // columns q, q + 4, q + 8, q + 12 reads them as one 16-byte load
             for (int c = 0; c < kBlk; ++c)
-                s.tile_cols[(size_t)(t * kBlk + c)] = s.restore_cols[(size_t)(c < width ? base + c : s.cols_offset[p])];
+                s.tile_cols[(size_t)(t * kBlk + (c & 3) * 4 + (c >> 2))] =
+                    s.restore_cols[(size_t)(c < width ? base + c : s.cols_offset[p])];
         }
     }
 }
@@ -624,6 +636,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             // the records' 32-bit fields bound what one range and the whole stream may hold
             if (NT + (int64_t)NW + 1 > (int64_t)INT32_MAX / 2) {
                 err = "too many tiles for the streaming kernel's batch records";
+                return CB_ERROR_NOT_SUPPORTED;
+            }
+            if (s.payload_bytes >= ((int64_t)1 << 48)) {
+                err = "payload too large for the tile records";
                 return CB_ERROR_NOT_SUPPORTED;
             }
             build_stream(s);

@@ -37,6 +37,12 @@ namespace {
 #ifndef CB_TUNE_PASS_PAIRS
 #define CB_TUNE_PASS_PAIRS 1  // flat entry passes two at a time (FP32/BF16 values)
 #endif
+#ifndef CB_TUNE_SPMM_MFMA
+#define CB_TUNE_SPMM_MFMA 1  // natural-order SpMM on the matrix cores (0: the tile-at-a-time kernel)
+#endif
+#ifndef CB_TUNE_SPMM_STAGES
+#define CB_TUNE_SPMM_STAGES 3  // tiles whose loads are in flight in the matrix-core SpMM (FP64: one fewer, at least 2)
+#endif
 #ifndef CB_TUNE_NT_LOADS
 #define CB_TUNE_NT_LOADS 0  // payload chunk loads with the nontemporal hint
 #endif
@@ -47,17 +53,35 @@ constexpr int kBlockThreads = kWave * kWavesPerBlock;
 
 template <int VT>
 struct Val;
+// load(p, i): value i of a packed value array; load4(p, i, v): values i .. i+3 (i a multiple of 4,
+// the array aligned to its value size) with the widest loads the alignment allows
 template <>
 struct Val<0> {
     using A = double;
     static constexpr int kSize = 8;
     __device__ static A load(const uint8_t *p, int i) { return reinterpret_cast<const double *>(p)[i]; }
+    __device__ static void load4(const uint8_t *p, int i, A *v) {
+        using d2 = double __attribute__((ext_vector_type(2), aligned(8)));
+        const d2 a = *reinterpret_cast<const d2 *>(p + 8 * i), b = *reinterpret_cast<const d2 *>(p + 8 * i + 16);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    }
 };
 template <>
 struct Val<1> {
     using A = float;
     static constexpr int kSize = 4;
     __device__ static A load(const uint8_t *p, int i) { return reinterpret_cast<const float *>(p)[i]; }
+    __device__ static void load4(const uint8_t *p, int i, A *v) {
+        using f4 = float __attribute__((ext_vector_type(4), aligned(4)));
+        const f4 a = *reinterpret_cast<const f4 *>(p + 4 * i);
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = a.z;
+        v[3] = a.w;
+    }
 };
 template <>
 struct Val<2> {
@@ -65,6 +89,10 @@ struct Val<2> {
     static constexpr int kSize = 2;
     __device__ static A load(const uint8_t *p, int i) {
         return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t *>(p)[i] << 16);
+    }
+    __device__ static void load4(const uint8_t *p, int i, A *v) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = load(p, i + j);
     }
 };
 
@@ -362,7 +390,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         for (int g = 0; g < NG; ++g) {
             if (4 * g < nt) {
                 const int t = min(tb + 4 * g + gj, t1 - 1);
-                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + glc] : d.tile_col[t];
+                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + (glc & 3) * 4 + (glc >> 2)] : d.tile_col[t];
             }
         }
     };
@@ -881,6 +909,248 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     return hipGetLastError();
 }
 
+// ---- k right-hand sides on the matrix cores (natural order) ----------------
+//
+// Y = alpha*A*X + beta*Y, KC columns of X per launch slice (blockIdx.y).  Every
+// tile, whatever its storage format, is a 16 x 16 block of A; times the tile's
+// 16 rows of X (a 16 x KC block) it is a small dense contraction, done on the
+// matrix cores as four 16x16x4 MFMA steps per 16 output columns.  The panel's
+// 16 x KC output block stays in the MFMA accumulators while the wavefront walks
+// the panel's tiles and is written to Y when the panel changes.  COO and CSR
+// tiles are expanded into a zero-filled 16 x 16 operand in LDS (their one-byte
+// codes give row and column, Algorithm 3); Dense tiles are the operand already
+// (Algorithm 4).  A tile whose staged X block holds an Inf or NaN is multiplied
+// entry by entry instead, so a zero fill never meets it.
+//
+// Loads run NS - 1 tiles ahead: after tile t is multiplied, the entries and
+// the X block of tile t+NS-1 and the column indices of tile t+NS are issued,
+// so NS - 2 tiles are multiplied while they are in flight.  The loop is
+// unrolled by NS so each tile's registers are fixed, and every load is issued
+// on every path (addresses clamped into the range).
+
+// operand and accumulator layouts (see Mfma): lane l holds A[l % 16][4kb + l / 16]
+// and B[4kb + l / 16][l % 16] in step kb
+template <int VT, int KC, bool AGG, int NS>
+__global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typename Val<VT>::A alpha,
+                                                                  typename Val<VT>::A beta,
+                                                                  const typename Val<VT>::A *__restrict__ X,
+                                                                  int64_t ldx, typename Val<VT>::A *__restrict__ Y,
+                                                                  int64_t ldy, int k) {
+    using A = typename Val<VT>::A;
+    using C = typename Mfma<A>::C;
+    constexpr int VS = Val<VT>::kSize;
+    constexpr int NB = KC / 16;  // 16-column output blocks
+    static_assert(KC == 16 || KC == 32, "16 or 32 columns per slice");
+    __shared__ __align__(16) A dense_all[kWavesPerBlock][256];
+    __shared__ A cs_all[kWavesPerBlock][16 * KC];
+    __shared__ A xs_all[kWavesPerBlock][16 * KC];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
+    if (w >= d.nwaves) return;
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    if (t0 >= t1) return;
+    A *dense = dense_all[wid];
+    A *cs = cs_all[wid];
+    A *xs = xs_all[wid];
+    const int j0 = blockIdx.y * KC;
+    const int kc = min(KC, k - j0);
+    const int lr = lane & 15, lg = lane >> 4;
+    const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
+    const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
+
+    // per-tile loads of one stage; the tile record arrives a stage before the entries need it.
+    // Lane l takes entries 4l .. 4l+3 of a COO/CSR tile (codes as one dword) or elements 4l .. 4l+3
+    // of a Dense tile (row l / 4, columns 4(l % 4) ..), so a stage is about a dozen wave loads and
+    // four stages stay within the 63 vector loads a wavefront can have in flight.
+    struct Stage {
+        i32x4 rec;      // {vp low, vp high | type << 16 | (nnz - 1) << 18, panel, column block}
+        u32x4 ci;       // aggregation: original columns lg, lg + 4, lg + 8, lg + 12 of the tile
+        A ev[4];        // values of entries (elements) 4l .. 4l+3
+        uint32_t ec;    // COO/CSR: codes of entries 4l .. 4l+3; Dense: occupancy bitmap word l % 8
+        A xb[NB][4];    // B operands: X[column 4kb + lg][j0 + 16ob + lr]
+    };
+    auto issue_idx = [&](Stage &S, int t) __attribute__((always_inline)) {
+        const int tc = min(t, t1 - 1);
+        S.rec = reinterpret_cast<const i32x4 *>(d.tile_rec)[tc];
+        if constexpr (AGG) S.ci = reinterpret_cast<const u32x4 *>(d.tile_cols)[4 * (size_t)tc + lg];
+    };
+    auto rec_ty = [](int y) { return (y >> 16) & 3; };
+    auto rec_nz = [](int y) { return ((y >> 18) & 0xFF) + 1; };
+    auto issue_ent = [&](Stage &S) __attribute__((always_inline)) {
+        const int y = __builtin_amdgcn_readfirstlane(S.rec.y);
+        const int nz = rec_nz(y), ty = rec_ty(y);
+        const int64_t vp = ((int64_t)(y & 0xFFFF) << 32) | (uint32_t)__builtin_amdgcn_readfirstlane(S.rec.x);
+        const uint8_t *base = d.payload + vp;
+        const int hb = ty == 1 ? 16 : 0;
+        const int e = 4 * lane < nz ? 4 * lane : 0;  // lanes past the tile re-read its first entries
+        const uint8_t *vals = ty == 2 ? base : base + hb + nz + pad_bytes(hb + nz, VS);
+        const int vi = ty == 2 ? 4 * lane : e;
+        S.ec = ty == 2 ? reinterpret_cast<const uint32_t *>(base + 256 * VS)[lane & 7]
+                       : *reinterpret_cast<const uint32_t *>(base + hb + e);
+        Val<VT>::load4(vals, vi, S.ev);
+    };
+    auto issue_x = [&](Stage &S) __attribute__((always_inline)) {
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            int col;
+            if constexpr (AGG) {
+                col = (int)S.ci[kb];
+            } else {
+                const int64_t c = 16 * (int64_t)__builtin_amdgcn_readfirstlane(S.rec.w) + 4 * kb + lg;
+                col = c < d.n ? (int)c : 0;
+            }
+            const A *xr = X + (int64_t)col * ldx;
+#pragma unroll
+            for (int ob = 0; ob < NB; ++ob) S.xb[ob][kb] = xr[min(j0 + 16 * ob + lr, k - 1)];
+        }
+    };
+
+    C acc[NB];
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) acc[ob] = C{A(0), A(0), A(0), A(0)};
+    auto flush = [&](int p) {
+        const bool shared = (p == p_first && sh_first) || (p == p_last && sh_last);
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+            const int col = 16 * ob + lr;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = 16 * (int64_t)p + Mfma<A>::row(lane, v);
+                if (row < d.m && col < kc) {
+                    A *yp = Y + row * ldy + j0 + col;
+                    if (shared) {
+                        global_add(yp, alpha * acc[ob][v]);
+                    } else {
+                        A out = alpha * acc[ob][v];
+                        if (beta != A(0)) out += beta * *yp;
+                        *yp = out;
+                    }
+                }
+            }
+            acc[ob] = C{A(0), A(0), A(0), A(0)};
+        }
+    };
+
+    // entry-by-entry product of a tile whose X block is not finite: the accumulators and the X
+    // block go through LDS and the entries come from the stage's registers by cross-lane reads, lanes
+    // over the KC columns.  No global loads, so the counts of the loads in flight stay exact.
+    auto exact_tile = [&](const Stage &S) __attribute__((always_inline)) {
+        const int y = __builtin_amdgcn_readfirstlane(S.rec.y);
+        const int nz = rec_nz(y), ty = rec_ty(y);
+        const A v0 = S.ev[0], v1 = S.ev[1], v2 = S.ev[2], v3 = S.ev[3];
+        const int ec = (int)S.ec;
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cs[Mfma<A>::row(lane, v) * KC + 16 * ob + lr] = acc[ob][v];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) xs[(4 * kb + lg) * KC + 16 * ob + lr] = S.xb[ob][kb];
+        }
+        __builtin_amdgcn_wave_barrier();
+        // Dense: ec of lane i holds word i % 8 of the occupancy bitmap and element (r, c) is value
+        // c % 4 of lane 4r + c / 4; COO/CSR: entry e is byte e % 4 of ec and value e % 4 of lane e / 4
+        const int n = ty == 2 ? 256 : nz;
+        for (int e = 0; e < n; ++e) {
+            int r, c, src, j;
+            if (ty == 2) {
+                if (!((__shfl(ec, e >> 5) >> (e & 31)) & 1)) continue;
+                r = e >> 4;
+                c = e & 15;
+                src = 4 * r + (c >> 2);
+                j = c & 3;
+            } else {
+                const int code = (__shfl(ec, e >> 2) >> (8 * (e & 3))) & 0xFF;
+                r = code & 15;
+                c = code >> 4;
+                src = e >> 2;
+                j = e & 3;
+            }
+            const A sel = j == 0 ? v0 : j == 1 ? v1 : j == 2 ? v2 : v3;
+            const A v = __shfl(sel, src);
+            if (lane < KC) cs[r * KC + lane] += v * xs[c * KC + lane];
+            __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[ob][v] = cs[Mfma<A>::row(lane, v) * KC + 16 * ob + lr];
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    int cur = -1;
+    auto multiply = [&](const Stage &S) __attribute__((always_inline)) {
+        const int p = __builtin_amdgcn_readfirstlane(S.rec.z);
+        if (p != cur) {
+            if (cur >= 0) flush(cur);
+            cur = p;
+        }
+        bool finite = true;
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) finite = finite && __builtin_isfinite(S.xb[ob][kb]);
+        if (__ballot(!finite) != 0) {
+            exact_tile(S);
+            return;
+        }
+        const int y = __builtin_amdgcn_readfirstlane(S.rec.y);
+        const int nz = rec_nz(y), ty = rec_ty(y);
+        // the 16 x 16 operand in LDS, element (r, c) at r*16 + (c%4)*4 + c/4, so lane l reads its four
+        // values A[lr][4kb + lg] as one contiguous group; COO/CSR tiles are zero-filled first
+        if (ty != 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dense[4 * lane + i] = A(0);
+            __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r, c;
+            if (ty == 2) {
+                r = lane >> 2;
+                c = 4 * (lane & 3) + i;
+            } else {
+                const int code = (S.ec >> (8 * i)) & 0xFF;
+                r = code & 15;
+                c = code >> 4;
+            }
+            if (ty == 2 || 4 * lane + i < nz) dense[r * 16 + (c & 3) * 4 + (c >> 2)] = S.ev[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        A a[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) a[kb] = dense[lr * 16 + lg * 4 + kb];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc[ob] = Mfma<A>::step(a[kb], S.xb[ob][kb], acc[ob]);
+    };
+
+    // prologue: tiles t0 .. t0+NS-2 in flight, metadata and column indices of tile t0+NS-1
+    Stage S[NS];
+#pragma unroll
+    for (int u = 0; u + 1 < NS; ++u) issue_idx(S[u], t0 + u);
+#pragma unroll
+    for (int u = 0; u + 1 < NS; ++u) {
+        issue_ent(S[u]);
+        issue_x(S[u]);
+    }
+    issue_idx(S[NS - 1], t0 + NS - 1);
+    for (int t = t0; t < t1; t += NS) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int tt = t + u;
+            if (tt >= t1) break;
+            multiply(S[u]);
+            issue_idx(S[u], tt + NS);
+            issue_ent(S[(u + NS - 1) % NS]);
+            issue_x(S[(u + NS - 1) % NS]);
+        }
+    }
+    if (cur >= 0) flush(cur);
+}
+
 template <int VT, int KC>
 hipError_t spmm_kc(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                    int64_t ldy, hipStream_t s) {
@@ -895,9 +1165,31 @@ hipError_t spmm_kc(const DevView &d, int k, double alpha, const void *X, int64_t
     return hipGetLastError();
 }
 
+template <int VT, int KC, bool AGG>
+hipError_t spmm_mfma(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
+                     int64_t ldy, hipStream_t s) {
+    using A = typename Val<VT>::A;
+    hipError_t e = prepass<A>(d, beta, Y, k, ldy, s);
+    if (e != hipSuccess) return e;
+    if (d.nwaves <= 0) return hipSuccess;
+    const int nb = (d.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int ny = (k + KC - 1) / KC;
+    constexpr int NS = VT == 0 && CB_TUNE_SPMM_STAGES > 2 ? CB_TUNE_SPMM_STAGES - 1 : CB_TUNE_SPMM_STAGES;  // FP64 stages are twice the registers
+    hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d, (A)alpha,
+                       (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
+    return hipGetLastError();
+}
+
 template <int VT>
 hipError_t spmm_vt(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                    int64_t ldy, hipStream_t s) {
+    if (d.natural_order && CB_TUNE_SPMM_MFMA) {
+        if (d.col_agg)
+            return k <= 16 ? spmm_mfma<VT, 16, true>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                           : spmm_mfma<VT, 32, true>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+        return k <= 16 ? spmm_mfma<VT, 16, false>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                       : spmm_mfma<VT, 32, false>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+    }
     if (k <= 4) return spmm_kc<VT, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 8) return spmm_kc<VT, 8>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 16) return spmm_kc<VT, 16>(d, k, alpha, X, ldx, beta, Y, ldy, s);

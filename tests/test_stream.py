@@ -126,7 +126,7 @@ def check_stream(A, X, vtype="f64", **opts):
                 xo = int(r[3])
                 if agg:
                     # the tile's 16 columns the kernel gathers x through
-                    tc = s["tile_cols"][16 * i:16 * i + 16]
+                    tc = s["tile_cols"][16 * i:16 * i + 16].reshape(4, 4).T.ravel()  # stored (c % 4) * 4 + c // 4
                     width = min(16, s["cols_offset"][row[i] + 1] - xo)
                     assert np.array_equal(tc[:width], s["restore_cols"][xo:xo + width])
                     assert np.all(tc[width:] == s["restore_cols"][s["cols_offset"][row[i]]])
