@@ -43,7 +43,7 @@ constexpr int kRingChunks = 4;    // payload chunks a batch may touch (the kerne
 constexpr int kRingBits = 12;     // the ring's 4096 bytes, the width of the packed positions
 static_assert(kChunk * kRingChunks == 1 << kRingBits, "packed positions address the ring");
 constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
-constexpr int kBatchPanels = 8;   // consecutive panels a batch may touch (accumulator slots)
+constexpr int kBatchPanels = 4;   // consecutive panels a batch may touch (accumulator slots)
 constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream
 constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes readable past their ends
 

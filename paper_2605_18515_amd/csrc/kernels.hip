@@ -29,7 +29,7 @@ namespace {
 
 // Tuning parameters (fixed at build time; the defaults are the measured best on MI355X)
 #ifndef CB_TUNE_WAVES_PER_BLOCK
-#define CB_TUNE_WAVES_PER_BLOCK 4
+#define CB_TUNE_WAVES_PER_BLOCK 1
 #endif
 #ifndef CB_TUNE_F64_DPP
 #define CB_TUNE_F64_DPP 0  // FP64 row sums: 0 = LDS atomics per entry, 1 = DPP segmented scan
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 // When the kernel order equals the packing order (contiguous or no load
 // balance), a wavefront's tiles occupy one contiguous byte range of the
 // payload.  The converter cuts the range into batches (at most 16 tiles whose
-// payload touches at most four 1 KB chunks and whose panels lie within eight
+// payload touches at most four 1 KB chunks and whose panels lie within four
 // consecutive ones) and writes each batch as a header and one record per tile
 // (format in cb_stream.h): the offsets the multiply needs, precomputed once.
 // The loads of a batch are spread over the three steps before the one that
@@ -306,6 +306,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
 
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 using i32x4 = int __attribute__((ext_vector_type(4)));
+using i32x2 = int __attribute__((ext_vector_type(2)));
 
 constexpr int kChunk = cbs::kChunk;
 constexpr int kRC = cbs::kRingChunks;
@@ -316,7 +317,7 @@ constexpr int kMaxPanels = cbs::kBatchPanels;
 constexpr int kRecs = kBatchTiles + 1;  // header and records of one batch
 static_assert(kChunk == kWave * 16 && (kPRing & kPMask) == 0, "one chunk per wavefront-wide 16-byte load");
 static_assert(kBatchTiles + 1 <= kWave && kBatchTiles % 4 == 0, "a batch's records fit one load; x gathers take four tiles each");
-static_assert(kMaxPanels * 16 <= 2 * kWave, "accumulators cleared by two stores per lane");
+static_assert(kMaxPanels * 16 <= kWave && kMaxPanels <= 4, "accumulators cleared by one store per lane, flushed by one group");
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
 
 template <int VT, bool AGG, bool DPPRED>
@@ -328,10 +329,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     constexpr int VS = Val<VT>::kSize;
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
-    __shared__ __align__(16) i32x4 rec_all[kWavesPerBlock][3][kRecs];  // three batches in flight
+    // three batches in flight: per tile {record word, last flat entry (COO/CSR) or region start (Dense)}
+    __shared__ __align__(16) i32x2 rec_all[kWavesPerBlock][3][kBatchTiles];
     __shared__ __align__(16) A acc_all[kWavesPerBlock][kMaxPanels * 16];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // with one wavefront per workgroup its LDS arrays sit at fixed addresses
+    const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
     if (w >= d.nwaves) return;
     const int o_begin = d.batch_ptr[w], o_end = d.batch_ptr[w + 1];
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     uint8_t *pring = pring_all[wid];
     A *xarea = xarea_all[wid];
     A *acc = acc_all[wid];
-    i32x4 *recs = rec_all[wid][0];
+    i32x2 *recs = rec_all[wid][0];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
     const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + d.tile_vp[t0]) + lane;
     const i32x4 *rstream = reinterpret_cast<const i32x4 *>(d.batch_stream);
@@ -351,8 +354,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     // header and records of the batch at record o: lane 0 the header, lane 1 + i record i
     i32x4 Q;
     auto qload = [&](int o) { Q = rstream[o + min(lane, kBatchTiles)]; };
-    auto put_recs = [&](i32x4 *rec) {
-        if (lane < kRecs) rec[lane] = Q;
+    // lane 1 + i holds record i; its last entry (COO/CSR) and region start (Dense) are never both set
+    auto put_recs = [&](i32x2 *rec) {
+        if (lane >= 1 && lane < kRecs) rec[lane - 1] = i32x2{Q.x, Q.y | Q.z};
     };
 
     // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued); re is the
@@ -414,38 +418,30 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             if (4 * g < nt) xarea[64 * g + lane] = XG[g];
     };
 
-    // panels finished by a batch: lane (k, r) holds row r of panel pb + k (YP[0]) and pb + 4 + k (YP[1])
+    // panels finished by a batch: lane (k, r) holds row r of panel pb + k
     const int fk = lane >> 4, fr = lane & 15;
-    A YP[2] = {A(0), A(0)};
+    A YP = A(0);
     int done_pb = 0, done_mask = 0;
     auto is_shared = [&](int p) { return (p == p_first && sh_first) || (p == p_last && sh_last); };
     auto issue_y = [&]() {
         if (beta == A(0)) return;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = fk + 4 * h;
-            const int64_t row = 16 * (int64_t)(done_pb + k) + fr;
-            if (((done_mask >> k) & 1) && row < d.m && !is_shared(done_pb + k)) YP[h] = y[row];
-        }
+        const int64_t row = 16 * (int64_t)(done_pb + fk) + fr;
+        if (((done_mask >> fk) & 1) && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
     };
     auto flush = [&]() {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = fk + 4 * h;
-            if ((done_mask >> k) & 1) {
-                const int p = done_pb + k;
-                A *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
-                const A v = *a;
-                *a = A(0);
-                const int64_t row = 16 * (int64_t)p + fr;
-                if (row < d.m) {
-                    if (is_shared(p)) {
-                        global_add(&y[row], alpha * v);
-                    } else {
-                        A r = alpha * v;
-                        if (beta != A(0)) r += beta * YP[h];
-                        y[row] = r;
-                    }
+        if ((done_mask >> fk) & 1) {
+            const int p = done_pb + fk;
+            A *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
+            const A v = *a;
+            *a = A(0);
+            const int64_t row = 16 * (int64_t)p + fr;
+            if (row < d.m) {
+                if (is_shared(p)) {
+                    global_add(&y[row], alpha * v);
+                } else {
+                    A r = alpha * v;
+                    if (beta != A(0)) r += beta * YP;
+                    y[row] = r;
                 }
             }
         }
@@ -454,12 +450,13 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
 
     // multiply one batch: records rec[1..], header fields hz = nt | nflat << 8 | ndense << 16 | done << 24
     // and etot (flat entries); positions in the packed record words are taken modulo the ring size
-    auto multiply = [&](const i32x4 *rec, int hz, int etot) {
+    auto multiply = [&](const i32x2 *rec, int hz, int etot) {
         const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
         // COO and CSR entries as one stream; lane i holds flat tile i's last entry (endv) and record
         // word (pkv), read once per batch
-        const int endv = rec[1 + min(lane, kBatchTiles - 1)].y;
-        const uint32_t pkv = (uint32_t)rec[1 + min(lane, kBatchTiles - 1)].x;
+        const i32x2 rl = rec[min(lane, kBatchTiles - 1)];
+        const int endv = rl.y;
+        const uint32_t pkv = (uint32_t)rl.x;
         // tile of entry E in the pass starting at entry e0, and its record word; j: the tile holding
         // entry e0, advanced to the tile holding entry e0 + 64
         auto tile_of = [&](int e0, int E, int &j, uint32_t &pk) {
@@ -517,9 +514,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
         for (int k = 0; k < ndense; ++k) {
-            const i32x4 r = rec[1 + nflat + k];
+            const i32x2 r = rec[nflat + k];
             const uint32_t pk = (uint32_t)__builtin_amdgcn_readfirstlane(r.x);
-            const int rel = __builtin_amdgcn_readfirstlane(r.z);
+            const int rel = __builtin_amdgcn_readfirstlane(r.y);
             const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
             const int vo = rel + (r4 * 16 + 4 * q4) * VS;
             const A *xs = xarea + ((pk >> 27) << 4) + 4 * q4;
@@ -532,10 +529,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         }
     };
 
-    if (lane < kMaxPanels * 16 / 2) {
-        acc[lane] = A(0);
-        acc[lane + kMaxPanels * 16 / 2] = A(0);
-    }
+    if (lane < kMaxPanels * 16) acc[lane] = A(0);
     // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
     // columns; batch 2's records.  At the top of step b the registers hold P and XG of batch b,
     // RG of batch b+1 and Q of batch b+2; LDS holds the records of batches b and b+1.
@@ -562,7 +556,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     if (o1 < o_end) {
         h1 = header();
         nt1 = h1.hz & 0xFF;
-        put_recs(recs + kRecs);
+        put_recs(recs + kBatchTiles);
         issue_cols(tb1, nt1);
         o2 = o1 + 1 + nt1;
         tb2 = tb1 + nt1;
@@ -583,7 +577,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         if (have2) {
             h2 = header();
             nt2 = h2.hz & 0xFF;
-            put_recs(recs + bufnn * kRecs);
+            put_recs(recs + bufnn * kBatchTiles);
         }
         __builtin_amdgcn_wave_barrier();
         // 2. loads: payload and x of batch b+1, x columns of batch b+2, records of batch b+3, and
@@ -601,7 +595,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         done_mask = (int)((uint32_t)h0.hz >> 24);
         issue_y();
         // 3. batch b
-        multiply(recs + bufb * kRecs, h0.hz, h0.etot);
+        multiply(recs + bufb * kBatchTiles, h0.hz, h0.etot);
         __builtin_amdgcn_wave_barrier();
         ob = o1;
         ntb = nt1;

@@ -3,7 +3,7 @@
 The converter cuts every work range into batches and writes a header and one
 record per tile (format in paper_2605_18515_amd/csrc/cb_stream.h).  These tests
 decode the records independently of the kernel and check that they (1) respect
-the batch limits the kernel relies on (16 tiles, 4 payload chunks, 8 panels),
+the batch limits the kernel relies on (16 tiles, 4 payload chunks, 4 panels),
 (2) cover every work range's tiles once and in order, (3) point at the codes
 and values the tile arrays locate, and (4) multiplied out entry by entry on the
 CPU, give exactly the oracle's product on dyadic inputs, where every partial
@@ -17,7 +17,7 @@ from paper_2605_18515_amd import matgen
 
 cb = pytest.importorskip("paper_2605_18515_amd.cbspmv", reason="libcbspmv.so not built")
 
-CHUNK, RING, TILES, PANELS = 1024, 4, 16, 8
+CHUNK, RING, TILES, PANELS = 1024, 4, 16, 4
 RINGB = CHUNK * RING
 VSIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
@@ -222,7 +222,7 @@ def test_limits_cut_batches():
     # a Dense FP64 region is 2080 bytes, so a batch holds at most two of them
     assert info["nbatches"] >= 20
     assert np.array_equal(check_stream(A, X, "f64", col_agg=0), oracle.spmv(A, X))
-    # one tile per panel over many panels: the 8-panel limit cuts
+    # one tile per panel over many panels: the 4-panel limit cuts
     A2, X2 = dyadic_case(matgen.identity(16 * 40))
     M = cb.CbMatrix.from_csr(A2, device=False)
     info2 = M.info
