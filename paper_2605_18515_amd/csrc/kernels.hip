@@ -43,6 +43,9 @@ namespace {
 #ifndef CB_TUNE_SPMM_STAGES
 #define CB_TUNE_SPMM_STAGES 3  // tiles whose loads are in flight in the matrix-core SpMM (FP64: one fewer, at least 2)
 #endif
+#ifndef CB_TUNE_SPMM_KC_MAX
+#define CB_TUNE_SPMM_KC_MAX 32  // widest column slice of the matrix-core SpMM (16 or 32)
+#endif
 #ifndef CB_TUNE_NT_LOADS
 #define CB_TUNE_NT_LOADS 0  // payload chunk loads with the nontemporal hint
 #endif
@@ -1178,11 +1181,12 @@ template <int VT>
 hipError_t spmm_vt(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                    int64_t ldy, hipStream_t s) {
     if (d.natural_order && CB_TUNE_SPMM_MFMA) {
+        const bool wide = k > 16 && CB_TUNE_SPMM_KC_MAX >= 32;
         if (d.col_agg)
-            return k <= 16 ? spmm_mfma<VT, 16, true>(d, k, alpha, X, ldx, beta, Y, ldy, s)
-                           : spmm_mfma<VT, 32, true>(d, k, alpha, X, ldx, beta, Y, ldy, s);
-        return k <= 16 ? spmm_mfma<VT, 16, false>(d, k, alpha, X, ldx, beta, Y, ldy, s)
-                       : spmm_mfma<VT, 32, false>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+            return wide ? spmm_mfma<VT, 32, true>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                        : spmm_mfma<VT, 16, true>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+        return wide ? spmm_mfma<VT, 32, false>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                    : spmm_mfma<VT, 16, false>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     }
     if (k <= 4) return spmm_kc<VT, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 8) return spmm_kc<VT, 8>(d, k, alpha, X, ldx, beta, Y, ldy, s);
