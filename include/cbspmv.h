@@ -192,10 +192,12 @@ cb_status_t cb_spmv(cb_matrix_t A, double alpha, const void *x, double beta, voi
 
 /* Y = alpha * A * X + beta * Y for k right-hand sides.  X is n x k and Y is
  * m x k, both row-major device arrays with leading dimensions ldx >= k and
- * ldy >= k (elements).  Element type as for cb_spmv.  k == 1 is cb_spmv.
- * Dense tiles use the matrix cores (MFMA) when k >= 8 and the values are
- * FP64.  Errors as for cb_spmv, plus CB_ERROR_INVALID_VALUE for k < 1 or
- * ld < k. */
+ * ldy >= k (elements).  Element type as for cb_spmv.  k == 1 with unit
+ * leading dimensions is cb_spmv.  With the contiguous or no load balance
+ * every tile is multiplied on the matrix cores (MFMA) as a 16 x 16 block times
+ * its 16 rows of X, 16 or 32 columns of X per launch slice; with Algorithm 2's
+ * order only Dense tiles are.  Errors as for cb_spmv, plus
+ * CB_ERROR_INVALID_VALUE for k < 1 or ld < k. */
 cb_status_t cb_spmm(cb_matrix_t A, int32_t k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                     int64_t ldy, void *stream);
 
@@ -220,6 +222,58 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *out);
  * bandwidth of the device.  src and dst must be 16-byte aligned device
  * pointers and must not overlap; bytes must be a multiple of 16. */
 cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
+/* ---- Conjugate gradient (NEXT to the product: A symmetric positive definite) ----
+ *
+ * Solvers built on cb_spmv.  Each iteration runs on the device (the product, dot
+ * products accumulated in FP64 as two-stage reductions, and the step lengths read
+ * by the update kernels from device scalars); the host reads the residual norm
+ * every check_every iterations, so the calls synchronise `stream` and must not
+ * be captured in a graph.  The caller supplies the device workspace (size from
+ * cb_cg_workspace_bytes); the solvers allocate nothing. */
+typedef struct {
+    uint32_t struct_size;   /* sizeof(cb_cg_options_t) */
+    int32_t max_iter;       /* iterations of one CG solve (of each inner solve when refining); 10000 */
+    double rtol;            /* stop when |b - A x|_2 <= rtol |b|_2; 1e-10 */
+    int32_t check_every;    /* iterations between host reads of the residual norm; 16 */
+    int32_t max_refine;     /* outer steps of cb_cg_refine; 50 */
+    double inner_rtol;      /* residual reduction each inner solve of cb_cg_refine aims at; 1e-4 */
+    int64_t reserved[4];
+} cb_cg_options_t;
+
+typedef struct {
+    int32_t converged;      /* 1 when the stopping test was met */
+    int32_t iterations;     /* CG iterations (all inner solves for cb_cg_refine) */
+    int32_t refinements;    /* outer steps of cb_cg_refine (0 for cb_cg) */
+    int32_t reserved0;
+    double rel_residual;    /* |b - A x|_2 / |b|_2 of the returned x, computed in FP64 from the true residual
+                               (FP64 handles); the CG recurrence's value for FP32/BF16 handles in cb_cg */
+    int64_t reserved[2];
+} cb_cg_result_t;
+
+cb_status_t cb_cg_options_default(cb_cg_options_t *opt);
+
+/* Device workspace bytes for cb_cg on A (A_low NULL) or for cb_cg_refine on A and A_low. */
+cb_status_t cb_cg_workspace_bytes(cb_matrix_t A, cb_matrix_t A_low, int64_t *bytes);
+
+/* Conjugate gradient on A x = b (Hestenes and Stiefel) starting from the caller's x.  b and x are n
+ * device elements of A's vector type (double for CB_VALUE_F64, float otherwise); x is overwritten
+ * with the solution.  work: device buffer of at least cb_cg_workspace_bytes(A, NULL) bytes (its
+ * contents are scratch).  A must be square; a non-positive-definite search direction stops the
+ * iteration with converged = 0.  opt may be NULL (defaults).  Errors: CB_ERROR_INVALID_VALUE (NULL
+ * arguments, workspace too small, bad options, non-square A), CB_ERROR_NOT_SUPPORTED (host-only
+ * handle), CB_ERROR_HIP. */
+cb_status_t cb_cg(cb_matrix_t A, const void *b, void *x, void *work, int64_t work_bytes, const cb_cg_options_t *opt,
+                  cb_cg_result_t *res, void *stream);
+
+/* Mixed-precision iterative refinement: with A stored in FP64 and A_low the same matrix stored in
+ * FP32 or BF16, repeat r = b - A x (FP64), solve A_low d = r / |r| by CG in FP32 to a relative
+ * residual of inner_rtol, x += |r| d, until |b - A x| <= rtol |b| (true FP64 residual) or the
+ * residual stops decreasing.  b and x are double device vectors; work as for cb_cg with both
+ * handles.  Errors as for cb_cg, plus CB_ERROR_INVALID_VALUE when the handles' precisions or
+ * sizes do not fit. */
+cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, double *x, void *work, int64_t work_bytes,
+                         const cb_cg_options_t *opt, cb_cg_result_t *res, void *stream);
 
 /* Message for the last non-success status returned on this thread. */
 const char *cb_last_error(void);

@@ -43,13 +43,15 @@ def build(verbose: bool = False) -> str:
         ["g++", *CXX_FLAGS, "-c", os.path.join(SRC, "convert.cpp"), "-o", os.path.join(OUT, "convert.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "capi.cpp"), "-o", os.path.join(OUT, "capi.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "kernels.hip"), "-o", os.path.join(OUT, "kernels.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "solver.hip"), "-o", os.path.join(OUT, "solver.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         for f in [ex.submit(_run, j) for j in jobs]:
             f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-o", tmp,
-          os.path.join(OUT, "convert.o"), os.path.join(OUT, "capi.o"), os.path.join(OUT, "kernels.o")])
+          os.path.join(OUT, "convert.o"), os.path.join(OUT, "capi.o"), os.path.join(OUT, "kernels.o"),
+          os.path.join(OUT, "solver.o")])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -60,7 +60,21 @@ class CbStructure(ctypes.Structure):
                                   "prepass_list", "tile_xoff", "batch_stream", "batch_ptr", "tile_cols")]
 
 
+class CbCgOptions(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("max_iter", _i32), ("rtol", _dbl), ("check_every", _i32),
+                ("max_refine", _i32), ("inner_rtol", _dbl), ("reserved", _i64 * 4)]
+
+
+class CbCgResult(ctypes.Structure):
+    _fields_ = [("converged", _i32), ("iterations", _i32), ("refinements", _i32), ("reserved0", _i32),
+                ("rel_residual", _dbl), ("reserved", _i64 * 2)]
+
+
 _lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
+_lib.cb_cg_options_default.argtypes = [ctypes.POINTER(CbCgOptions)]
+_lib.cb_cg_workspace_bytes.argtypes = [_p, _p, ctypes.POINTER(_i64)]
+_lib.cb_cg.argtypes = [_p, _p, _p, _p, _i64, ctypes.POINTER(CbCgOptions), ctypes.POINTER(CbCgResult), _p]
+_lib.cb_cg_refine.argtypes = [_p, _p, _p, _p, _p, _i64, ctypes.POINTER(CbCgOptions), ctypes.POINTER(CbCgResult), _p]
 _lib.cb_create.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions), _p]
 _lib.cb_create_host.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions)]
 _lib.cb_spmv.argtypes = [_p, _dbl, _p, _dbl, _p, _p]
@@ -73,7 +87,8 @@ _lib.cb_copy_probe.argtypes = [_p, _p, _i64, _p]
 _lib.cb_last_error.argtypes = []
 _lib.cb_last_error.restype = ctypes.c_char_p
 for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
-           "cb_get_info", "cb_export_structure", "cb_copy_probe"):
+           "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_cg_options_default", "cb_cg_workspace_bytes",
+           "cb_cg", "cb_cg_refine"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -181,6 +196,42 @@ def cb_spmm(A: int, k: int, alpha: float, X, ldx: int, beta: float, Y, ldy: int,
                         _stream_ptr(stream)))
 
 
+def cb_cg_options_default(**kw) -> CbCgOptions:
+    o = CbCgOptions()
+    _check(_lib.cb_cg_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k) or k.startswith("reserved") or k == "struct_size":
+            raise ValueError(f"unknown CG option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def cb_cg_workspace_bytes(A: int, A_low: int | None = None) -> int:
+    b = _i64()
+    _check(_lib.cb_cg_workspace_bytes(A, A_low, ctypes.byref(b)))
+    return b.value
+
+
+def _cg_result(r: CbCgResult) -> dict:
+    return {"converged": bool(r.converged), "iterations": r.iterations, "refinements": r.refinements,
+            "rel_residual": r.rel_residual}
+
+
+def cb_cg(A: int, b, x, work, work_bytes: int, opt: CbCgOptions | None = None, stream=None) -> dict:
+    r = CbCgResult()
+    _check(_lib.cb_cg(A, _dev_ptr(b), _dev_ptr(x), _dev_ptr(work), int(work_bytes),
+                      ctypes.byref(opt) if opt is not None else None, ctypes.byref(r), _stream_ptr(stream)))
+    return _cg_result(r)
+
+
+def cb_cg_refine(A: int, A_low: int, b, x, work, work_bytes: int, opt: CbCgOptions | None = None,
+                 stream=None) -> dict:
+    r = CbCgResult()
+    _check(_lib.cb_cg_refine(A, A_low, _dev_ptr(b), _dev_ptr(x), _dev_ptr(work), int(work_bytes),
+                             ctypes.byref(opt) if opt is not None else None, ctypes.byref(r), _stream_ptr(stream)))
+    return _cg_result(r)
+
+
 def cb_get_info(A: int) -> dict:
     info = CbInfo()
     info.struct_size = ctypes.sizeof(CbInfo)
@@ -281,6 +332,40 @@ class CbMatrix:
 
     def structure(self) -> dict:
         return cb_export_structure(self.handle)
+
+    def cg(self, b, x, work=None, stream=None, **opts) -> dict:
+        """Solve A x = b by CG from the given x (device tensors of the vector type); work: a device
+        uint8 tensor of at least cb_cg_workspace_bytes bytes, allocated here when None."""
+        n = self.info["n"]
+        _dev_ptr(b, self.vector_dtype)
+        _dev_ptr(x, self.vector_dtype)
+        if b.numel() != n or x.numel() != n:
+            raise ValueError("b and x must have n elements")
+        need = cb_cg_workspace_bytes(self.handle)
+        work = self._workspace(work, need, x)
+        return cb_cg(self.handle, b, x, work, need, cb_cg_options_default(**opts), stream)
+
+    def cg_refine(self, low: "CbMatrix", b, x, work=None, stream=None, **opts) -> dict:
+        """FP64 iterative refinement with CG on the low-precision copy `low` (float64 b and x)."""
+        n = self.info["n"]
+        import torch
+
+        for t in (b, x):
+            if t.dtype != torch.float64 or t.numel() != n:
+                raise ValueError("b and x must be float64 device tensors with n elements")
+        need = cb_cg_workspace_bytes(self.handle, low.handle)
+        work = self._workspace(work, need, x)
+        return cb_cg_refine(self.handle, low.handle, b, x, work, need, cb_cg_options_default(**opts), stream)
+
+    @staticmethod
+    def _workspace(work, need, like):
+        import torch
+
+        if work is None:
+            return torch.empty(need, dtype=torch.uint8, device=like.device)
+        if work.numel() * work.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        return work
 
     def close(self):
         if self.handle:

@@ -14,6 +14,14 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+namespace cbh {
+void set_last_error(const std::string &msg) { g_err = msg; }
+}  // namespace cbh
+
+namespace {
+
 cb_status_t fail(cb_status_t st, const std::string &msg) {
     g_err = msg;
     return st;

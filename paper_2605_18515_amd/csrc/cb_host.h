@@ -63,5 +63,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
 cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_idx, void *values, std::string &err);
 void fill_info(const HostStructure &s, cb_info_t &info);
 int64_t spmv_bytes(const HostStructure &s);
+// message returned by cb_last_error on this thread (set by the parts of the library outside capi.cpp)
+void set_last_error(const std::string &msg);
 
 }  // namespace cbh
