@@ -123,6 +123,71 @@ def time_calls(fn, steps: int, warmup: int):
     return wall / steps, e0.elapsed_time(e1) / 1e3 / steps
 
 
+def run_cg(args, cb, matgen) -> int:
+    """Solves of A x = b from x = 0 on the 192^3 Poisson operator (b ~ U[-1, 1]) until the FP64
+    residual |b - A x| / |b| is at most 1e-10: FP64 CG, and FP64 refinement around CG on the
+    FP32 and on the BF16 copy of A.  Each solve is timed whole (host polling included)."""
+    import numpy as np
+    import torch
+
+    rtol = 1e-10
+    A = matgen.poisson_3d(192)
+    b = matgen.vector(A.n, 5)
+    bd = torch.from_numpy(b).to("cuda")
+    M = cb.CbMatrix.from_csr(A, value_type="f64")
+    legs = {}
+    xs = {}
+    for name in ("fp64_cg", "refine_f32", "refine_bf16"):
+        L = None if name == "fp64_cg" else cb.CbMatrix.from_csr(A, value_type=name.split("_")[1])
+        xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        work = torch.empty(cb.cb_cg_workspace_bytes(M.handle, L.handle if L else None), dtype=torch.uint8,
+                           device="cuda")
+        solve = (lambda: M.cg(bd, xd, work, rtol=rtol)) if L is None else \
+            (lambda: M.cg_refine(L, bd, xd, work, rtol=rtol))
+        times = []
+        for rep in range(1 + max(1, min(args.steps, 5))):
+            xd.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = solve()
+            torch.cuda.synchronize()
+            if rep:  # the first solve is warm-up
+                times.append(time.perf_counter() - t0)
+        sec = float(np.median(times))
+        legs[name] = {"solves_per_s": 1.0 / sec, "seconds": sec, "iterations": res["iterations"],
+                      "refinements": res["refinements"], "rel_residual_device": res["rel_residual"],
+                      "converged": res["converged"]}
+        xs[name] = xd.cpu().numpy()
+        log(f"{name}: {json.dumps(legs[name])}")
+        if L is not None:
+            L.close()
+        del work, xd
+        torch.cuda.empty_cache()
+    M.close()
+    ok = True
+    if not args.no_check:
+        from oracle import solvers
+
+        for name, x in xs.items():
+            legs[name]["rel_residual_oracle"] = r = solvers.residual(A, b, x)
+            ok = ok and r <= rtol and legs[name]["converged"]
+        log("oracle residuals: " + ", ".join(f"{k} {v['rel_residual_oracle']:.3e}" for k, v in legs.items()))
+    best = max(legs, key=lambda k: legs[k]["solves_per_s"])
+    out = {
+        "metric": "CG solves/s to |b - Ax| / |b| <= 1e-10 (FP64 vs mixed-precision refinement)",
+        "value": round(legs[best]["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(times), "warmup": 1, "ms_per_step": legs[best]["seconds"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "CG on the 3D 7-point Poisson operator, 192^3 grid, b ~ U[-1,1], x0 = 0",
+                   "n": A.n, "nnz": A.nnz, "method": best},
+        "roofline": None, "cpu_baseline": None,
+        "extra": {"legs": legs, "speedup_vs_fp64_cg": {k: legs[k]["solves_per_s"] / legs["fp64_cg"]["solves_per_s"]
+                                                       for k in legs}},
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,13 +206,16 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true",
                     help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
+    ap.add_argument("--cg", action="store_true",
+                    help="instead of the SpMV line: CG solves/s on the 192^3 Poisson operator to a true FP64 "
+                         "residual of 1e-10, FP64 CG against FP64 refinement around FP32 and BF16 CG")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the CB-SpMV path here runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented); run with --gpus 1", file=sys.stderr)
+              "(no multi-GPU sharding is implemented); run with --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -166,6 +234,8 @@ def main() -> int:
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": args.steps + args.warmup,
                           "GBs": 2 * nbytes / k_s / 1e9}), flush=True)
         return 0
+    if args.cg:
+        return run_cg(args, cb, matgen)
     t = time.perf_counter()
     A = make_matrix(args.workload, args.side)
     x = matgen.vector(A.n, 1)

@@ -58,7 +58,9 @@ typedef enum {
 /* Storage precision of the matrix values (the paper evaluates FP64,
  * Section 4.2).  F64: x and y are double, FP64 arithmetic.  F32 / BF16:
  * values rounded to nearest-even straight from the FP64 input at creation,
- * x and y are float, products and sums in FP32. */
+ * x and y are float, products in FP32, row sums in FP32 (at least: the
+ * streaming SpMV kernel keeps them in FP64 by default, see row_reduce),
+ * alpha and beta applied in FP32. */
 typedef enum { CB_VALUE_F64 = 0, CB_VALUE_F32 = 1, CB_VALUE_BF16 = 2 } cb_value_t;
 
 /* Tile formats (Section 3.3.2). */
@@ -89,7 +91,15 @@ typedef struct {
     int32_t host_threads;   /* converter threads; 0 = all hardware threads */
     double th0;             /* super-sparse share that turns aggregation on (default 0.15) */
     int64_t wave_nnz;       /* target non-zeros per wavefront work range; 0 = automatic */
-    int64_t reserved[6];
+    int32_t row_reduce;     /* how the streaming SpMV kernel sums a pass's products into row
+                               accumulators: 0 = one LDS atomic add per entry; 1 = a DPP segmented
+                               scan over lanes of the same (tile, row), then one add per run;
+                               2 = one FP64 LDS atomic add per entry (FP32/BF16 values: row sums
+                               kept in FP64 until written; same as 0 for FP64); -1 (default) =
+                               automatic: 0 for FP64 values, 2 for FP32/BF16.  Results agree
+                               within the storage precision's tolerance either way. */
+    int32_t reserved32;
+    int64_t reserved[5];
 } cb_options_t;
 
 typedef struct {
@@ -126,7 +136,10 @@ typedef struct {
     int32_t reserved0;
     int64_t nbatches;       /* batches of the streaming kernel (0 with CB_LB_PAPER) */
     int64_t stream_bytes;   /* its batch records: 16 bytes per batch and per tile */
-    int64_t reserved[6];
+    double flat_run_mean;   /* COO/CSR entries per (tile, row) run: the lanes one scan step merges */
+    int32_t row_reduce;     /* the resolved row_reduce option (0, 1 or 2) */
+    int32_t reserved1;
+    int64_t reserved[4];
 } cb_info_t;
 
 /* Host buffers receiving the structure in kernel order (ntiles entries for the

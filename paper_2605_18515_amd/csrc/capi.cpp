@@ -190,6 +190,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.nprepass = (int32_t)s.nprepass;
     v.col_agg = s.col_agg;
     v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
+    v.row_reduce = s.row_reduce;
     // the device copy is the structure from now on
     std::vector<int32_t>().swap(s.tile_row);
     std::vector<int32_t>().swap(s.tile_col);
@@ -285,6 +286,7 @@ cb_status_t cb_options_default(cb_options_t *opt) {
     opt->host_threads = 0;
     opt->th0 = 0.15;
     opt->wave_nnz = 0;
+    opt->row_reduce = -1;
     return CB_SUCCESS;
 }
 

@@ -29,6 +29,7 @@ struct DevView {
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
+    int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan
 };
 
 // vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float)

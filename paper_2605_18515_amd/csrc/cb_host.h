@@ -51,6 +51,8 @@ struct HostStructure {
     int64_t quantum_nnz_max = 0, wave_nnz_max = 0;
     double quantum_nnz_mean = 0, quantum_nnz_std = 0, wave_nnz_mean = 0, wave_nnz_std = 0;
     double convert_seconds = 0.0;
+    int64_t flat_entries = 0, flat_runs = 0;  // COO/CSR entries and their (tile, row) runs
+    int row_reduce = 0;                       // resolved: 0 LDS atomics, 1 DPP segmented scan
 };
 
 int padding(int64_t index_bytes, int vsize);

@@ -87,6 +87,7 @@ inline void store_value(uint8_t *dst, double v, int vtype) {
 
 struct PanelCounts {
     int64_t tiles = 0, bytes = 0, cols = 0, fmt[3] = {0, 0, 0};
+    int64_t flat = 0, runs = 0;  // COO/CSR entries and (tile, row) runs
 };
 
 // Groups the entries of one 16-row panel into tiles.  With aggregation the
@@ -318,6 +319,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.quantum_tiles < 1 || opt.quantum_tiles > (1 << 20)) { err = "quantum_tiles out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.lb_mode < 0 || opt.lb_mode > 2) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.row_reduce < -1 || opt.row_reduce > 2) { err = "row_reduce must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
     if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
     const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
 
@@ -401,11 +403,16 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                     pb.build(p, agg);
                     PanelCounts c;
                     c.cols = agg ? (int64_t)pb.cols().size() : 0;
-                    for_each_tile(pb.entries(), [&](int64_t, size_t lo, size_t hi) {
+                    const std::vector<Entry> &ent = pb.entries();
+                    for_each_tile(ent, [&](int64_t, size_t lo, size_t hi) {
                         const int fmt = select_format((int64_t)(hi - lo), opt.th1, opt.th2);
                         c.tiles += 1;
                         c.fmt[fmt] += 1;
                         c.bytes += region_bytes(fmt, (int64_t)(hi - lo), s.vsize);
+                        if (fmt != CB_FMT_DENSE) {
+                            c.flat += (int64_t)(hi - lo);
+                            for (size_t i = lo; i < hi; ++i) c.runs += (i == lo || (ent[i].key >> 4) != (ent[i - 1].key >> 4));
+                        }
                     });
                     pc[p] = c;
                 }
@@ -417,9 +424,16 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             byte_base[p + 1] = byte_base[p] + pc[p].bytes;
             col_base[p + 1] = col_base[p] + pc[p].cols;
             for (int f = 0; f < 3; ++f) s.tiles_fmt[f] += pc[p].fmt[f];
+            s.flat_entries += pc[p].flat;
+            s.flat_runs += pc[p].runs;
         }
         const int64_t NT = tile_base[P];
         s.ntiles = NT;
+        // row sums of the streaming kernel (measured on gfx950): FP64 LDS atomics beat the
+        // segmented scan on every workload tried, FP32 LDS atomics lose to it on every one, so
+        // FP32/BF16 products are summed with FP64 atomics too
+        if (opt.row_reduce >= 0) s.row_reduce = opt.row_reduce;
+        else s.row_reduce = s.vtype == CB_VALUE_F64 ? 0 : 2;
         if (NT >= kLim || col_base[P] >= kLim) { err = "structure too large"; return CB_ERROR_NOT_SUPPORTED; }
 
         // natural-order arrays and the packed payload (Section 3.2)
@@ -773,6 +787,8 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.nbatches = s.nbatches;
     info.stream_bytes = 16 * s.nrecords;
     info.convert_seconds = s.convert_seconds;
+    info.flat_run_mean = s.flat_runs ? (double)s.flat_entries / (double)s.flat_runs : 0.0;
+    info.row_reduce = s.row_reduce;
 }
 
 }  // namespace cbh

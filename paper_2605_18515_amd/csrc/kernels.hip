@@ -21,6 +21,8 @@
 // atomic add for panels shared with other wavefronts (pre-scaled by a pre-pass).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cb_device.h"
 #include "cb_stream.h"
 
@@ -30,9 +32,6 @@ namespace {
 // Tuning parameters (fixed at build time; the defaults are the measured best on MI355X)
 #ifndef CB_TUNE_WAVES_PER_BLOCK
 #define CB_TUNE_WAVES_PER_BLOCK 1
-#endif
-#ifndef CB_TUNE_F64_DPP
-#define CB_TUNE_F64_DPP 0  // FP64 row sums: 0 = LDS atomics per entry, 1 = DPP segmented scan
 #endif
 #ifndef CB_TUNE_PASS_PAIRS
 #define CB_TUNE_PASS_PAIRS 1  // flat entry passes two at a time (FP32/BF16 values)
@@ -323,18 +322,23 @@ static_assert(kBatchTiles + 1 <= kWave && kBatchTiles % 4 == 0, "a batch's recor
 static_assert(kMaxPanels * 16 <= kWave && kMaxPanels <= 4, "accumulators cleared by one store per lane, flushed by one group");
 constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima
 
-template <int VT, bool AGG, bool DPPRED>
+// RR, the row sums: 0 = one LDS atomic add per entry, 1 = DPP segmented scan then one add per run,
+// 2 = one FP64 LDS atomic add per entry (FP32/BF16 values: the products widened, the row sums kept
+// in FP64 until they are written)
+template <int VT, bool AGG, int RR>
 __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
                                                                      typename Val<VT>::A beta,
                                                                      const typename Val<VT>::A *__restrict__ x,
                                                                      typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
+    using AC = typename std::conditional<RR == 2, double, A>::type;  // accumulator type
+    constexpr bool DPPRED = RR == 1;
     constexpr int VS = Val<VT>::kSize;
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
     // three batches in flight: per tile {record word, last flat entry (COO/CSR) or region start (Dense)}
     __shared__ __align__(16) i32x2 rec_all[kWavesPerBlock][3][kBatchTiles];
-    __shared__ __align__(16) A acc_all[kWavesPerBlock][kMaxPanels * 16];
+    __shared__ __align__(16) AC acc_all[kWavesPerBlock][kMaxPanels * 16];
     const int lane = threadIdx.x & (kWave - 1);
     // with one wavefront per workgroup its LDS arrays sit at fixed addresses
     const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     if (o_begin >= o_end) return;
     uint8_t *pring = pring_all[wid];
     A *xarea = xarea_all[wid];
-    A *acc = acc_all[wid];
+    AC *acc = acc_all[wid];
     i32x2 *recs = rec_all[wid][0];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
     const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + d.tile_vp[t0]) + lane;
@@ -434,9 +438,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     auto flush = [&]() {
         if ((done_mask >> fk) & 1) {
             const int p = done_pb + fk;
-            A *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
-            const A v = *a;
-            *a = A(0);
+            AC *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
+            const A v = (A)*a;
+            *a = AC(0);
             const int64_t row = 16 * (int64_t)p + fr;
             if (row < d.m) {
                 if (is_shared(p)) {
@@ -484,12 +488,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
                    xarea[((pk >> 27) << 4) + (code >> 4)];
         };
         auto accumulate = [&](A prod, int ti, uint32_t code, uint32_t pk, bool valid) {
-            A *dst = &acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + (code & 15)];
-            if (DPPRED)
+            AC *dst = &acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + (code & 15)];
+            if constexpr (DPPRED)
                 segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
                                   dst);
             else if (valid)
-                lds_add(dst, prod);
+                lds_add(dst, (AC)prod);
         };
         int j = 0;
         int e0 = 0;
@@ -528,11 +532,11 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
             for (int jj = 0; jj < 4; ++jj)
                 if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
             sum = quad_sum(sum);
-            if (q4 == 0) lds_add(&acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + r4], sum);
+            if (q4 == 0) lds_add(&acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + r4], (AC)sum);
         }
     };
 
-    if (lane < kMaxPanels * 16) acc[lane] = A(0);
+    if (lane < kMaxPanels * 16) acc[lane] = AC(0);
     // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
     // columns; batch 2's records.  At the top of step b the registers hold P and XG of batch b,
     // RG of batch b+1 and Q of batch b+2; LDS holds the records of batches b and b+1.
@@ -892,15 +896,25 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     if (e != hipSuccess) return e;
     if (d.nwaves <= 0) return hipSuccess;
     const int nb = (d.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
-    // FP32 LDS atomics with colliding lanes are slow on gfx950; FP64 ones are not
-    constexpr bool kDpp = VT != 0 || CB_TUNE_F64_DPP;
-    if (d.natural_order && d.col_agg)
-        hipLaunchKernelGGL((spmv_stream_kernel<VT, true, kDpp>), dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha,
-                           (A)beta, (const A *)x, (A *)y);
-    else if (d.natural_order)
-        hipLaunchKernelGGL((spmv_stream_kernel<VT, false, kDpp>), dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha,
-                           (A)beta, (const A *)x, (A *)y);
-    else
+    // row sums: FP32 LDS atomics are slow where many lanes of a pass hit one row (long runs),
+    // the segmented scan costs the same whatever the runs; the handle holds the choice
+    const A a = (A)alpha, b = (A)beta;
+    if (d.natural_order) {
+        // FP64 values: modes 0 and 2 are the same kernel
+        const int rr = VT == 0 && d.row_reduce == 2 ? 0 : d.row_reduce;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
+        };
+        if (d.col_agg) {
+            if (rr == 1) go(spmv_stream_kernel<VT, true, 1>);
+            else if (rr == 2 && VT != 0) go(spmv_stream_kernel<VT, true, VT != 0 ? 2 : 0>);
+            else go(spmv_stream_kernel<VT, true, 0>);
+        } else {
+            if (rr == 1) go(spmv_stream_kernel<VT, false, 1>);
+            else if (rr == 2 && VT != 0) go(spmv_stream_kernel<VT, false, VT != 0 ? 2 : 0>);
+            else go(spmv_stream_kernel<VT, false, 0>);
+        }
+    } else
         hipLaunchKernelGGL(spmv_kernel<VT>, dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha, (A)beta,
                            (const A *)x, (A *)y);
     return hipGetLastError();

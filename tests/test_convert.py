@@ -283,7 +283,7 @@ def test_malformed_csr_is_rejected(case):
 def test_bad_options_are_rejected():
     A = matgen.identity(20)
     for k, v in [("value_type", 3), ("col_agg", 2), ("th1", -1), ("quantum_tiles", 0), ("lb_mode", 7),
-                 ("wave_nnz", -5), ("th0", float("nan"))]:
+                 ("wave_nnz", -5), ("th0", float("nan")), ("row_reduce", 3), ("row_reduce", -2)]:
         o = cb.cb_options_default()
         setattr(o, k, v)
         st, _ = _status(cb.cb_create_host, 20, 20, 20, A.row_ptr, A.col_idx, A.values, o)
@@ -291,6 +291,25 @@ def test_bad_options_are_rejected():
     o = cb.cb_options_default()
     o.struct_size = 12
     assert _status(cb.cb_create_host, 20, 20, 20, A.row_ptr, A.col_idx, A.values, o)[0] == cb.CB_ERROR_INVALID_VALUE
+
+
+def test_row_reduce_resolution_and_run_statistic():
+    # 2 x 2 block diagonal pattern: one 16 x 16 tile, rows 0-15 with 2 entries each in one run
+    n = 16
+    rows = np.repeat(np.arange(n), 2)
+    cols = np.stack([np.arange(n), (np.arange(n) + 1) % n], 1)
+    cols.sort(axis=1)
+    A = matgen.Csr(n, n, np.arange(0, 2 * n + 1, 2, dtype=np.int64), cols.ravel().astype(np.int32),
+                   np.ones(2 * n))
+    assert rows.size == A.nnz
+    for vt, want in (("f64", 0), ("f32", 2), ("bf16", 2)):
+        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, th1=64, th2=256)
+        assert M.info["row_reduce"] == want and M.info["flat_run_mean"] == 2.0
+        M.close()
+    for rr in (0, 1, 2):
+        M = cb.CbMatrix.from_csr(A, device=False, row_reduce=rr)
+        assert M.info["row_reduce"] == rr
+        M.close()
 
 
 def test_host_handle_cannot_multiply():

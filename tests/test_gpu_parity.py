@@ -111,6 +111,30 @@ def test_spmv_low_precision(cb, name, vtype):
         check(cb, A, x, vtype=vtype, label=name, col_agg=agg, th1=16, th2=64)
 
 
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("rr", [0, 1, 2])
+@pytest.mark.parametrize("name", ["block8", "power", "lap64", "dense_mix", "rect"])
+def test_row_reduce_modes(cb, name, rr, vtype):
+    """Every way the streaming kernel sums rows (LDS atomics, DPP segmented scan, FP64 atomics),
+    with and without column aggregation, and with several work ranges sharing panels."""
+    A = SMALL[name]()
+    x = matgen.vector(A.n, 12)
+    y0 = matgen.vector(A.m, 3, stream=matgen.STREAM_Y0)
+    for agg in (0, 1):
+        check(cb, A, x, vtype=vtype, label=f"{name} rr={rr}", col_agg=agg, row_reduce=rr, th1=16, th2=64)
+    check(cb, A, x, 1.5, -0.5, y0, vtype, label=f"{name} rr={rr} shared", row_reduce=rr, wave_nnz=64)
+
+
+def test_row_reduce_exact_bitwise(cb):
+    rng = np.random.default_rng(21)
+    B = SMALL["block8"]()
+    A = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx, rng.integers(-64, 65, B.nnz).astype(np.float64) / 64)
+    x = rng.integers(-64, 65, A.n).astype(np.float64) / 64
+    ref = oracle.spmv(A, x)
+    for rr in (0, 1, 2):
+        assert np.array_equal(run_spmv(cb, A, x, row_reduce=rr), ref)
+
+
 @pytest.mark.parametrize("vtype", ["f64", "f32"])
 def test_alpha_beta(cb, vtype):
     A = SMALL["power"]()
