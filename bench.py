@@ -125,8 +125,9 @@ def time_calls(fn, steps: int, warmup: int):
 
 def run_cg(args, cb, matgen) -> int:
     """Solves of A x = b from x = 0 on the 192^3 Poisson operator (b ~ U[-1, 1]) until the FP64
-    residual |b - A x| / |b| is at most 1e-10: FP64 CG, and FP64 refinement around CG on the
-    FP32 and on the BF16 copy of A.  Each solve is timed whole (host polling included)."""
+    residual |b - A x| / |b| is at most 1e-10: FP64 CG, and the two mixed-precision solvers
+    (residual replacement and restarted refinement) with the products on the FP32 and on the BF16
+    copy of A.  Each solve is timed whole (host polling included)."""
     import numpy as np
     import torch
 
@@ -137,13 +138,18 @@ def run_cg(args, cb, matgen) -> int:
     M = cb.CbMatrix.from_csr(A, value_type="f64")
     legs = {}
     xs = {}
-    for name in ("fp64_cg", "refine_f32", "refine_bf16"):
-        L = None if name == "fp64_cg" else cb.CbMatrix.from_csr(A, value_type=name.split("_")[1])
+    # <method>_<storage>[w]: w = double vectors on the low-precision copy
+    for name in ("fp64_cg", "replace_f32", "replace_bf16", "replace_f32w", "replace_bf16w", "restart_f32",
+                 "restart_bf16", "restart_f32w"):
+        vt = name.split("_")[-1]
+        L = None if name == "fp64_cg" else cb.CbMatrix.from_csr(A, value_type=vt.rstrip("w"),
+                                                                 vector_f64=int(vt.endswith("w")))
+        meth = cb.CB_REFINE_RESTART if name.startswith("restart") else cb.CB_REFINE_REPLACE
         xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
         work = torch.empty(cb.cb_cg_workspace_bytes(M.handle, L.handle if L else None), dtype=torch.uint8,
                            device="cuda")
         solve = (lambda: M.cg(bd, xd, work, rtol=rtol)) if L is None else \
-            (lambda: M.cg_refine(L, bd, xd, work, rtol=rtol))
+            (lambda: M.cg_refine(L, bd, xd, work, rtol=rtol, refine_method=meth))
         times = []
         for rep in range(1 + max(1, min(args.steps, 5))):
             xd.zero_()
@@ -155,7 +161,8 @@ def run_cg(args, cb, matgen) -> int:
                 times.append(time.perf_counter() - t0)
         sec = float(np.median(times))
         legs[name] = {"solves_per_s": 1.0 / sec, "seconds": sec, "iterations": res["iterations"],
-                      "refinements": res["refinements"], "rel_residual_device": res["rel_residual"],
+                      "refinements": res["refinements"], "restarts": res["restarts"],
+                      "rel_residual_device": res["rel_residual"],
                       "converged": res["converged"]}
         xs[name] = xd.cpu().numpy()
         log(f"{name}: {json.dumps(legs[name])}")
@@ -208,7 +215,7 @@ def main() -> int:
                     help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
     ap.add_argument("--cg", action="store_true",
                     help="instead of the SpMV line: CG solves/s on the 192^3 Poisson operator to a true FP64 "
-                         "residual of 1e-10, FP64 CG against FP64 refinement around FP32 and BF16 CG")
+                         "residual of 1e-10, FP64 CG against the mixed-precision solvers on FP32 and BF16 copies")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()

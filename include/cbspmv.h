@@ -60,7 +60,8 @@ typedef enum {
  * values rounded to nearest-even straight from the FP64 input at creation,
  * x and y are float, products in FP32, row sums in FP32 (at least: the
  * streaming SpMV kernel keeps them in FP64 by default, see row_reduce),
- * alpha and beta applied in FP32. */
+ * alpha and beta applied in FP32 -- or, with the vector_f64 option, x and y
+ * double and all arithmetic in FP64 on the widened stored values. */
 typedef enum { CB_VALUE_F64 = 0, CB_VALUE_F32 = 1, CB_VALUE_BF16 = 2 } cb_value_t;
 
 /* Tile formats (Section 3.3.2). */
@@ -98,7 +99,9 @@ typedef struct {
                                kept in FP64 until written; same as 0 for FP64); -1 (default) =
                                automatic: 0 for FP64 values, 2 for FP32/BF16.  Results agree
                                within the storage precision's tolerance either way. */
-    int32_t reserved32;
+    int32_t vector_f64;     /* FP32/BF16 storage only: 1 = x and y are double and the products,
+                               sums, alpha and beta are FP64 (the stored values widened exactly);
+                               0 (default) = x and y are float.  FP64 storage: always double. */
     int64_t reserved[5];
 } cb_options_t;
 
@@ -138,7 +141,7 @@ typedef struct {
     int64_t stream_bytes;   /* its batch records: 16 bytes per batch and per tile */
     double flat_run_mean;   /* COO/CSR entries per (tile, row) run: the lanes one scan step merges */
     int32_t row_reduce;     /* the resolved row_reduce option (0, 1 or 2) */
-    int32_t reserved1;
+    int32_t vector_f64;     /* 1 when x and y are double (FP64 storage, or vector_f64 set) */
     int64_t reserved[4];
 } cb_info_t;
 
@@ -239,26 +242,42 @@ cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *strea
 /* ---- Conjugate gradient (NEXT to the product: A symmetric positive definite) ----
  *
  * Solvers built on cb_spmv.  Each iteration runs on the device (the product, dot
- * products accumulated in FP64 as two-stage reductions, and the step lengths read
- * by the update kernels from device scalars); the host reads the residual norm
- * every check_every iterations, so the calls synchronise `stream` and must not
- * be captured in a graph.  The caller supplies the device workspace (size from
- * cb_cg_workspace_bytes); the solvers allocate nothing. */
+ * products accumulated in FP64 and reduced in a fixed order, and the step lengths
+ * read by the update kernels from device scalars); the host reads the residual
+ * norm every check_every iterations, so the calls synchronise `stream` and must
+ * not be captured in a graph.  The caller supplies the device workspace (size
+ * from cb_cg_workspace_bytes); the solvers allocate nothing. */
+
+/* How cb_cg_refine wins back FP64 accuracy from products on the low-precision copy.
+ *   CB_REFINE_REPLACE: one CG whose products q = A_low p run in FP32 on the FP32/BF16
+ *     copy while x, r, the dot products and the step lengths stay in FP64; whenever the
+ *     recurrence residual has fallen by replace_factor since the last replacement, r is
+ *     replaced by the true residual b - A x computed with the FP64 matrix (residual
+ *     replacement, van der Vorst and Ye 2000), and only a true residual ends the solve.
+ *   CB_REFINE_RESTART: classic iterative refinement: r = b - A x in FP64, an FP32 CG
+ *     on A_low d = r / |r| to inner_rtol from d = 0, x += |r| d, repeated. */
+typedef enum { CB_REFINE_RESTART = 0, CB_REFINE_REPLACE = 1 } cb_refine_t;
+
 typedef struct {
     uint32_t struct_size;   /* sizeof(cb_cg_options_t) */
     int32_t max_iter;       /* iterations of one CG solve (of each inner solve when refining); 10000 */
     double rtol;            /* stop when |b - A x|_2 <= rtol |b|_2; 1e-10 */
     int32_t check_every;    /* iterations between host reads of the residual norm; 16 */
     int32_t max_refine;     /* outer steps of cb_cg_refine; 50 */
-    double inner_rtol;      /* residual reduction each inner solve of cb_cg_refine aims at; 1e-4 */
-    int64_t reserved[4];
+    double inner_rtol;      /* CB_REFINE_RESTART: residual reduction each inner solve aims at; 1e-4 */
+    int32_t refine_method;  /* cb_refine_t; CB_REFINE_REPLACE */
+    int32_t reserved32;
+    double replace_factor;  /* CB_REFINE_REPLACE: recurrence reduction between residual
+                               replacements, in (0, 1); 1e-2 */
+    int64_t reserved[2];
 } cb_cg_options_t;
 
 typedef struct {
     int32_t converged;      /* 1 when the stopping test was met */
     int32_t iterations;     /* CG iterations (all inner solves for cb_cg_refine) */
-    int32_t refinements;    /* outer steps of cb_cg_refine (0 for cb_cg) */
-    int32_t reserved0;
+    int32_t refinements;    /* cb_cg_refine: residual replacements (CB_REFINE_REPLACE) or outer
+                               steps (CB_REFINE_RESTART); 0 for cb_cg */
+    int32_t restarts;       /* CB_REFINE_REPLACE: replacements that also restarted the direction */
     double rel_residual;    /* |b - A x|_2 / |b|_2 of the returned x, computed in FP64 from the true residual
                                (FP64 handles); the CG recurrence's value for FP32/BF16 handles in cb_cg */
     int64_t reserved[2];
@@ -270,7 +289,7 @@ cb_status_t cb_cg_options_default(cb_cg_options_t *opt);
 cb_status_t cb_cg_workspace_bytes(cb_matrix_t A, cb_matrix_t A_low, int64_t *bytes);
 
 /* Conjugate gradient on A x = b (Hestenes and Stiefel) starting from the caller's x.  b and x are n
- * device elements of A's vector type (double for CB_VALUE_F64, float otherwise); x is overwritten
+ * device elements of A's vector type (double with FP64 storage or vector_f64, else float); x is overwritten
  * with the solution.  work: device buffer of at least cb_cg_workspace_bytes(A, NULL) bytes (its
  * contents are scratch).  A must be square; a non-positive-definite search direction stops the
  * iteration with converged = 0.  opt may be NULL (defaults).  Errors: CB_ERROR_INVALID_VALUE (NULL
@@ -279,12 +298,14 @@ cb_status_t cb_cg_workspace_bytes(cb_matrix_t A, cb_matrix_t A_low, int64_t *byt
 cb_status_t cb_cg(cb_matrix_t A, const void *b, void *x, void *work, int64_t work_bytes, const cb_cg_options_t *opt,
                   cb_cg_result_t *res, void *stream);
 
-/* Mixed-precision iterative refinement: with A stored in FP64 and A_low the same matrix stored in
- * FP32 or BF16, repeat r = b - A x (FP64), solve A_low d = r / |r| by CG in FP32 to a relative
- * residual of inner_rtol, x += |r| d, until |b - A x| <= rtol |b| (true FP64 residual) or the
- * residual stops decreasing.  b and x are double device vectors; work as for cb_cg with both
- * handles.  Errors as for cb_cg, plus CB_ERROR_INVALID_VALUE when the handles' precisions or
- * sizes do not fit. */
+/* Mixed-precision solve of A x = b to an FP64 accuracy: A stored in FP64, A_low the same matrix
+ * stored in FP32 or BF16 (float or, with vector_f64, double vectors), the products on A_low and
+ * the accuracy won back with FP64 residuals as
+ * refine_method says (see cb_refine_t), until |b - A x| <= rtol |b| for the true FP64 residual, or
+ * until the true residual stops decreasing (converged = 0).  b and x are double device vectors, x
+ * the start and the solution; work: device buffer of at least cb_cg_workspace_bytes(A, A_low)
+ * bytes.  Errors as for cb_cg, plus CB_ERROR_INVALID_VALUE when the handles' precisions or sizes
+ * do not fit. */
 cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, double *x, void *work, int64_t work_bytes,
                          const cb_cg_options_t *opt, cb_cg_result_t *res, void *stream);
 

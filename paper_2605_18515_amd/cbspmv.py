@@ -30,6 +30,7 @@ CB_SUCCESS, CB_ERROR_INVALID_VALUE, CB_ERROR_OUT_OF_MEMORY, CB_ERROR_HIP, CB_ERR
 CB_VALUE_F64, CB_VALUE_F32, CB_VALUE_BF16 = range(3)
 CB_FMT_COO, CB_FMT_CSR, CB_FMT_DENSE = range(3)
 CB_LB_NONE, CB_LB_PAPER, CB_LB_CONTIGUOUS = range(3)
+CB_REFINE_RESTART, CB_REFINE_REPLACE = range(2)
 VALUE_TYPES = {"f64": CB_VALUE_F64, "f32": CB_VALUE_F32, "bf16": CB_VALUE_BF16}
 LB_MODES = {"none": CB_LB_NONE, "paper": CB_LB_PAPER, "contiguous": CB_LB_CONTIGUOUS}
 
@@ -39,7 +40,7 @@ _i32, _i64, _u32, _dbl, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ct
 class CbOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
                 ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
-                ("wave_nnz", _i64), ("row_reduce", _i32), ("reserved32", _i32), ("reserved", _i64 * 5)]
+                ("wave_nnz", _i64), ("row_reduce", _i32), ("vector_f64", _i32), ("reserved", _i64 * 5)]
 
 
 class CbInfo(ctypes.Structure):
@@ -52,7 +53,7 @@ class CbInfo(ctypes.Structure):
                 ("quantum_nnz_std", _dbl), ("wave_nnz_max", _i64), ("wave_nnz_mean", _dbl), ("wave_nnz_std", _dbl),
                 ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
                 ("reserved0", _i32), ("nbatches", _i64), ("stream_bytes", _i64), ("flat_run_mean", _dbl),
-                ("row_reduce", _i32), ("reserved1", _i32), ("reserved", _i64 * 4)]
+                ("row_reduce", _i32), ("vector_f64", _i32), ("reserved", _i64 * 4)]
 
 
 class CbStructure(ctypes.Structure):
@@ -63,11 +64,12 @@ class CbStructure(ctypes.Structure):
 
 class CbCgOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("max_iter", _i32), ("rtol", _dbl), ("check_every", _i32),
-                ("max_refine", _i32), ("inner_rtol", _dbl), ("reserved", _i64 * 4)]
+                ("max_refine", _i32), ("inner_rtol", _dbl), ("refine_method", _i32), ("reserved32", _i32),
+                ("replace_factor", _dbl), ("reserved", _i64 * 2)]
 
 
 class CbCgResult(ctypes.Structure):
-    _fields_ = [("converged", _i32), ("iterations", _i32), ("refinements", _i32), ("reserved0", _i32),
+    _fields_ = [("converged", _i32), ("iterations", _i32), ("refinements", _i32), ("restarts", _i32),
                 ("rel_residual", _dbl), ("reserved", _i64 * 2)]
 
 
@@ -215,7 +217,7 @@ def cb_cg_workspace_bytes(A: int, A_low: int | None = None) -> int:
 
 def _cg_result(r: CbCgResult) -> dict:
     return {"converged": bool(r.converged), "iterations": r.iterations, "refinements": r.refinements,
-            "rel_residual": r.rel_residual}
+            "restarts": r.restarts, "rel_residual": r.rel_residual}
 
 
 def cb_cg(A: int, b, x, work, work_bytes: int, opt: CbCgOptions | None = None, stream=None) -> dict:
@@ -305,7 +307,7 @@ class CbMatrix:
 
     @property
     def vector_dtype(self) -> str:
-        return "torch.float64" if self.vtype == CB_VALUE_F64 else "torch.float32"
+        return "torch.float64" if self.info["vector_f64"] else "torch.float32"
 
     def spmv(self, x, y, alpha: float = 1.0, beta: float = 0.0, stream=None):
         inf = self.info

@@ -87,6 +87,9 @@ struct cb_matrix_s {
 
 namespace {
 
+// kernel value code: storage precision, plus 2 for FP32/BF16 values with double vectors
+int kernel_vtype(const cbh::HostStructure &h) { return h.vtype != CB_VALUE_F64 && h.vector_f64 ? h.vtype + 2 : h.vtype; }
+
 cb_status_t check_options(const cb_options_t *opt, cb_options_t &o) {
     cb_options_default(&o);
     if (!opt) return CB_SUCCESS;
@@ -329,7 +332,7 @@ cb_status_t cb_spmv(cb_matrix_t A, double alpha, const void *x, double beta, voi
     if (A->h.m > 0 && !y) return fail(CB_ERROR_INVALID_VALUE, "y is NULL");
     if (A->h.nnz > 0 && !x) return fail(CB_ERROR_INVALID_VALUE, "x is NULL");
     if (A->h.m == 0) return CB_SUCCESS;
-    hipError_t e = cbd::launch_spmv(A->view, A->h.vtype, alpha, x, beta, y, (hipStream_t)stream);
+    hipError_t e = cbd::launch_spmv(A->view, kernel_vtype(A->h), alpha, x, beta, y, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "cb_spmv launch");
     return CB_SUCCESS;
 }
@@ -344,7 +347,7 @@ cb_status_t cb_spmm(cb_matrix_t A, int32_t k, double alpha, const void *X, int64
     if (A->h.nnz > 0 && !X) return fail(CB_ERROR_INVALID_VALUE, "X is NULL");
     if (A->h.m == 0) return CB_SUCCESS;
     if (k == 1 && ldx == 1 && ldy == 1) return cb_spmv(A, alpha, X, beta, Y, stream);
-    hipError_t e = cbd::launch_spmm(A->view, A->h.vtype, k, alpha, X, ldx, beta, Y, ldy, (hipStream_t)stream);
+    hipError_t e = cbd::launch_spmm(A->view, kernel_vtype(A->h), k, alpha, X, ldx, beta, Y, ldy, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "cb_spmm launch");
     return CB_SUCCESS;
 }

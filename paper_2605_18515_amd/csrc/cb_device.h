@@ -32,7 +32,8 @@ struct DevView {
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan
 };
 
-// vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float)
+// vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float);
+// 3 = FP32 values, 4 = BF16 values with x, y double and FP64 arithmetic
 hipError_t launch_spmv(const DevView &d, int vtype, double alpha, const void *x, double beta, void *y,
                        hipStream_t stream);
 hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const void *X, int64_t ldx, double beta,

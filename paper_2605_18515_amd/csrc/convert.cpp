@@ -320,6 +320,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.lb_mode < 0 || opt.lb_mode > 2) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.row_reduce < -1 || opt.row_reduce > 2) { err = "row_reduce must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
     const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
 
@@ -359,6 +360,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     s.n = n;
     s.nnz = nnz;
     s.vtype = opt.value_type;
+    s.vector_f64 = opt.value_type == CB_VALUE_F64 || opt.vector_f64 ? 1 : 0;
     s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
     s.lb_mode = opt.lb_mode;
     s.quantum_tiles = opt.quantum_tiles;
@@ -433,7 +435,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // segmented scan on every workload tried, FP32 LDS atomics lose to it on every one, so
         // FP32/BF16 products are summed with FP64 atomics too
         if (opt.row_reduce >= 0) s.row_reduce = opt.row_reduce;
-        else s.row_reduce = s.vtype == CB_VALUE_F64 ? 0 : 2;
+        else s.row_reduce = s.vector_f64 ? 0 : 2;
         if (NT >= kLim || col_base[P] >= kLim) { err = "structure too large"; return CB_ERROR_NOT_SUPPORTED; }
 
         // natural-order arrays and the packed payload (Section 3.2)
@@ -736,7 +738,7 @@ cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_id
 }
 
 int64_t spmv_bytes(const HostStructure &s) {
-    const int64_t xe = s.vtype == CB_VALUE_F64 ? 8 : 4;
+    const int64_t xe = s.vector_f64 ? 8 : 4;
     int64_t b = s.payload_bytes + xe * s.n + xe * s.m;  // payload, x read once, y written once
     if (s.lb_mode == CB_LB_PAPER) {
         // tile-at-a-time kernel: high-level arrays (4+4+4+8+1 per tile), restore_cols through
@@ -789,6 +791,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.convert_seconds = s.convert_seconds;
     info.flat_run_mean = s.flat_runs ? (double)s.flat_entries / (double)s.flat_runs : 0.0;
     info.row_reduce = s.row_reduce;
+    info.vector_f64 = s.vector_f64;
 }
 
 }  // namespace cbh

@@ -97,6 +97,29 @@ struct Val<2> {
         for (int j = 0; j < 4; ++j) v[j] = load(p, i + j);
     }
 };
+// FP32 / BF16 values with double vectors: the stored value widened exactly, FP64 arithmetic
+template <>
+struct Val<3> {
+    using A = double;
+    static constexpr int kSize = 4;
+    __device__ static A load(const uint8_t *p, int i) { return (double)Val<1>::load(p, i); }
+    __device__ static void load4(const uint8_t *p, int i, A *v) {
+        float f[4];
+        Val<1>::load4(p, i, f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (double)f[j];
+    }
+};
+template <>
+struct Val<4> {
+    using A = double;
+    static constexpr int kSize = 2;
+    __device__ static A load(const uint8_t *p, int i) { return (double)Val<2>::load(p, i); }
+    __device__ static void load4(const uint8_t *p, int i, A *v) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = load(p, i + j);
+    }
+};
 
 // Algorithm 3's padding between the one-byte indices and the values
 __device__ __forceinline__ int pad_bytes(int index_bytes, int vsize) {
@@ -900,18 +923,20 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     // the segmented scan costs the same whatever the runs; the handle holds the choice
     const A a = (A)alpha, b = (A)beta;
     if (d.natural_order) {
-        // FP64 values: modes 0 and 2 are the same kernel
-        const int rr = VT == 0 && d.row_reduce == 2 ? 0 : d.row_reduce;
+        // double accumulators already: modes 0 and 2 are the same kernel
+        constexpr bool kWide = std::is_same<A, double>::value;
+        constexpr int kRR2 = kWide ? 0 : 2;
+        const int rr = kWide && d.row_reduce == 2 ? 0 : d.row_reduce;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
         };
         if (d.col_agg) {
             if (rr == 1) go(spmv_stream_kernel<VT, true, 1>);
-            else if (rr == 2 && VT != 0) go(spmv_stream_kernel<VT, true, VT != 0 ? 2 : 0>);
+            else if (rr == 2) go(spmv_stream_kernel<VT, true, kRR2>);
             else go(spmv_stream_kernel<VT, true, 0>);
         } else {
             if (rr == 1) go(spmv_stream_kernel<VT, false, 1>);
-            else if (rr == 2 && VT != 0) go(spmv_stream_kernel<VT, false, VT != 0 ? 2 : 0>);
+            else if (rr == 2) go(spmv_stream_kernel<VT, false, kRR2>);
             else go(spmv_stream_kernel<VT, false, 0>);
         }
     } else
@@ -1185,7 +1210,8 @@ hipError_t spmm_mfma(const DevView &d, int k, double alpha, const void *X, int64
     if (d.nwaves <= 0) return hipSuccess;
     const int nb = (d.nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
     const int ny = (k + KC - 1) / KC;
-    constexpr int NS = VT == 0 && CB_TUNE_SPMM_STAGES > 2 ? CB_TUNE_SPMM_STAGES - 1 : CB_TUNE_SPMM_STAGES;  // FP64 stages are twice the registers
+    constexpr bool kWide = std::is_same<A, double>::value;
+    constexpr int NS = kWide && CB_TUNE_SPMM_STAGES > 2 ? CB_TUNE_SPMM_STAGES - 1 : CB_TUNE_SPMM_STAGES;  // FP64 stages are twice the registers
     hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d, (A)alpha,
                        (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
     return hipGetLastError();
@@ -1216,6 +1242,8 @@ hipError_t launch_spmv(const DevView &d, int vtype, double alpha, const void *x,
         case 0: return spmv_vt<0>(d, alpha, x, beta, y, stream);
         case 1: return spmv_vt<1>(d, alpha, x, beta, y, stream);
         case 2: return spmv_vt<2>(d, alpha, x, beta, y, stream);
+        case 3: return spmv_vt<3>(d, alpha, x, beta, y, stream);
+        case 4: return spmv_vt<4>(d, alpha, x, beta, y, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1226,6 +1254,8 @@ hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const v
         case 0: return spmm_vt<0>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
         case 1: return spmm_vt<1>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
         case 2: return spmm_vt<2>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
+        case 3: return spmm_vt<3>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
+        case 4: return spmm_vt<4>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
         default: return hipErrorInvalidValue;
     }
 }

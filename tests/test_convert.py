@@ -283,7 +283,8 @@ def test_malformed_csr_is_rejected(case):
 def test_bad_options_are_rejected():
     A = matgen.identity(20)
     for k, v in [("value_type", 3), ("col_agg", 2), ("th1", -1), ("quantum_tiles", 0), ("lb_mode", 7),
-                 ("wave_nnz", -5), ("th0", float("nan")), ("row_reduce", 3), ("row_reduce", -2)]:
+                 ("wave_nnz", -5), ("th0", float("nan")), ("row_reduce", 3), ("row_reduce", -2),
+                 ("vector_f64", 2), ("vector_f64", -1)]:
         o = cb.cb_options_default()
         setattr(o, k, v)
         st, _ = _status(cb.cb_create_host, 20, 20, 20, A.row_ptr, A.col_idx, A.values, o)
@@ -309,6 +310,12 @@ def test_row_reduce_resolution_and_run_statistic():
     for rr in (0, 1, 2):
         M = cb.CbMatrix.from_csr(A, device=False, row_reduce=rr)
         assert M.info["row_reduce"] == rr
+        M.close()
+    # double vectors: always with FP64 storage, on request with FP32/BF16 (then FP64 atomics suffice)
+    for vt, wide, want in (("f64", 0, 1), ("f32", 0, 0), ("f32", 1, 1), ("bf16", 1, 1)):
+        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, vector_f64=wide)
+        assert M.info["vector_f64"] == want
+        assert M.info["row_reduce"] == (0 if want else 2)
         M.close()
 
 

@@ -26,7 +26,7 @@ def cb():
 
 
 def run_spmv(cb, A, x, alpha=1.0, beta=0.0, y0=None, vtype="f64", **opts):
-    dt = torch.float64 if vtype == "f64" else torch.float32
+    dt = torch.float64 if vtype == "f64" or opts.get("vector_f64") else torch.float32
     M = cb.CbMatrix.from_csr(A, value_type=vtype, **opts)
     xd = torch.from_numpy(np.asarray(x, dtype=np.float64)).to("cuda", dt)
     if y0 is None:
@@ -125,6 +125,61 @@ def test_row_reduce_modes(cb, name, rr, vtype):
     check(cb, A, x, 1.5, -0.5, y0, vtype, label=f"{name} rr={rr} shared", row_reduce=rr, wave_nnz=64)
 
 
+def rounded(A, vtype):
+    return matgen.Csr(A.m, A.n, A.row_ptr, A.col_idx, lowp(A.values, vtype))
+
+
+@pytest.mark.parametrize("vtype", ["f32", "bf16"])
+@pytest.mark.parametrize("rr", [0, 1, 2])
+@pytest.mark.parametrize("name", ["block8", "power", "lap64", "dense_mix", "rect"])
+def test_wide_vectors(cb, name, rr, vtype):
+    """FP32/BF16 storage with double x and y: FP64 arithmetic on the widened stored values, so the
+    result is the FP64 oracle's on the rounded values to 1e-12, and the FP64 matrix's to the
+    storage precision's tolerance."""
+    A = SMALL[name]()
+    Ar = rounded(A, vtype)
+    x = matgen.vector(A.n, 13)
+    y0 = matgen.vector(A.m, 4, stream=matgen.STREAM_Y0)
+    for lb, agg in (("contiguous", 0), ("contiguous", 1), ("paper", -1)):
+        for al, be, yy in ((1.0, 0.0, None), (1.5, -0.5, y0)):
+            y = run_spmv(cb, A, x, al, be, yy, vtype, vector_f64=1, lb_mode=lb, col_agg=agg, row_reduce=rr,
+                         th1=16, th2=64)
+            e, viol, w = oracle.scaled_error(y, oracle.spmv(Ar, x, al, be, yy, comp=True),
+                                             oracle.scale(Ar, x, al, be, yy), 1e-12)
+            print(f"[{name} {vtype} wide rr={rr} {lb} agg={agg}] max scaled error vs rounded values {e:.3e}")
+            assert viol == 0, (lb, agg, e, w)
+            e2, v2, _ = oracle.scaled_error(y, oracle.spmv(A, x, al, be, yy, comp=True),
+                                            oracle.scale(A, x, al, be, yy), TOL[vtype])
+            assert v2 == 0, (lb, agg, e2)
+
+
+@pytest.mark.parametrize("k", [1, 8, 17, 32])
+@pytest.mark.parametrize("vtype", ["f32", "bf16"])
+def test_wide_vectors_spmm(cb, k, vtype):
+    A = SMALL["dense_mix"]() if k % 2 else SMALL["block8"]()
+    Ar = rounded(A, vtype)
+    X = matgen.rhs(A.n, k, k + 3)
+    Y0 = matgen.rhs(A.m, k, k + 60)
+    for lb, agg in (("contiguous", -1), ("paper", 0), ("contiguous", 1)):
+        Y = run_spmm(cb, A, X, 1.5, -0.5, Y0, vtype, ld_pad=2, vector_f64=1, lb_mode=lb, col_agg=agg, th1=8, th2=40)
+        e, viol, _ = oracle.scaled_error(Y, oracle.spmm(Ar, X, 1.5, -0.5, Y0, comp=True),
+                                         oracle.spmm_scale(Ar, X, 1.5, -0.5, Y0), 1e-12)
+        print(f"spmm wide k={k} {vtype} {lb} agg={agg} max scaled error {e:.3e}")
+        assert viol == 0, (k, vtype, lb, e)
+
+
+def test_wide_vectors_exact_bitwise(cb):
+    # values and x with at most 7 significant bits: exact in BF16, every product and sum exact in FP64
+    rng = np.random.default_rng(23)
+    B = SMALL["power"]()
+    A = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx, rng.integers(-64, 65, B.nnz).astype(np.float64) / 64)
+    x = rng.integers(-64, 65, A.n).astype(np.float64) / 64
+    ref = oracle.spmv(A, x)
+    for vt in ("f32", "bf16"):
+        for rr in (0, 1, 2):
+            assert np.array_equal(run_spmv(cb, A, x, vtype=vt, vector_f64=1, row_reduce=rr), ref), (vt, rr)
+
+
 def test_row_reduce_exact_bitwise(cb):
     rng = np.random.default_rng(21)
     B = SMALL["block8"]()
@@ -202,7 +257,7 @@ def test_nonfinite_x_and_values(cb):
 
 
 def run_spmm(cb, A, X, alpha, beta, Y0, vtype="f64", ld_pad=0, **opts):
-    dt = torch.float64 if vtype == "f64" else torch.float32
+    dt = torch.float64 if vtype == "f64" or opts.get("vector_f64") else torch.float32
     k = X.shape[1]
     M = cb.CbMatrix.from_csr(A, value_type=vtype, **opts)
     Xd = torch.zeros((A.n, k + ld_pad), dtype=dt, device="cuda")

@@ -89,15 +89,17 @@ def test_cg_f32_storage(cb):
     assert true <= 1e-4
 
 
-@pytest.mark.parametrize("low", ["f32", "bf16"])
-def test_cg_refine_reaches_fp64_accuracy(cb, low):
+@pytest.mark.parametrize("method", ["replace", "restart"])
+@pytest.mark.parametrize("low", ["f32", "bf16", "f32-wide", "bf16-wide"])
+def test_cg_refine_reaches_fp64_accuracy(cb, low, method):
     side = 24
     A = scaled_poisson(side)
     b = matgen.vector(A.n, 7)
     M = cb.CbMatrix.from_csr(A, value_type="f64")
-    L = cb.CbMatrix.from_csr(A, value_type=low)
+    L = cb.CbMatrix.from_csr(A, value_type=low.split("-")[0], vector_f64=int(low.endswith("wide")))
     xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-    res = M.cg_refine(L, dev(b), xd, rtol=5e-11)
+    meth = cb.CB_REFINE_REPLACE if method == "replace" else cb.CB_REFINE_RESTART
+    res = M.cg_refine(L, dev(b), xd, rtol=5e-11, refine_method=meth)
     x64 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     res64 = M.cg(dev(b), x64, rtol=5e-11)
     torch.cuda.synchronize()
@@ -105,14 +107,17 @@ def test_cg_refine_reaches_fp64_accuracy(cb, low):
     L.close()
     x = host(xd)
     true = solvers.residual(A, b, x)
-    print(f"[cg refine {low}] outer {res['refinements']} inner iters {res['iterations']} true residual {true:.3e}; "
-          f"fp64 cg iters {res64['iterations']}")
-    assert res["converged"] and res["refinements"] >= 2
+    print(f"[cg refine {low} {method}] refinements {res['refinements']} iterations {res['iterations']} "
+          f"true residual {true:.3e}; fp64 cg iters {res64['iterations']}")
+    assert res["converged"] and res["refinements"] >= (1 if method == "replace" else 2)
     assert true <= 1e-10
     assert abs(res["rel_residual"] - true) <= 1e-3 * true + 1e-15
     xo = host(x64)
     assert res64["converged"] and solvers.residual(A, b, xo) <= 1e-10
-    assert np.linalg.norm(x - xo) <= 2 * (1.25 / 0.8) ** 2 * poisson_cond(side) * 1e-10 * np.linalg.norm(xo)
+    cond = (1.25 / 0.8) ** 2 * poisson_cond(side)
+    assert np.linalg.norm(x - xo) <= 2 * cond * 1e-10 * np.linalg.norm(xo)
+    xr, _, conv_o, _ = solvers.cg(A, b, rtol=5e-11)
+    assert conv_o and np.linalg.norm(x - xr) <= 2 * cond * 1e-10 * np.linalg.norm(xr)
 
 
 def test_cg_breakdown_on_negative_definite(cb):

@@ -88,6 +88,7 @@ def test_cg_options_default(cb):
     o = cb.cb_cg_options_default()
     assert o.struct_size == ctypes.sizeof(cb.CbCgOptions)
     assert (o.max_iter, o.rtol, o.check_every, o.max_refine, o.inner_rtol) == (10000, 1e-10, 16, 50, 1e-4)
+    assert (o.refine_method, o.replace_factor) == (cb.CB_REFINE_REPLACE, 1e-2)
     assert ctypes.sizeof(cb.CbCgResult) == 40 and ctypes.sizeof(cb.CbCgOptions) == 64
     with pytest.raises(ValueError):
         cb.cb_cg_options_default(tolerance=1.0)
@@ -106,7 +107,8 @@ def test_cg_rejects_host_handles_and_bad_arguments(cb):
         with pytest.raises(cb.CbError) as e:
             cb.cb_cg_refine(h, h, 0, 0, 0, 0)
         assert e.value.status == cb.CB_ERROR_NOT_SUPPORTED
-        for bad in ({"max_iter": 0}, {"check_every": 0}, {"rtol": -1.0}, {"inner_rtol": 1.0}, {"max_refine": 0}):
+        for bad in ({"max_iter": 0}, {"check_every": 0}, {"rtol": -1.0}, {"inner_rtol": 1.0}, {"max_refine": 0},
+                    {"replace_factor": 0.0}, {"replace_factor": 1.0}, {"refine_method": 2}):
             with pytest.raises(cb.CbError) as e:
                 cb.cb_cg(h, 0, 0, 0, 0, cb.cb_cg_options_default(**bad))
             assert e.value.status == cb.CB_ERROR_INVALID_VALUE
