@@ -312,6 +312,103 @@ cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, doub
 /* Message for the last non-success status returned on this thread. */
 const char *cb_last_error(void);
 
+/* ---- Serving loop (NEXT to the solvers): many resident matrices, continuous batching ----
+ *
+ * A server keeps registered (resident) handles and serves requests on them from a worker thread
+ * of its own: SpMM requests (Y = alpha A X + beta Y, k right-hand sides) and CG solves.  Requests
+ * are admitted in arrival order as soon as their device footprint fits in the server's memory
+ * arena (allocated once, at creation) and, for a solve, a solve slot is free; requests that
+ * arrive while others run join at the next step.  Active solves advance together: one step runs
+ * the products of every active solve as batched launches (one launch per value type, aggregation
+ * and row-sum mode, covering the work ranges of all their matrices) and the vector updates of all
+ * of them as batched launches; check_every steps are captured once as a HIP graph and replayed
+ * until the set of active solves changes.  SpMM requests run on their own streams beside the
+ * solves.  A solve's arithmetic does not depend on what else is active (fixed per-solve
+ * reductions), so its result alone and in a mix is the same up to the order of the global atomic
+ * adds of shared panels.  Host vectors of a request must stay valid until it completes. */
+typedef struct cb_server_s *cb_server_t;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(cb_server_options_t) */
+    int32_t max_active;     /* solves advanced together (solve slots per vector type); 64 */
+    int64_t arena_bytes;    /* device bytes for request vectors and solve workspaces; 1 GiB */
+    int32_t check_every;    /* solve steps between host reads of the solves' scalars; 8 */
+    int32_t use_graph;      /* 1: replay the captured steps as a HIP graph (default); 0: launch them */
+    int32_t spmm_streams;   /* streams for SpMM requests; 2 */
+    int32_t reserved32;
+    int64_t reserved[4];
+} cb_server_options_t;
+
+typedef enum { CB_REQ_SPMM = 0, CB_REQ_CG = 1 } cb_request_kind_t;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(cb_request_t) */
+    int32_t kind;           /* cb_request_kind_t */
+    int32_t matrix;         /* id from cb_server_add_matrix */
+    int32_t k;              /* SpMM: right-hand sides (>= 1); CG: ignored */
+    double alpha, beta;     /* SpMM */
+    const void *in;         /* host, the matrix's vector type: SpMM X (n x k row-major); CG b (n) */
+    void *out;              /* host: SpMM Y (m x k, read when beta != 0, written); CG x (n: the start,
+                               overwritten with the solution) */
+    double rtol;            /* CG: stop when the recurrence residual is <= rtol |b|; 0 = 1e-10 */
+    int32_t max_iter;       /* CG: iteration cap (rounded up to a multiple of check_every); 0 = 500 */
+    int32_t reserved32;
+    int64_t reserved[4];
+} cb_request_t;
+
+typedef struct {
+    int32_t done;           /* 1 once the request has completed */
+    int32_t status;         /* cb_status_t of the request */
+    int32_t iterations;     /* CG iterations */
+    int32_t converged;      /* CG: 1 when the residual test was met */
+    double rel_residual;    /* CG: recurrence |r| / |b| at the end */
+    double latency_us;      /* submission to completion */
+    double queue_us;        /* submission to admission */
+    int64_t reserved[2];
+} cb_response_t;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t spmm_done, cg_done;
+    double p50_us, p99_us, mean_us;  /* latency over completed requests */
+    double elapsed_s;                /* first submission to last completion */
+    double requests_per_s;           /* completed / elapsed_s */
+    double solves_per_s;             /* completed CG solves / elapsed_s */
+    int64_t arena_peak_bytes;        /* most arena bytes in use at once */
+    int32_t active_peak;             /* most solves active at once */
+    int32_t graph_builds;            /* HIP graphs captured (one per change of the active set) */
+    int64_t steps;                   /* solve steps run */
+    int64_t reserved[4];
+} cb_server_stats_t;
+
+cb_status_t cb_server_options_default(cb_server_options_t *opt);
+
+/* Creates a server on the current device (allocates its arena and tables).  Errors:
+ * CB_ERROR_INVALID_VALUE (bad options), CB_ERROR_OUT_OF_MEMORY, CB_ERROR_HIP. */
+cb_status_t cb_server_create(const cb_server_options_t *opt, cb_server_t *out);
+
+/* Registers a device handle of a natural-order structure (lb_mode contiguous or none) on the
+ * server's device, at any time; *id is its number for requests.  The server does not own the
+ * handle: keep it until cb_server_destroy.  At most 16384 handles per server.  Errors:
+ * CB_ERROR_INVALID_VALUE, CB_ERROR_NOT_SUPPORTED (host-only or paper-order handle, another device,
+ * too many handles). */
+cb_status_t cb_server_add_matrix(cb_server_t S, cb_matrix_t A, int32_t *id);
+
+/* Queues a request; *ticket names it.  CB_ERROR_INVALID_VALUE for a bad request (unknown matrix,
+ * k < 1, NULL vectors, CG on a non-square matrix), CB_ERROR_OUT_OF_MEMORY when its footprint can
+ * never fit the arena (counted as rejected). */
+cb_status_t cb_server_submit(cb_server_t S, const cb_request_t *req, int64_t *ticket);
+
+/* Response of a ticket: done = 0 while it is queued or running (poll), or after blocking until it
+ * completes (wait).  CB_ERROR_INVALID_VALUE for an unknown ticket. */
+cb_status_t cb_server_poll(cb_server_t S, int64_t ticket, cb_response_t *resp);
+cb_status_t cb_server_wait(cb_server_t S, int64_t ticket, cb_response_t *resp);
+
+cb_status_t cb_server_stats(cb_server_t S, cb_server_stats_t *stats);
+
+/* Completes every queued request, stops the worker and frees the server's memory. */
+cb_status_t cb_server_destroy(cb_server_t S);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,39 @@ class CbCgResult(ctypes.Structure):
                 ("rel_residual", _dbl), ("reserved", _i64 * 2)]
 
 
+class CbServerOptions(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("max_active", _i32), ("arena_bytes", _i64), ("check_every", _i32),
+                ("use_graph", _i32), ("spmm_streams", _i32), ("reserved32", _i32), ("reserved", _i64 * 4)]
+
+
+class CbRequest(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("kind", _i32), ("matrix", _i32), ("k", _i32), ("alpha", _dbl),
+                ("beta", _dbl), ("in_", _p), ("out", _p), ("rtol", _dbl), ("max_iter", _i32),
+                ("reserved32", _i32), ("reserved", _i64 * 4)]
+
+
+class CbResponse(ctypes.Structure):
+    _fields_ = [("done", _i32), ("status", _i32), ("iterations", _i32), ("converged", _i32),
+                ("rel_residual", _dbl), ("latency_us", _dbl), ("queue_us", _dbl), ("reserved", _i64 * 2)]
+
+
+class CbServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("spmm_done", _i64),
+                ("cg_done", _i64), ("p50_us", _dbl), ("p99_us", _dbl), ("mean_us", _dbl), ("elapsed_s", _dbl),
+                ("requests_per_s", _dbl), ("solves_per_s", _dbl), ("arena_peak_bytes", _i64),
+                ("active_peak", _i32), ("graph_builds", _i32), ("steps", _i64), ("reserved", _i64 * 4)]
+
+
+CB_REQ_SPMM, CB_REQ_CG = range(2)
+
+_lib.cb_server_options_default.argtypes = [ctypes.POINTER(CbServerOptions)]
+_lib.cb_server_create.argtypes = [ctypes.POINTER(CbServerOptions), ctypes.POINTER(_p)]
+_lib.cb_server_add_matrix.argtypes = [_p, _p, ctypes.POINTER(_i32)]
+_lib.cb_server_submit.argtypes = [_p, ctypes.POINTER(CbRequest), ctypes.POINTER(_i64)]
+_lib.cb_server_poll.argtypes = [_p, _i64, ctypes.POINTER(CbResponse)]
+_lib.cb_server_wait.argtypes = [_p, _i64, ctypes.POINTER(CbResponse)]
+_lib.cb_server_stats.argtypes = [_p, ctypes.POINTER(CbServerStats)]
+_lib.cb_server_destroy.argtypes = [_p]
 _lib.cb_options_default.argtypes = [ctypes.POINTER(CbOptions)]
 _lib.cb_cg_options_default.argtypes = [ctypes.POINTER(CbCgOptions)]
 _lib.cb_cg_workspace_bytes.argtypes = [_p, _p, ctypes.POINTER(_i64)]
@@ -91,7 +124,8 @@ _lib.cb_last_error.argtypes = []
 _lib.cb_last_error.restype = ctypes.c_char_p
 for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
            "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_cg_options_default", "cb_cg_workspace_bytes",
-           "cb_cg", "cb_cg_refine"):
+           "cb_cg", "cb_cg_refine", "cb_server_options_default", "cb_server_create", "cb_server_add_matrix",
+           "cb_server_submit", "cb_server_poll", "cb_server_wait", "cb_server_stats", "cb_server_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -386,3 +420,95 @@ class CbMatrix:
             self.close()
         except Exception:
             pass
+
+
+def _struct_dict(st) -> dict:
+    return {n: getattr(st, n) for n, _ in st._fields_ if not n.startswith("reserved")}
+
+
+def cb_server_options_default(**kw) -> CbServerOptions:
+    o = CbServerOptions()
+    _check(_lib.cb_server_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k) or k.startswith("reserved") or k == "struct_size":
+            raise ValueError(f"unknown server option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class CbServer:
+    """A serving loop on the current device (cb_server_*).  Host vectors given to submit_* are
+    numpy arrays of the matrix's vector type; they are kept alive here until their request is
+    collected with wait()."""
+
+    def __init__(self, **opts):
+        h = _p()
+        _check(_lib.cb_server_create(ctypes.byref(cb_server_options_default(**opts)), ctypes.byref(h)))
+        self.handle = h.value
+        self._keep = {}
+        self._mats = []
+
+    def add_matrix(self, M: "CbMatrix") -> int:
+        i = _i32()
+        _check(_lib.cb_server_add_matrix(self.handle, M.handle, ctypes.byref(i)))
+        self._mats.append(M)
+        return i.value
+
+    def _dtype(self, mid):
+        return np.float64 if self._mats[mid].info["vector_f64"] else np.float32
+
+    def _submit(self, r: CbRequest, keep) -> int:
+        t = _i64()
+        r.struct_size = ctypes.sizeof(CbRequest)
+        _check(_lib.cb_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_spmm(self, mid: int, X: np.ndarray, Y: np.ndarray, alpha: float = 1.0, beta: float = 0.0) -> int:
+        dt = self._dtype(mid)
+        inf = self._mats[mid].info
+        if X.dtype != dt or Y.dtype != dt or not X.flags.c_contiguous or not Y.flags.c_contiguous:
+            raise ValueError(f"X and Y must be C-contiguous {np.dtype(dt).name} arrays")
+        k = 1 if X.ndim == 1 else X.shape[1]
+        if X.size != inf["n"] * k or Y.size != inf["m"] * k:
+            raise ValueError("X must be n x k and Y m x k")
+        r = CbRequest(kind=CB_REQ_SPMM, matrix=mid, k=k, alpha=alpha, beta=beta, in_=X.ctypes.data,
+                      out=Y.ctypes.data)
+        return self._submit(r, (X, Y))
+
+    def submit_cg(self, mid: int, b: np.ndarray, x: np.ndarray, rtol: float = 0.0, max_iter: int = 0) -> int:
+        dt = self._dtype(mid)
+        n = self._mats[mid].info["n"]
+        if b.dtype != dt or x.dtype != dt or b.size != n or x.size != n or not x.flags.c_contiguous:
+            raise ValueError(f"b and x must be {np.dtype(dt).name} arrays of n elements")
+        r = CbRequest(kind=CB_REQ_CG, matrix=mid, k=1, in_=b.ctypes.data, out=x.ctypes.data, rtol=rtol,
+                      max_iter=max_iter)
+        return self._submit(r, (b, x))
+
+    def poll(self, ticket: int) -> dict:
+        r = CbResponse()
+        _check(_lib.cb_server_poll(self.handle, ticket, ctypes.byref(r)))
+        return _struct_dict(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = CbResponse()
+        _check(_lib.cb_server_wait(self.handle, ticket, ctypes.byref(r)))
+        self._keep.pop(ticket, None)
+        return _struct_dict(r)
+
+    def stats(self) -> dict:
+        s = CbServerStats()
+        _check(_lib.cb_server_stats(self.handle, ctypes.byref(s)))
+        return _struct_dict(s)
+
+    def close(self):
+        if self.handle:
+            _check(_lib.cb_server_destroy(self.handle))
+            self.handle = 0
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -8,6 +8,7 @@
 
 #include "cb_device.h"
 #include "cb_host.h"
+#include "cb_internal.h"
 #include "cbspmv.h"
 
 namespace {
@@ -423,3 +424,26 @@ cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *strea
 const char *cb_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+namespace cbh {
+
+cb_status_t matrix_view(cb_matrix_t A, MatrixView &out) {
+    if (!A) return fail(CB_ERROR_INVALID_VALUE, "NULL matrix handle");
+    if (!A->on_device) return fail(CB_ERROR_NOT_SUPPORTED, "host-only handle (cb_create_host)");
+    out.view = A->view;
+    out.kernel_vt = kernel_vtype(A->h);
+    out.vtype = A->h.vtype;
+    out.vector_f64 = A->h.vector_f64;
+    out.col_agg = A->h.col_agg;
+    out.row_reduce = A->h.row_reduce;
+    out.natural = A->h.lb_mode != CB_LB_PAPER;
+    out.device = A->device;
+    out.m = A->h.m;
+    out.n = A->h.n;
+    out.nnz = A->h.nnz;
+    out.nprepass = A->h.nprepass;
+    out.device_bytes = (int64_t)A->L.total;
+    return CB_SUCCESS;
+}
+
+}  // namespace cbh

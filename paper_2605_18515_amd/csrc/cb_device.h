@@ -32,6 +32,23 @@ struct DevView {
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan
 };
 
+// One product of a batched launch: y = alpha A x + beta y for the natural-order structure d, its
+// work ranges at global workgroups wave_base .. wave_base + d.nwaves - 1 of the launch.
+struct BatchJob {
+    DevView d;
+    const void *x;
+    void *y;
+    double alpha, beta;
+    int32_t wave_base;
+    int32_t pad;
+};
+
+// Products of several natural-order structures in one launch.  wave_job[b] (total entries, device
+// memory) is the job of workgroup b; every job has kernel value code vtype, aggregation agg and
+// row-sum mode rr; y rows of shared panels must be prepared as for one product.
+hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
+                             hipStream_t stream);
+
 // vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float);
 // 3 = FP32 values, 4 = BF16 values with x, y double and FP64 arithmetic
 hipError_t launch_spmv(const DevView &d, int vtype, double alpha, const void *x, double beta, void *y,

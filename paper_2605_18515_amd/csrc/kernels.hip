@@ -348,11 +348,12 @@ constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left
 // RR, the row sums: 0 = one LDS atomic add per entry, 1 = DPP segmented scan then one add per run,
 // 2 = one FP64 LDS atomic add per entry (FP32/BF16 values: the products widened, the row sums kept
 // in FP64 until they are written)
+// One work range w of the structure d (the body of the streaming kernel, shared by the one-matrix
+// and the batched launch).
 template <int VT, bool AGG, int RR>
-__global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
-                                                                     typename Val<VT>::A beta,
-                                                                     const typename Val<VT>::A *__restrict__ x,
-                                                                     typename Val<VT>::A *__restrict__ y) {
+__device__ __forceinline__ void stream_range(const DevView &d, int w, typename Val<VT>::A alpha,
+                                             typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
+                                             typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
     using AC = typename std::conditional<RR == 2, double, A>::type;  // accumulator type
     constexpr bool DPPRED = RR == 1;
@@ -365,7 +366,6 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
     const int lane = threadIdx.x & (kWave - 1);
     // with one wavefront per workgroup its LDS arrays sit at fixed addresses
     const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int w = xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid;
     if (w >= d.nwaves) return;
     const int o_begin = d.batch_ptr[w], o_end = d.batch_ptr[w + 1];
     if (o_begin >= o_end) return;
@@ -638,6 +638,29 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
         bufb = bufn;
     }
     flush();
+}
+
+template <int VT, bool AGG, int RR>
+__global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
+                                                                     typename Val<VT>::A beta,
+                                                                     const typename Val<VT>::A *__restrict__ x,
+                                                                     typename Val<VT>::A *__restrict__ y) {
+    const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    stream_range<VT, AGG, RR>(d, xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid, alpha, beta, x, y);
+}
+
+// Products of several matrices in one launch (the serving loop's batches): workgroup b, after the
+// XCD remap, runs work range b - jobs[j].wave_base of job j = wave_job[b]; every job of a launch has
+// the same value type, aggregation and row-sum mode.
+template <int VT, bool AGG, int RR>
+__global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJob *__restrict__ jobs,
+                                                                    const int32_t *__restrict__ wave_job, int total) {
+    static_assert(kWavesPerBlock == 1, "one work range per workgroup");
+    using A = typename Val<VT>::A;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= total) return;
+    const BatchJob &J = jobs[wave_job[b]];
+    stream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
 // ---- k right-hand sides ---------------------------------------------------
@@ -1256,6 +1279,38 @@ hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const v
         case 2: return spmm_vt<2>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
         case 3: return spmm_vt<3>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
         case 4: return spmm_vt<4>(d, k, alpha, X, ldx, beta, Y, ldy, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <int VT, bool AGG>
+hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, hipStream_t s) {
+    constexpr bool kWide = std::is_same<typename Val<VT>::A, double>::value;
+    const dim3 grid((unsigned)total), block(kBlockThreads);
+    if (rr == 1)
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1>), grid, block, 0, s, jobs, wave_job, total);
+    else if (rr == 2 && !kWide)
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 0 : 2>), grid, block, 0, s, jobs, wave_job, total);
+    else
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 0>), grid, block, 0, s, jobs, wave_job, total);
+    return hipGetLastError();
+}
+template <int VT>
+hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, hipStream_t s) {
+    return agg ? batch_rr<VT, true>(jobs, wave_job, total, rr, s) : batch_rr<VT, false>(jobs, wave_job, total, rr, s);
+}
+}  // namespace
+
+hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
+                             hipStream_t stream) {
+    if (total <= 0) return hipSuccess;
+    switch (vtype) {
+        case 0: return batch_vt<0>(jobs, wave_job, total, agg, rr, stream);
+        case 1: return batch_vt<1>(jobs, wave_job, total, agg, rr, stream);
+        case 2: return batch_vt<2>(jobs, wave_job, total, agg, rr, stream);
+        case 3: return batch_vt<3>(jobs, wave_job, total, agg, rr, stream);
+        case 4: return batch_vt<4>(jobs, wave_job, total, agg, rr, stream);
         default: return hipErrorInvalidValue;
     }
 }

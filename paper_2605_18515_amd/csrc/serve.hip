@@ -1,0 +1,896 @@
+// Serving loop: resident matrices, continuous batching of SpMM requests and CG solves.
+//
+// One worker thread per server owns every HIP call.  Requests wait in arrival order and are
+// admitted when their vectors fit in the server's arena (one device allocation made at creation,
+// handed out first-fit) and, for a solve, a solve slot of its vector type is free.  The active
+// solves advance together in periods of check_every steps; a step is the products of all of them
+// (one batched launch per value type, aggregation and row-sum mode, covering the work ranges of
+// all their matrices) followed by batched vector updates with one grid row per solve.  A period
+// is captured once as a HIP graph and replayed until the active set changes.  After each period
+// the solves' scalars come back to the host, finished solves return their x and leave, and queued
+// solves join.  SpMM requests run on streams of their own beside the periods.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "cb_host.h"
+#include "cb_internal.h"
+#include "cbspmv.h"
+
+namespace {
+
+constexpr int kT = 256;   // threads per block of the solve kernels
+constexpr int kGB = 64;   // blocks per solve in the batched vector kernels (the reduction order)
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxMatrices = 1 << 14;  // registered handles (storage reserved up front, so the
+                                          // worker reads entries while new ones are appended)
+
+using Clock = std::chrono::steady_clock;
+
+struct SolveScal {
+    double rr, pq, rrn, bb;
+    int32_t bad, pad;
+};
+
+template <class T>
+struct SolveJob {
+    T *x, *r, *p, *q;
+    const T *b;
+    int64_t n;
+    int32_t active;
+    int32_t zero_q;  // the product's shared or empty panels need q cleared before it
+};
+
+__device__ double block_sum(double v) {
+    __shared__ double sh[kT / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kT / 64; ++i) s += sh[i];
+    return s;
+}
+
+// grid (kGB, solves): block sums of p.q per solve
+template <class T>
+__global__ __launch_bounds__(kT) void sb_dot_pq(const SolveJob<T> *__restrict__ jobs, double *__restrict__ partial) {
+    const SolveJob<T> &J = jobs[blockIdx.y];
+    if (!J.active) return;
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT)
+        v += (double)J.p[i] * (double)J.q[i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partial[blockIdx.y * kGB + blockIdx.x] = s;
+}
+
+static_assert(kGB == 64, "one block sum per lane of the reduction");
+
+// grid (solves), 64 threads: the kGB block sums of a solve in block order; mode 0: rr <- rrn,
+// pq = sum; mode 1: rrn = sum; mode 2 (one solve): rr = rrn = sum; mode 3 (one solve): bb = sum,
+// pq = 0, bad = 0
+template <class T>
+__global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ jobs, const double *__restrict__ partial,
+                                                SolveScal *__restrict__ scal, int mode, int one) {
+    const int j = one >= 0 ? one : (int)blockIdx.x;
+    if (!jobs[j].active) return;
+    double v = partial[j * kGB + threadIdx.x];  // kGB == 64: one block sum per lane
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if (threadIdx.x == 0) {
+        SolveScal &s = scal[j];
+        if (mode == 0) {
+            s.rr = s.rrn;
+            s.pq = v;
+        } else if (mode == 1) {
+            s.rrn = v;
+        } else if (mode == 2) {
+            s.rr = v;
+            s.rrn = v;
+        } else {
+            s.bb = v;
+            s.pq = 0.0;
+            s.bad = 0;
+        }
+    }
+}
+
+// grid (kGB, solves): x += alpha p, r -= alpha q (alpha = rr / pq), block sums of the new r.r
+template <class T>
+__global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict__ jobs, SolveScal *__restrict__ scal,
+                                                   double *__restrict__ partial) {
+    const SolveJob<T> &J = jobs[blockIdx.y];
+    if (!J.active) return;
+    SolveScal &s = scal[blockIdx.y];
+    const double pq = s.pq;
+    const bool ok = pq > 0.0 && std::isfinite(pq);
+    if (!ok && blockIdx.x == 0 && threadIdx.x == 0) s.bad = 1;
+    const double alpha = ok ? s.rr / pq : 0.0;
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
+        J.x[i] = (T)((double)J.x[i] + alpha * (double)J.p[i]);
+        const T ri = (T)((double)J.r[i] - alpha * (double)J.q[i]);
+        J.r[i] = ri;
+        v += (double)ri * (double)ri;
+    }
+    const double sum = block_sum(v);
+    if (threadIdx.x == 0) partial[blockIdx.y * kGB + blockIdx.x] = sum;
+}
+
+// grid (kGB, solves): p = r + beta p (beta = rrn / rr); q cleared where the product needs it
+template <class T>
+__global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<T> *__restrict__ jobs,
+                                                  const SolveScal *__restrict__ scal) {
+    const SolveJob<T> &J = jobs[blockIdx.y];
+    if (!J.active) return;
+    const SolveScal &s = scal[blockIdx.y];
+    const double beta = s.rr > 0.0 ? s.rrn / s.rr : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
+        J.p[i] = (T)((double)J.r[i] + beta * (double)J.p[i]);
+        if (J.zero_q) J.q[i] = T(0);
+    }
+}
+
+// one solve's start: r = b (before r -= A x), then p = r and q = 0; block sums of a.b
+template <class T>
+__global__ __launch_bounds__(kT) void sb_copy(T *__restrict__ dst, const T *__restrict__ src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) dst[i] = src[i];
+}
+template <class T>
+__global__ __launch_bounds__(kT) void sb_start(T *__restrict__ p, T *__restrict__ q, const T *__restrict__ r,
+                                               int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        p[i] = r[i];
+        q[i] = T(0);
+    }
+}
+template <class T>
+__global__ __launch_bounds__(kT) void sb_dot_one(const T *__restrict__ a, const T *__restrict__ b, int64_t n,
+                                                 double *__restrict__ partial) {
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)kGB * kT)
+        v += (double)a[i] * (double)b[i];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// first-fit allocator over [0, size)
+class Arena {
+  public:
+    void init(size_t size) {
+        size_ = size;
+        free_.clear();
+        if (size) free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    bool alloc(size_t bytes, size_t &off) {
+        bytes = align_up(bytes ? bytes : 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(bytes ? bytes : 1);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+    size_t peak() const { return peak_; }
+
+  private:
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+struct Req {
+    int64_t ticket = 0;
+    cb_request_t r{};
+    Clock::time_point t_submit, t_admit;
+    size_t off = 0, bytes = 0;
+    int slot = -1;     // solve slot
+    int stream = -1;   // SpMM stream
+    hipEvent_t ev = nullptr;
+    int iters = 0;
+    int max_iter = 500;
+    double rtol = 1e-10;
+    int conv = 0;      // outcome of a finished solve, reported once its x has landed
+    double rel = 0.0;
+};
+
+struct Mat {
+    cb_matrix_t A;
+    cbh::MatrixView v;
+    int esize;  // vector element bytes
+};
+
+// solve slots and device tables of one vector type
+template <class T>
+struct Group {
+    int S = 0;
+    std::vector<SolveJob<T>> jobs;  // host copy of the table
+    std::vector<Req *> req;         // slot -> request
+    SolveJob<T> *d_jobs = nullptr;
+    SolveScal *d_scal = nullptr;
+    double *d_partial = nullptr;
+    SolveScal *h_scal = nullptr;  // pinned
+    int active = 0;
+    int top = 0;  // slots [0, top) hold every active solve
+    // batched products: per (kernel value code, aggregation, row-sum mode)
+    struct Launch {
+        int kvt, agg, rr, first, count, total;
+    };
+    std::vector<Launch> launches;
+    cbd::BatchJob *d_bjobs = nullptr;
+    int32_t *d_wave_job = nullptr;
+    size_t wave_cap = 0;
+};
+
+}  // namespace
+
+struct cb_server_s {
+    cb_server_options_t o{};
+    int device = 0;
+    void *arena_base = nullptr;
+    Arena arena;
+    std::vector<Mat> mats;
+    Group<double> g64;
+    Group<float> g32;
+    hipStream_t cg_stream = nullptr;
+    std::vector<hipStream_t> spmm_streams;
+    hipEvent_t period_ev = nullptr;
+    hipGraphExec_t graph = nullptr;
+    bool dirty = true;
+    bool period_inflight = false;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> pending;
+    std::list<Req *> spmm_inflight;
+    std::unordered_map<int64_t, cb_response_t> resp;
+    int64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+
+    // statistics (guarded by mu)
+    std::vector<double> lat_us;
+    int64_t submitted = 0, rejected = 0, spmm_done = 0, cg_done = 0, steps = 0;
+    int active_peak = 0, graph_builds = 0;
+    bool started = false;
+    Clock::time_point t_first, t_last;
+
+    void run();
+    bool admit_one(Req *q, bool &blocked_by_memory);
+    template <class T>
+    bool start_solve(Group<T> &g, Req *q, const Mat &M);
+    template <class T>
+    void retire_solves(Group<T> &g, std::vector<Req *> &done);
+    template <class T>
+    hipError_t build_launches(Group<T> &g);
+    template <class T>
+    hipError_t enqueue_steps(Group<T> &g, int nsteps);
+    hipError_t enqueue_period();
+    void complete(Req *q, cb_status_t st, int iters, int conv, double rel);
+};
+
+namespace {
+
+cb_status_t fail(cb_status_t st, const std::string &msg) {
+    cbh::set_last_error(msg);
+    return st;
+}
+
+cb_status_t hipfail(hipError_t e, const char *what) {
+    return fail(CB_ERROR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+hipError_t group_alloc(Group<T> &g, int S) {
+    g.S = S;
+    g.jobs.assign(S, SolveJob<T>{});
+    g.req.assign(S, nullptr);
+    hipError_t e;
+    if ((e = hipMalloc(&g.d_jobs, sizeof(SolveJob<T>) * S)) != hipSuccess) return e;
+    if ((e = hipMalloc(&g.d_scal, sizeof(SolveScal) * S)) != hipSuccess) return e;
+    if ((e = hipMalloc(&g.d_partial, sizeof(double) * kGB * S)) != hipSuccess) return e;
+    if ((e = hipMalloc(&g.d_bjobs, sizeof(cbd::BatchJob) * S)) != hipSuccess) return e;
+    if ((e = hipHostMalloc(&g.h_scal, sizeof(SolveScal) * S, hipHostMallocDefault)) != hipSuccess) return e;
+    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<T>) * S, hipMemcpyHostToDevice);
+}
+
+template <class T>
+void group_free(Group<T> &g) {
+    hipFree(g.d_jobs);
+    hipFree(g.d_scal);
+    hipFree(g.d_partial);
+    hipFree(g.d_bjobs);
+    hipFree(g.d_wave_job);
+    if (g.h_scal) hipHostFree(g.h_scal);
+}
+
+double us_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::micro>(b - a).count();
+}
+
+}  // namespace
+
+// arena bytes of a request
+static size_t footprint(const cb_request_t &r, const Mat &M) {
+    const size_t es = (size_t)M.esize;
+    if (r.kind == CB_REQ_SPMM)
+        return align_up((size_t)M.v.n * r.k * es) + align_up((size_t)M.v.m * r.k * es);
+    return 5 * align_up((size_t)M.v.n * es);  // b, x, r, p, q
+}
+
+void cb_server_s::complete(Req *q, cb_status_t st, int iters, int conv, double rel) {
+    const auto now = Clock::now();
+    cb_response_t rs{};
+    rs.done = 1;
+    rs.status = st;
+    rs.iterations = iters;
+    rs.converged = conv;
+    rs.rel_residual = rel;
+    rs.latency_us = us_between(q->t_submit, now);
+    rs.queue_us = us_between(q->t_submit, q->t_admit);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        resp[q->ticket] = rs;
+        lat_us.push_back(rs.latency_us);
+        if (q->r.kind == CB_REQ_SPMM) ++spmm_done;
+        else ++cg_done;
+        t_last = now;
+    }
+    cv_done.notify_all();
+    if (q->bytes) arena.release(q->off, q->bytes);
+    if (q->ev) hipEventDestroy(q->ev);
+    delete q;
+}
+
+template <class T>
+bool cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
+    int slot = -1;
+    for (int i = 0; i < g.S; ++i)
+        if (!g.req[i]) {
+            slot = i;
+            break;
+        }
+    if (slot < 0) return false;
+    const int64_t n = M.v.n;
+    const size_t vb = align_up((size_t)n * sizeof(T));
+    uint8_t *base = static_cast<uint8_t *>(arena_base) + q->off;
+    T *b = reinterpret_cast<T *>(base), *x = reinterpret_cast<T *>(base + vb), *r = reinterpret_cast<T *>(base + 2 * vb),
+      *p = reinterpret_cast<T *>(base + 3 * vb), *qq = reinterpret_cast<T *>(base + 4 * vb);
+    hipStream_t s = cg_stream;
+    if (n > 0) {
+        hipMemcpyAsync(b, q->r.in, n * sizeof(T), hipMemcpyHostToDevice, s);
+        hipMemcpyAsync(x, q->r.out, n * sizeof(T), hipMemcpyHostToDevice, s);
+        const int gb = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
+        hipLaunchKernelGGL(sb_copy<T>, dim3(gb), dim3(kT), 0, s, r, b, n);
+        cb_spmv(M.A, -1.0, x, 1.0, r, s);  // r = b - A x
+        hipLaunchKernelGGL(sb_start<T>, dim3(gb), dim3(kT), 0, s, p, qq, r, n);
+    }
+    SolveJob<T> J{};
+    J.x = x;
+    J.r = r;
+    J.p = p;
+    J.q = qq;
+    J.b = b;
+    J.n = n;
+    J.active = 1;
+    J.zero_q = M.v.nprepass > 0;
+    g.jobs[slot] = J;
+    g.req[slot] = q;
+    q->slot = slot;
+    hipMemcpyAsync(g.d_jobs + slot, &g.jobs[slot], sizeof(SolveJob<T>), hipMemcpyHostToDevice, s);
+    double *part = g.d_partial + (size_t)slot * kGB;
+    hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, r, r, n, part);
+    hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 2, slot);
+    hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, b, b, n, part);
+    hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 3, slot);
+    // the host copy of the table must outlive the copy above: it is only rewritten between periods
+    ++g.active;
+    g.top = std::max(g.top, slot + 1);
+    dirty = true;
+    return true;
+}
+
+bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
+    blocked_by_memory = false;
+    const Mat &M = mats[q->r.matrix];
+    if (q->r.kind == CB_REQ_CG) {
+        if (period_inflight) return false;
+        Group<double> *gd = M.esize == 8 ? &g64 : nullptr;
+        Group<float> *gf = M.esize == 4 ? &g32 : nullptr;
+        if ((gd && gd->active >= gd->S) || (gf && gf->active >= gf->S)) return false;
+    }
+    size_t off = 0;
+    const size_t bytes = footprint(q->r, M);
+    if (!arena.alloc(bytes, off)) {
+        blocked_by_memory = true;
+        return false;
+    }
+    q->off = off;
+    q->bytes = bytes;
+    q->t_admit = Clock::now();
+    if (q->r.kind == CB_REQ_CG) {
+        const bool ok = M.esize == 8 ? start_solve(g64, q, M) : start_solve(g32, q, M);
+        if (!ok) {
+            arena.release(off, bytes);
+            q->bytes = 0;
+            return false;
+        }
+        return true;
+    }
+    // SpMM on the least recently used stream
+    const int si = (int)(q->ticket % (int64_t)spmm_streams.size());
+    hipStream_t s = spmm_streams[si];
+    const size_t es = (size_t)M.esize;
+    uint8_t *base = static_cast<uint8_t *>(arena_base) + off;
+    void *X = base, *Y = base + align_up((size_t)M.v.n * q->r.k * es);
+    const size_t xb = (size_t)M.v.n * q->r.k * es, yb = (size_t)M.v.m * q->r.k * es;
+    cb_status_t st = CB_SUCCESS;
+    if (xb) hipMemcpyAsync(X, q->r.in, xb, hipMemcpyHostToDevice, s);
+    if (yb && q->r.beta != 0.0) hipMemcpyAsync(Y, q->r.out, yb, hipMemcpyHostToDevice, s);
+    st = cb_spmm(M.A, q->r.k, q->r.alpha, X, q->r.k, q->r.beta, Y, q->r.k, s);
+    if (yb) hipMemcpyAsync(q->r.out, Y, yb, hipMemcpyDeviceToHost, s);
+    hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
+    hipEventRecord(q->ev, s);
+    q->stream = si;
+    if (st != CB_SUCCESS) {
+        hipEventSynchronize(q->ev);
+        complete(q, st, 0, 0, 0.0);
+        return true;
+    }
+    spmm_inflight.push_back(q);
+    return true;
+}
+
+template <class T>
+hipError_t cb_server_s::build_launches(Group<T> &g) {
+    g.launches.clear();
+    if (!g.active) return hipSuccess;
+    // order the active solves by (kernel value code, aggregation, row-sum mode)
+    std::vector<int> order;
+    for (int i = 0; i < g.top; ++i)
+        if (g.req[i]) order.push_back(i);
+    auto key = [&](int i) {
+        const cbh::MatrixView &v = mats[g.req[i]->r.matrix].v;
+        return v.kernel_vt * 16 + v.col_agg * 4 + v.row_reduce;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+    std::vector<cbd::BatchJob> bj;
+    std::vector<int32_t> wave_job;
+    size_t i = 0;
+    while (i < order.size()) {
+        const int k0 = key(order[i]);
+        typename Group<T>::Launch L{};
+        const cbh::MatrixView &v0 = mats[g.req[order[i]]->r.matrix].v;
+        L.kvt = v0.kernel_vt;
+        L.agg = v0.col_agg;
+        L.rr = v0.row_reduce;
+        L.first = (int)bj.size();
+        L.total = 0;
+        for (; i < order.size() && key(order[i]) == k0; ++i) {
+            const int slot = order[i];
+            const cbh::MatrixView &v = mats[g.req[slot]->r.matrix].v;
+            cbd::BatchJob J{};
+            J.d = v.view;
+            J.x = g.jobs[slot].p;
+            J.y = g.jobs[slot].q;
+            J.alpha = 1.0;
+            J.beta = 0.0;
+            J.wave_base = L.total;
+            const int jid = (int)bj.size() - L.first;
+            for (int w = 0; w < v.view.nwaves; ++w) wave_job.push_back(jid);
+            L.total += v.view.nwaves;
+            bj.push_back(J);
+        }
+        L.count = (int)bj.size() - L.first;
+        g.launches.push_back(L);
+    }
+    hipError_t e;
+    if (wave_job.size() > g.wave_cap) {
+        if (g.d_wave_job) hipFree(g.d_wave_job);
+        g.wave_cap = std::max<size_t>(wave_job.size(), 2 * g.wave_cap);
+        if ((e = hipMalloc(&g.d_wave_job, sizeof(int32_t) * g.wave_cap)) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpy(g.d_bjobs, bj.data(), sizeof(cbd::BatchJob) * bj.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return e;
+    // wave_job: each launch's slice numbers its jobs from the launch's first
+    if (!wave_job.empty())
+        if ((e = hipMemcpy(g.d_wave_job, wave_job.data(), sizeof(int32_t) * wave_job.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return e;
+    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<T>) * g.S, hipMemcpyHostToDevice);
+}
+
+template <class T>
+hipError_t cb_server_s::enqueue_steps(Group<T> &g, int nsteps) {
+    if (!g.active) return hipSuccess;
+    hipStream_t s = cg_stream;
+    const dim3 grid(kGB, g.top);
+    for (int step = 0; step < nsteps; ++step) {
+        size_t wofs = 0;
+        for (const auto &L : g.launches) {
+            hipError_t e = cbd::launch_spmv_batch(g.d_bjobs + L.first, g.d_wave_job + wofs, L.total, L.kvt, L.agg, L.rr, s);
+            if (e != hipSuccess) return e;
+            wofs += (size_t)L.total;
+        }
+        hipLaunchKernelGGL(sb_dot_pq<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_partial);
+        hipLaunchKernelGGL(sb_reduce<T>, dim3(g.top), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 0, -1);
+        hipLaunchKernelGGL(sb_update_xr<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, g.d_partial);
+        hipLaunchKernelGGL(sb_reduce<T>, dim3(g.top), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 1, -1);
+        hipLaunchKernelGGL(sb_update_p<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal);
+    }
+    return hipGetLastError();
+}
+
+hipError_t cb_server_s::enqueue_period() {
+    hipError_t e;
+    if (dirty) {
+        if ((e = build_launches(g64)) != hipSuccess) return e;
+        if ((e = build_launches(g32)) != hipSuccess) return e;
+        if (graph) {
+            hipGraphExecDestroy(graph);
+            graph = nullptr;
+        }
+        if (o.use_graph) {
+            hipGraph_t gr = nullptr;
+            if ((e = hipStreamBeginCapture(cg_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+            hipError_t e1 = enqueue_steps(g64, o.check_every);
+            hipError_t e2 = enqueue_steps(g32, o.check_every);
+            e = hipStreamEndCapture(cg_stream, &gr);
+            if (e1 != hipSuccess) return e1;
+            if (e2 != hipSuccess) return e2;
+            if (e != hipSuccess) return e;
+            e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
+            hipGraphDestroy(gr);
+            if (e != hipSuccess) return e;
+            std::lock_guard<std::mutex> lk(mu);
+            ++graph_builds;
+        }
+        dirty = false;
+    }
+    if (o.use_graph) {
+        if ((e = hipGraphLaunch(graph, cg_stream)) != hipSuccess) return e;
+    } else {
+        if ((e = enqueue_steps(g64, o.check_every)) != hipSuccess) return e;
+        if ((e = enqueue_steps(g32, o.check_every)) != hipSuccess) return e;
+    }
+    if (g64.active)
+        hipMemcpyAsync(g64.h_scal, g64.d_scal, sizeof(SolveScal) * g64.top, hipMemcpyDeviceToHost, cg_stream);
+    if (g32.active)
+        hipMemcpyAsync(g32.h_scal, g32.d_scal, sizeof(SolveScal) * g32.top, hipMemcpyDeviceToHost, cg_stream);
+    return hipEventRecord(period_ev, cg_stream);
+}
+
+template <class T>
+void cb_server_s::retire_solves(Group<T> &g, std::vector<Req *> &done) {
+    for (int i = 0; i < g.top; ++i) {
+        Req *q = g.req[i];
+        if (!q) continue;
+        q->iters += o.check_every;
+        const SolveScal &s = g.h_scal[i];
+        const bool conv = std::sqrt(s.rrn) <= q->rtol * std::sqrt(s.bb);
+        if (conv || s.bad || q->iters >= q->max_iter) {
+            // x back to the caller
+            hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(T), hipMemcpyDeviceToHost, cg_stream);
+            q->slot = -1;
+            g.req[i] = nullptr;
+            g.jobs[i].active = 0;
+            --g.active;
+            dirty = true;
+            q->conv = conv ? 1 : 0;
+            q->rel = s.bb > 0.0 ? std::sqrt(s.rrn / s.bb) : std::sqrt(s.rrn);
+            done.push_back(q);
+        }
+    }
+    while (g.top > 0 && !g.req[g.top - 1]) --g.top;
+}
+
+void cb_server_s::run() {
+    hipSetDevice(device);
+    for (;;) {
+        bool progressed = false;
+        // SpMM completions
+        for (auto it = spmm_inflight.begin(); it != spmm_inflight.end();) {
+            if (hipEventQuery((*it)->ev) == hipSuccess) {
+                Req *q = *it;
+                it = spmm_inflight.erase(it);
+                complete(q, CB_SUCCESS, 0, 0, 0.0);
+                progressed = true;
+            } else {
+                ++it;
+            }
+        }
+        // end of a solve period: retire finished solves
+        if (period_inflight && hipEventQuery(period_ev) == hipSuccess) {
+            period_inflight = false;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                steps += o.check_every;
+            }
+            std::vector<Req *> done;
+            retire_solves(g64, done);
+            retire_solves(g32, done);
+            if (!done.empty()) hipStreamSynchronize(cg_stream);
+            for (Req *q : done) complete(q, CB_SUCCESS, q->iters, q->conv, q->rel);
+            progressed = true;
+        }
+        // admission in arrival order; a solve waiting for the period's end lets SpMM requests pass,
+        // a request waiting for memory holds everything behind it
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            for (auto it = pending.begin(); it != pending.end();) {
+                Req *q = *it;
+                lk.unlock();
+                bool mem = false;
+                const bool ok = admit_one(q, mem);
+                lk.lock();
+                if (ok) {
+                    it = pending.erase(it);
+                    progressed = true;
+                } else if (mem) {
+                    break;
+                } else {
+                    ++it;
+                }
+            }
+            active_peak = std::max(active_peak, g64.active + g32.active);
+        }
+        // next period of the active solves
+        if (!period_inflight && g64.active + g32.active > 0) {
+            hipError_t e = enqueue_period();
+            if (e != hipSuccess) {
+                // fail every active solve
+                std::vector<Req *> all;
+                for (int i = 0; i < g64.top; ++i)
+                    if (g64.req[i]) all.push_back(g64.req[i]), g64.req[i] = nullptr;
+                for (int i = 0; i < g32.top; ++i)
+                    if (g32.req[i]) all.push_back(g32.req[i]), g32.req[i] = nullptr;
+                g64.active = g32.active = g64.top = g32.top = 0;
+                for (Req *q : all) complete(q, CB_ERROR_HIP, q->iters, 0, 0.0);
+                dirty = true;
+                hipGetLastError();
+            } else {
+                period_inflight = true;
+            }
+            progressed = true;
+        }
+        std::unique_lock<std::mutex> lk(mu);
+        const bool busy = period_inflight || !spmm_inflight.empty();
+        if (stop && pending.empty() && !busy && g64.active + g32.active == 0) break;
+        if (!progressed) {
+            if (busy || !pending.empty())
+                cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else
+                cv_work.wait_for(lk, std::chrono::milliseconds(50));
+        }
+    }
+}
+
+extern "C" {
+
+cb_status_t cb_server_options_default(cb_server_options_t *opt) {
+    if (!opt) return fail(CB_ERROR_INVALID_VALUE, "NULL options");
+    *opt = cb_server_options_t{};
+    opt->struct_size = sizeof(cb_server_options_t);
+    opt->max_active = 64;
+    opt->arena_bytes = (int64_t)1 << 30;
+    opt->check_every = 8;
+    opt->use_graph = 1;
+    opt->spmm_streams = 2;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_create(const cb_server_options_t *opt, cb_server_t *out) {
+    if (!out) return fail(CB_ERROR_INVALID_VALUE, "NULL output");
+    cb_server_options_t o;
+    cb_server_options_default(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(cb_server_options_t))
+            return fail(CB_ERROR_INVALID_VALUE, "cb_server_options_t.struct_size mismatch");
+        o = *opt;
+    }
+    if (o.max_active < 1 || o.max_active > 4096 || o.arena_bytes < (int64_t)kAlign || o.check_every < 1 ||
+        o.check_every > 1024 || (o.use_graph != 0 && o.use_graph != 1) || o.spmm_streams < 1 || o.spmm_streams > 16)
+        return fail(CB_ERROR_INVALID_VALUE, "invalid server options");
+    cb_server_s *S = new (std::nothrow) cb_server_s();
+    if (!S) return fail(CB_ERROR_OUT_OF_MEMORY, "server");
+    S->o = o;
+    hipError_t e = hipGetDevice(&S->device);
+    if (e == hipSuccess) e = hipMalloc(&S->arena_base, (size_t)o.arena_bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        delete S;
+        return fail(CB_ERROR_OUT_OF_MEMORY, "server arena");
+    }
+    if (e == hipSuccess) e = group_alloc(S->g64, o.max_active);
+    if (e == hipSuccess) e = group_alloc(S->g32, o.max_active);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cg_stream, hipStreamNonBlocking);
+    for (int i = 0; e == hipSuccess && i < o.spmm_streams; ++i) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) S->spmm_streams.push_back(s);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->period_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        cb_server_destroy(S);
+        return hipfail(e, "server creation");
+    }
+    S->arena.init((size_t)o.arena_bytes);
+    S->mats.reserve(kMaxMatrices);
+    S->worker = std::thread([S] { S->run(); });
+    *out = S;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_add_matrix(cb_server_t S, cb_matrix_t A, int32_t *id) {
+    if (!S || !id) return fail(CB_ERROR_INVALID_VALUE, "NULL argument");
+    Mat M{};
+    M.A = A;
+    cb_status_t st = cbh::matrix_view(A, M.v);
+    if (st != CB_SUCCESS) return st;
+    if (!M.v.natural) return fail(CB_ERROR_NOT_SUPPORTED, "the server runs natural-order structures (lb_mode contiguous or none)");
+    if (M.v.device != S->device) return fail(CB_ERROR_NOT_SUPPORTED, "matrix on another device");
+    M.esize = M.v.vector_f64 ? 8 : 4;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->mats.size() >= kMaxMatrices) return fail(CB_ERROR_NOT_SUPPORTED, "too many matrices");
+    S->mats.push_back(M);
+    *id = (int32_t)S->mats.size() - 1;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_submit(cb_server_t S, const cb_request_t *req, int64_t *ticket) {
+    if (!S || !req || !ticket) return fail(CB_ERROR_INVALID_VALUE, "NULL argument");
+    if (req->struct_size != sizeof(cb_request_t)) return fail(CB_ERROR_INVALID_VALUE, "cb_request_t.struct_size mismatch");
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (req->matrix < 0 || req->matrix >= (int32_t)S->mats.size()) return fail(CB_ERROR_INVALID_VALUE, "unknown matrix");
+    const Mat &M = S->mats[req->matrix];
+    if (req->kind != CB_REQ_SPMM && req->kind != CB_REQ_CG) return fail(CB_ERROR_INVALID_VALUE, "unknown request kind");
+    if (req->kind == CB_REQ_SPMM && req->k < 1) return fail(CB_ERROR_INVALID_VALUE, "k must be at least 1");
+    if (req->kind == CB_REQ_CG && M.v.m != M.v.n) return fail(CB_ERROR_INVALID_VALUE, "CG needs a square matrix");
+    if (req->kind == CB_REQ_CG && (req->rtol < 0.0 || req->max_iter < 0))
+        return fail(CB_ERROR_INVALID_VALUE, "invalid CG parameters");
+    const bool need_in = M.v.n > 0, need_out = req->kind == CB_REQ_CG ? M.v.n > 0 : M.v.m > 0;
+    if ((need_in && !req->in) || (need_out && !req->out)) return fail(CB_ERROR_INVALID_VALUE, "NULL vector");
+    Req *q = new (std::nothrow) Req();
+    if (!q) return fail(CB_ERROR_OUT_OF_MEMORY, "request");
+    q->r = *req;
+    if (req->kind == CB_REQ_SPMM) q->r.k = req->k;
+    q->rtol = req->rtol > 0.0 ? req->rtol : 1e-10;
+    const int cap = req->max_iter > 0 ? req->max_iter : 500;
+    q->max_iter = ((cap + S->o.check_every - 1) / S->o.check_every) * S->o.check_every;
+    const size_t fp = footprint(q->r, M);
+    ++S->submitted;
+    if (fp > S->arena.size()) {
+        ++S->rejected;
+        delete q;
+        return fail(CB_ERROR_OUT_OF_MEMORY, "request larger than the server's arena");
+    }
+    q->ticket = S->next_ticket++;
+    q->t_submit = Clock::now();
+    if (!S->started) {
+        S->started = true;
+        S->t_first = q->t_submit;
+    }
+    cb_response_t rs{};
+    S->resp[q->ticket] = rs;
+    S->pending.push_back(q);
+    *ticket = q->ticket;
+    lk.unlock();
+    S->cv_work.notify_one();
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_poll(cb_server_t S, int64_t ticket, cb_response_t *resp) {
+    if (!S || !resp) return fail(CB_ERROR_INVALID_VALUE, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->resp.find(ticket);
+    if (it == S->resp.end()) return fail(CB_ERROR_INVALID_VALUE, "unknown ticket");
+    *resp = it->second;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_wait(cb_server_t S, int64_t ticket, cb_response_t *resp) {
+    if (!S || !resp) return fail(CB_ERROR_INVALID_VALUE, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->resp.find(ticket);
+    if (it == S->resp.end()) return fail(CB_ERROR_INVALID_VALUE, "unknown ticket");
+    S->cv_done.wait(lk, [&] { return S->resp[ticket].done != 0; });
+    *resp = S->resp[ticket];
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_stats(cb_server_t S, cb_server_stats_t *st) {
+    if (!S || !st) return fail(CB_ERROR_INVALID_VALUE, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    cb_server_stats_t r{};
+    r.submitted = S->submitted;
+    r.rejected = S->rejected;
+    r.completed = (int64_t)S->lat_us.size();
+    r.spmm_done = S->spmm_done;
+    r.cg_done = S->cg_done;
+    if (!S->lat_us.empty()) {
+        std::vector<double> v = S->lat_us;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            const size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(p * (double)v.size()) - 1);
+            return v[i];
+        };
+        r.p50_us = pct(0.50);
+        r.p99_us = pct(0.99);
+        double sum = 0.0;
+        for (double x : v) sum += x;
+        r.mean_us = sum / (double)v.size();
+        r.elapsed_s = std::chrono::duration<double>(S->t_last - S->t_first).count();
+        if (r.elapsed_s > 0.0) {
+            r.requests_per_s = (double)r.completed / r.elapsed_s;
+            r.solves_per_s = (double)r.cg_done / r.elapsed_s;
+        }
+    }
+    r.arena_peak_bytes = (int64_t)S->arena.peak();
+    r.active_peak = S->active_peak;
+    r.graph_builds = S->graph_builds;
+    r.steps = S->steps;
+    *st = r;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_server_destroy(cb_server_t S) {
+    if (!S) return CB_SUCCESS;
+    if (S->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        S->worker.join();
+    }
+    hipDeviceSynchronize();
+    if (S->graph) hipGraphExecDestroy(S->graph);
+    if (S->period_ev) hipEventDestroy(S->period_ev);
+    for (hipStream_t s : S->spmm_streams) hipStreamDestroy(s);
+    if (S->cg_stream) hipStreamDestroy(S->cg_stream);
+    group_free(S->g64);
+    group_free(S->g32);
+    if (S->arena_base) hipFree(S->arena_base);
+    delete S;
+    return CB_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+"""GPU tests of the serving loop (cb_server_*): SpMM requests against the oracle and against
+the direct product, CG solves alone and in a mix of other solves and SpMM requests (the same
+result, iteration for iteration), graph replay against plain launches, admission under a small
+memory arena, the iteration cap, breakdown on a negative definite matrix, and the statistics."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import solvers
+from paper_2605_18515_amd import matgen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def cb():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2605_18515_amd import cbspmv
+
+    torch.cuda.init()
+    return cbspmv
+
+
+def spd_matrices():
+    """SPD operators of uneven sizes: 2D Laplacians, 3D Poisson operators, a scaled Poisson."""
+    out = [matgen.laplacian_2d(s) for s in (9, 23, 40)] + [matgen.poisson_3d(s) for s in (6, 13)]
+    P = matgen.poisson_3d(10)
+    s = np.random.default_rng(4).uniform(0.8, 1.25, P.n)
+    out.append(matgen.Csr(P.m, P.n, P.row_ptr, P.col_idx, s[P.rows()] * P.values * s[P.col_idx]))
+    return out
+
+
+def general_matrices():
+    return [matgen.block_3d(5, seed=1), matgen.power_law(3000, seed=2, max_len=800, window=300),
+            matgen.random_csr(200, 333, 0.05, 4), matgen.laplacian_2d(17)]
+
+
+def make(cb, A, vt):
+    if vt == "f32w":
+        return cb.CbMatrix.from_csr(A, value_type="f32", vector_f64=1)
+    return cb.CbMatrix.from_csr(A, value_type=vt)
+
+
+def ndt(vt):
+    return np.float64 if vt in ("f64", "f32w") else np.float32
+
+
+def test_spmm_requests_match_oracle_and_direct(cb):
+    mats = []
+    with cb.CbServer(max_active=8) as S:
+        reqs = []
+        rng = np.random.default_rng(5)
+        for A in general_matrices():
+            for vt in ("f64", "f32", "f32w"):
+                M = make(cb, A, vt)
+                mats.append(M)
+                mid = S.add_matrix(M)
+                for k in (1, 3, 16):
+                    X = rng.uniform(-1, 1, (A.n, k)).astype(ndt(vt))
+                    Y0 = rng.uniform(-1, 1, (A.m, k)).astype(ndt(vt))
+                    Y = Y0.copy()
+                    reqs.append((A, M, vt, k, X, Y0, Y, S.submit_spmm(mid, X, Y, 1.5, -0.5)))
+        for A, M, vt, k, X, Y0, Y, t in reqs:
+            r = S.wait(t)
+            assert r["done"] == 1 and r["status"] == cb.CB_SUCCESS
+            Xd = X.astype(np.float64)
+            ref = oracle.spmm(A, Xd, 1.5, -0.5, Y0.astype(np.float64), comp=True)
+            scl = oracle.spmm_scale(A, Xd, 1.5, -0.5, Y0.astype(np.float64))
+            tol = TOL["f64"] if vt == "f64" else TOL["f32"]
+            e, viol, _ = oracle.scaled_error(Y.astype(np.float64).ravel(), ref.ravel(), scl.ravel(), tol)
+            assert viol == 0, (vt, k, e)
+            # the same product straight through cb_spmm
+            dt = torch.float64 if ndt(vt) == np.float64 else torch.float32
+            Yd = torch.from_numpy(Y0).to("cuda")
+            M.spmm(torch.from_numpy(X).to("cuda", dt).reshape(A.n, k), Yd.reshape(A.m, k), 1.5, -0.5)
+            torch.cuda.synchronize()
+            e2, viol2, _ = oracle.scaled_error(Y.astype(np.float64).ravel(), Yd.cpu().double().numpy().ravel(),
+                                               scl.ravel(), 1e-13 if vt != "f32" else 1e-6)
+            assert viol2 == 0, (vt, k, e2)
+        st = S.stats()
+        assert st["spmm_done"] == len(reqs) and st["completed"] == len(reqs) and st["rejected"] == 0
+    for M in mats:
+        M.close()
+
+
+def run_solves(cb, specs, mix_spmm=False, **opts):
+    """Submit every CG request (A, vector type, seed of b) at once, with SpMM requests in between
+    when mix_spmm; returns [(x, response)] in submission order."""
+    mats, out = [], []
+    with cb.CbServer(**opts) as S:
+        ids = []
+        for A, vt, _ in specs:
+            M = make(cb, A, vt)
+            mats.append(M)
+            ids.append(S.add_matrix(M))
+        extra = []
+        if mix_spmm:
+            G = matgen.block_3d(6, seed=3)
+            MG = cb.CbMatrix.from_csr(G)
+            mats.append(MG)
+            gid = S.add_matrix(MG)
+        tickets = []
+        for i, (A, vt, seed) in enumerate(specs):
+            b = matgen.vector(A.n, seed).astype(ndt(vt))
+            x = np.zeros(A.n, ndt(vt))
+            tickets.append((x, S.submit_cg(ids[i], b, x, rtol=1e-10 if ndt(vt) == np.float64 else 1e-5,
+                                           max_iter=2000)))
+            if mix_spmm:
+                X = np.random.default_rng(i).uniform(-1, 1, (G.n, 4))
+                Y = np.zeros((G.m, 4))
+                extra.append(S.submit_spmm(gid, X, Y))
+        for x, t in tickets:
+            out.append((x, S.wait(t)))
+        for t in extra:
+            assert S.wait(t)["status"] == cb.CB_SUCCESS
+        stats = S.stats()
+    for M in mats:
+        M.close()
+    return out, stats
+
+
+def test_cg_alone_and_in_a_mix_agree(cb):
+    spd = spd_matrices()
+    specs = [(A, vt, 30 + 3 * i + j) for i, A in enumerate(spd) for j, vt in enumerate(("f64", "f32", "f32w"))]
+    alone = [run_solves(cb, [s])[0][0] for s in specs]
+    mixed, stats = run_solves(cb, specs, mix_spmm=True, max_active=8)
+    assert stats["active_peak"] > 1 and stats["graph_builds"] >= 2
+    for (A, vt, seed), (xa, ra), (xm, rm) in zip(specs, alone, mixed):
+        assert ra["status"] == rm["status"] == cb.CB_SUCCESS
+        assert ra["converged"] and rm["converged"], (A.name, vt, ra, rm)
+        # the same arithmetic per solve: bit for bit unless panels shared between work ranges are
+        # summed with global atomics (their order varies)
+        shared = cb.CbMatrix.from_csr(A, device=False, value_type="f64" if vt == "f64" else "f32").info["shared_panels"]
+        if shared == 0:
+            assert ra["iterations"] == rm["iterations"]
+            assert np.array_equal(xa, xm), (A.name, vt, np.abs(xa - xm).max())
+        else:
+            assert abs(ra["iterations"] - rm["iterations"]) <= 8
+            tol = 1e-8 if ndt(vt) == np.float64 else 1e-3
+            assert np.abs(xa - xm).max() <= tol * np.abs(xa).max(), (A.name, vt, np.abs(xa - xm).max())
+        if ndt(vt) == np.float64:
+            b = matgen.vector(A.n, seed)
+            Aeff = A if vt == "f64" else matgen.Csr(A.m, A.n, A.row_ptr, A.col_idx, oracle.f32_values(A.values))
+            assert solvers.residual(Aeff, b, xm) <= 2e-10, (A.name, vt)
+
+
+def test_graph_replay_matches_plain_launches(cb):
+    specs = [(A, "f64", 40 + i) for i, A in enumerate(spd_matrices()[:4])]
+    g, _ = run_solves(cb, specs, use_graph=1, max_active=4)
+    p, _ = run_solves(cb, specs, use_graph=0, max_active=4)
+    for (xg, rg), (xp, rp) in zip(g, p):
+        assert rg["iterations"] == rp["iterations"] and np.array_equal(xg, xp)
+
+
+def test_admission_under_a_small_arena(cb):
+    A = matgen.laplacian_2d(40)  # 1600 unknowns: a solve takes 5 x 12.8 KB
+    specs = [(A, "f64", 50 + i) for i in range(12)]
+    res, st = run_solves(cb, specs, arena_bytes=3 * 5 * 12800 + 4096, max_active=8)
+    assert all(r["converged"] for _, r in res)
+    assert st["arena_peak_bytes"] <= 3 * 5 * 12800 + 4096 and st["active_peak"] <= 3
+    assert max(r["queue_us"] for _, r in res) > 0
+    # a request that can never fit is refused at submission
+    M = cb.CbMatrix.from_csr(matgen.laplacian_2d(64))
+    with cb.CbServer(arena_bytes=4096) as S:
+        mid = S.add_matrix(M)
+        with pytest.raises(cb.CbError) as e:
+            S.submit_cg(mid, np.ones(4096), np.zeros(4096))
+        assert e.value.status == cb.CB_ERROR_OUT_OF_MEMORY
+        assert S.stats()["rejected"] == 1
+    M.close()
+
+
+def test_iteration_cap_and_breakdown(cb):
+    A = matgen.poisson_3d(12)
+    N = matgen.laplacian_2d(12)
+    N = matgen.Csr(N.m, N.n, N.row_ptr, N.col_idx, -N.values)
+    Ms = [cb.CbMatrix.from_csr(A), cb.CbMatrix.from_csr(N)]
+    with cb.CbServer(check_every=4) as S:
+        a, n = S.add_matrix(Ms[0]), S.add_matrix(Ms[1])
+        x1, x2 = np.zeros(A.n), np.zeros(N.n)
+        t1 = S.submit_cg(a, matgen.vector(A.n, 1), x1, max_iter=6)
+        t2 = S.submit_cg(n, matgen.vector(N.n, 2), x2)
+        r1, r2 = S.wait(t1), S.wait(t2)
+    assert not r1["converged"] and r1["iterations"] == 8  # the cap rounded up to whole periods
+    assert not r2["converged"] and r2["iterations"] == 4 and not x2.any()
+    for M in Ms:
+        M.close()
+
+
+def test_stats_and_errors(cb):
+    A = matgen.laplacian_2d(20)
+    M = cb.CbMatrix.from_csr(A)
+    R = cb.CbMatrix.from_csr(matgen.random_csr(30, 40, 0.2, 1))
+    P = cb.CbMatrix.from_csr(A, lb_mode="paper")
+    with cb.CbServer() as S:
+        with pytest.raises(cb.CbError) as e:
+            S.add_matrix(P)
+        assert e.value.status == cb.CB_ERROR_NOT_SUPPORTED
+        mid, rid = S.add_matrix(M), S.add_matrix(R)
+        with pytest.raises(cb.CbError):
+            S.submit_cg(rid, np.ones(40), np.zeros(40))  # not square
+        with pytest.raises(ValueError):
+            S.submit_cg(mid, np.ones(A.n, np.float32), np.zeros(A.n, np.float32))  # wrong vector type
+        ts = [S.submit_cg(mid, matgen.vector(A.n, i), np.zeros(A.n)) for i in range(6)]
+        for t in ts:
+            assert S.wait(t)["converged"]
+        with pytest.raises(cb.CbError):
+            S.poll(10 ** 9)
+        st = S.stats()
+    assert st["cg_done"] == 6 and st["completed"] == 6 and st["submitted"] == 6
+    assert 0 < st["p50_us"] <= st["p99_us"] and st["solves_per_s"] > 0 and st["steps"] > 0
+    for h in (M, R, P):
+        h.close()

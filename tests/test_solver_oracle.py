@@ -123,3 +123,34 @@ def test_cg_rejects_host_handles_and_bad_arguments(cb):
         with pytest.raises(cb.CbError) as e:
             f()
         assert e.value.status == cb.CB_ERROR_INVALID_VALUE
+
+
+# ---------------------------------------------------------------- serving loop, host side
+
+
+def test_server_option_defaults_and_struct_sizes(cb):
+    o = cb.cb_server_options_default()
+    assert (o.max_active, o.arena_bytes, o.check_every, o.use_graph, o.spmm_streams) == (64, 1 << 30, 8, 1, 2)
+    assert [ctypes.sizeof(t) for t in (cb.CbServerOptions, cb.CbRequest, cb.CbResponse, cb.CbServerStats)] == \
+        [64, 96, 56, 144]
+    with pytest.raises(ValueError):
+        cb.cb_server_options_default(slots=3)
+
+
+def test_server_rejects_bad_options_and_null_arguments(cb):
+    lib = cb.library_handle()
+    for bad in ({"max_active": 0}, {"check_every": 0}, {"use_graph": 2}, {"spmm_streams": 0}, {"arena_bytes": 16}):
+        h = ctypes.c_void_p()
+        st = lib.cb_server_create(ctypes.byref(cb.cb_server_options_default(**bad)), ctypes.byref(h))
+        assert st == cb.CB_ERROR_INVALID_VALUE, bad
+    o = cb.cb_server_options_default()
+    o.struct_size = 4
+    assert lib.cb_server_create(ctypes.byref(o), ctypes.byref(ctypes.c_void_p())) == cb.CB_ERROR_INVALID_VALUE
+    r = cb.CbRequest()
+    t = ctypes.c_int64()
+    assert lib.cb_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_server_poll(None, 1, ctypes.byref(cb.CbResponse())) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_server_wait(None, 1, ctypes.byref(cb.CbResponse())) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_server_stats(None, ctypes.byref(cb.CbServerStats())) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_server_add_matrix(None, None, ctypes.byref(ctypes.c_int32())) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_server_destroy(None) == cb.CB_SUCCESS
