@@ -195,6 +195,143 @@ def run_cg(args, cb, matgen) -> int:
     return 0 if ok else 1
 
 
+def _serve_matrix(spec):
+    """One resident matrix of the serving workload: (family, n, seed) -> Csr."""
+    from paper_2605_18515_amd import matgen
+
+    fam, n, seed = spec
+    if fam == "block3d":
+        return matgen.block_3d(max(2, round((n / 3) ** (1 / 3))), 3, 10.0, seed=seed)
+    if fam == "powerlaw":
+        return matgen.power_law(n, seed=seed, max_len=min(100_000, max(16, n // 4)))
+    return matgen.poisson_3d(max(2, round(n ** (1 / 3))))
+
+
+def run_serve(args, cb, matgen) -> int:
+    """Serving workload: 256 resident matrices from the three families (3D block, power-law, 3D
+    Poisson) with n log-uniform in [1e3, 1e6], every other one stored in FP32; requests are SpMM
+    with k uniform in 1..16 on any matrix, or a CG solve (cap 500 iterations, rtol 1e-8 for FP64,
+    1e-5 for FP32) on a Poisson matrix, half each.  Three runs of the same request list: the
+    server with every request submitted at once (throughput), the server under Poisson arrivals at
+    half that rate (p50/p99 latency), and the plain path, one request at a time through cb_spmm
+    and cb_cg."""
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(2026)
+    fams = ("block3d", "powerlaw", "poisson")
+    specs = [(fams[i % 3], int(round(10 ** rng.uniform(3, 6))), 100 + i) for i in range(256)]
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(8) as pool:
+        csrs = pool.map(_serve_matrix, specs)
+    log(f"generated 256 matrices ({sum(A.nnz for A in csrs) / 1e6:.0f} M non-zeros) in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32") for i, A in enumerate(csrs)]
+    log(f"converted and uploaded in {time.perf_counter() - t:.1f}s, "
+        f"{sum(M.info['device_bytes'] for M in mats) / 2 ** 30:.2f} GiB on the device")
+    dts = [np.float64 if i % 2 == 0 else np.float32 for i in range(256)]
+    spd = [i for i, s in enumerate(specs) if s[0] == "poisson"]
+    # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix
+    xin = [np.random.default_rng(i).uniform(-1, 1, A.n * 16).astype(dts[i]) for i, A in enumerate(csrs)]
+    reqs = []
+    for r in range(args.requests):
+        if rng.random() < 0.5:
+            i = int(rng.choice(spd))
+            reqs.append(("cg", i, 1))
+        else:
+            reqs.append(("spmm", int(rng.integers(0, 256)), int(rng.integers(1, 17))))
+
+    def rtol(i):
+        return 1e-8 if dts[i] == np.float64 else 1e-5
+
+    def outputs():
+        return [np.zeros(csrs[i].n * k if kind == "spmm" else csrs[i].n, dts[i]) for kind, i, k in reqs]
+
+    def submit_all(S, outs, gaps=None, count=None):
+        tickets = []
+        for j, (kind, i, k) in enumerate(reqs[:count]):
+            if gaps is not None:
+                time.sleep(gaps[j])
+            if kind == "cg":
+                tickets.append(S.submit_cg(i, xin[i][:csrs[i].n], outs[j], rtol=rtol(i), max_iter=500))
+            else:
+                tickets.append(S.submit_spmm(i, xin[i][:csrs[i].n * k].reshape(csrs[i].n, k),
+                                             outs[j].reshape(csrs[i].m, k)))
+        return tickets
+
+    def serve(gaps=None, count=None):
+        outs = outputs()
+        S = cb.CbServer(max_active=64, arena_bytes=8 << 30)
+        for M in mats:
+            S.add_matrix(M)
+        tickets = submit_all(S, outs, gaps, count)
+        resp = [S.wait(t) for t in tickets]
+        st = S.stats()
+        S.close()
+        return outs, resp, st
+
+    serve(count=64)  # warm-up: code objects, arena, graphs
+    outs_b, resp_b, st_b = serve()
+    log(f"server, all at once: {st_b['requests_per_s']:.0f} requests/s, {st_b['solves_per_s']:.1f} solves/s, "
+        f"p50 {st_b['p50_us'] / 1e3:.2f} ms, p99 {st_b['p99_us'] / 1e3:.2f} ms, active peak {st_b['active_peak']}")
+    lam = 0.5 * st_b["requests_per_s"]
+    gaps = np.random.default_rng(7).exponential(1.0 / lam, len(reqs))
+    outs_p, resp_p, st_p = serve(gaps)
+    log(f"server, Poisson arrivals at {lam:.0f}/s: {st_p['requests_per_s']:.0f} requests/s, "
+        f"p50 {st_p['p50_us'] / 1e3:.2f} ms, p99 {st_p['p99_us'] / 1e3:.2f} ms")
+
+    # the plain path: one request at a time
+    dev = torch.device("cuda:0")
+    lat = []
+    t0 = time.perf_counter()
+    outs_s = outputs()
+    for j, (kind, i, k) in enumerate(reqs):
+        ts = time.perf_counter()
+        M, A, tdt = mats[i], csrs[i], torch.float64 if dts[i] == np.float64 else torch.float32
+        if kind == "cg":
+            b = torch.from_numpy(xin[i][:A.n]).to(dev)
+            x = torch.zeros(A.n, dtype=tdt, device=dev)
+            M.cg(b, x, rtol=rtol(i), max_iter=500, check_every=8)
+            outs_s[j][:] = x.cpu().numpy()
+        else:
+            X = torch.from_numpy(xin[i][:A.n * k]).to(dev).reshape(A.n, k)
+            Y = torch.zeros((A.m, k), dtype=tdt, device=dev)
+            M.spmm(X, Y)
+            outs_s[j][:] = Y.cpu().numpy().ravel()
+        lat.append(time.perf_counter() - ts)
+    el = time.perf_counter() - t0
+    ncg = sum(1 for r in reqs if r[0] == "cg")
+    seq = {"requests_per_s": len(reqs) / el, "solves_per_s": ncg / el, "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+           "p99_ms": float(np.percentile(lat, 99)) * 1e3}
+    log(f"one at a time: {seq['requests_per_s']:.0f} requests/s, {seq['solves_per_s']:.1f} solves/s")
+    # the served results against the plain path's
+    worst = 0.0
+    for j, (kind, i, k) in enumerate(reqs):
+        a, b_ = outs_b[j].astype(np.float64), outs_s[j].astype(np.float64)
+        worst = max(worst, float(np.abs(a - b_).max() / max(1e-300, np.abs(b_).max())))
+    conv = sum(1 for (kind, _, _), r in zip(reqs, resp_b) if kind == "cg" and r["converged"])
+    for M in mats:
+        M.close()
+    out = {
+        "metric": "batched solves/s, p50/p99 (serving)",
+        "value": round(st_b["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 1, "ms_per_step": 1e3 / st_b["requests_per_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "serving: 256 resident matrices (3D block, power-law, 3D Poisson; n log-uniform in "
+                               "[1e3, 1e6]; FP64 and FP32), SpMM k in 1..16 or CG (cap 500) requests",
+                   "requests": len(reqs), "cg_requests": ncg},
+        "roofline": None, "cpu_baseline": None,
+        "extra": {"all_at_once": st_b, "poisson_arrivals": dict(st_p, rate_per_s=lam), "one_at_a_time": seq,
+                  "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
+                  "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +353,10 @@ def main() -> int:
     ap.add_argument("--cg", action="store_true",
                     help="instead of the SpMV line: CG solves/s on the 192^3 Poisson operator to a true FP64 "
                          "residual of 1e-10, FP64 CG against the mixed-precision solvers on FP32 and BF16 copies")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of the SpMV line: the serving workload (256 resident matrices, SpMM and CG "
+                         "requests with Poisson arrivals), p50/p99 latency and solves/s")
+    ap.add_argument("--requests", type=int, default=1000, help="requests of the serving workload")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -243,6 +384,8 @@ def main() -> int:
         return 0
     if args.cg:
         return run_cg(args, cb, matgen)
+    if args.serve:
+        return run_serve(args, cb, matgen)
     t = time.perf_counter()
     A = make_matrix(args.workload, args.side)
     x = matgen.vector(A.n, 1)

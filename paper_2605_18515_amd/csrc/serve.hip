@@ -16,7 +16,6 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <list>
 #include <map>
 #include <mutex>
@@ -280,7 +279,9 @@ struct cb_server_s {
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<Req *> pending;
+    // a list: the worker walks it with the lock released around each admission while submit()
+    // appends, and list insertions leave the worker's iterator valid (a deque's would not be)
+    std::list<Req *> pending;
     std::list<Req *> spmm_inflight;
     std::unordered_map<int64_t, cb_response_t> resp;
     int64_t next_ticket = 1;

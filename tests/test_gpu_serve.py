@@ -215,3 +215,34 @@ def test_stats_and_errors(cb):
     assert 0 < st["p50_us"] <= st["p99_us"] and st["solves_per_s"] > 0 and st["steps"] > 0
     for h in (M, R, P):
         h.close()
+
+
+def test_many_requests_submitted_while_the_worker_admits(cb):
+    """Hundreds of submissions racing the worker's admission pass (the queue grows while the
+    worker walks it)."""
+    A, P = matgen.block_3d(4, seed=2), matgen.poisson_3d(7)
+    MA, MP = cb.CbMatrix.from_csr(A), cb.CbMatrix.from_csr(P)
+    rng = np.random.default_rng(9)
+    with cb.CbServer(max_active=16) as S:
+        a, p = S.add_matrix(MA), S.add_matrix(MP)
+        jobs = []
+        for j in range(400):
+            if j % 5 == 0:
+                b = matgen.vector(P.n, 200 + j)
+                x = np.zeros(P.n)
+                jobs.append(("cg", b, x, S.submit_cg(p, b, x, rtol=1e-9)))
+            else:
+                X = rng.uniform(-1, 1, A.n)
+                Y = np.zeros(A.m)
+                jobs.append(("spmm", X, Y, S.submit_spmm(a, X, Y)))
+        for kind, u, v, t in jobs:
+            r = S.wait(t)
+            assert r["status"] == cb.CB_SUCCESS
+            if kind == "cg":
+                assert r["converged"] and solvers.residual(P, u, v) <= 2e-9
+            else:
+                e, viol, _ = oracle.scaled_error(v, oracle.spmv(A, u, comp=True), oracle.scale(A, u), 1e-12)
+                assert viol == 0
+        assert S.stats()["completed"] == 400
+    MA.close()
+    MP.close()
