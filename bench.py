@@ -332,6 +332,48 @@ def run_serve(args, cb, matgen) -> int:
     return 0
 
 
+def run_tune(args, cb, matgen) -> int:
+    """cb_tune on the three full-size matrices in FP64 and FP32 storage: SpMV time with the default
+    options against the tuned ones (HIP events, 100 launches each), and the tuner's own time."""
+    import numpy as np
+    import torch
+
+    rows = {}
+    for wl in ("block3d", "poisson", "powerlaw"):
+        A = make_matrix(wl, 100)
+        x = matgen.vector(A.n, 1)
+        for vt in ("f64", "f32"):
+            dt = torch.float64 if vt == "f64" else torch.float32
+            xd = torch.from_numpy(x).to("cuda", dt)
+            yd = torch.empty(A.m, dtype=dt, device="cuda")
+            M = cb.CbMatrix.from_csr(A, value_type=vt)
+            _, k_def = time_calls(lambda: M.spmv(xd, yd), 100, 10)
+            M.close()
+            t = time.perf_counter()
+            Mt, best, cands = cb.cb_tune(A, value_type=vt)
+            tune_s = time.perf_counter() - t
+            _, k_tun = time_calls(lambda: Mt.spmv(xd, yd), 100, 10)
+            Mt.close()
+            key = f"{wl}_{vt}"
+            rows[key] = {"default_us": k_def * 1e6, "tuned_us": k_tun * 1e6, "speedup": k_def / k_tun,
+                         "tune_seconds": tune_s, "candidates": len(cands),
+                         "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "wave_nnz")}}
+            log(f"{key}: default {k_def * 1e6:.1f} us, tuned {k_tun * 1e6:.1f} us ({k_def / k_tun:.3f}x) "
+                f"in {tune_s:.1f}s, best {rows[key]['best']}; candidates: " + "; ".join(
+                    f"agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) rr={c['row_reduce']} "
+                    f"wn={c['opt']['wave_nnz']} {c['us']:.1f}" for c in cands))
+            del xd, yd
+            torch.cuda.empty_cache()
+    geo = float(np.exp(np.mean([np.log(r["speedup"]) for r in rows.values()])))
+    out = {"metric": "autotuned SpMV speedup over default options (geometric mean)", "value": round(geo, 4),
+           "unit": "x", "n_gpus": 1, "steps": 100, "warmup": 10, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": "cb_tune on the 3D block (100^3 x 3), 192^3 Poisson and 4M power-law matrices"},
+           "roofline": None, "cpu_baseline": None, "extra": rows}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +399,9 @@ def main() -> int:
                     help="instead of the SpMV line: the serving workload (256 resident matrices, SpMM and CG "
                          "requests with Poisson arrivals), p50/p99 latency and solves/s")
     ap.add_argument("--requests", type=int, default=1000, help="requests of the serving workload")
+    ap.add_argument("--tune", action="store_true",
+                    help="instead of the SpMV line: the autotuner on the block, Poisson and power-law matrices in "
+                         "FP64 and FP32, tuned against default options")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -386,6 +431,8 @@ def main() -> int:
         return run_cg(args, cb, matgen)
     if args.serve:
         return run_serve(args, cb, matgen)
+    if args.tune:
+        return run_tune(args, cb, matgen)
     t = time.perf_counter()
     A = make_matrix(args.workload, args.side)
     x = matgen.vector(A.n, 1)

@@ -312,6 +312,51 @@ cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, doub
 /* Message for the last non-success status returned on this thread. */
 const char *cb_last_error(void);
 
+/* ---- Autotuner (NEXT: per-matrix layout choices by measurement) ----
+ *
+ * cb_tune converts the matrix under a short list of candidate options and times cb_spmv on each
+ * (HIP events on `stream`, median of reps launches with x = 1 and beta = 0), by coordinate
+ * descent from `base` over: column aggregation on/off, the format thresholds th1/th2 (the
+ * paper's (32, 128), COO for everything below Dense at 200, COO only), the row-sum mode, and the
+ * work per wavefront (half and twice the automatic size).  A choice is kept when it is at least
+ * 1 % faster.  Every candidate computes the same product within the storage precision's
+ * tolerance; the tile size stays 16 (the one-byte (row, column) codes).  The tuner allocates:
+ * candidate structures, x and y. */
+#define CB_TUNE_MAX_CANDIDATES 16
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(cb_tune_options_t) */
+    int32_t reps;           /* timed launches per candidate (after 3 untimed); 20 */
+    int32_t max_candidates; /* 1 .. CB_TUNE_MAX_CANDIDATES; CB_TUNE_MAX_CANDIDATES */
+    int32_t reserved32;
+    int64_t reserved[4];
+} cb_tune_options_t;
+
+typedef struct {
+    cb_options_t opt;       /* the candidate's options as given to cb_create */
+    double us;              /* median kernel time of one cb_spmv, microseconds */
+    int64_t spmv_bytes;     /* its algorithmic bytes per launch */
+    int32_t col_agg;        /* resolved aggregation */
+    int32_t row_reduce;     /* resolved row-sum mode */
+} cb_tune_candidate_t;
+
+typedef struct {
+    int32_t ncandidates;
+    int32_t best;           /* index into cand */
+    cb_tune_candidate_t cand[CB_TUNE_MAX_CANDIDATES];
+} cb_tune_report_t;
+
+cb_status_t cb_tune_options_default(cb_tune_options_t *opt);
+
+/* Tunes the options for the CSR matrix (arguments as cb_create; base NULL = defaults, its
+ * value_type and vector_f64 are kept).  *best receives the fastest candidate's options; out, if
+ * not NULL, receives that candidate's handle (else it is destroyed); report may be NULL.  Errors
+ * as cb_create, plus CB_ERROR_INVALID_VALUE for bad tuner options and CB_ERROR_NOT_SUPPORTED for
+ * lb_mode CB_LB_PAPER in base (the tuner works on the streaming kernel's structures). */
+cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                    const int32_t *col_idx, const double *values, const cb_options_t *base,
+                    const cb_tune_options_t *topt, cb_options_t *best, cb_tune_report_t *report, void *stream);
+
 /* ---- Serving loop (NEXT to the solvers): many resident matrices, continuous batching ----
  *
  * A server keeps registered (resident) handles and serves requests on them from a worker thread

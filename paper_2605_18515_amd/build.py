@@ -45,6 +45,7 @@ def build(verbose: bool = False) -> str:
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "kernels.hip"), "-o", os.path.join(OUT, "kernels.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "solver.hip"), "-o", os.path.join(OUT, "solver.o")],
         [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "serve.hip"), "-o", os.path.join(OUT, "serve.o")],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(SRC, "tune.hip"), "-o", os.path.join(OUT, "tune.o")],
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         for f in [ex.submit(_run, j) for j in jobs]:
@@ -52,7 +53,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-pthread", "-o", tmp,
           os.path.join(OUT, "convert.o"), os.path.join(OUT, "capi.o"), os.path.join(OUT, "kernels.o"),
-          os.path.join(OUT, "solver.o"), os.path.join(OUT, "serve.o")])
+          os.path.join(OUT, "solver.o"), os.path.join(OUT, "serve.o"), os.path.join(OUT, "tune.o")])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

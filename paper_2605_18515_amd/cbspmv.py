@@ -97,6 +97,25 @@ class CbServerStats(ctypes.Structure):
 
 
 CB_REQ_SPMM, CB_REQ_CG = range(2)
+CB_TUNE_MAX_CANDIDATES = 16
+
+
+class CbTuneOptions(ctypes.Structure):
+    _fields_ = [("struct_size", _u32), ("reps", _i32), ("max_candidates", _i32), ("reserved32", _i32),
+                ("reserved", _i64 * 4)]
+
+
+class CbTuneCandidate(ctypes.Structure):
+    _fields_ = [("opt", CbOptions), ("us", _dbl), ("spmv_bytes", _i64), ("col_agg", _i32), ("row_reduce", _i32)]
+
+
+class CbTuneReport(ctypes.Structure):
+    _fields_ = [("ncandidates", _i32), ("best", _i32), ("cand", CbTuneCandidate * CB_TUNE_MAX_CANDIDATES)]
+
+
+_lib.cb_tune_options_default.argtypes = [ctypes.POINTER(CbTuneOptions)]
+_lib.cb_tune.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions),
+                         ctypes.POINTER(CbTuneOptions), ctypes.POINTER(CbOptions), ctypes.POINTER(CbTuneReport), _p]
 
 _lib.cb_server_options_default.argtypes = [ctypes.POINTER(CbServerOptions)]
 _lib.cb_server_create.argtypes = [ctypes.POINTER(CbServerOptions), ctypes.POINTER(_p)]
@@ -125,7 +144,8 @@ _lib.cb_last_error.restype = ctypes.c_char_p
 for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
            "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_cg_options_default", "cb_cg_workspace_bytes",
            "cb_cg", "cb_cg_refine", "cb_server_options_default", "cb_server_create", "cb_server_add_matrix",
-           "cb_server_submit", "cb_server_poll", "cb_server_wait", "cb_server_stats", "cb_server_destroy"):
+           "cb_server_submit", "cb_server_poll", "cb_server_wait", "cb_server_stats", "cb_server_destroy",
+           "cb_tune_options_default", "cb_tune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -512,3 +532,36 @@ class CbServer:
 
     def __exit__(self, *a):
         self.close()
+
+
+def cb_tune_options_default(**kw) -> CbTuneOptions:
+    o = CbTuneOptions()
+    _check(_lib.cb_tune_options_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k) or k.startswith("reserved") or k == "struct_size":
+            raise ValueError(f"unknown tuner option {k}")
+        setattr(o, k, v)
+    return o
+
+
+_OPT_NAMES = [n for n, _ in CbOptions._fields_ if not n.startswith("reserved") and n != "struct_size"]
+
+
+def cb_tune(csr, stream=None, keep: bool = True, reps: int = 20, **base):
+    """Tunes the options for csr (cb_tune).  Returns (CbMatrix or None, best options as a dict,
+    candidates: list of dicts with the options, us, spmv_bytes, col_agg, row_reduce, best)."""
+    rp, ci, va = _csr_args(csr.row_ptr, csr.col_idx, csr.values)
+    b = cb_options_default(**base)
+    best = CbOptions()
+    rep = CbTuneReport()
+    h = _p()
+    _check(_lib.cb_tune(ctypes.byref(h) if keep else None, csr.m, csr.n, csr.nnz, rp.ctypes.data, ci.ctypes.data,
+                        va.ctypes.data, ctypes.byref(b), ctypes.byref(cb_tune_options_default(reps=reps)),
+                        ctypes.byref(best), ctypes.byref(rep), _stream_ptr(stream)))
+    cands = []
+    for i in range(rep.ncandidates):
+        c = rep.cand[i]
+        cands.append({"opt": {n: getattr(c.opt, n) for n in _OPT_NAMES}, "us": c.us, "spmv_bytes": c.spmv_bytes,
+                      "col_agg": c.col_agg, "row_reduce": c.row_reduce, "best": i == rep.best})
+    M = CbMatrix(h.value, best.value_type) if keep else None
+    return M, {n: getattr(best, n) for n in _OPT_NAMES}, cands

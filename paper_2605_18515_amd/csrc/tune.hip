@@ -1,0 +1,228 @@
+// Autotuner: per-matrix layout options chosen by timing cb_spmv on candidate structures.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "cb_host.h"
+#include "cbspmv.h"
+
+namespace {
+
+cb_status_t fail(cb_status_t st, const std::string &msg) {
+    cbh::set_last_error(msg);
+    return st;
+}
+
+cb_status_t hipfail(hipError_t e, const char *what) {
+    return fail(CB_ERROR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+__global__ void fill_one(void *x, int64_t n, int wide) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (wide) static_cast<double *>(x)[i] = 1.0;
+        else static_cast<float *>(x)[i] = 1.0f;
+    }
+}
+
+struct Bench {
+    hipStream_t s;
+    void *x = nullptr, *y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int reps = 20;
+};
+
+// median kernel time of one cb_spmv (microseconds) over reps single-launch measurements
+cb_status_t time_spmv(cb_matrix_t A, Bench &B, double &us) {
+    std::vector<float> t;
+    for (int i = 0; i < 3; ++i) {
+        const cb_status_t st = cb_spmv(A, 1.0, B.x, 0.0, B.y, B.s);
+        if (st != CB_SUCCESS) return st;
+    }
+    for (int i = 0; i < B.reps; ++i) {
+        hipEventRecord(B.e0, B.s);
+        const cb_status_t st = cb_spmv(A, 1.0, B.x, 0.0, B.y, B.s);
+        if (st != CB_SUCCESS) return st;
+        hipEventRecord(B.e1, B.s);
+        hipError_t e = hipEventSynchronize(B.e1);
+        if (e != hipSuccess) return hipfail(e, "timing");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, B.e0, B.e1);
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    us = 1e3 * (double)t[t.size() / 2];
+    return CB_SUCCESS;
+}
+
+struct Tuner {
+    int64_t m, n, nnz;
+    const int64_t *rp;
+    const int32_t *ci;
+    const double *va;
+    Bench B;
+    std::vector<cb_tune_candidate_t> cand;
+    std::vector<cb_matrix_t> handles;
+    int best = -1;
+    int max_cand = CB_TUNE_MAX_CANDIDATES;
+
+    // converts and times one candidate; returns its index (-1 when the candidate list is full)
+    cb_status_t eval(const cb_options_t &o, int &idx) {
+        idx = -1;
+        if ((int)cand.size() >= max_cand) return CB_SUCCESS;
+        cb_matrix_t A = nullptr;
+        cb_status_t st = cb_create(&A, m, n, nnz, rp, ci, va, &o, B.s);
+        if (st != CB_SUCCESS) return st;
+        cb_tune_candidate_t c{};
+        c.opt = o;
+        cb_info_t info{};
+        info.struct_size = sizeof(cb_info_t);
+        if ((st = cb_get_info(A, &info)) != CB_SUCCESS || (st = time_spmv(A, B, c.us)) != CB_SUCCESS) {
+            cb_destroy(A);
+            return st;
+        }
+        c.spmv_bytes = info.spmv_bytes;
+        c.col_agg = info.col_agg;
+        c.row_reduce = info.row_reduce;
+        idx = (int)cand.size();
+        cand.push_back(c);
+        handles.push_back(A);
+        // keep only the best structure on the device
+        if (best < 0 || c.us < 0.99 * cand[best].us) {
+            if (best >= 0) {
+                cb_destroy(handles[best]);
+                handles[best] = nullptr;
+            }
+            best = idx;
+        } else {
+            cb_destroy(A);
+            handles[idx] = nullptr;
+        }
+        return CB_SUCCESS;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+cb_status_t cb_tune_options_default(cb_tune_options_t *opt) {
+    if (!opt) return fail(CB_ERROR_INVALID_VALUE, "NULL options");
+    *opt = cb_tune_options_t{};
+    opt->struct_size = sizeof(cb_tune_options_t);
+    opt->reps = 20;
+    opt->max_candidates = CB_TUNE_MAX_CANDIDATES;
+    return CB_SUCCESS;
+}
+
+cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                    const int32_t *col_idx, const double *values, const cb_options_t *base,
+                    const cb_tune_options_t *topt, cb_options_t *best, cb_tune_report_t *report, void *stream) {
+    if (!best) return fail(CB_ERROR_INVALID_VALUE, "NULL output");
+    cb_tune_options_t to;
+    cb_tune_options_default(&to);
+    if (topt) {
+        if (topt->struct_size != sizeof(cb_tune_options_t))
+            return fail(CB_ERROR_INVALID_VALUE, "cb_tune_options_t.struct_size mismatch");
+        to = *topt;
+    }
+    if (to.reps < 1 || to.reps > 10000 || to.max_candidates < 1 || to.max_candidates > CB_TUNE_MAX_CANDIDATES)
+        return fail(CB_ERROR_INVALID_VALUE, "invalid tuner options");
+    cb_options_t b0;
+    cb_options_default(&b0);
+    if (base) {
+        if (base->struct_size != sizeof(cb_options_t))
+            return fail(CB_ERROR_INVALID_VALUE, "cb_options_t.struct_size does not match this library");
+        b0 = *base;
+    }
+    if (b0.lb_mode == CB_LB_PAPER) return fail(CB_ERROR_NOT_SUPPORTED, "the tuner works on natural-order structures");
+    Tuner T;
+    T.m = m;
+    T.n = n;
+    T.nnz = nnz;
+    T.rp = row_ptr;
+    T.ci = col_idx;
+    T.va = values;
+    T.max_cand = to.max_candidates;
+    T.B.s = (hipStream_t)stream;
+    T.B.reps = to.reps;
+    const int wide = b0.value_type == CB_VALUE_F64 || b0.vector_f64;
+    const size_t es = wide ? 8 : 4;
+    hipError_t e = hipMalloc(&T.B.x, std::max<size_t>(es * (size_t)std::max<int64_t>(n, 1), 256));
+    if (e == hipSuccess) e = hipMalloc(&T.B.y, std::max<size_t>(es * (size_t)std::max<int64_t>(m, 1), 256));
+    if (e == hipSuccess) e = hipEventCreate(&T.B.e0);
+    if (e == hipSuccess) e = hipEventCreate(&T.B.e1);
+    cb_status_t st = CB_SUCCESS;
+    if (e != hipSuccess) st = hipfail(e, "tuner buffers");
+    if (st == CB_SUCCESS && n > 0) {
+        hipLaunchKernelGGL(fill_one, dim3(256), dim3(256), 0, T.B.s, T.B.x, n, wide);
+        if ((e = hipGetLastError()) != hipSuccess) st = hipfail(e, "tuner fill");
+    }
+    // coordinate descent: every knob tried against the best options so far
+    int idx = -1;
+    if (st == CB_SUCCESS) st = T.eval(b0, idx);
+    if (st == CB_SUCCESS && idx >= 0) {
+        auto cur = [&]() { return T.cand[T.best].opt; };
+        // column aggregation: the other choice than the resolved one
+        {
+            cb_options_t o = cur();
+            o.col_agg = T.cand[T.best].col_agg ? 0 : 1;
+            if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
+        // format thresholds: COO below Dense at 200, COO only (the streaming kernel reads COO and
+        // CSR entries alike, so a CSR tile's row header is extra bytes there)
+        for (const auto th : {std::pair<int, int>{257, 200}, std::pair<int, int>{257, 257}}) {
+            cb_options_t o = cur();
+            if (o.th1 == th.first && o.th2 == th.second) continue;
+            o.th1 = th.first;
+            o.th2 = th.second;
+            if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
+        // row sums
+        {
+            const int rr0 = T.cand[T.best].row_reduce;
+            const std::vector<int> alts = wide ? std::vector<int>{rr0 == 0 ? 1 : 0} : std::vector<int>{rr0 == 2 ? 1 : 2};
+            for (int rr : alts) {
+                cb_options_t o = cur();
+                o.row_reduce = rr;
+                if (st == CB_SUCCESS) st = T.eval(o, idx);
+            }
+        }
+        // work per wavefront: half and twice the current ranges' mean
+        {
+            cb_matrix_t hb = T.handles[T.best];
+            cb_info_t info{};
+            info.struct_size = sizeof(cb_info_t);
+            if (st == CB_SUCCESS && hb) st = cb_get_info(hb, &info);
+            const double mean = info.wave_nnz_mean;
+            for (double f : {0.5, 2.0}) {
+                cb_options_t o = cur();
+                o.wave_nnz = std::max<int64_t>(64, (int64_t)(f * mean));
+                if (st == CB_SUCCESS && mean > 0) st = T.eval(o, idx);
+            }
+        }
+    }
+    if (st == CB_SUCCESS && T.best >= 0) {
+        *best = T.cand[T.best].opt;
+        if (report) {
+            *report = cb_tune_report_t{};
+            report->ncandidates = (int32_t)T.cand.size();
+            report->best = T.best;
+            for (size_t i = 0; i < T.cand.size(); ++i) report->cand[i] = T.cand[i];
+        }
+        if (out) {
+            *out = T.handles[T.best];
+            T.handles[T.best] = nullptr;
+        }
+    }
+    for (cb_matrix_t h : T.handles)
+        if (h) cb_destroy(h);
+    if (T.B.x) hipFree(T.B.x);
+    if (T.B.y) hipFree(T.B.y);
+    if (T.B.e0) hipEventDestroy(T.B.e0);
+    if (T.B.e1) hipEventDestroy(T.B.e1);
+    return st;
+}
+
+}  // extern "C"
