@@ -332,6 +332,58 @@ def run_serve(args, cb, matgen) -> int:
     return 0
 
 
+def run_ablation(args, cb, matgen) -> int:
+    """Section 4's ablation (Fig. 12) on the synthetic matrices, FP64: SpMV time under each option
+    set of diagnostics.ABLATION; the non-zeros-per-tile histogram of the plain partition (Fig. 3);
+    non-zeros per unit of work with and without Algorithm 2 (Fig. 4); converter time against nnz
+    (Fig. 13(b)) on the block matrix at three sizes."""
+    import torch
+
+    from paper_2605_18515_amd import diagnostics
+
+    res = {}
+    for wl in ("block3d", "poisson", "powerlaw"):
+        A = make_matrix(wl, 100)
+        x = torch.from_numpy(matgen.vector(A.n, 1)).to("cuda")
+        y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+        row = {"nnz": A.nnz}
+        for name, opts in diagnostics.ABLATION.items():
+            M = cb.CbMatrix.from_csr(A, **opts)
+            _, k = time_calls(lambda: M.spmv(x, y), 100, 10)
+            inf = M.info
+            row[name] = {"us": k * 1e6, "gflops": 2.0 * A.nnz / k / 1e9, "spmv_bytes": inf["spmv_bytes"],
+                         "convert_seconds": inf["convert_seconds"], "col_agg": inf["col_agg"],
+                         "tiles": inf["ntiles"], "balance": diagnostics.balance(M)}
+            if name == "CB-I":
+                row["tile_histogram_plain"] = diagnostics.tile_nnz_histogram(M)
+            M.close()
+            log(f"{wl} {name}: {k * 1e6:.1f} us, {2.0 * A.nnz / k / 1e9:.0f} GFLOP/s, tiles {inf['ntiles']}, "
+                f"wave nnz std {row[name]['balance']['wave_nnz_std']:.0f}, "
+                f"quantum nnz std {row[name]['balance']['quantum_nnz_std']:.0f}")
+        base = row["CB-I"]["us"]
+        row["speedup_vs_CB-I"] = {n: base / row[n]["us"] for n in diagnostics.ABLATION}
+        log(f"{wl}: speedup over CB-I {row['speedup_vs_CB-I']}; plain tiles by nnz "
+            f"{row['tile_histogram_plain']['shares']}")
+        res[wl] = row
+        del x, y
+        torch.cuda.empty_cache()
+    conv = []
+    for side in (25, 50, 100):
+        A = matgen.block_3d(side, 3, 10.0, seed=1)
+        M = cb.CbMatrix.from_csr(A, device=False)
+        conv.append({"nnz": A.nnz, "convert_seconds": M.info["convert_seconds"]})
+        M.close()
+    log(f"converter time against nnz: {conv}")
+    out = {"metric": "ablation: SpMV speedup of the full method over CB-I (3D block matrix, FP64)",
+           "value": round(res["block3d"]["speedup_vs_CB-I"]["CB (contiguous)"], 4), "unit": "x", "n_gpus": 1,
+           "steps": 100, "warmup": 10, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "ablation on the 3D block (100^3 x 3), 192^3 Poisson and 4M power-law matrices"},
+           "roofline": None, "cpu_baseline": None, "extra": {"matrices": res, "converter": conv}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def run_tune(args, cb, matgen) -> int:
     """cb_tune on the three full-size matrices in FP64 and FP32 storage: SpMV time with the default
     options against the tuned ones (HIP events, 100 launches each), and the tuner's own time."""
@@ -399,6 +451,10 @@ def main() -> int:
                     help="instead of the SpMV line: the serving workload (256 resident matrices, SpMM and CG "
                          "requests with Poisson arrivals), p50/p99 latency and solves/s")
     ap.add_argument("--requests", type=int, default=1000, help="requests of the serving workload")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the SpMV line: the ablation (CB-I, CB-II, full with Algorithm 2 and with the "
+                         "contiguous split) on the three full-size matrices in FP64, the tile histogram, the work "
+                         "balance and the converter's time against nnz")
     ap.add_argument("--tune", action="store_true",
                     help="instead of the SpMV line: the autotuner on the block, Poisson and power-law matrices in "
                          "FP64 and FP32, tuned against default options")
@@ -433,6 +489,8 @@ def main() -> int:
         return run_serve(args, cb, matgen)
     if args.tune:
         return run_tune(args, cb, matgen)
+    if args.ablation:
+        return run_ablation(args, cb, matgen)
     t = time.perf_counter()
     A = make_matrix(args.workload, args.side)
     x = matgen.vector(A.n, 1)
