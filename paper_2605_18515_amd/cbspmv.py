@@ -23,6 +23,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2605_18515_amd.build)")
 
+# torch ships its own HIP runtime under the same soname as the system one the library links to; the
+# first one loaded serves the whole process.  Loading torch first makes the library bind to torch's
+# runtime (one runtime, shared streams); the other order leaves torch's HIP without a device.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library also works without torch (raw device pointers)
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 CB_SUCCESS, CB_ERROR_INVALID_VALUE, CB_ERROR_OUT_OF_MEMORY, CB_ERROR_HIP, CB_ERROR_NOT_SUPPORTED, \

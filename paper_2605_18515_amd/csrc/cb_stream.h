@@ -36,11 +36,16 @@
 // q + 8, q + 12 of one matrix-core operand lane are adjacent.
 #pragma once
 
+#ifndef CB_TUNE_RING_CHUNKS
+#define CB_TUNE_RING_CHUNKS 4
+#endif
+
 namespace cbs {
 
 constexpr int kChunk = 1024;      // payload bytes one wavefront-wide 16-byte load covers
-constexpr int kRingChunks = 4;    // payload chunks a batch may touch (the kernel's LDS ring)
-constexpr int kRingBits = 12;     // the ring's 4096 bytes, the width of the packed positions
+constexpr int kRingChunks = CB_TUNE_RING_CHUNKS;  // payload chunks a batch may touch (the kernel's LDS ring)
+constexpr int kRingBits = kRingChunks == 2 ? 11 : kRingChunks == 4 ? 12 : 13;  // log2 of the ring's bytes: the
+                                                                              // width of the packed positions
 static_assert(kChunk * kRingChunks == 1 << kRingBits, "packed positions address the ring");
 constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
 constexpr int kBatchPanels = 4;   // consecutive panels a batch may touch (accumulator slots)
