@@ -36,6 +36,9 @@
 // q + 8, q + 12 of one matrix-core operand lane are adjacent.
 #pragma once
 
+#ifndef CB_TUNE_BATCH_TILES
+#define CB_TUNE_BATCH_TILES 16
+#endif
 #ifndef CB_TUNE_RING_CHUNKS
 #define CB_TUNE_RING_CHUNKS 4
 #endif
@@ -47,7 +50,8 @@ constexpr int kRingChunks = CB_TUNE_RING_CHUNKS;  // payload chunks a batch may 
 constexpr int kRingBits = kRingChunks == 2 ? 11 : kRingChunks == 4 ? 12 : 13;  // log2 of the ring's bytes: the
                                                                               // width of the packed positions
 static_assert(kChunk * kRingChunks == 1 << kRingBits, "packed positions address the ring");
-constexpr int kBatchTiles = 16;   // tiles per batch (their records fill one 16-lane DPP row)
+constexpr int kBatchTiles = CB_TUNE_BATCH_TILES;  // tiles per batch (at most 16: 4-bit positions in the record word)
+static_assert(kBatchTiles >= 4 && kBatchTiles <= 16 && kBatchTiles % 4 == 0, "tile positions take 4 bits");
 constexpr int kBatchPanels = 4;   // consecutive panels a batch may touch (accumulator slots)
 constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream
 constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes readable past their ends
