@@ -36,7 +36,7 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 // byte offsets of every array inside the single device allocation
 struct Layout {
     size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
-        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, tile_rec, total;
+        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, tile_rec, panel_tile, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -71,6 +71,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)cbh::kBlk * NT : 0);
     L.tile_rec = put(stream ? 16 * NT : 0);
+    L.panel_tile = put(stream ? 4 * ((size_t)s.npanels + 1) : 0);
     L.total = off;
     return L;
 }
@@ -160,6 +161,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.batch_ptr, s.batch_ptr);
         put_array(stage, L.tile_cols, s.tile_cols);
         put_array(stage, L.tile_rec, s.tile_rec);
+        put_array(stage, L.panel_tile, s.panel_tile);
         e = hipMalloc(&A->dbuf, L.total);
         if (e != hipSuccess) {
             A->dbuf = nullptr;
@@ -187,6 +189,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.batch_ptr = dptr<int32_t>(A, L.batch_ptr);
     v.tile_cols = dptr<int32_t>(A, L.tile_cols);
     v.tile_rec = dptr<int32_t>(A, L.tile_rec);
+    v.panel_tile = dptr<int32_t>(A, L.panel_tile);
     v.m = s.m;
     v.n = s.n;
     v.nwaves = (int32_t)s.nwaves;
@@ -195,6 +198,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.col_agg = s.col_agg;
     v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
     v.row_reduce = s.row_reduce;
+    v.rows_kernel = s.spmv_kernel;
     // the device copy is the structure from now on
     std::vector<int32_t>().swap(s.tile_row);
     std::vector<int32_t>().swap(s.tile_col);
@@ -214,6 +218,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     std::vector<int32_t>().swap(s.batch_ptr);
     std::vector<int32_t>().swap(s.tile_cols);
     std::vector<int32_t>().swap(s.tile_rec);
+    std::vector<int32_t>().swap(s.panel_tile);
     A->on_device = true;
     return CB_SUCCESS;
 }
@@ -291,6 +296,7 @@ cb_status_t cb_options_default(cb_options_t *opt) {
     opt->th0 = 0.15;
     opt->wave_nnz = 0;
     opt->row_reduce = -1;
+    opt->spmv_kernel = -1;
     return CB_SUCCESS;
 }
 

@@ -30,6 +30,8 @@ struct DevView {
     int32_t nwaves, npanels, nprepass, col_agg;
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan
+    int32_t rows_kernel;          // natural order: 1 = the rows-per-lane kernel instead of the streaming one
+    const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
 };
 
 // One product of a batched launch: y = alpha A x + beta y for the natural-order structure d, its

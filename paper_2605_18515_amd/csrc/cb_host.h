@@ -54,6 +54,9 @@ struct HostStructure {
     int64_t flat_entries = 0, flat_runs = 0;  // COO/CSR entries and their (tile, row) runs
     int row_reduce = 0;                       // resolved: 0 LDS atomics, 1 DPP segmented scan, 2 FP64 atomics
     int vector_f64 = 1;                       // x and y are double
+    int spmv_kernel = 0;                      // resolved: 0 entries per lane, 1 rows per lane
+    // natural order: first tile of every panel (npanels + 1)
+    std::vector<int32_t> panel_tile;
 };
 
 int padding(int64_t index_bytes, int vsize);

@@ -235,6 +235,14 @@ void build_stream(HostStructure &s) {
     s.batch_ptr[NW] = (int32_t)(bs.size() / 4);
     s.nbatches = nb;
     s.nrecords = (int64_t)(bs.size() / 4);
+    s.panel_tile.assign((size_t)s.npanels + 1, 0);
+    {
+        int64_t t = 0;
+        for (int64_t p = 0; p <= s.npanels; ++p) {
+            while (t < s.ntiles && s.tile_row[t] < p) ++t;
+            s.panel_tile[(size_t)p] = (int32_t)t;
+        }
+    }
     s.tile_rec.resize((size_t)s.ntiles * 4);
     for (int64_t t = 0; t < s.ntiles; ++t) {
         const uint64_t vp = (uint64_t)s.tile_vp[t];
@@ -321,6 +329,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.row_reduce < -1 || opt.row_reduce > 2) { err = "row_reduce must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.spmv_kernel < -1 || opt.spmv_kernel > 1) { err = "spmv_kernel must be -1, 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
     const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
 
@@ -361,6 +370,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     s.nnz = nnz;
     s.vtype = opt.value_type;
     s.vector_f64 = opt.value_type == CB_VALUE_F64 || opt.vector_f64 ? 1 : 0;
+    s.spmv_kernel = opt.spmv_kernel > 0 ? 1 : 0;
     s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
     s.lb_mode = opt.lb_mode;
     s.quantum_tiles = opt.quantum_tiles;
@@ -792,6 +802,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.flat_run_mean = s.flat_runs ? (double)s.flat_entries / (double)s.flat_runs : 0.0;
     info.row_reduce = s.row_reduce;
     info.vector_f64 = s.vector_f64;
+    info.spmv_kernel = s.spmv_kernel;
 }
 
 }  // namespace cbh

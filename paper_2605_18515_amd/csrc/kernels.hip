@@ -663,6 +663,112 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJo
     stream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
+// ---- rows per lane (natural order) -----------------------------------------
+//
+// Each 16-lane group of the wavefront takes every fourth panel of the work range and walks the
+// panel's tiles; lane r of the group owns row r of the panel and keeps its sum in a register.  CSR
+// tiles: lane r multiplies the entries of row r (the tile's one-byte row starts give them);
+// COO tiles: lanes take entries r, r + 16, ... and add their products into the group's 16 row sums
+// in LDS; Dense tiles: lane r takes row r's 16 values, occupancy bits honoured.  The group gathers a
+// tile's 16 x values (lane c takes column c) into its LDS x area; the next tile's record and column
+// are loaded while the current tile is multiplied.  Sums are kept in FP64.
+template <int VT, bool AGG>
+__global__ __launch_bounds__(kBlockThreads) void spmv_rows_kernel(DevView d, typename Val<VT>::A alpha,
+                                                                   typename Val<VT>::A beta,
+                                                                   const typename Val<VT>::A *__restrict__ x,
+                                                                   typename Val<VT>::A *__restrict__ y) {
+    static_assert(kWavesPerBlock == 1, "one wavefront per workgroup");
+    using A = typename Val<VT>::A;
+    constexpr int VS = Val<VT>::kSize;
+    __shared__ double gacc[4][16];
+    __shared__ A xs[4][16];
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, r = lane & 15;
+    const int w = xcd_block(blockIdx.x, gridDim.x);
+    if (w >= d.nwaves) return;
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    if (t0 >= t1) return;
+    const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
+    const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
+    const i32x4 *recs = reinterpret_cast<const i32x4 *>(d.tile_rec);
+    gacc[g][r] = 0.0;
+    // column of lane r in tile t: tile_cols holds column c at position (c mod 4) * 4 + c / 4
+    auto column = [&](int t, int cb) -> int {
+        if (AGG) return d.tile_cols[16 * (size_t)t + (r & 3) * 4 + (r >> 2)];
+        const int64_t c = 16 * (int64_t)cb + r;
+        return c < d.n ? (int)c : 0;
+    };
+    for (int p = p_first + g; p <= p_last; p += 4) {
+        const int tb = max(d.panel_tile[p], t0), te = min(d.panel_tile[p + 1], t1);
+        double acc = 0.0;
+        i32x4 rec_n = recs[min(tb, t1 - 1)];
+        int col_n = column(min(tb, t1 - 1), rec_n.w);
+        for (int t = tb; t < te; ++t) {
+            const i32x4 rec = rec_n;
+            const int col = col_n;
+            if (t + 1 < te) {
+                rec_n = recs[t + 1];
+                col_n = column(t + 1, rec_n.w);
+            }
+            const A xv = x[col];
+            const uint64_t vp = (uint64_t)(uint32_t)rec.x | ((uint64_t)((uint32_t)rec.y & 0xFFFFu) << 32);
+            const int type = ((uint32_t)rec.y >> 16) & 3, nnz = (int)((uint32_t)rec.y >> 18) + 1;
+            const uint8_t *base = d.payload + vp;
+            xs[g][r] = xv;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the group's x values are in LDS
+            __builtin_amdgcn_wave_barrier();
+            if (type == 1) {
+                // CSR: row starts, codes, values
+                const int s0 = base[r], s1 = r < 15 ? (int)base[r + 1] : nnz;
+                const uint8_t *codes = base + 16;
+                const uint8_t *vals = codes + nnz + pad_bytes(16 + nnz, VS);
+                int e = s0;
+                for (; e + 1 < s1; e += 2) {
+                    const uint32_t c0 = codes[e], c1 = codes[e + 1];
+                    const A v0 = Val<VT>::load(vals, e), v1 = Val<VT>::load(vals, e + 1);
+                    acc += (double)v0 * (double)xs[g][c0 >> 4];
+                    acc += (double)v1 * (double)xs[g][c1 >> 4];
+                }
+                if (e < s1) acc += (double)Val<VT>::load(vals, e) * (double)xs[g][codes[e] >> 4];
+            } else if (type == 0) {
+                // COO: codes, values; entries r, r + 16, ...
+                const uint8_t *vals = base + nnz + pad_bytes(nnz, VS);
+                for (int e = r; e < nnz; e += 16) {
+                    const uint32_t c = base[e];
+                    const double prod = (double)Val<VT>::load(vals, e) * (double)xs[g][c >> 4];
+                    __hip_atomic_fetch_add(&gacc[g][c & 15], prod, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            } else {
+                // Dense: 256 values, then the 32-byte occupancy bitmap
+                const uint32_t bits = (uint32_t)base[256 * VS + 2 * r] | ((uint32_t)base[256 * VS + 2 * r + 1] << 8);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    A v[4];
+                    Val<VT>::load4(base, 16 * r + 4 * q, v);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if ((bits >> (4 * q + j)) & 1u) acc += (double)v[j] * (double)xs[g][4 * q + j];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // the panel's row sums: registers plus the COO contributions in LDS
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        acc += gacc[g][r];
+        gacc[g][r] = 0.0;
+        const int64_t row = 16 * (int64_t)p + r;
+        if (tb < te && row < d.m) {
+            const A v = (A)acc;
+            if ((p == p_first && sh_first) || (p == p_last && sh_last)) {
+                global_add(&y[row], alpha * v);
+            } else {
+                A out = alpha * v;
+                if (beta != A(0)) out += beta * y[row];
+                y[row] = out;
+            }
+        }
+    }
+}
+
 // ---- k right-hand sides ---------------------------------------------------
 //
 // Y = alpha*A*X + beta*Y with X (n x k) and Y (m x k) row-major.  A launch
@@ -945,7 +1051,14 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     // row sums: FP32 LDS atomics are slow where many lanes of a pass hit one row (long runs),
     // the segmented scan costs the same whatever the runs; the handle holds the choice
     const A a = (A)alpha, b = (A)beta;
-    if (d.natural_order) {
+    if (d.natural_order && d.rows_kernel) {
+        if (d.col_agg)
+            hipLaunchKernelGGL((spmv_rows_kernel<VT, true>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
+                               (const A *)x, (A *)y);
+        else
+            hipLaunchKernelGGL((spmv_rows_kernel<VT, false>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
+                               (const A *)x, (A *)y);
+    } else if (d.natural_order) {
         // double accumulators already: modes 0 and 2 are the same kernel
         constexpr bool kWide = std::is_same<A, double>::value;
         constexpr int kRR2 = kWide ? 0 : 2;

@@ -125,6 +125,32 @@ def test_row_reduce_modes(cb, name, rr, vtype):
     check(cb, A, x, 1.5, -0.5, y0, vtype, label=f"{name} rr={rr} shared", row_reduce=rr, wave_nnz=64)
 
 
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16", "wide"])
+@pytest.mark.parametrize("name", ["block8", "power", "lap64", "dense_mix", "rect", "wide", "poisson12"])
+def test_rows_kernel(cb, name, vtype):
+    """The rows-per-lane kernel (spmv_kernel = 1): every format mix, with and without aggregation,
+    alpha and beta, and panels shared between work ranges."""
+    A = SMALL[name]()
+    x = matgen.vector(A.n, 14)
+    y0 = matgen.vector(A.m, 5, stream=matgen.STREAM_Y0)
+    vt = "f32" if vtype == "wide" else vtype
+    extra = {"vector_f64": 1} if vtype == "wide" else {}
+    for agg, th in ((0, (32, 128)), (1, (32, 128)), (1, (8, 40)), (0, (1, 1)), (1, (300, 300))):
+        check(cb, A, x, vtype=vt, label=f"{name} rows agg={agg} th={th}", col_agg=agg, th1=th[0], th2=th[1],
+              spmv_kernel=1, **extra)
+    check(cb, A, x, 1.5, -0.5, y0, vt, label=f"{name} rows shared", spmv_kernel=1, wave_nnz=64, **extra)
+
+
+def test_rows_kernel_exact_bitwise(cb):
+    rng = np.random.default_rng(29)
+    for B in (SMALL["block8"](), SMALL["dense_mix"](), SMALL["power"]()):
+        A = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx, rng.integers(-64, 65, B.nnz).astype(np.float64) / 64)
+        x = rng.integers(-64, 65, A.n).astype(np.float64) / 64
+        ref = oracle.spmv(A, x)
+        for th in ((32, 128), (8, 40)):
+            assert np.array_equal(run_spmv(cb, A, x, spmv_kernel=1, th1=th[0], th2=th[1]), ref)
+
+
 def rounded(A, vtype):
     return matgen.Csr(A.m, A.n, A.row_ptr, A.col_idx, lowp(A.values, vtype))
 
