@@ -487,21 +487,26 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         const i32x2 rl = rec[min(lane, kBatchTiles - 1)];
         const int endv = rl.y;
         const uint32_t pkv = (uint32_t)rl.x;
-        // tile of entry E in the pass starting at entry e0, and its record word; j: the tile holding
-        // entry e0, advanced to the tile holding entry e0 + 64
+        // pass (64 entries) holding each flat tile's last entry
+        const int passv = lane < nflat ? endv / kWave : -1;
+        // tile of entry E in the pass starting at entry e0 (a multiple of 64), and its record word;
+        // j: the tile holding entry e0, advanced to the tile holding entry e0 + 64.  The tiles that
+        // end inside the pass are j, j + 1, ...: their number comes from one ballot, and only they
+        // are walked (selects, not branches, keep the walk uniform)
         auto tile_of = [&](int e0, int E, int &j, uint32_t &pk) {
             int ti = j;
             pk = __builtin_amdgcn_readlane(pkv, min(j, kBatchTiles - 1));
-            while (j < nflat) {
-                const int ej = __builtin_amdgcn_readlane(endv, j);
-                if (ej >= e0 + kWave) break;
-                // selects, not a branch, keep the loop uniform
-                const uint32_t pn = __builtin_amdgcn_readlane(pkv, min(j + 1, kBatchTiles - 1));
-                const bool past = E > ej;
+            const int c = __builtin_popcountll(__builtin_amdgcn_ballot_w64(passv == e0 / kWave));
+            for (int k = 0; k < c; ++k) {
+                const int i = j + k;
+                const int ei = __builtin_amdgcn_readlane(endv, i);
+                // i + 1 <= 16: lanes from kBatchTiles on hold the last record again
+                const uint32_t pn = __builtin_amdgcn_readlane(pkv, i + 1);
+                const bool past = E > ei;
                 ti += past ? 1 : 0;
                 pk = past ? pn : pk;
-                ++j;
             }
+            j += c;
             return ti;
         };
         // one entry: code, value and x through the tile's packed record word
@@ -533,7 +538,17 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
             accumulate(prod_a, ta, ca, pa, true);
             accumulate(prod_b, tb, cb, pb, Eb < etot);
         }
-        for (; e0 < etot; e0 += kWave) {
+        // full passes, then the partial one: only the last pass needs the lane mask
+        const int efull = etot & ~(kWave - 1);
+        for (; e0 < efull; e0 += kWave) {
+            const int E = e0 + lane;
+            uint32_t pk;
+            const int ti = tile_of(e0, E, j, pk);
+            uint32_t code;
+            const A prod = entry(pk, E, code);
+            accumulate(prod, ti, code, pk, true);
+        }
+        if (e0 < etot) {
             const int E = e0 + lane;
             uint32_t pk;
             const int ti = tile_of(e0, E, j, pk);
