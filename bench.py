@@ -429,8 +429,8 @@ def run_tune(args, cb, matgen) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--side", type=int, default=100, help="grid side of the 3D block matrix")
     ap.add_argument("--workload", default="block3d", choices=list(WORKLOADS),
                     help="matrix: block3d (default, 100^3 x 3 dof), powerlaw (n = 4M, Zipf 2.1 rows, mean 16), "
@@ -595,6 +595,21 @@ def main() -> int:
                "sample": f"the full {args.workload} matrix ({A.nnz} nnz), {reps} plain FP64 COO-loop SpMVs in "
                          f"{el:.1f}s on one host core"}
         log(f"cpu oracle: {cpu['value']:.3f} GFLOP/s")
+        # the same rows on every core this process may use (a CSR loop, not the oracle's COO loop)
+        ncores = len(os.sched_getaffinity(0))
+        rp, ci, va = (np.ascontiguousarray(A.row_ptr), np.ascontiguousarray(A.col_idx),
+                      np.ascontiguousarray(A.values))
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            lib.oracle_spmv_csr_par(A.m, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, x.ctypes.data, 1.0,
+                                    yb.ctypes.data, ncores)
+            reps += 1
+            if time.perf_counter() - t0 >= min(3.0, args.cpu_seconds):
+                break
+        el = time.perf_counter() - t0
+        extra["cpu_all_cores"] = {"value": 2.0 * A.nnz * reps / el / 1e9, "unit": "GFLOP/s", "cores": ncores,
+                                  "sample": f"{reps} CSR-loop SpMVs on {ncores} threads in {el:.1f}s"}
+        log(f"cpu all cores ({ncores}): {extra['cpu_all_cores']['value']:.2f} GFLOP/s")
 
     traffic = measured_traffic()
     out = {

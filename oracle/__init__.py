@@ -5,7 +5,8 @@ leg may import this package.  The product path (the HIP library and its Python
 binding) never imports it, and it imports nothing from the product.
 
 * ``spmv_oracle.c`` (built to ``liboracle.so`` with plain gcc, no fast-math):
-  the plain FP64 sparse product over COO triplets (Section 2.1-2.2), its
+  the plain FP64 sparse product over COO triplets (Section 2.1-2.2), the same
+  product over CSR rows on several threads (the all-core CPU reference), its
   Neumaier-compensated checking variant, the |A||x| scale of the accuracy
   metric, the k-right-hand-side product, and FP64 -> FP32 / BF16
   round-to-nearest-even of stored values.
@@ -33,7 +34,7 @@ _p = ctypes.c_void_p
 
 def build() -> str:
     """Compile the C oracle with gcc (no -ffast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-o", _LIB, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp", "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     return _LIB
 
@@ -49,6 +50,7 @@ def lib():
         L.oracle_scale_coo.argtypes = [_i64, _i64, _p, _p, _p, _p, _dbl, _dbl, _p, _p]
         L.oracle_spmm_coo.argtypes = [_i64, _i64, _i32, _p, _p, _p, _p, _i64, _dbl, _dbl, _p, _p, _i64,
                                       ctypes.c_int, _p]
+        L.oracle_spmv_csr_par.argtypes = [_i64, _p, _p, _p, _p, _dbl, _p, ctypes.c_int]
         L.oracle_round_f32_bits.argtypes = [_dbl]
         L.oracle_round_f32_bits.restype = ctypes.c_uint32
         L.oracle_round_bf16_bits.argtypes = [_dbl]

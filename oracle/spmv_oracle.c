@@ -49,6 +49,20 @@ void oracle_spmv_coo(int64_t m, int64_t nnz, const int32_t *row, const int32_t *
     }
 }
 
+/* The same product over CSR rows with the rows split over `threads` OpenMP threads: the
+ * all-core CPU reference the benchmark times.  Each row is summed in entry order, exactly as
+ * oracle_spmv_coo forms it (beta = 0). */
+void oracle_spmv_csr_par(int64_t m, const int64_t *row_ptr, const int32_t *col, const double *val,
+                         const double *x, double alpha, double *y, int threads)
+{
+#pragma omp parallel for num_threads(threads) schedule(static, 1024)
+    for (int64_t i = 0; i < m; ++i) {
+        double s = 0.0;
+        for (int64_t t = row_ptr[i]; t < row_ptr[i + 1]; ++t) s += val[t] * x[col[t]];
+        y[i] = alpha * s;
+    }
+}
+
 /* Neumaier-compensated variant of oracle_spmv_coo (checking reference). */
 void oracle_spmv_coo_comp(int64_t m, int64_t nnz, const int32_t *row, const int32_t *col,
                           const double *val, const double *x, double alpha, double beta,

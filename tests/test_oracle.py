@@ -270,3 +270,16 @@ def test_compensated_sum_with_non_finite_terms():
         assert np.array_equal(y[~np.isnan(y)], ref[~np.isnan(ref)])
         Y = oracle.spmm(A, np.stack([x, 2 * x], axis=1), comp=comp)
         assert np.array_equal(np.isnan(Y[:, 0]), np.isnan(ref)) and Y[0, 0] == np.inf and Y[3, 1] == np.inf
+
+
+@pytest.mark.parametrize("threads", [1, 4])
+def test_parallel_csr_product_equals_the_plain_loop(threads):
+    # each row summed in entry order either way: bit for bit
+    A = matgen.power_law(3000, seed=4, max_len=500, window=100)
+    x = matgen.vector(A.n, 2)
+    y = np.empty(A.m)
+    rp, ci, va = (np.ascontiguousarray(A.row_ptr), np.ascontiguousarray(A.col_idx),
+                  np.ascontiguousarray(A.values))
+    oracle.lib().oracle_spmv_csr_par(A.m, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, x.ctypes.data, 1.5,
+                                     y.ctypes.data, threads)
+    assert np.array_equal(y, oracle.spmv(A, x, alpha=1.5))
