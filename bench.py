@@ -528,7 +528,10 @@ def main() -> int:
             log("FAILED: result outside the 1e-12 tolerance")
             return 1
 
-    extra = {"convert_seconds": info["convert_seconds"], "create_seconds": create_s,
+    # the paper's width model of the same structure (21 bytes of metadata per tile, payload, column maps)
+    paper_bytes = info["meta_bytes"] + info["payload_bytes"] + info["restore_bytes"] + 8 * (A.n + A.m)
+    extra = {"bytes_paper_model": paper_bytes, "GBs_paper_model": paper_bytes / kern_s / 1e9,
+             "convert_seconds": info["convert_seconds"], "create_seconds": create_s,
              "kernel_us": kern_s * 1e6, "max_scaled_error_fp64": err,
              "structure": {k: info[k] for k in ("ntiles", "tiles_coo", "tiles_csr", "tiles_dense", "col_agg",
                                                 "super_sparse_share", "payload_bytes", "meta_bytes",
