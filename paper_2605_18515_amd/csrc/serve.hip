@@ -230,6 +230,7 @@ struct Req {
     double rtol = 1e-10;
     int conv = 0;      // outcome of a finished solve, reported once its x has landed
     double rel = 0.0;
+    bool failed = false;
 };
 
 struct Mat {
@@ -298,7 +299,7 @@ struct cb_server_s {
     void run();
     bool admit_one(Req *q, bool &blocked_by_memory);
     template <class T>
-    bool start_solve(Group<T> &g, Req *q, const Mat &M);
+    int start_solve(Group<T> &g, Req *q, const Mat &M);
     template <class T>
     void retire_solves(Group<T> &g, std::vector<Req *> &done);
     template <class T>
@@ -382,29 +383,38 @@ void cb_server_s::complete(Req *q, cb_status_t st, int iters, int conv, double r
     delete q;
 }
 
+// 1: the solve started; 0: no free slot; -1: a HIP call failed (nothing is left in the slot)
 template <class T>
-bool cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
+int cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
     int slot = -1;
     for (int i = 0; i < g.S; ++i)
         if (!g.req[i]) {
             slot = i;
             break;
         }
-    if (slot < 0) return false;
+    if (slot < 0) return 0;
     const int64_t n = M.v.n;
     const size_t vb = align_up((size_t)n * sizeof(T));
     uint8_t *base = static_cast<uint8_t *>(arena_base) + q->off;
     T *b = reinterpret_cast<T *>(base), *x = reinterpret_cast<T *>(base + vb), *r = reinterpret_cast<T *>(base + 2 * vb),
       *p = reinterpret_cast<T *>(base + 3 * vb), *qq = reinterpret_cast<T *>(base + 4 * vb);
     hipStream_t s = cg_stream;
+    hipError_t e = hipSuccess;
     if (n > 0) {
-        hipMemcpyAsync(b, q->r.in, n * sizeof(T), hipMemcpyHostToDevice, s);
-        hipMemcpyAsync(x, q->r.out, n * sizeof(T), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(b, q->r.in, n * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(x, q->r.out, n * sizeof(T), hipMemcpyHostToDevice, s);
         const int gb = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
-        hipLaunchKernelGGL(sb_copy<T>, dim3(gb), dim3(kT), 0, s, r, b, n);
-        cb_spmv(M.A, -1.0, x, 1.0, r, s);  // r = b - A x
-        hipLaunchKernelGGL(sb_start<T>, dim3(gb), dim3(kT), 0, s, p, qq, r, n);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(sb_copy<T>, dim3(gb), dim3(kT), 0, s, r, b, n);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && cb_spmv(M.A, -1.0, x, 1.0, r, s) != CB_SUCCESS) e = hipErrorLaunchFailure;  // r = b - A x
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(sb_start<T>, dim3(gb), dim3(kT), 0, s, p, qq, r, n);
+            e = hipGetLastError();
+        }
     }
+    if (e != hipSuccess) return -1;
     SolveJob<T> J{};
     J.x = x;
     J.r = r;
@@ -417,17 +427,26 @@ bool cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
     g.jobs[slot] = J;
     g.req[slot] = q;
     q->slot = slot;
-    hipMemcpyAsync(g.d_jobs + slot, &g.jobs[slot], sizeof(SolveJob<T>), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(g.d_jobs + slot, &g.jobs[slot], sizeof(SolveJob<T>), hipMemcpyHostToDevice, s);
     double *part = g.d_partial + (size_t)slot * kGB;
-    hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, r, r, n, part);
-    hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 2, slot);
-    hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, b, b, n, part);
-    hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 3, slot);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, r, r, n, part);
+        hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 2, slot);
+        hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, b, b, n, part);
+        hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 3, slot);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        g.jobs[slot].active = 0;
+        g.req[slot] = nullptr;
+        q->slot = -1;
+        return -1;
+    }
     // the host copy of the table must outlive the copy above: it is only rewritten between periods
     ++g.active;
     g.top = std::max(g.top, slot + 1);
     dirty = true;
-    return true;
+    return 1;
 }
 
 bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
@@ -449,11 +468,16 @@ bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
     q->bytes = bytes;
     q->t_admit = Clock::now();
     if (q->r.kind == CB_REQ_CG) {
-        const bool ok = M.esize == 8 ? start_solve(g64, q, M) : start_solve(g32, q, M);
-        if (!ok) {
+        const int ok = M.esize == 8 ? start_solve(g64, q, M) : start_solve(g32, q, M);
+        if (ok == 0) {
             arena.release(off, bytes);
             q->bytes = 0;
             return false;
+        }
+        if (ok < 0) {
+            hipStreamSynchronize(cg_stream);
+            hipGetLastError();
+            complete(q, CB_ERROR_HIP, 0, 0, 0.0);
         }
         return true;
     }
@@ -465,16 +489,18 @@ bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
     void *X = base, *Y = base + align_up((size_t)M.v.n * q->r.k * es);
     const size_t xb = (size_t)M.v.n * q->r.k * es, yb = (size_t)M.v.m * q->r.k * es;
     cb_status_t st = CB_SUCCESS;
-    if (xb) hipMemcpyAsync(X, q->r.in, xb, hipMemcpyHostToDevice, s);
-    if (yb && q->r.beta != 0.0) hipMemcpyAsync(Y, q->r.out, yb, hipMemcpyHostToDevice, s);
-    st = cb_spmm(M.A, q->r.k, q->r.alpha, X, q->r.k, q->r.beta, Y, q->r.k, s);
-    if (yb) hipMemcpyAsync(q->r.out, Y, yb, hipMemcpyDeviceToHost, s);
-    hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
-    hipEventRecord(q->ev, s);
+    hipError_t e = hipSuccess;
+    if (xb) e = hipMemcpyAsync(X, q->r.in, xb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && yb && q->r.beta != 0.0) e = hipMemcpyAsync(Y, q->r.out, yb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) st = cb_spmm(M.A, q->r.k, q->r.alpha, X, q->r.k, q->r.beta, Y, q->r.k, s);
+    if (e == hipSuccess && st == CB_SUCCESS && yb) e = hipMemcpyAsync(q->r.out, Y, yb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && st == CB_SUCCESS) e = hipEventCreateWithFlags(&q->ev, hipEventDisableTiming);
+    if (e == hipSuccess && st == CB_SUCCESS) e = hipEventRecord(q->ev, s);
     q->stream = si;
-    if (st != CB_SUCCESS) {
-        hipEventSynchronize(q->ev);
-        complete(q, st, 0, 0, 0.0);
+    if (e != hipSuccess || st != CB_SUCCESS) {
+        hipStreamSynchronize(s);
+        hipGetLastError();
+        complete(q, st != CB_SUCCESS ? st : CB_ERROR_HIP, 0, 0, 0.0);
         return true;
     }
     spmm_inflight.push_back(q);
@@ -610,7 +636,9 @@ void cb_server_s::retire_solves(Group<T> &g, std::vector<Req *> &done) {
         const bool conv = std::sqrt(s.rrn) <= q->rtol * std::sqrt(s.bb);
         if (conv || s.bad || q->iters >= q->max_iter) {
             // x back to the caller
-            hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(T), hipMemcpyDeviceToHost, cg_stream);
+            if (hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(T), hipMemcpyDeviceToHost,
+                               cg_stream) != hipSuccess)
+                q->failed = true;
             q->slot = -1;
             g.req[i] = nullptr;
             g.jobs[i].active = 0;
@@ -650,7 +678,7 @@ void cb_server_s::run() {
             retire_solves(g64, done);
             retire_solves(g32, done);
             if (!done.empty()) hipStreamSynchronize(cg_stream);
-            for (Req *q : done) complete(q, CB_SUCCESS, q->iters, q->conv, q->rel);
+            for (Req *q : done) complete(q, q->failed ? CB_ERROR_HIP : CB_SUCCESS, q->iters, q->conv, q->rel);
             progressed = true;
         }
         // admission in arrival order; a solve waiting for the period's end lets SpMM requests pass,
@@ -681,9 +709,10 @@ void cb_server_s::run() {
                 // fail every active solve
                 std::vector<Req *> all;
                 for (int i = 0; i < g64.top; ++i)
-                    if (g64.req[i]) all.push_back(g64.req[i]), g64.req[i] = nullptr;
+                    if (g64.req[i]) all.push_back(g64.req[i]), g64.req[i] = nullptr, g64.jobs[i].active = 0;
                 for (int i = 0; i < g32.top; ++i)
-                    if (g32.req[i]) all.push_back(g32.req[i]), g32.req[i] = nullptr;
+                    if (g32.req[i]) all.push_back(g32.req[i]), g32.req[i] = nullptr, g32.jobs[i].active = 0;
+                hipStreamSynchronize(cg_stream);
                 g64.active = g32.active = g64.top = g32.top = 0;
                 for (Req *q : all) complete(q, CB_ERROR_HIP, q->iters, 0, 0.0);
                 dirty = true;
