@@ -1117,7 +1117,8 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
 
 // operand and accumulator layouts (see Mfma): lane l holds A[l % 16][4kb + l / 16]
 // and B[4kb + l / 16][l % 16] in step kb
-template <int VT, int KC, bool AGG, int NS>
+// X32: every element of X lies within 4 GiB of X, so its address is X plus a 32-bit byte offset
+template <int VT, int KC, bool AGG, int NS, bool X32>
 __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typename Val<VT>::A alpha,
                                                                   typename Val<VT>::A beta,
                                                                   const typename Val<VT>::A *__restrict__ X,
@@ -1187,9 +1188,18 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
                 const int64_t c = 16 * (int64_t)__builtin_amdgcn_readfirstlane(S.rec.w) + 4 * kb + lg;
                 col = c < d.n ? (int)c : 0;
             }
-            const A *xr = X + (int64_t)col * ldx;
+            if constexpr (X32) {
+                const uint32_t row = (uint32_t)col * (uint32_t)ldx;
 #pragma unroll
-            for (int ob = 0; ob < NB; ++ob) S.xb[ob][kb] = xr[min(j0 + 16 * ob + lr, k - 1)];
+                for (int ob = 0; ob < NB; ++ob) {
+                    const uint32_t off = (row + (uint32_t)min(j0 + 16 * ob + lr, k - 1)) * (uint32_t)sizeof(A);
+                    S.xb[ob][kb] = *reinterpret_cast<const A *>(reinterpret_cast<const char *>(X) + off);
+                }
+            } else {
+                const A *xr = X + (int64_t)col * ldx;
+#pragma unroll
+                for (int ob = 0; ob < NB; ++ob) S.xb[ob][kb] = xr[min(j0 + 16 * ob + lr, k - 1)];
+            }
         }
     };
 
@@ -1363,8 +1373,13 @@ hipError_t spmm_mfma(const DevView &d, int k, double alpha, const void *X, int64
     const int ny = (k + KC - 1) / KC;
     constexpr bool kWide = std::is_same<A, double>::value;
     constexpr int NS = kWide && CB_TUNE_SPMM_STAGES > 2 ? CB_TUNE_SPMM_STAGES - 1 : CB_TUNE_SPMM_STAGES;  // FP64 stages are twice the registers
-    hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d, (A)alpha,
-                       (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
+    const bool x32 = ((uint64_t)d.n * (uint64_t)ldx + (uint64_t)k) * sizeof(A) < ((uint64_t)1 << 32);
+    if (x32)
+        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, true>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
+                           (A)alpha, (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
+    else
+        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, false>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
+                           (A)alpha, (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
     return hipGetLastError();
 }
 

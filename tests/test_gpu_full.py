@@ -122,3 +122,31 @@ def test_powerlaw_4m_sampled_rows(cb):
                                      np.random.default_rng(3).choice(A.m, 20000, replace=False), [0, A.m - 1]]))
     sub = rows_of(A, rows)
     check_rows(y[rows], sub, x, "f64", "power-law 4M (sampled rows)")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("vtype", ["f32", "f64"])
+def test_spmm_x_beyond_4gib(cb, vtype):
+    """X whose rows lie more than 4 GiB apart in total (a wide leading dimension): the SpMM kernel
+    addresses X with 64-bit offsets there and 32-bit ones otherwise; sampled rows against the oracle."""
+    A = matgen.block_3d(40, seed=4)
+    k, ldx = 8, 6000 if vtype == "f32" else 3000
+    dt = torch.float32 if vtype == "f32" else torch.float64
+    assert A.n * ldx * (4 if vtype == "f32" else 8) > 2 ** 32
+    X = matgen.rhs(A.n, k, 9)
+    Xd = torch.zeros((A.n, ldx), dtype=dt, device="cuda")
+    Xd[:, :k] = torch.from_numpy(X).to("cuda", dt)
+    Yd = torch.full((A.m, k), float("nan"), dtype=dt, device="cuda")
+    M = cb.CbMatrix.from_csr(A, value_type=vtype)
+    M.spmm(Xd[:, :k], Yd)
+    torch.cuda.synchronize()
+    M.close()
+    del Xd
+    rows = np.unique(np.concatenate([np.random.default_rng(8).choice(A.m, 3000, replace=False), [0, A.m - 1]]))
+    sub = rows_of(A, rows)
+    Xr = X if vtype == "f64" else X.astype(np.float32).astype(np.float64)
+    ref = oracle.spmm(sub, Xr)
+    scl = oracle.spmm(matgen.Csr(sub.m, sub.n, sub.row_ptr, sub.col_idx, np.abs(sub.values)), np.abs(Xr))
+    e, viol, _ = oracle.scaled_error(Yd.cpu().double().numpy()[rows].ravel(), ref.ravel(), scl.ravel(), TOL[vtype])
+    print(f"[spmm wide ldx {vtype}] max scaled error {e:.3e}")
+    assert viol == 0
