@@ -545,8 +545,14 @@ def main() -> int:
         dst = torch.empty_like(src)
         cw, ck = time_calls(lambda: cb.cb_copy_probe(src, dst, nbytes), 20, 3)
         extra["copy_probe_GBs"] = 2 * nbytes / ck / 1e9
-        del src, dst
-        log(f"copy probe: {extra['copy_probe_GBs']:.0f} GB/s")
+        # and of a read-only stream (the product reads its structure and x and writes only y)
+        sink = torch.zeros(2, dtype=torch.float64, device=dev)
+        rw, rk = time_calls(lambda: cb.cb_read_probe(src, nbytes, sink), 20, 3)
+        extra["read_probe_GBs"] = nbytes / rk / 1e9
+        extra["spmv_frac_of_read_probe"] = achieved / extra["read_probe_GBs"]
+        del src, dst, sink
+        log(f"copy probe: {extra['copy_probe_GBs']:.0f} GB/s; read probe: {extra['read_probe_GBs']:.0f} GB/s "
+            f"(the product's algorithmic rate is {100 * extra['spmv_frac_of_read_probe']:.1f} % of it)")
         M.close()
         torch.cuda.empty_cache()
         import oracle

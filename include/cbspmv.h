@@ -245,6 +245,18 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *out);
  * pointers and must not overlap; bytes must be a multiple of 16. */
 cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
 
+/* Read-bandwidth probe: reads `bytes` of device memory at `src` with 16-byte
+ * loads, each wavefront a contiguous 16 KB span with four loads in flight per
+ * lane, and folds them into one word per thread,
+ * which is stored to `sink` only when it equals a fixed value (a store the
+ * compiler cannot remove, so every load stays; in practice nothing is
+ * written).  It measures the achievable read bandwidth of the device, the
+ * ceiling of a kernel that mostly reads (a product reads the structure and x
+ * and writes only y).  src: 16-byte aligned device pointer; bytes: a
+ * non-negative multiple of 16; sink: a device buffer of at least 16 bytes.
+ * Enqueued on `stream`; errors as for cb_copy_probe. */
+cb_status_t cb_read_probe(const void *src, int64_t bytes, void *sink, void *stream);
+
 /* ---- Conjugate gradient (NEXT to the product: A symmetric positive definite) ----
  *
  * Solvers built on cb_spmv.  Each iteration runs on the device (the product, dot

@@ -149,10 +149,12 @@ _lib.cb_export_csr.argtypes = [_p, _p, _p, _p]
 _lib.cb_get_info.argtypes = [_p, ctypes.POINTER(CbInfo)]
 _lib.cb_export_structure.argtypes = [_p, ctypes.POINTER(CbStructure)]
 _lib.cb_copy_probe.argtypes = [_p, _p, _i64, _p]
+_lib.cb_read_probe.argtypes = [_p, _i64, _p, _p]
 _lib.cb_last_error.argtypes = []
 _lib.cb_last_error.restype = ctypes.c_char_p
 for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
-           "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_cg_options_default", "cb_cg_workspace_bytes",
+           "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_read_probe",
+           "cb_cg_options_default", "cb_cg_workspace_bytes",
            "cb_cg", "cb_cg_refine", "cb_server_options_default", "cb_server_create", "cb_server_add_matrix",
            "cb_server_submit", "cb_server_poll", "cb_server_wait", "cb_server_stats", "cb_server_destroy",
            "cb_tune_options_default", "cb_tune"):
@@ -344,6 +346,10 @@ def cb_export_structure(A: int) -> dict:
 
 def cb_copy_probe(src, dst, nbytes: int, stream=None) -> None:
     _check(_lib.cb_copy_probe(_dev_ptr(src), _dev_ptr(dst), int(nbytes), _stream_ptr(stream)))
+
+
+def cb_read_probe(src, nbytes: int, sink, stream=None) -> None:
+    _check(_lib.cb_read_probe(_dev_ptr(src), int(nbytes), _dev_ptr(sink), _stream_ptr(stream)))
 
 
 class CbMatrix:

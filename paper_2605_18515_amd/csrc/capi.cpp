@@ -427,6 +427,16 @@ cb_status_t cb_copy_probe(const void *src, void *dst, int64_t bytes, void *strea
     return CB_SUCCESS;
 }
 
+cb_status_t cb_read_probe(const void *src, int64_t bytes, void *sink, void *stream) {
+    if (bytes < 0 || (bytes & 15)) return fail(CB_ERROR_INVALID_VALUE, "bytes must be a non-negative multiple of 16");
+    if (bytes == 0) return CB_SUCCESS;
+    if (!src || !sink || ((uintptr_t)src & 15) || ((uintptr_t)sink & 15))
+        return fail(CB_ERROR_INVALID_VALUE, "src and sink must be non-NULL and 16-byte aligned");
+    hipError_t e = cbd::launch_read(src, bytes, sink, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "cb_read_probe launch");
+    return CB_SUCCESS;
+}
+
 const char *cb_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

@@ -58,5 +58,6 @@ hipError_t launch_spmv(const DevView &d, int vtype, double alpha, const void *x,
 hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const void *X, int64_t ldx, double beta,
                        void *Y, int64_t ldy, hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t stream);
+hipError_t launch_read(const void *src, int64_t bytes, void *sink, hipStream_t stream);
 
 }  // namespace cbd

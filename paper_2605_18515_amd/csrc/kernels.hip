@@ -1046,6 +1046,29 @@ __global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src
     for (; i < n16; i += stride) dst[i] = src[i];
 }
 
+// Each wavefront reads its own contiguous 16 KB span (as a product's wavefront reads its range),
+// four 16-byte loads in flight per lane, folded into one word; the store happens only when the fold
+// equals a fixed value, which keeps every load.  Measured the fastest read pattern on gfx950
+// (grid-stride loops reach about 10 % less).
+constexpr int64_t kReadSpan16 = 1024;  // 16-byte units per wavefront
+__global__ __launch_bounds__(256) void read_kernel(const uint4 *__restrict__ src, int64_t n16,
+                                                   uint4 *__restrict__ sink) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (int64_t)blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    const int64_t end = min(w * kReadSpan16 + kReadSpan16, n16);
+    int64_t i = w * kReadSpan16 + lane;
+    uint32_t f = 0;
+    for (; i + 3 * kWave < end; i += 4 * kWave) {
+        const uint4 a = src[i], b = src[i + kWave], c = src[i + 2 * kWave], e = src[i + 3 * kWave];
+        f ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ e.x ^ e.y ^ e.z ^ e.w;
+    }
+    for (; i < end; i += kWave) {
+        const uint4 a = src[i];
+        f ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    if (f == 0x9E3779B9u) sink[0] = make_uint4(f, f, f, f);
+}
+
 template <class A>
 hipError_t prepass(const DevView &d, double beta, void *y, int k, int64_t ldy, hipStream_t s) {
     if (d.nprepass <= 0) return hipSuccess;
@@ -1464,6 +1487,15 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes, hipStream_t st
     if (nb > 8192) nb = 8192;
     if (nb < 1) return hipSuccess;
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)nb), dim3(256), 0, stream, (const uint4 *)src, (uint4 *)dst, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_read(const void *src, int64_t bytes, void *sink, hipStream_t stream) {
+    const int64_t n16 = bytes / 16;
+    const int64_t nw = (n16 + kReadSpan16 - 1) / kReadSpan16, nb = (nw + 256 / kWave - 1) / (256 / kWave);
+    if (nb < 1) return hipSuccess;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(read_kernel, dim3((unsigned)nb), dim3(256), 0, stream, (const uint4 *)src, n16, (uint4 *)sink);
     return hipGetLastError();
 }
 

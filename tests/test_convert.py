@@ -339,6 +339,15 @@ def test_copy_probe_validates_arguments():
     assert lib.cb_copy_probe(16, 32, 0, None) == cb.CB_SUCCESS
 
 
+def test_read_probe_validates_arguments():
+    lib = cb.library_handle()
+    assert lib.cb_read_probe(16, 17, 4096, None) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_read_probe(8, 64, 4096, None) == cb.CB_ERROR_INVALID_VALUE  # misaligned source
+    assert lib.cb_read_probe(16, 64, None, None) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_read_probe(16, -16, 4096, None) == cb.CB_ERROR_INVALID_VALUE
+    assert lib.cb_read_probe(16, 0, 4096, None) == cb.CB_SUCCESS
+
+
 @settings(max_examples=40, deadline=None)
 @given(m=st.integers(0, 60), n=st.integers(0, 60), dens=st.floats(0, 1), seed=st.integers(0, 10 ** 6),
        vtype=st.sampled_from(["f64", "f32", "bf16"]), agg=st.sampled_from([-1, 0, 1]),

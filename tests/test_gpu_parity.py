@@ -367,6 +367,17 @@ def test_copy_probe(cb):
     assert torch.equal(src, dst)
 
 
+def test_read_probe(cb):
+    """Reads without writing: a zero buffer folds to 0, so the sink keeps its contents; a ragged
+    size (not a multiple of the four-load step) runs the tail loop."""
+    for n16 in (1, 4096 * 256 + 3, 1 << 22):
+        src = torch.zeros(2 * n16, dtype=torch.float64, device="cuda")
+        sink = torch.full((2,), 7.0, dtype=torch.float64, device="cuda")
+        cb.cb_read_probe(src, n16 * 16, sink)
+        torch.cuda.synchronize()
+        assert sink.tolist() == [7.0, 7.0]
+
+
 @pytest.mark.parametrize("vtype", ["f64", "f32"])
 def test_spmm_dense_tiles_with_nonfinite_x(cb, vtype):
     """Dense tiles go to the matrix cores unless the staged X rows hold Inf/NaN:
