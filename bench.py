@@ -105,6 +105,17 @@ def time_graph(fn, steps: int, warmup: int, replays: int = 5):
     return wall / (steps * replays), e0.elapsed_time(e1) / 1e3 / (steps * replays)
 
 
+def kernel_name(info: dict, lb: str) -> str:
+    """The product kernel a handle launches (value type FP64), as the trace names it with its template
+    arguments spelled out."""
+    if lb == "paper":
+        return "spmv_kernel<FP64> (Algorithm 2 order)"
+    agg = "aggregated" if info["col_agg"] else "plain columns"
+    if info["spmv_kernel"] == 1:
+        return f"spmv_rows_kernel<FP64, {agg}>"
+    return f"spmv_stream_kernel<FP64, {agg}, row sums {info['row_reduce']}>"
+
+
 def time_calls(fn, steps: int, warmup: int):
     import torch
 
@@ -639,7 +650,7 @@ def main() -> int:
                    "col_agg": info["col_agg"], "value_storage": "f64"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_launch": info["spmv_bytes"], "kernel": "spmv_kernel<0>"},
+                     "bytes_per_launch": info["spmv_bytes"], "kernel": kernel_name(info, args.lb)},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -96,9 +96,13 @@ typedef struct {
                                accumulators: 0 = one LDS atomic add per entry; 1 = a DPP segmented
                                scan over lanes of the same (tile, row), then one add per run;
                                2 = one FP64 LDS atomic add per entry (FP32/BF16 values: row sums
-                               kept in FP64 until written; same as 0 for FP64); -1 (default) =
-                               automatic: 0 for FP64 values, 2 for FP32/BF16.  Results agree
-                               within the storage precision's tolerance either way. */
+                               kept in FP64 until written; same as 0 for FP64); 3 and 4 = 0 and 2
+                               with the accumulators in two copies, odd lanes adding into the
+                               second (halves the collisions of a row's neighbouring entries on
+                               one LDS address); -1 (default) = automatic: 0 (FP64 values) or 2
+                               (FP32/BF16), or 3 or 4 where the tiles' rows hold their entries in
+                               runs of two or more on average.  Results agree within the storage
+                               precision's tolerance either way. */
     int32_t vector_f64;     /* FP32/BF16 storage only: 1 = x and y are double and the products,
                                sums, alpha and beta are FP64 (the stored values widened exactly);
                                0 (default) = x and y are float.  FP64 storage: always double. */
@@ -144,7 +148,7 @@ typedef struct {
     int64_t nbatches;       /* batches of the streaming kernel (0 with CB_LB_PAPER) */
     int64_t stream_bytes;   /* its batch records: 16 bytes per batch and per tile */
     double flat_run_mean;   /* COO/CSR entries per (tile, row) run: the lanes one scan step merges */
-    int32_t row_reduce;     /* the resolved row_reduce option (0, 1 or 2) */
+    int32_t row_reduce;     /* the resolved row_reduce option (0 .. 4) */
     int32_t vector_f64;     /* 1 when x and y are double (FP64 storage, or vector_f64 set) */
     int32_t spmv_kernel;    /* the resolved spmv_kernel option (0 or 1) */
     int32_t reserved2;

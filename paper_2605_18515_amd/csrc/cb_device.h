@@ -29,7 +29,8 @@ struct DevView {
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
-    int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan
+    int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan,
+                                  // 2 FP64 LDS atomics, 3 and 4 = 0 and 2 with two accumulator copies
     int32_t rows_kernel;          // natural order: 1 = the rows-per-lane kernel instead of the streaming one
     const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
 };

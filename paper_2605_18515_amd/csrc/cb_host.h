@@ -52,7 +52,8 @@ struct HostStructure {
     double quantum_nnz_mean = 0, quantum_nnz_std = 0, wave_nnz_mean = 0, wave_nnz_std = 0;
     double convert_seconds = 0.0;
     int64_t flat_entries = 0, flat_runs = 0;  // COO/CSR entries and their (tile, row) runs
-    int row_reduce = 0;                       // resolved: 0 LDS atomics, 1 DPP segmented scan, 2 FP64 atomics
+    int row_reduce = 0;                       // resolved: 0 LDS atomics, 1 DPP segmented scan, 2 FP64 atomics,
+                                              // 3 and 4 = 0 and 2 with two accumulator copies
     int vector_f64 = 1;                       // x and y are double
     int spmv_kernel = 0;                      // resolved: 0 entries per lane, 1 rows per lane
     // natural order: first tile of every panel (npanels + 1)

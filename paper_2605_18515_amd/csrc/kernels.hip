@@ -339,7 +339,6 @@ constexpr int kPRing = kRC * kChunk;  // payload ring per wavefront
 constexpr int kPMask = kPRing - 1;
 constexpr int kBatchTiles = cbs::kBatchTiles;
 constexpr int kMaxPanels = cbs::kBatchPanels;
-constexpr int kRecs = kBatchTiles + 1;  // header and records of one batch
 static_assert(kChunk == kWave * 16 && (kPRing & kPMask) == 0, "one chunk per wavefront-wide 16-byte load");
 static_assert(kBatchTiles + 1 <= kWave && kBatchTiles % 4 == 0, "a batch's records fit one load; x gathers take four tiles each");
 static_assert(kMaxPanels * 16 <= kWave && kMaxPanels <= 4, "accumulators cleared by one store per lane, flushed by one group");
@@ -347,7 +346,9 @@ constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left
 
 // RR, the row sums: 0 = one LDS atomic add per entry, 1 = DPP segmented scan then one add per run,
 // 2 = one FP64 LDS atomic add per entry (FP32/BF16 values: the products widened, the row sums kept
-// in FP64 until they are written)
+// in FP64 until they are written), 3 and 4 = 0 and 2 with two copies of the accumulators, odd lanes
+// adding into the second (entries of a row sit in neighbouring lanes, so long rows collide half as
+// often on one LDS address; the copies are added when the panel is written)
 // One work range w of the structure d (the body of the streaming kernel, shared by the one-matrix
 // and the batched launch).
 template <int VT, bool AGG, int RR>
@@ -355,14 +356,13 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
                                              typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                              typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
-    using AC = typename std::conditional<RR == 2, double, A>::type;  // accumulator type
+    using AC = typename std::conditional<RR == 2 || RR == 4, double, A>::type;  // accumulator type
     constexpr bool DPPRED = RR == 1;
+    constexpr int NACC = RR >= 3 ? 2 : 1;  // accumulator copies
     constexpr int VS = Val<VT>::kSize;
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
     __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
-    // three batches in flight: per tile {record word, last flat entry (COO/CSR) or region start (Dense)}
-    __shared__ __align__(16) i32x2 rec_all[kWavesPerBlock][3][kBatchTiles];
-    __shared__ __align__(16) AC acc_all[kWavesPerBlock][kMaxPanels * 16];
+    __shared__ __align__(16) AC acc_all[kWavesPerBlock][kMaxPanels * 16 * NACC];
     const int lane = threadIdx.x & (kWave - 1);
     // with one wavefront per workgroup its LDS arrays sit at fixed addresses
     const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -372,7 +372,6 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     uint8_t *pring = pring_all[wid];
     A *xarea = xarea_all[wid];
     AC *acc = acc_all[wid];
-    i32x2 *recs = rec_all[wid][0];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
     const u32x4 *pstream = reinterpret_cast<const u32x4 *>(d.payload + d.tile_vp[t0]) + lane;
     const i32x4 *rstream = reinterpret_cast<const i32x4 *>(d.batch_stream);
@@ -381,13 +380,12 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
     const int gj = lane >> 4, glc = lane & 15;
 
-    // header and records of the batch at record o: lane 0 the header, lane 1 + i record i
+    // header and records of the batch at record o: lane i < 16 record i (lanes 16 .. 62 record 15
+    // again), lane 63 the header.  Three batches' records stay in registers, one tile per lane:
+    // {record word, last flat entry (COO/CSR) or region start (Dense)}, never both set
     i32x4 Q;
-    auto qload = [&](int o) { Q = rstream[o + min(lane, kBatchTiles)]; };
-    // lane 1 + i holds record i; its last entry (COO/CSR) and region start (Dense) are never both set
-    auto put_recs = [&](i32x2 *rec) {
-        if (lane >= 1 && lane < kRecs) rec[lane - 1] = i32x2{Q.x, Q.y | Q.z};
-    };
+    auto qload = [&](int o) { Q = rstream[o + (lane == kWave - 1 ? 0 : 1 + min(lane, kBatchTiles - 1))]; };
+    auto recv = [&]() { return i32x2{Q.x, Q.y | Q.z}; };
 
     // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued); re is the
     // batch's end, and it starts where the previous batch ended
@@ -461,9 +459,14 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     auto flush = [&]() {
         if ((done_mask >> fk) & 1) {
             const int p = done_pb + fk;
-            AC *a = &acc[(p & (kMaxPanels - 1)) * 16 + fr];
-            const A v = (A)*a;
+            AC *a = &acc[(p & (kMaxPanels - 1)) * 16 * NACC + fr];
+            AC sv = *a;
             *a = AC(0);
+            if constexpr (NACC == 2) {
+                sv += a[16];
+                a[16] = AC(0);
+            }
+            const A v = (A)sv;
             const int64_t row = 16 * (int64_t)p + fr;
             if (row < d.m) {
                 if (is_shared(p)) {
@@ -480,13 +483,14 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
 
     // multiply one batch: records rec[1..], header fields hz = nt | nflat << 8 | ndense << 16 | done << 24
     // and etot (flat entries); positions in the packed record words are taken modulo the ring size
-    auto multiply = [&](const i32x2 *rec, int hz, int etot) {
+    auto multiply = [&](const i32x2 rl, int hz, int etot) {
         const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
         // COO and CSR entries as one stream; lane i holds flat tile i's last entry (endv) and record
-        // word (pkv), read once per batch
-        const i32x2 rl = rec[min(lane, kBatchTiles - 1)];
+        // word (pkv); lanes from nflat on hold the last flat tile's word, which the lanes past the
+        // batch's last entry select (their tile position then stays inside the x area)
         const int endv = rl.y;
-        const uint32_t pkv = (uint32_t)rl.x;
+        const uint32_t pkv =
+            lane < nflat ? (uint32_t)rl.x : (uint32_t)__builtin_amdgcn_readlane(rl.x, nflat > 0 ? nflat - 1 : 0);
         // pass (64 entries) holding each flat tile's last entry
         const int passv = lane < nflat ? endv / kWave : -1;
         // tile of entry E in the pass starting at entry e0 (a multiple of 64), and its record word;
@@ -516,12 +520,14 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
                    xarea[((pk >> 27) << 4) + (code >> 4)];
         };
         auto accumulate = [&](A prod, int ti, uint32_t code, uint32_t pk, bool valid) {
-            AC *dst = &acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + (code & 15)];
-            if constexpr (DPPRED)
+            const int slot = (pk >> 24) & (kMaxPanels - 1);
+            AC *dst = &acc[slot * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0) + (code & 15)];
+            if constexpr (DPPRED) {
                 segmented_row_add(valid ? prod : A(0), valid ? (ti << 4) | (int)(code & 15) : 0x10000 + lane, valid,
                                   dst);
-            else if (valid)
+            } else if (valid) {
                 lds_add(dst, (AC)prod);
+            }
         };
         int j = 0;
         int e0 = 0;
@@ -559,9 +565,8 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         // dense tiles, four lanes per row
         const int r4 = lane >> 2, q4 = lane & 3;
         for (int k = 0; k < ndense; ++k) {
-            const i32x2 r = rec[nflat + k];
-            const uint32_t pk = (uint32_t)__builtin_amdgcn_readfirstlane(r.x);
-            const int rel = __builtin_amdgcn_readfirstlane(r.y);
+            const uint32_t pk = (uint32_t)__builtin_amdgcn_readlane(rl.x, nflat + k);
+            const int rel = __builtin_amdgcn_readlane(rl.y, nflat + k);
             const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
             const int vo = rel + (r4 * 16 + 4 * q4) * VS;
             const A *xs = xarea + ((pk >> 27) << 4) + 4 * q4;
@@ -570,27 +575,28 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
             for (int jj = 0; jj < 4; ++jj)
                 if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
             sum = quad_sum(sum);
-            if (q4 == 0) lds_add(&acc[(((pk >> 24) & (kMaxPanels - 1)) << 4) + r4], (AC)sum);
+            if (q4 == 0) lds_add(&acc[((pk >> 24) & (kMaxPanels - 1)) * 16 * NACC + r4], (AC)sum);
         }
     };
 
     if (lane < kMaxPanels * 16) acc[lane] = AC(0);
+    if constexpr (NACC == 2) acc[lane + 64] = AC(0);
     // Prologue: batch 0's records, x columns, x values and payload; batch 1's records and x
     // columns; batch 2's records.  At the top of step b the registers hold P and XG of batch b,
-    // RG of batch b+1 and Q of batch b+2; LDS holds the records of batches b and b+1.
+    // RG of batch b+1 and Q of batch b+2, and R0, R1 the records of batches b and b+1.
     // header fields of a batch: hz (nt | nflat << 8 | ndense << 16 | done << 24), etot, first panel
     struct Hdr {
         int re, hz, etot, pb;
     };
     auto header = [&]() {
-        return Hdr{__builtin_amdgcn_readlane(Q.x, 0), __builtin_amdgcn_readlane(Q.z, 0),
-                   __builtin_amdgcn_readlane(Q.w, 0), __builtin_amdgcn_readlane(Q.y, 0)};
+        return Hdr{__builtin_amdgcn_readlane(Q.x, kWave - 1), __builtin_amdgcn_readlane(Q.z, kWave - 1),
+                   __builtin_amdgcn_readlane(Q.w, kWave - 1), __builtin_amdgcn_readlane(Q.y, kWave - 1)};
     };
     int ob = o_begin;
     qload(ob);
     Hdr h0 = header(), h1{}, h2{};
     int ntb = h0.hz & 0xFF;
-    put_recs(recs);
+    i32x2 R0 = recv(), R1{}, R2{};
     issue_cols(t0, ntb);
     issue_payload(h0.re);
     int o1 = ob + 1 + ntb, nt1 = 0;
@@ -601,15 +607,13 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     if (o1 < o_end) {
         h1 = header();
         nt1 = h1.hz & 0xFF;
-        put_recs(recs + kBatchTiles);
+        R1 = recv();
         issue_cols(tb1, nt1);
         o2 = o1 + 1 + nt1;
         tb2 = tb1 + nt1;
         if (o2 < o_end) qload(o2);
     }
-    int bufb = 0;
     while (ob < o_end) {
-        const int bufn = bufb == 2 ? 0 : bufb + 1, bufnn = bufn == 2 ? 0 : bufn + 1;
         // the one wait of a step: every load issued by the previous step has landed (loads are
         // issued conditionally, so the compiler's own counting would wait inside step 2)
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -622,7 +626,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         if (have2) {
             h2 = header();
             nt2 = h2.hz & 0xFF;
-            put_recs(recs + bufnn * kBatchTiles);
+            R2 = recv();
         }
         __builtin_amdgcn_wave_barrier();
         // 2. loads: payload and x of batch b+1, x columns of batch b+2, records of batch b+3, and
@@ -640,7 +644,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         done_mask = (int)((uint32_t)h0.hz >> 24);
         issue_y();
         // 3. batch b
-        multiply(recs + bufb * kBatchTiles, h0.hz, h0.etot);
+        multiply(R0, h0.hz, h0.etot);
         __builtin_amdgcn_wave_barrier();
         ob = o1;
         ntb = nt1;
@@ -650,7 +654,8 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         h1 = h2;
         o2 = o3;
         tb2 += nt2;
-        bufb = bufn;
+        R0 = R1;
+        R1 = R2;
     }
     flush();
 }
@@ -1097,20 +1102,24 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
             hipLaunchKernelGGL((spmv_rows_kernel<VT, false>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
                                (const A *)x, (A *)y);
     } else if (d.natural_order) {
-        // double accumulators already: modes 0 and 2 are the same kernel
+        // double accumulators already: modes 2 and 4 are modes 0 and 3
         constexpr bool kWide = std::is_same<A, double>::value;
-        constexpr int kRR2 = kWide ? 0 : 2;
-        const int rr = kWide && d.row_reduce == 2 ? 0 : d.row_reduce;
+        constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
+        const int rr = d.row_reduce;
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
         };
         if (d.col_agg) {
             if (rr == 1) go(spmv_stream_kernel<VT, true, 1>);
             else if (rr == 2) go(spmv_stream_kernel<VT, true, kRR2>);
+            else if (rr == 3) go(spmv_stream_kernel<VT, true, 3>);
+            else if (rr == 4) go(spmv_stream_kernel<VT, true, kRR4>);
             else go(spmv_stream_kernel<VT, true, 0>);
         } else {
             if (rr == 1) go(spmv_stream_kernel<VT, false, 1>);
             else if (rr == 2) go(spmv_stream_kernel<VT, false, kRR2>);
+            else if (rr == 3) go(spmv_stream_kernel<VT, false, 3>);
+            else if (rr == 4) go(spmv_stream_kernel<VT, false, kRR4>);
             else go(spmv_stream_kernel<VT, false, 0>);
         }
     } else
@@ -1456,8 +1465,12 @@ hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, in
     const dim3 grid((unsigned)total), block(kBlockThreads);
     if (rr == 1)
         hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1>), grid, block, 0, s, jobs, wave_job, total);
-    else if (rr == 2 && !kWide)
+    else if (rr == 2)
         hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 0 : 2>), grid, block, 0, s, jobs, wave_job, total);
+    else if (rr == 3)
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 3>), grid, block, 0, s, jobs, wave_job, total);
+    else if (rr == 4)
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 3 : 4>), grid, block, 0, s, jobs, wave_job, total);
     else
         hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 0>), grid, block, 0, s, jobs, wave_job, total);
     return hipGetLastError();

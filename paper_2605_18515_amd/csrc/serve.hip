@@ -517,7 +517,7 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
         if (g.req[i]) order.push_back(i);
     auto key = [&](int i) {
         const cbh::MatrixView &v = mats[g.req[i]->r.matrix].v;
-        return v.kernel_vt * 16 + v.col_agg * 4 + v.row_reduce;
+        return v.kernel_vt * 16 + v.col_agg * 8 + v.row_reduce;  // row_reduce < 8
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     std::vector<cbd::BatchJob> bj;

@@ -179,11 +179,12 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             o.th2 = th.second;
             if (st == CB_SUCCESS) st = T.eval(o, idx);
         }
-        // row sums
+        // row sums: the modes other than the resolved one (FP32/BF16 values: the FP64-accumulator
+        // modes and the segmented scan; FP32 LDS atomics lose everywhere)
         {
             const int rr0 = T.cand[T.best].row_reduce;
-            const std::vector<int> alts = wide ? std::vector<int>{rr0 == 0 ? 1 : 0} : std::vector<int>{rr0 == 2 ? 1 : 2};
-            for (int rr : alts) {
+            for (int rr : wide ? std::vector<int>{0, 3, 1} : std::vector<int>{2, 4, 1}) {
+                if (rr == rr0) continue;
                 cb_options_t o = cur();
                 o.row_reduce = rr;
                 if (st == CB_SUCCESS) st = T.eval(o, idx);

@@ -283,7 +283,7 @@ def test_malformed_csr_is_rejected(case):
 def test_bad_options_are_rejected():
     A = matgen.identity(20)
     for k, v in [("value_type", 3), ("col_agg", 2), ("th1", -1), ("quantum_tiles", 0), ("lb_mode", 7),
-                 ("wave_nnz", -5), ("th0", float("nan")), ("row_reduce", 3), ("row_reduce", -2),
+                 ("wave_nnz", -5), ("th0", float("nan")), ("row_reduce", 5), ("row_reduce", -2),
                  ("vector_f64", 2), ("vector_f64", -1)]:
         o = cb.cb_options_default()
         setattr(o, k, v)
@@ -303,11 +303,18 @@ def test_row_reduce_resolution_and_run_statistic():
     A = matgen.Csr(n, n, np.arange(0, 2 * n + 1, 2, dtype=np.int64), cols.ravel().astype(np.int32),
                    np.ones(2 * n))
     assert rows.size == A.nnz
-    for vt, want in (("f64", 0), ("f32", 2), ("bf16", 2)):
+    # runs of two entries per tile row: the two-copy accumulator modes
+    for vt, want in (("f64", 3), ("f32", 4), ("bf16", 4)):
         M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, th1=64, th2=256)
         assert M.info["row_reduce"] == want and M.info["flat_run_mean"] == 2.0
         M.close()
-    for rr in (0, 1, 2):
+    # one entry per tile row (a permutation matrix): one copy
+    P = matgen.Csr(n, n, np.arange(n + 1, dtype=np.int64), ((np.arange(n) * 5) % n).astype(np.int32), np.ones(n))
+    for vt, want in (("f64", 0), ("f32", 2)):
+        M = cb.CbMatrix.from_csr(P, device=False, value_type=vt)
+        assert M.info["row_reduce"] == want and M.info["flat_run_mean"] == 1.0
+        M.close()
+    for rr in (0, 1, 2, 3, 4):
         M = cb.CbMatrix.from_csr(A, device=False, row_reduce=rr)
         assert M.info["row_reduce"] == rr
         M.close()
@@ -315,7 +322,7 @@ def test_row_reduce_resolution_and_run_statistic():
     for vt, wide, want in (("f64", 0, 1), ("f32", 0, 0), ("f32", 1, 1), ("bf16", 1, 1)):
         M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, vector_f64=wide)
         assert M.info["vector_f64"] == want
-        assert M.info["row_reduce"] == (0 if want else 2)
+        assert M.info["row_reduce"] == (3 if want else 4)
         M.close()
 
 

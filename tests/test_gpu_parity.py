@@ -112,11 +112,12 @@ def test_spmv_low_precision(cb, name, vtype):
 
 
 @pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("rr", [0, 1, 2])
+@pytest.mark.parametrize("rr", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("name", ["block8", "power", "lap64", "dense_mix", "rect"])
 def test_row_reduce_modes(cb, name, rr, vtype):
-    """Every way the streaming kernel sums rows (LDS atomics, DPP segmented scan, FP64 atomics),
-    with and without column aggregation, and with several work ranges sharing panels."""
+    """Every way the streaming kernel sums rows (LDS atomics, DPP segmented scan, FP64 atomics,
+    and the atomics into two accumulator copies), with and without column aggregation, and with
+    several work ranges sharing panels."""
     A = SMALL[name]()
     x = matgen.vector(A.n, 12)
     y0 = matgen.vector(A.m, 3, stream=matgen.STREAM_Y0)
@@ -156,7 +157,7 @@ def rounded(A, vtype):
 
 
 @pytest.mark.parametrize("vtype", ["f32", "bf16"])
-@pytest.mark.parametrize("rr", [0, 1, 2])
+@pytest.mark.parametrize("rr", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("name", ["block8", "power", "lap64", "dense_mix", "rect"])
 def test_wide_vectors(cb, name, rr, vtype):
     """FP32/BF16 storage with double x and y: FP64 arithmetic on the widened stored values, so the
@@ -202,7 +203,7 @@ def test_wide_vectors_exact_bitwise(cb):
     x = rng.integers(-64, 65, A.n).astype(np.float64) / 64
     ref = oracle.spmv(A, x)
     for vt in ("f32", "bf16"):
-        for rr in (0, 1, 2):
+        for rr in (0, 1, 2, 3, 4):
             assert np.array_equal(run_spmv(cb, A, x, vtype=vt, vector_f64=1, row_reduce=rr), ref), (vt, rr)
 
 
@@ -212,7 +213,7 @@ def test_row_reduce_exact_bitwise(cb):
     A = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx, rng.integers(-64, 65, B.nnz).astype(np.float64) / 64)
     x = rng.integers(-64, 65, A.n).astype(np.float64) / 64
     ref = oracle.spmv(A, x)
-    for rr in (0, 1, 2):
+    for rr in (0, 1, 2, 3, 4):
         assert np.array_equal(run_spmv(cb, A, x, row_reduce=rr), ref)
 
 
