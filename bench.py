@@ -134,11 +134,15 @@ def time_calls(fn, steps: int, warmup: int):
     return wall / steps, e0.elapsed_time(e1) / 1e3 / steps
 
 
-def run_cg(args, cb, matgen) -> int:
+CG_LEGS = ("fp64_cg", "replace_f32", "replace_bf16", "replace_f32w", "replace_bf16w", "restart_f32", "restart_bf16",
+           "restart_f32w")
+
+
+def cg_legs(args, cb, matgen, names=CG_LEGS):
     """Solves of A x = b from x = 0 on the 192^3 Poisson operator (b ~ U[-1, 1]) until the FP64
     residual |b - A x| / |b| is at most 1e-10: FP64 CG, and the two mixed-precision solvers
     (residual replacement and restarted refinement) with the products on the FP32 and on the BF16
-    copy of A.  Each solve is timed whole (host polling included)."""
+    copy of A.  Each solve is timed whole (host polling included).  Returns (legs, A, ok)."""
     import numpy as np
     import torch
 
@@ -150,8 +154,7 @@ def run_cg(args, cb, matgen) -> int:
     legs = {}
     xs = {}
     # <method>_<storage>[w]: w = double vectors on the low-precision copy
-    for name in ("fp64_cg", "replace_f32", "replace_bf16", "replace_f32w", "replace_bf16w", "restart_f32",
-                 "restart_bf16", "restart_f32w"):
+    for name in names:
         vt = name.split("_")[-1]
         L = None if name == "fp64_cg" else cb.CbMatrix.from_csr(A, value_type=vt.rstrip("w"),
                                                                  vector_f64=int(vt.endswith("w")))
@@ -190,11 +193,17 @@ def run_cg(args, cb, matgen) -> int:
             legs[name]["rel_residual_oracle"] = r = solvers.residual(A, b, x)
             ok = ok and r <= rtol and legs[name]["converged"]
         log("oracle residuals: " + ", ".join(f"{k} {v['rel_residual_oracle']:.3e}" for k, v in legs.items()))
+    return legs, A, ok
+
+
+def run_cg(args, cb, matgen) -> int:
+    legs, A, ok = cg_legs(args, cb, matgen)
     best = max(legs, key=lambda k: legs[k]["solves_per_s"])
     out = {
         "metric": "CG solves/s to |b - Ax| / |b| <= 1e-10 (FP64 vs mixed-precision refinement)",
         "value": round(legs[best]["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
-        "steps": len(times), "warmup": 1, "ms_per_step": legs[best]["seconds"] * 1e3, "higher_is_better": True,
+        "steps": max(1, min(args.steps, 5)), "warmup": 1, "ms_per_step": legs[best]["seconds"] * 1e3,
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "CG on the 3D 7-point Poisson operator, 192^3 grid, b ~ U[-1,1], x0 = 0",
                    "n": A.n, "nnz": A.nnz, "method": best},
@@ -218,14 +227,14 @@ def _serve_matrix(spec):
     return matgen.poisson_3d(max(2, round(n ** (1 / 3))))
 
 
-def run_serve(args, cb, matgen) -> int:
+def serve_legs(args, cb, matgen, nreq: int) -> dict:
     """Serving workload: 256 resident matrices from the three families (3D block, power-law, 3D
     Poisson) with n log-uniform in [1e3, 1e6], every other one stored in FP32; requests are SpMM
     with k uniform in 1..16 on any matrix, or a CG solve (cap 500 iterations, rtol 1e-8 for FP64,
     1e-5 for FP32) on a Poisson matrix, half each.  Three runs of the same request list: the
     server with every request submitted at once (throughput), the server under Poisson arrivals at
     half that rate (p50/p99 latency), and the plain path, one request at a time through cb_spmm
-    and cb_cg."""
+    and cb_cg.  Returns the measurements."""
     import multiprocessing as mp
     import threading
 
@@ -248,7 +257,7 @@ def run_serve(args, cb, matgen) -> int:
     # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix
     xin = [np.random.default_rng(i).uniform(-1, 1, A.n * 16).astype(dts[i]) for i, A in enumerate(csrs)]
     reqs = []
-    for r in range(args.requests):
+    for r in range(nreq):
         if rng.random() < 0.5:
             i = int(rng.choice(spd))
             reqs.append(("cg", i, 1))
@@ -326,18 +335,29 @@ def run_serve(args, cb, matgen) -> int:
     conv = sum(1 for (kind, _, _), r in zip(reqs, resp_b) if kind == "cg" and r["converged"])
     for M in mats:
         M.close()
+    del mats
+    torch.cuda.empty_cache()
+    return {"requests": len(reqs), "cg_requests": ncg, "all_at_once": st_b,
+            "poisson_arrivals": dict(st_p, rate_per_s=lam), "one_at_a_time": seq,
+            "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
+            "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst}
+
+
+SERVE_WORKLOAD = ("serving: 256 resident matrices (3D block, power-law, 3D Poisson; n log-uniform in [1e3, 1e6]; "
+                  "FP64 and FP32), SpMM k in 1..16 or CG (cap 500) requests")
+
+
+def run_serve(args, cb, matgen) -> int:
+    r = serve_legs(args, cb, matgen, args.requests)
+    st_b = r["all_at_once"]
     out = {
         "metric": "batched solves/s, p50/p99 (serving)",
-        "value": round(st_b["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1, "steps": len(reqs),
+        "value": round(st_b["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1, "steps": r["requests"],
         "warmup": 1, "ms_per_step": 1e3 / st_b["requests_per_s"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": "serving: 256 resident matrices (3D block, power-law, 3D Poisson; n log-uniform in "
-                               "[1e3, 1e6]; FP64 and FP32), SpMM k in 1..16 or CG (cap 500) requests",
-                   "requests": len(reqs), "cg_requests": ncg},
+        "config": {"workload": SERVE_WORKLOAD, "requests": r["requests"], "cg_requests": r["cg_requests"]},
         "roofline": None, "cpu_baseline": None,
-        "extra": {"all_at_once": st_b, "poisson_arrivals": dict(st_p, rate_per_s=lam), "one_at_a_time": seq,
-                  "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
-                  "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst},
+        "extra": {k: v for k, v in r.items() if k not in ("requests", "cg_requests")},
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -452,6 +472,9 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32/BF16, SpMM and copy legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
+    ap.add_argument("--no-solves", action="store_true",
+                    help="skip the CG (FP64 vs mixed) and serving legs of the extra measurements")
+    ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving leg of the extras")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true",
                     help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
@@ -592,6 +615,27 @@ def main() -> int:
             Mv.close()
             del x32, y32
             torch.cuda.empty_cache()
+        if not args.no_solves:
+            # the metric's other half: solves/s of FP64 CG against the mixed-precision solver, and of the
+            # serving loop's batches against one request at a time, with p50/p99 latency
+            legs, _, ok = cg_legs(args, cb, matgen, ("fp64_cg", "replace_f32", "replace_bf16"))
+            base = legs["fp64_cg"]["solves_per_s"]
+            extra["cg_poisson192"] = {
+                k: {kk: v[kk] for kk in ("solves_per_s", "iterations", "refinements", "rel_residual_oracle")
+                    if kk in v} for k, v in legs.items()}
+            extra["cg_poisson192"]["speedup_vs_fp64_cg"] = {k: v["solves_per_s"] / base for k, v in legs.items()}
+            if not ok:
+                log("FAILED: a CG solve missed the 1e-10 residual")
+                return 1
+            srv = serve_legs(args, cb, matgen, args.serve_requests)
+            extra["serving"] = {
+                "workload": SERVE_WORKLOAD, "requests": srv["requests"], "cg_requests": srv["cg_requests"],
+                "batched_solves_per_s": srv["all_at_once"]["solves_per_s"],
+                "one_at_a_time_solves_per_s": srv["one_at_a_time"]["solves_per_s"],
+                "speedup_solves": srv["speedup_solves_vs_one_at_a_time"],
+                "poisson_arrivals_per_s": srv["poisson_arrivals"]["rate_per_s"],
+                "p50_ms": srv["poisson_arrivals"]["p50_us"] / 1e3, "p99_ms": srv["poisson_arrivals"]["p99_us"] / 1e3,
+                "cg_converged": srv["cg_converged"], "max_rel_diff_vs_one_at_a_time": srv["max_rel_diff_vs_one_at_a_time"]}
     else:
         M.close()
 
