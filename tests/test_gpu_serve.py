@@ -39,10 +39,10 @@ def general_matrices():
             matgen.random_csr(200, 333, 0.05, 4), matgen.laplacian_2d(17)]
 
 
-def make(cb, A, vt):
+def make(cb, A, vt, **opts):
     if vt == "f32w":
-        return cb.CbMatrix.from_csr(A, value_type="f32", vector_f64=1)
-    return cb.CbMatrix.from_csr(A, value_type=vt)
+        return cb.CbMatrix.from_csr(A, value_type="f32", vector_f64=1, **opts)
+    return cb.CbMatrix.from_csr(A, value_type=vt, **opts)
 
 
 def ndt(vt):
@@ -88,13 +88,13 @@ def test_spmm_requests_match_oracle_and_direct(cb):
 
 
 def run_solves(cb, specs, mix_spmm=False, **opts):
-    """Submit every CG request (A, vector type, seed of b) at once, with SpMM requests in between
-    when mix_spmm; returns [(x, response)] in submission order."""
+    """Submit every CG request (A, vector type, seed of b[, conversion options]) at once, with SpMM
+    requests in between when mix_spmm; returns [(x, response)] in submission order."""
     mats, out = [], []
     with cb.CbServer(**opts) as S:
         ids = []
-        for A, vt, _ in specs:
-            M = make(cb, A, vt)
+        for A, vt, _, *conv in specs:
+            M = make(cb, A, vt, **(conv[0] if conv else {}))
             mats.append(M)
             ids.append(S.add_matrix(M))
         extra = []
@@ -104,7 +104,7 @@ def run_solves(cb, specs, mix_spmm=False, **opts):
             mats.append(MG)
             gid = S.add_matrix(MG)
         tickets = []
-        for i, (A, vt, seed) in enumerate(specs):
+        for i, (A, vt, seed, *_) in enumerate(specs):
             b = matgen.vector(A.n, seed).astype(ndt(vt))
             x = np.zeros(A.n, ndt(vt))
             tickets.append((x, S.submit_cg(ids[i], b, x, rtol=1e-10 if ndt(vt) == np.float64 else 1e-5,
@@ -146,6 +146,27 @@ def test_cg_alone_and_in_a_mix_agree(cb):
             b = matgen.vector(A.n, seed)
             Aeff = A if vt == "f64" else matgen.Csr(A.m, A.n, A.row_ptr, A.col_idx, oracle.f32_values(A.values))
             assert solvers.residual(Aeff, b, xm) <= 2e-10, (A.name, vt)
+
+
+@pytest.mark.parametrize("vt,modes", [("f64", (0, 1, 3)), ("f32", (1, 2, 4))])
+def test_batched_products_in_every_row_sum_mode(cb, vt, modes):
+    """The batched product kernel in each row-sum mode: the automatic choice gives these operators
+    the one-copy modes, so every mode is forced; one server holds the solves of all modes at once
+    (one launch per mode), and each result equals the same solve served alone."""
+    specs = [(A, vt, 70 + 5 * i + j, {"row_reduce": rr})
+             for i, A in enumerate((matgen.poisson_3d(9), matgen.laplacian_2d(30))) for j, rr in enumerate(modes)]
+    alone = [run_solves(cb, [s])[0][0] for s in specs]
+    mixed, stats = run_solves(cb, specs, max_active=16)
+    assert stats["active_peak"] >= 2
+    for (A, _, seed, conv), (xa, ra), (xm, rm) in zip(specs, alone, mixed):
+        assert ra["converged"] and rm["converged"], (A.name, conv, ra, rm)
+        shared = cb.CbMatrix.from_csr(A, device=False, value_type=vt, **conv).info["shared_panels"]
+        if shared == 0:
+            assert ra["iterations"] == rm["iterations"] and np.array_equal(xa, xm), (A.name, conv)
+        else:
+            assert np.abs(xa - xm).max() <= 1e-3 * np.abs(xa).max(), (A.name, conv)
+        if vt == "f64":
+            assert solvers.residual(A, matgen.vector(A.n, seed), xm) <= 2e-10, (A.name, conv)
 
 
 def test_graph_replay_matches_plain_launches(cb):
