@@ -66,15 +66,17 @@ def kernel_source_hash() -> str:
     return hashlib.sha256("\n".join(code).encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, when
-    they were taken on the current kernel source."""
+def measured_traffic(nnz: int, spmv_bytes: int):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, when they were taken on the
+    current kernel source and on this structure (the same non-zeros and algorithmic bytes)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if t.get("nnz") != nnz or t.get("spmv_bytes") != spmv_bytes:
         return None
     return t.get("bytes_per_launch")
 
@@ -675,7 +677,7 @@ def main() -> int:
                                   "sample": f"{reps} CSR-loop SpMVs on {ncores} threads in {el:.1f}s"}
         log(f"cpu all cores ({ncores}): {extra['cpu_all_cores']['value']:.2f} GFLOP/s")
 
-    traffic = measured_traffic()
+    traffic = measured_traffic(A.nnz, info["spmv_bytes"])
     out = {
         "metric": METRIC,
         "value": round(gflops, 2),
