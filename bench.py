@@ -442,11 +442,11 @@ def run_tune(args, cb, matgen) -> int:
             key = f"{wl}_{vt}"
             rows[key] = {"default_us": k_def * 1e6, "tuned_us": k_tun * 1e6, "speedup": k_def / k_tun,
                          "tune_seconds": tune_s, "candidates": len(cands),
-                         "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "wave_nnz")}}
+                         "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "lb_mode", "wave_nnz")}}
             log(f"{key}: default {k_def * 1e6:.1f} us, tuned {k_tun * 1e6:.1f} us ({k_def / k_tun:.3f}x) "
                 f"in {tune_s:.1f}s, best {rows[key]['best']}; candidates: " + "; ".join(
                     f"agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) rr={c['row_reduce']} "
-                    f"wn={c['opt']['wave_nnz']} {c['us']:.1f}" for c in cands))
+                    f"lb={c['opt']['lb_mode']} wn={c['opt']['wave_nnz']} {c['us']:.1f}" for c in cands))
             del xd, yd
             torch.cuda.empty_cache()
     geo = float(np.exp(np.mean([np.log(r["speedup"]) for r in rows.values()])))

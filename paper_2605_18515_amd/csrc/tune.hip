@@ -190,6 +190,14 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
                 if (st == CB_SUCCESS) st = T.eval(o, idx);
             }
         }
+        // load balance: the other natural-order split (nnz-balanced ranges cut at panel boundaries, or
+        // ranges of equal tile counts cut anywhere); Algorithm 2's scattered order is not tried, its
+        // kernel measured several times slower on every workload
+        {
+            cb_options_t o = cur();
+            o.lb_mode = o.lb_mode == CB_LB_CONTIGUOUS ? CB_LB_NONE : CB_LB_CONTIGUOUS;
+            if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
         // work per wavefront: half and twice the current ranges' mean
         {
             cb_matrix_t hb = T.handles[T.best];

@@ -42,7 +42,7 @@ def test_tuned_handle_and_every_candidate_are_correct(cb, name, vt, wide):
     M, best, cands = cb.cb_tune(A, value_type=vt, vector_f64=wide, reps=5)
     print(f"[tune {name} {vt}] " + "; ".join(
         f"agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) rr={c['row_reduce']} "
-        f"wn={c['opt']['wave_nnz']} {c['us']:.1f}us{' *' if c['best'] else ''}" for c in cands))
+        f"lb={c['opt']['lb_mode']} wn={c['opt']['wave_nnz']} {c['us']:.1f}us{' *' if c['best'] else ''}" for c in cands))
     assert 5 <= len(cands) <= cb.CB_TUNE_MAX_CANDIDATES and sum(c["best"] for c in cands) == 1
     b = next(c for c in cands if c["best"])
     assert b["opt"] == best and b["us"] <= min(c["us"] for c in cands) / 0.99 + 1e-9
@@ -59,4 +59,5 @@ def test_tuned_handle_and_every_candidate_are_correct(cb, name, vt, wide):
 def test_tuner_without_keeping_the_handle(cb):
     A = matgen.laplacian_2d(40)
     M, best, cands = cb.cb_tune(A, keep=False, reps=3)
-    assert M is None and len(cands) >= 5 and best["lb_mode"] == cb.CB_LB_CONTIGUOUS
+    assert M is None and len(cands) >= 5 and best["lb_mode"] in (cb.CB_LB_CONTIGUOUS, cb.CB_LB_NONE)
+    assert {c["opt"]["lb_mode"] for c in cands} == {cb.CB_LB_CONTIGUOUS, cb.CB_LB_NONE}
