@@ -1,6 +1,6 @@
 """CPU oracle for the solvers built on the sparse product -- TEST INFRASTRUCTURE ONLY.
 
-Conjugate gradient and the true residual that the solver tests are judged by.
+Conjugate gradient and the true residual that the solver tests are checked against.
 These are not part of the paper's method: they consume its product (y = A x,
 Section 2.1) as the adjacent step of a mixed-precision solver.  CG is the
 method of Hestenes and Stiefel (1952), as stated in Saad, "Iterative Methods

@@ -1,6 +1,6 @@
 """GPU tests of the solvers built on the CB product: FP64 CG, CG on FP32
 storage, and FP64 iterative refinement around a CG on an FP32 or BF16 copy of
-the matrix.  Judged by the oracle: the FP64 true residual |b - A x| / |b| of the
+the matrix.  Checked by the oracle: the FP64 true residual |b - A x| / |b| of the
 returned x, agreement with the oracle's FP64 CG within the bound the condition
 number gives, exact breakdown on a negative definite matrix, and the argument
 errors of the entry points."""
@@ -81,7 +81,7 @@ def test_cg_f32_storage(cb):
     res = M.cg(dev(b, torch.float32), xd, rtol=1e-5, check_every=4)
     torch.cuda.synchronize()
     M.close()
-    # the stored values (6, -1) and b rounded to FP32 define the solved system; judge in FP64
+    # the stored values (6, -1) and b rounded to FP32 define the solved system; check in FP64
     bf = b.astype(np.float32).astype(np.float64)
     true = solvers.residual(A, bf, host(xd))
     print(f"[cg f32 poisson 20^3] iters {res['iterations']} recurrence {res['rel_residual']:.3e} true {true:.3e}")
