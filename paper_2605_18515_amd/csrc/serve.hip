@@ -78,9 +78,22 @@ __global__ __launch_bounds__(kT) void sb_dot_pq(const SolveJob<T> *__restrict__ 
 
 static_assert(kGB == 64, "one block sum per lane of the reduction");
 
-// grid (solves), 64 threads: the kGB block sums of a solve in block order; mode 0: rr <- rrn,
-// pq = sum; mode 1: rrn = sum; mode 2 (one solve): rr = rrn = sum; mode 3 (one solve): bb = sum,
-// pq = 0, bad = 0
+// the kGB block sums of one solve added as sb_reduce adds them (one per lane of the first
+// wavefront, then a shuffle tree), so every block of a kernel sees the same value
+__device__ double solve_total(const double *__restrict__ part) {
+    __shared__ double tot;
+    if (threadIdx.x < 64) {
+        double v = part[threadIdx.x];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (threadIdx.x == 0) tot = v;
+    }
+    __syncthreads();
+    return tot;
+}
+
+// grid (solves), 64 threads: the kGB block sums of a solve in block order; mode 2 (one solve, its
+// start): rr = rrn = sum; mode 3 (one solve): bb = sum, pq = 0, bad = 0.  (The steps add their block
+// sums inside the kernels that use them, solve_total.)
 template <class T>
 __global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ jobs, const double *__restrict__ partial,
                                                 SolveScal *__restrict__ scal, int mode, int one) {
@@ -90,12 +103,7 @@ __global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ 
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
     if (threadIdx.x == 0) {
         SolveScal &s = scal[j];
-        if (mode == 0) {
-            s.rr = s.rrn;
-            s.pq = v;
-        } else if (mode == 1) {
-            s.rrn = v;
-        } else if (mode == 2) {
+        if (mode == 2) {
             s.rr = v;
             s.rrn = v;
         } else {
@@ -106,17 +114,24 @@ __global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ 
     }
 }
 
-// grid (kGB, solves): x += alpha p, r -= alpha q (alpha = rr / pq), block sums of the new r.r
+// grid (kGB, solves): x += alpha p, r -= alpha q with alpha = rr / pq, where pq adds the block sums
+// of p.q (pq_part) and rr is the previous step's new r.r (rrn); block sums of the new r.r (rr_part).
+// Block 0 records rr and pq for sb_update_p and the host; no other block reads them here.
 template <class T>
 __global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict__ jobs, SolveScal *__restrict__ scal,
-                                                   double *__restrict__ partial) {
+                                                   const double *__restrict__ pq_part, double *__restrict__ rr_part) {
     const SolveJob<T> &J = jobs[blockIdx.y];
     if (!J.active) return;
     SolveScal &s = scal[blockIdx.y];
-    const double pq = s.pq;
+    const double pq = solve_total(pq_part + blockIdx.y * kGB);
+    const double rr = s.rrn;
     const bool ok = pq > 0.0 && std::isfinite(pq);
-    if (!ok && blockIdx.x == 0 && threadIdx.x == 0) s.bad = 1;
-    const double alpha = ok ? s.rr / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.rr = rr;
+        s.pq = pq;
+        if (!ok) s.bad = 1;
+    }
+    const double alpha = ok ? rr / pq : 0.0;
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
         J.x[i] = (T)((double)J.x[i] + alpha * (double)J.p[i]);
@@ -125,17 +140,22 @@ __global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict
         v += (double)ri * (double)ri;
     }
     const double sum = block_sum(v);
-    if (threadIdx.x == 0) partial[blockIdx.y * kGB + blockIdx.x] = sum;
+    if (threadIdx.x == 0) rr_part[blockIdx.y * kGB + blockIdx.x] = sum;
 }
 
-// grid (kGB, solves): p = r + beta p (beta = rrn / rr); q cleared where the product needs it
+// grid (kGB, solves): p = r + beta p with beta = rrn / rr, where rrn adds the block sums of the new
+// r.r (rr_part); q cleared where the product needs it.  Block 0 records rrn for the next step and
+// the host; no other block reads it here.
 template <class T>
-__global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<T> *__restrict__ jobs,
-                                                  const SolveScal *__restrict__ scal) {
+__global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<T> *__restrict__ jobs, SolveScal *__restrict__ scal,
+                                                  const double *__restrict__ rr_part) {
     const SolveJob<T> &J = jobs[blockIdx.y];
     if (!J.active) return;
-    const SolveScal &s = scal[blockIdx.y];
-    const double beta = s.rr > 0.0 ? s.rrn / s.rr : 0.0;
+    SolveScal &s = scal[blockIdx.y];
+    const double rrn = solve_total(rr_part + blockIdx.y * kGB);
+    const double rr = s.rr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.rrn = rrn;
+    const double beta = rr > 0.0 ? rrn / rr : 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
         J.p[i] = (T)((double)J.r[i] + beta * (double)J.p[i]);
         if (J.zero_q) J.q[i] = T(0);
@@ -329,7 +349,9 @@ hipError_t group_alloc(Group<T> &g, int S) {
     hipError_t e;
     if ((e = hipMalloc(&g.d_jobs, sizeof(SolveJob<T>) * S)) != hipSuccess) return e;
     if ((e = hipMalloc(&g.d_scal, sizeof(SolveScal) * S)) != hipSuccess) return e;
-    if ((e = hipMalloc(&g.d_partial, sizeof(double) * kGB * S)) != hipSuccess) return e;
+    // two sets of block sums: p.q (written by sb_dot_pq, read by sb_update_xr) and r.r (written by
+    // sb_update_xr, read by sb_update_p), so no kernel reads the set it writes
+    if ((e = hipMalloc(&g.d_partial, sizeof(double) * kGB * 2 * S)) != hipSuccess) return e;
     if ((e = hipMalloc(&g.d_bjobs, sizeof(cbd::BatchJob) * S)) != hipSuccess) return e;
     if ((e = hipHostMalloc(&g.h_scal, sizeof(SolveScal) * S, hipHostMallocDefault)) != hipSuccess) return e;
     return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<T>) * S, hipMemcpyHostToDevice);
@@ -578,11 +600,10 @@ hipError_t cb_server_s::enqueue_steps(Group<T> &g, int nsteps) {
             if (e != hipSuccess) return e;
             wofs += (size_t)L.total;
         }
-        hipLaunchKernelGGL(sb_dot_pq<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_partial);
-        hipLaunchKernelGGL(sb_reduce<T>, dim3(g.top), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 0, -1);
-        hipLaunchKernelGGL(sb_update_xr<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, g.d_partial);
-        hipLaunchKernelGGL(sb_reduce<T>, dim3(g.top), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 1, -1);
-        hipLaunchKernelGGL(sb_update_p<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal);
+        double *pq_part = g.d_partial, *rr_part = g.d_partial + (size_t)kGB * g.S;
+        hipLaunchKernelGGL(sb_dot_pq<T>, grid, dim3(kT), 0, s, g.d_jobs, pq_part);
+        hipLaunchKernelGGL(sb_update_xr<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, pq_part, rr_part);
+        hipLaunchKernelGGL(sb_update_p<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, rr_part);
     }
     return hipGetLastError();
 }
