@@ -91,6 +91,8 @@ def test_spmv_f64(cb, name, lb, col_agg):
     A = SMALL[name]()
     x = matgen.vector(A.n, 7)
     check(cb, A, x, label=name, lb_mode=lb, col_agg=col_agg)
+    # short work ranges: these matrices then span many ranges, with panels shared between them
+    check(cb, A, x, label=f"{name} short ranges", lb_mode=lb, col_agg=col_agg, wave_nnz=64)
 
 
 @pytest.mark.parametrize("name", ["dense_mix", "power", "block8"])
@@ -306,8 +308,10 @@ def test_spmm(cb, k, vtype):
     A = SMALL["dense_mix"]() if k % 2 else SMALL["block8"]()
     X = matgen.rhs(A.n, k, k)
     Y0 = matgen.rhs(A.m, k, k + 50)
-    for lb, agg, th in (("contiguous", -1, (32, 128)), ("paper", 0, (8, 40)), ("contiguous", 1, (8, 40))):
-        Y = run_spmm(cb, A, X, 1.5, -0.5, Y0, vtype, ld_pad=3, lb_mode=lb, col_agg=agg, th1=th[0], th2=th[1])
+    for lb, agg, th, wn in (("contiguous", -1, (32, 128), 0), ("paper", 0, (8, 40), 0), ("contiguous", 1, (8, 40), 0),
+                            ("contiguous", -1, (32, 128), 64), ("none", 1, (8, 40), 64)):
+        Y = run_spmm(cb, A, X, 1.5, -0.5, Y0, vtype, ld_pad=3, lb_mode=lb, col_agg=agg, th1=th[0], th2=th[1],
+                     wave_nnz=wn)
         ref = oracle.spmm(A, X, 1.5, -0.5, Y0, comp=True)
         scl = oracle.spmm_scale(A, X, 1.5, -0.5, Y0)
         e, viol, _ = oracle.scaled_error(Y, ref, scl, TOL[vtype])
