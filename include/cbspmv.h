@@ -443,7 +443,7 @@ typedef struct {
     double solves_per_s;             /* completed CG solves / elapsed_s */
     int64_t arena_peak_bytes;        /* most arena bytes in use at once */
     int32_t active_peak;             /* most solves active at once */
-    int32_t graph_builds;            /* HIP graphs captured (one per change of the active set) */
+    int32_t graph_builds;            /* HIP graphs captured (one per active set that lasts beyond its first period) */
     int64_t steps;                   /* solve steps run */
     int64_t reserved[4];
 } cb_server_stats_t;

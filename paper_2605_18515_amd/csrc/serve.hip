@@ -296,6 +296,7 @@ struct cb_server_s {
     hipEvent_t period_ev = nullptr;
     hipGraphExec_t graph = nullptr;
     bool dirty = true;
+    int same_periods = 0;  // periods run since the active set last changed
     bool period_inflight = false;
 
     std::mutex mu;
@@ -617,24 +618,30 @@ hipError_t cb_server_s::enqueue_period() {
             hipGraphExecDestroy(graph);
             graph = nullptr;
         }
-        if (o.use_graph) {
-            hipGraph_t gr = nullptr;
-            if ((e = hipStreamBeginCapture(cg_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-            hipError_t e1 = enqueue_steps(g64, o.check_every);
-            hipError_t e2 = enqueue_steps(g32, o.check_every);
-            e = hipStreamEndCapture(cg_stream, &gr);
-            if (e1 != hipSuccess) return e1;
-            if (e2 != hipSuccess) return e2;
-            if (e != hipSuccess) return e;
-            e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
-            hipGraphDestroy(gr);
-            if (e != hipSuccess) return e;
-            std::lock_guard<std::mutex> lk(mu);
-            ++graph_builds;
-        }
         dirty = false;
+        same_periods = 0;
     }
-    if (o.use_graph) {
+    // the first period of a new active set runs as plain launches: under steady arrivals most sets
+    // last one period, and capturing a graph for one replay costs more than it saves; from the
+    // second period on the set is captured once and replayed
+    const bool replay = o.use_graph && same_periods >= 1;
+    ++same_periods;
+    if (replay && !graph) {
+        hipGraph_t gr = nullptr;
+        if ((e = hipStreamBeginCapture(cg_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+        hipError_t e1 = enqueue_steps(g64, o.check_every);
+        hipError_t e2 = enqueue_steps(g32, o.check_every);
+        e = hipStreamEndCapture(cg_stream, &gr);
+        if (e1 != hipSuccess) return e1;
+        if (e2 != hipSuccess) return e2;
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        if (e != hipSuccess) return e;
+        std::lock_guard<std::mutex> lk(mu);
+        ++graph_builds;
+    }
+    if (replay) {
         if ((e = hipGraphLaunch(graph, cg_stream)) != hipSuccess) return e;
     } else {
         if ((e = enqueue_steps(g64, o.check_every)) != hipSuccess) return e;

@@ -171,8 +171,10 @@ def test_batched_products_in_every_row_sum_mode(cb, vt, modes):
 
 def test_graph_replay_matches_plain_launches(cb):
     specs = [(A, "f64", 40 + i) for i, A in enumerate(spd_matrices()[:4])]
-    g, _ = run_solves(cb, specs, use_graph=1, max_active=4)
-    p, _ = run_solves(cb, specs, use_graph=0, max_active=4)
+    g, sg = run_solves(cb, specs, use_graph=1, max_active=4)
+    p, sp = run_solves(cb, specs, use_graph=0, max_active=4)
+    # a set's first period runs as plain launches, the later ones replay its graph
+    assert sg["graph_builds"] >= 1 and sp["graph_builds"] == 0
     for (xg, rg), (xp, rp) in zip(g, p):
         assert rg["iterations"] == rp["iterations"] and np.array_equal(xg, xp)
 
