@@ -363,6 +363,49 @@ def test_repeated_calls_and_streams(cb):
     M.close()
 
 
+@pytest.mark.parametrize("lb,wn", [("contiguous", 64), ("paper", 0)])
+def test_graph_replays(cb, lb, wn):
+    """cb_spmv and cb_spmm captured in one HIP graph (with shared panels, so the y <- beta y pre-pass is
+    captured too) and replayed several times, with eager work and synchronisations between the
+    replays: every replay meets the oracle."""
+    A = SMALL["power"]()
+    k = 8
+    x, y0 = matgen.vector(A.n, 2), matgen.vector(A.m, 5, stream=matgen.STREAM_Y0)
+    X, Y0 = matgen.rhs(A.n, k, 3), matgen.rhs(A.m, k, 4)
+    M = cb.CbMatrix.from_csr(A, lb_mode=lb, wave_nnz=wn)
+    if lb == "contiguous":
+        assert M.info["shared_panels"] > 0
+    xd, y0d = torch.from_numpy(x).cuda(), torch.from_numpy(y0).cuda()
+    Xd, Y0d = torch.from_numpy(X).cuda(), torch.from_numpy(Y0).cuda()
+    yd, Yd = torch.empty_like(y0d), torch.empty_like(Y0d)
+    ref = oracle.spmv(A, x, 1.5, -0.5, y0, comp=True)
+    scl = oracle.scale(A, x, 1.5, -0.5, y0)
+    refm = oracle.spmm(A, X, 1.5, -0.5, Y0, comp=True)
+    sclm = oracle.spmm_scale(A, X, 1.5, -0.5, Y0)
+
+    def step():
+        yd.copy_(y0d)
+        M.spmv(xd, yd, 1.5, -0.5)
+        Yd.copy_(Y0d)
+        M.spmm(Xd, Yd, 1.5, -0.5)
+
+    step()  # eager: code objects loaded before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(4):
+        yd.fill_(float("nan"))
+        Yd.fill_(7.0)
+        M.spmv(xd, torch.empty_like(yd))  # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert oracle.scaled_error(yd.cpu().numpy(), ref, scl, 1e-12)[1] == 0, rep
+        assert oracle.scaled_error(Yd.cpu().numpy(), refm, sclm, 1e-12)[1] == 0, rep
+    M.close()
+
+
 def test_copy_probe(cb):
     n = 1 << 22
     src = torch.arange(n, dtype=torch.float64, device="cuda")
