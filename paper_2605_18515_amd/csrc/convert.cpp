@@ -18,7 +18,10 @@
 // Automatic work per wavefront range (non-zero equivalents): enough ranges to occupy every
 // wavefront slot of the device about once (256 CUs x 22 resident wavefronts = 5632; aiming at 5120
 // keeps a count that rounds up from spilling into a second, nearly empty round), no range below 256
-// (a range's fixed cost, its pipeline fill, dominates shorter ones) and none above 4096.  Measured
+// (a range's fixed cost, its pipeline fill, dominates shorter ones) and none above about 18 KB of
+// codes and values (2048 entries of FP64 values, 3686 of FP32, 4096 of BF16): on the largest matrices
+// shorter ranges balance the last round better, FP64 1.7-3.8 % faster than at 4096, while the
+// smaller FP32/BF16 entries keep the longer ranges they measured best with.  Measured
 // against 16384 ranges of at least 64: a 7-point operator on 100^3 nodes 27.6 against 34.2 us, on
 // 50^3 6.5 against 11.4 us, a 64 x 64 Laplacian 3.3 against 2.9 us (graph replay), and the serving
 // loop's batched products 1.38x the solves per second.
@@ -27,6 +30,9 @@
 #endif
 #ifndef CB_TUNE_WAVE_RANGES
 #define CB_TUNE_WAVE_RANGES 5120
+#endif
+#ifndef CB_TUNE_MAX_RANGE_BYTES
+#define CB_TUNE_MAX_RANGE_BYTES 18432
 #endif
 
 namespace cbh {
@@ -584,7 +590,8 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         const int64_t total_w = nnz + (int64_t)kTileCost * NT;
         int64_t target = opt.wave_nnz;
         if (target == 0)
-            target = std::min<int64_t>(4096, std::max<int64_t>(CB_TUNE_MIN_WAVE_NNZ, (total_w + CB_TUNE_WAVE_RANGES - 1) / CB_TUNE_WAVE_RANGES));
+            target = std::min<int64_t>(std::min<int64_t>(4096, CB_TUNE_MAX_RANGE_BYTES / (1 + s.vsize)),
+                                       std::max<int64_t>(CB_TUNE_MIN_WAVE_NNZ, (total_w + CB_TUNE_WAVE_RANGES - 1) / CB_TUNE_WAVE_RANGES));
         auto tw = [&](int32_t i) { return (int64_t)nnzv[i] + kTileCost; };
 
         std::vector<int32_t> wptr;
