@@ -3,11 +3,12 @@
 // an FP32 or BF16 copy of the matrix.
 //
 // Every iteration runs on the device: the product through cb_spmv, the dot
-// products accumulated in FP64 (block sums, then a one-block kernel that adds
-// them in block order, so results do not depend on timing; a last-block-done
-// reduction inside the same kernel needs a device-scope fence per block, which
-// writes back the XCD's L2 and measured slower), and the step lengths computed
-// by the update kernels from device scalars.  The host reads the residual norm
+// products accumulated in FP64 (block sums, then added in block order by a
+// one-block kernel, or for p.q by every block of the update kernel that needs
+// it, so results do not depend on timing; a last-block-done reduction inside
+// the same kernel needs a device-scope fence per block, which writes back the
+// XCD's L2 and measured slower), and the step lengths computed by the update
+// kernels from device scalars.  The host reads the residual norm
 // every check_every iterations.
 #include <hip/hip_runtime.h>
 
@@ -75,16 +76,32 @@ __global__ __launch_bounds__(64) void reduce_kernel(const double *__restrict__ p
     }
 }
 
-// x += alpha p, r -= alpha q with alpha = rr / pq (in FP64, rounded on store); block sums of the
-// new r.r
+// x += alpha p, r -= alpha q with alpha = rr / pq (in FP64, rounded on store), where pq adds the g
+// block sums of p.q (pq_part) in reduce_kernel's order, in every block, and rr is the r.r the
+// previous step ended with (rrn); block sums of the new r.r (rr_part).  Block 0 records rr and pq
+// for update_p_kernel and the host; no other block reads them here.
 template <class TR, class TV>
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(TR *__restrict__ x, TR *__restrict__ r,
                                                              const TV *__restrict__ p, const TV *__restrict__ q,
-                                                             int64_t n, Scal *s, double *__restrict__ partial) {
-    const double pq = s->pq;
+                                                             int64_t n, Scal *s, const double *__restrict__ pq_part,
+                                                             int g, double *__restrict__ rr_part) {
+    __shared__ double tot;
+    if (threadIdx.x < 64) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < g; i += 64) v += pq_part[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (threadIdx.x == 0) tot = v;
+    }
+    __syncthreads();
+    const double pq = tot;
+    const double rr = s->rrn;
     const bool ok = pq > 0.0 && std::isfinite(pq);
-    if (!ok && blockIdx.x == 0 && threadIdx.x == 0) s->bad = 1;
-    const double alpha = ok ? s->rr / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rr = rr;
+        s->pq = pq;
+        if (!ok) s->bad = 1;
+    }
+    const double alpha = ok ? rr / pq : 0.0;
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         x[i] = (TR)((double)x[i] + alpha * (double)p[i]);
@@ -93,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void update_xr_kernel(TR *__restrict__ x,
         v += (double)ri * (double)ri;
     }
     const double sum = block_sum(v);
-    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = sum;
 }
 
 // p = r + beta p with beta = rrn / rr
@@ -173,9 +190,9 @@ cb_status_t mat_of(cb_matrix_t A, Mat &M) {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // workspace of one CG run: residual (sr bytes per element), direction and product (sv bytes),
-// block sums, scalars
+// two sets of block sums (p.q, read by the update kernel, and r.r, which it writes), scalars
 size_t cg_bytes(int64_t n, int sr, int sv) {
-    return align256((size_t)n * sr) + 2 * align256((size_t)n * sv) + align256(sizeof(double) * kMaxBlocks) +
+    return align256((size_t)n * sr) + 2 * align256((size_t)n * sv) + align256(sizeof(double) * 2 * kMaxBlocks) +
            align256(sizeof(Scal));
 }
 
@@ -190,7 +207,7 @@ template <class TR, class TV>
 struct Work {
     TR *r;
     TV *p, *q;
-    double *partial;
+    double *partial, *partial2;
     Scal *s;
 };
 
@@ -203,7 +220,8 @@ Work<TR, TV> carve(void *work, int64_t n) {
     c.p = reinterpret_cast<TV *>(w + vr);
     c.q = reinterpret_cast<TV *>(w + vr + vv);
     c.partial = reinterpret_cast<double *>(w + vr + 2 * vv);
-    c.s = reinterpret_cast<Scal *>(w + vr + 2 * vv + align256(sizeof(double) * kMaxBlocks));
+    c.partial2 = c.partial + kMaxBlocks;
+    c.s = reinterpret_cast<Scal *>(w + vr + 2 * vv + align256(sizeof(double) * 2 * kMaxBlocks));
     return c;
 }
 
@@ -274,11 +292,12 @@ cb_status_t cg_run(cb_matrix_t Aop, cb_matrix_t Ahi, int64_t n, const TR *b, TR 
     }
     for (int it = 1; it <= max_iter; ++it) {
         if ((e = cb_spmv(Aop, 1.0, w.p, 0.0, w.q, st)) != CB_SUCCESS) return e;
-        // pq = p.q, and rr <- rrn from the previous iteration (the first has rr set already)
-        dot(w.p, w.q, n, w.partial, w.s, &w.s->pq, st, it > 1 ? &w.s->rrn : nullptr, it > 1 ? &w.s->rr : nullptr);
+        // block sums of p.q; the update adds them itself and takes rr from the r.r the previous step
+        // (or the start, or a replacement) left in rrn
+        hipLaunchKernelGGL((dot_kernel<TV, TV>), dim3(g), dim3(kThreads), 0, st, w.p, w.q, n, w.partial);
         hipLaunchKernelGGL((update_xr_kernel<TR, TV>), dim3(g), dim3(kThreads), 0, st, x, w.r, w.p, w.q, n, w.s,
-                           w.partial);
-        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(64), 0, st, w.partial, g, &w.s->rrn, nullptr, nullptr);
+                           w.partial, g, w.partial2);
+        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(64), 0, st, w.partial2, g, &w.s->rrn, nullptr, nullptr);
         if ((e = hipcheck(hipGetLastError(), "CG step launch")) != CB_SUCCESS) return e;
         out.iters = it;
         if (it % check_every == 0 || it == max_iter) {
