@@ -368,3 +368,29 @@ def test_random_round_trip(m, n, dens, seed, vtype, agg, th, lb):
     roundtrip(A, vtype, col_agg=agg, th1=th[0], th2=th[1], lb_mode=lb, wave_nnz=int(rng.integers(0, 300)))
     if m * n <= 900 and vtype == "f64":
         check_against_model(A, col_agg=agg, th1=th[0], th2=th[1], lb=lb)
+
+
+def test_automatic_range_size():
+    """The automatic work per range: about 5120 ranges, none below 256 non-zero equivalents, and none
+    above about 18 KB of codes and values (2048 FP64 entries, 3686 FP32, 4096 BF16); panels heavier
+    than twice the target are the only ranges allowed past it."""
+    small = matgen.laplacian_2d(64)  # 20,224 non-zeros: the floor (256 in non-zeros plus a cost per tile)
+    M = cb.CbMatrix.from_csr(small, device=False)
+    i = M.info
+    assert 100 <= i["wave_nnz_mean"] <= 256 and i["nwaves"] <= small.nnz // 100, (i["wave_nnz_mean"], i["nwaves"])
+    M.close()
+    big = matgen.block_3d(60, seed=1)  # 13.4 M non-zeros: the FP64 byte cap binds, the others do not
+    caps = {"f64": 2048, "f32": 3686, "bf16": 4096}
+    means = {}
+    for vt, cap in caps.items():
+        M = cb.CbMatrix.from_csr(big, device=False, value_type=vt)
+        i = M.info
+        means[vt] = i["wave_nnz_mean"]
+        assert i["wave_nnz_mean"] <= cap and i["wave_nnz_max"] <= 2 * cap, (vt, i["wave_nnz_mean"], i["wave_nnz_max"])
+        M.close()
+    # FP64 entries (9 bytes) reach the cap, and get more, shorter ranges than FP32 (5 bytes) and BF16 (3)
+    assert means["f64"] < means["f32"] == means["bf16"]
+    # an explicit wave_nnz overrides the rule
+    M = cb.CbMatrix.from_csr(big, device=False, wave_nnz=500)
+    assert M.info["wave_nnz_mean"] <= 600
+    M.close()
