@@ -481,8 +481,9 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         done_mask = 0;
     };
 
-    // multiply one batch: records rec[1..], header fields hz = nt | nflat << 8 | ndense << 16 | done << 24
-    // and etot (flat entries); positions in the packed record words are taken modulo the ring size
+    // multiply one batch: its records in rl (lane i holds tile i's), header fields hz = nt | nflat << 8 |
+    // ndense << 16 | done << 24 and etot (flat entries); positions in the packed record words are taken
+    // modulo the ring size
     auto multiply = [&](const i32x2 rl, int hz, int etot) {
         const int nflat = (hz >> 8) & 0xFF, ndense = (hz >> 16) & 0xFF;
         // COO and CSR entries as one stream; lane i holds flat tile i's last entry (endv) and record
