@@ -33,6 +33,8 @@ WORKLOADS = {
     "block3d": "FP64 y=A*x, 3D block matrix {side}^3 grid x 3 dof (7-point, dense 3x3 blocks, diag +10)",
     "powerlaw": "FP64 y=A*x, power-law rows: n=4,000,000, Zipf(2.1) lengths in [1,1e5] scaled to mean 16, "
                 "70% of columns within +-2048 of the diagonal",
+    "powerlaw_literal": "FP64 y=A*x, power-law rows: n=4,000,000, Zipf(2.1) lengths in [1,1e5] unscaled (mean 4.8), "
+                        "70% of columns within +-2048 of the diagonal",
     "poisson": "FP64 y=A*x, 3D 7-point Poisson operator on a 192^3 grid",
     "laplacian": "FP64 y=A*x, 2D 5-point Laplacian on a 64x64 grid",
 }
@@ -45,6 +47,8 @@ def make_matrix(name: str, side: int):
         return matgen.block_3d(side, 3, 10.0, seed=1)
     if name == "powerlaw":
         return matgen.power_law(4_000_000, seed=2)
+    if name == "powerlaw_literal":
+        return matgen.power_law(4_000_000, seed=2, mean_len=None)
     if name == "poisson":
         return matgen.poisson_3d(192)
     return matgen.laplacian_2d(64)
@@ -467,6 +471,7 @@ def main() -> int:
     ap.add_argument("--side", type=int, default=100, help="grid side of the 3D block matrix")
     ap.add_argument("--workload", default="block3d", choices=list(WORKLOADS),
                     help="matrix: block3d (default, 100^3 x 3 dof), powerlaw (n = 4M, Zipf 2.1 rows, mean 16), "
+                         "powerlaw_literal (the same rows unscaled, mean 4.8), "
                          "poisson (7-point, 192^3), laplacian (5-point, 64 x 64)")
     ap.add_argument("--lb", default="contiguous", choices=["contiguous", "paper", "none"])
     ap.add_argument("--col-agg", type=int, default=-1)

@@ -124,6 +124,18 @@ def test_powerlaw_4m_sampled_rows(cb):
     check_rows(y[rows], sub, x, "f64", "power-law 4M (sampled rows)")
 
 
+def test_powerlaw_literal_sampled_rows(cb):
+    """The power-law generator's unscaled row lengths (Zipf 2.1 truncated to [1, 1e5], mean 4.8)."""
+    A = matgen.power_law(4_000_000, seed=2, mean_len=None)
+    x = matgen.vector(A.n, 1)
+    y, _ = spmv_gpu(cb, A, x, "f64")
+    lens = np.diff(A.row_ptr)
+    rows = np.unique(np.concatenate([np.argsort(lens)[-64:],
+                                     np.random.default_rng(4).choice(A.m, 20000, replace=False), [0, A.m - 1]]))
+    sub = rows_of(A, rows)
+    check_rows(y[rows], sub, x, "f64", "power-law 4M, unscaled lengths (sampled rows)")
+
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("vtype", ["f32", "f64"])
 def test_spmm_x_beyond_4gib(cb, vtype):
