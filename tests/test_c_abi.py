@@ -55,3 +55,18 @@ def test_host_conversion_from_c(c_output):
     assert "roundtrip ok" in line and "on_device 0" in line and "nnz 6" in line
     bad = next(l for l in c_output if l.startswith("bad row_ptr"))
     assert f"status {cb.CB_ERROR_INVALID_VALUE}" in bad and bad.endswith("set")
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the binding next to no built library refuses to import (there is no fallback path)."""
+    import importlib.util
+    import shutil as sh
+
+    src = os.path.join(ROOT, "paper_2605_18515_amd", "cbspmv.py")
+    pkg = tmp_path / "pkg"
+    pkg.mkdir()
+    sh.copy(src, pkg / "cbspmv.py")
+    spec = importlib.util.spec_from_file_location("cbspmv_copy", str(pkg / "cbspmv.py"))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="libcbspmv.so is missing"):
+        spec.loader.exec_module(mod)
