@@ -288,9 +288,11 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
                                              outs[j].reshape(csrs[i].m, k)))
         return tickets
 
+    max_active, arena = args.serve_active, args.serve_arena_gib
+
     def serve(gaps=None, count=None):
         outs = outputs()
-        S = cb.CbServer(max_active=64, arena_bytes=8 << 30)
+        S = cb.CbServer(max_active=max_active, arena_bytes=arena << 30)
         for M in mats:
             S.add_matrix(M)
         tickets = submit_all(S, outs, gaps, count)
@@ -482,6 +484,8 @@ def main() -> int:
     ap.add_argument("--no-solves", action="store_true",
                     help="skip the CG (FP64 vs mixed) and serving legs of the extra measurements")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving leg of the extras")
+    ap.add_argument("--serve-active", type=int, default=128, help="solve slots per vector type of the server")
+    ap.add_argument("--serve-arena-gib", type=int, default=16, help="device arena of the server, GiB")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true",
                     help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
