@@ -140,6 +140,132 @@ def time_calls(fn, steps: int, warmup: int):
     return wall / steps, e0.elapsed_time(e1) / 1e3 / steps
 
 
+STORAGE_TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2}
+
+
+def settle(fn, seconds: float):
+    """Untimed launches of fn for at least `seconds` of wall time, synchronising every 16 launches:
+    the GPU leaves its idle clocks within milliseconds to tens of milliseconds of sustained work, so
+    a short timed window right after host-side work would otherwise measure part of that ramp.
+    Returns (launches, seconds)."""
+    import torch
+
+    n, t0 = 0, time.perf_counter()
+    while True:
+        for _ in range(16):
+            fn()
+        n += 16
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return n, el
+
+
+def gpu_sclk():
+    """The shader clock level the driver reports as current (sysfs pp_dpm_sclk, the line marked
+    '*'), or None where it is not readable."""
+    import glob
+
+    for f in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(f) as fh:
+                for line in fh:
+                    if line.rstrip().endswith("*"):
+                        return line.split(":", 1)[-1].replace("*", "").strip()
+        except OSError:
+            continue
+    return None
+
+
+def rows_of(A, rows):
+    """The sub-matrix of the given rows (same columns): its oracle product is exactly those rows."""
+    import numpy as np
+
+    from paper_2605_18515_amd import matgen
+
+    rows = np.asarray(rows)
+    starts, ends = A.row_ptr[rows], A.row_ptr[rows + 1]
+    idx = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)]) if rows.size else np.zeros(0, np.int64)
+    rp = np.concatenate([[0], np.cumsum(ends - starts)]).astype(np.int64)
+    return matgen.Csr(rows.size, A.n, rp, A.col_idx[idx], A.values[idx])
+
+
+def sample_rows(A, count: int, seed: int):
+    """A seeded sample of rows, plus the first, the last and the longest ones."""
+    import numpy as np
+
+    lens = np.diff(A.row_ptr)
+    pick = np.random.default_rng(seed).choice(A.m, min(count, A.m), replace=False)
+    return np.unique(np.concatenate([pick, np.argsort(lens)[-16:], [0, A.m - 1]]))
+
+
+def spmv_leg(cb, A, dev, steps: int, settle_s: float, check: bool, workload: str) -> dict:
+    """FP64 SpMV of A (default options: the paper's rules, contiguous ranges), x from seed 1: kernel
+    time from HIP events over `steps` launches after an untimed settle, algorithmic bytes and their
+    fraction of the HBM peak, and the max scaled error of every row against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2605_18515_amd import matgen
+
+    x = matgen.vector(A.n, 1)
+    M = cb.CbMatrix.from_csr(A)
+    info = M.info
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.empty(A.m, dtype=torch.float64, device=dev)
+    step = lambda: M.spmv(xd, yd)  # noqa: E731
+    settle(step, settle_s)
+    wall, kern = time_calls(step, steps, 0)
+    leg = {"workload": workload, "n": A.n, "nnz": A.nnz, "kernel_us": kern * 1e6, "gflops": 2.0 * A.nnz / wall / 1e9,
+           "spmv_bytes": info["spmv_bytes"], "GBs": info["spmv_bytes"] / kern / 1e9,
+           "frac": info["spmv_bytes"] / kern / 1e9 / HBM_PEAK_GBS, "col_agg": info["col_agg"],
+           "row_reduce": info["row_reduce"], "nwaves": info["nwaves"], "shared_panels": info["shared_panels"],
+           "kernel": kernel_name(info, "contiguous")}
+    if check:
+        import oracle
+
+        y = yd.cpu().numpy()
+        e, viol, _ = oracle.scaled_error(y, oracle.spmv(A, x, comp=True), oracle.scale(A, x), 1e-12)
+        leg["max_scaled_error"] = e
+        leg["violations"] = viol
+        if viol:
+            raise RuntimeError(f"{workload}: {viol} rows outside the 1e-12 tolerance (max {e})")
+    M.close()
+    del xd, yd
+    return leg
+
+
+def laplacian_leg(cb, dev, check: bool) -> dict:
+    """The 64 x 64 five-point Laplacian (20,224 non-zeros, cache-resident): latency of one SpMV
+    launched on its own, and per launch when 1000 launches replay as one captured HIP graph."""
+    import torch
+
+    from paper_2605_18515_amd import matgen
+
+    A = matgen.laplacian_2d(64)
+    x = matgen.vector(A.n, 1)
+    M = cb.CbMatrix.from_csr(A)
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.empty(A.m, dtype=torch.float64, device=dev)
+    step = lambda: M.spmv(xd, yd)  # noqa: E731
+    settle(step, 0.2)
+    w1, k1 = time_calls(step, 1000, 0)
+    wg, kg = time_graph(step, 1000, 10)
+    leg = {"workload": WORKLOADS["laplacian"], "nnz": A.nnz, "stream_launch_us": w1 * 1e6,
+           "stream_kernel_us": k1 * 1e6, "graph_replay_us_per_launch": kg * 1e6,
+           "graph_gflops": 2.0 * A.nnz / kg / 1e9, "spmv_bytes": M.info["spmv_bytes"],
+           "note": "working set in cache: launch-bound, not an HBM roofline figure"}
+    if check:
+        import oracle
+
+        e, viol, _ = oracle.scaled_error(yd.cpu().numpy(), oracle.spmv(A, x, comp=True), oracle.scale(A, x), 1e-12)
+        leg["max_scaled_error"] = e
+        if viol:
+            raise RuntimeError(f"laplacian: {viol} rows outside the 1e-12 tolerance (max {e})")
+    M.close()
+    return leg
+
+
 CG_LEGS = ("fp64_cg", "replace_f32", "replace_bf16", "replace_f32w", "replace_bf16w", "restart_f32", "restart_bf16",
            "restart_f32w")
 
@@ -487,6 +613,11 @@ def main() -> int:
     ap.add_argument("--serve-active", type=int, default=128, help="solve slots per vector type of the server")
     ap.add_argument("--serve-arena-gib", type=int, default=16, help="device arena of the server, GiB")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--settle-seconds", type=float, default=1.0,
+                    help="untimed launches of the headline SpMV for this long after the warm-up, before the "
+                         "timed region (clocks reach their steady state); reported in extra.untimed_settle")
+    ap.add_argument("--leg-settle-seconds", type=float, default=0.3,
+                    help="the same before each leg of the extra measurements")
     ap.add_argument("--graph", action="store_true",
                     help="time the SpMV steps as replays of one captured HIP graph (launch-bound workloads)")
     ap.add_argument("--cg", action="store_true",
@@ -517,6 +648,17 @@ def main() -> int:
 
     from paper_2605_18515_amd import matgen
     from paper_2605_18515_amd import cbspmv as cb
+
+    # the stencil and power-law legs of the extras need their matrices; worker processes (forked
+    # before this process touches the GPU, CPU work only) generate them while the GPU runs the
+    # headline and the block-matrix legs
+    pool, pending = None, {}
+    if (not args.no_extras and args.workload == "block3d" and not args.copy_only and not args.cg and not args.serve
+            and not args.tune and not args.ablation):
+        import multiprocessing as mp
+
+        pool = mp.get_context("fork").Pool(2)
+        pending = {wl: pool.apply_async(make_matrix, (wl, 0)) for wl in ("powerlaw", "poisson")}
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
@@ -552,11 +694,16 @@ def main() -> int:
     xd = torch.from_numpy(x).to(dev)
     yd = torch.empty(A.m, dtype=torch.float64, device=dev)
     step = lambda: M.spmv(xd, yd)  # noqa: E731
-    wall_s, kern_s = (time_graph if args.graph else time_calls)(step, args.steps, args.warmup)
+    sclk0 = gpu_sclk()
+    for _ in range(args.warmup):
+        step()
+    settled = settle(step, args.settle_seconds) if not args.graph else None
+    wall_s, kern_s = (time_graph if args.graph else time_calls)(step, args.steps, 0)
+    sclk1 = gpu_sclk()
     gflops = 2.0 * A.nnz / wall_s / 1e9
     achieved = info["spmv_bytes"] / kern_s / 1e9
     log(f"FP64 SpMV: {wall_s * 1e6:.1f} us/step wall, {kern_s * 1e6:.1f} us kernel, {gflops:.1f} GFLOP/s, "
-        f"{achieved:.0f} GB/s algorithmic")
+        f"{achieved:.0f} GB/s algorithmic (clock before warm-up {sclk0}, after the timed launches {sclk1})")
 
     err = None
     coo = None
@@ -578,6 +725,11 @@ def main() -> int:
     extra = {"bytes_paper_model": paper_bytes, "GBs_paper_model": paper_bytes / kern_s / 1e9,
              "convert_seconds": info["convert_seconds"], "create_seconds": create_s,
              "kernel_us": kern_s * 1e6, "max_scaled_error_fp64": err,
+             "untimed_settle": None if settled is None else
+             {"launches": settled[0], "seconds": settled[1],
+              "note": "untimed launches after the warm-up and before the timed region, until the GPU's "
+                      "clocks reach the steady state of a long run"},
+             "sclk": {"before_warmup": sclk0, "after_timed": sclk1},
              "structure": {k: info[k] for k in ("ntiles", "tiles_coo", "tiles_csr", "tiles_dense", "col_agg",
                                                 "super_sparse_share", "payload_bytes", "meta_bytes",
                                                 "restore_bytes", "sched_bytes", "nwaves", "shared_panels",
@@ -602,30 +754,71 @@ def main() -> int:
         torch.cuda.empty_cache()
         import oracle
 
+        lsteps = max(50, args.steps // 3)
+        srows = sample_rows(A, 4096, 7)
+        sub = rows_of(A, srows)
         for vt in ("f32", "bf16"):
             Mv = cb.CbMatrix.from_csr(A, value_type=vt, lb_mode=args.lb, col_agg=args.col_agg,
                                       wave_nnz=args.wave_nnz)
             iv = Mv.info
             x32 = torch.from_numpy(x).to(dev, torch.float32)
             y32 = torch.empty(A.m, dtype=torch.float32, device=dev)
-            w1, k1 = time_calls(lambda: Mv.spmv(x32, y32), max(50, args.steps // 3), 5)
+            spmv32 = lambda: Mv.spmv(x32, y32)  # noqa: E731
+            settle(spmv32, args.leg_settle_seconds)
+            w1, k1 = time_calls(spmv32, lsteps, 0)
             leg = {"spmv_gflops": 2.0 * A.nnz / w1 / 1e9, "spmv_kernel_us": k1 * 1e6,
-                   "spmv_GBs": iv["spmv_bytes"] / k1 / 1e9, "spmv_bytes": iv["spmv_bytes"]}
+                   "spmv_GBs": iv["spmv_bytes"] / k1 / 1e9, "spmv_frac": iv["spmv_bytes"] / k1 / 1e9 / HBM_PEAK_GBS,
+                   "spmv_bytes": iv["spmv_bytes"], "row_reduce": iv["row_reduce"]}
             if not args.no_check:
                 e, _, _ = oracle.scaled_error(y32.cpu().double().numpy(), ref, oracle.scale(A, x, coo=coo), 1.0)
                 leg["max_scaled_error_vs_fp64_oracle"] = e
+            del x32, y32
             for k in (8, 32):
-                Xd = torch.empty((A.n, k), dtype=torch.float32, device=dev).uniform_(-1, 1)
+                # X column j from seed 3 + j, rounded to FP32; checked on sampled rows against the FP64
+                # oracle on the original values and X
+                Xh = matgen.rhs_columns(A.n, k, 3)
+                Xd = torch.from_numpy(Xh).to(dev, torch.float32)
                 Yd = torch.empty((A.m, k), dtype=torch.float32, device=dev)
-                wk, kk = time_calls(lambda: Mv.spmm(Xd, Yd), 20, 3)
+                spmmk = lambda: Mv.spmm(Xd, Yd)  # noqa: E731
+                settle(spmmk, args.leg_settle_seconds)
+                wk, kk = time_calls(spmmk, 20, 0)
+                sb = iv["spmv_bytes"] - 4 * (A.n + A.m) + 4 * k * (A.n + A.m)
                 leg[f"spmm_k{k}_gflops"] = 2.0 * A.nnz * k / wk / 1e9
                 leg[f"spmm_k{k}_kernel_us"] = kk * 1e6
-                del Xd, Yd
+                leg[f"spmm_k{k}_bytes"] = sb
+                leg[f"spmm_k{k}_GBs"] = sb / kk / 1e9
+                if not args.no_check:
+                    Ys = Yd.cpu().double().numpy()[srows]
+                    refk = oracle.spmm(sub, Xh)
+                    sclk = oracle.spmm(matgen.Csr(sub.m, sub.n, sub.row_ptr, sub.col_idx, np.abs(sub.values)),
+                                       np.abs(Xh))
+                    ek, vk, _ = oracle.scaled_error(Ys.ravel(), refk.ravel(), sclk.ravel(), STORAGE_TOL[vt])
+                    leg[f"spmm_k{k}_max_scaled_error_vs_fp64_oracle"] = ek
+                    leg[f"spmm_k{k}_checked_rows"] = int(srows.size)
+                    if vk:
+                        log(f"FAILED: {vt} SpMM k={k} outside {STORAGE_TOL[vt]} on sampled rows (max {ek:.3e})")
+                        return 1
+                del Xd, Yd, Xh
             extra[vt] = leg
             log(f"{vt}: {json.dumps(leg)}")
             Mv.close()
-            del x32, y32
             torch.cuda.empty_cache()
+        del ref, sub
+        # the other FP64 workloads of the metric, each checked row by row against the oracle: the
+        # stencil family at scale (192^3 Poisson), the power-law rows, and the 64 x 64 Laplacian,
+        # whose whole working set sits in cache (launch latency, not HBM)
+        for wl in ("poisson", "powerlaw"):
+            Aw = pending[wl].get() if wl in pending else make_matrix(wl, 0)
+            extra[f"spmv_{wl}"] = spmv_leg(cb, Aw, dev, lsteps, args.leg_settle_seconds, not args.no_check,
+                                           WORKLOADS[wl])
+            log(f"{wl}: {json.dumps(extra[f'spmv_{wl}'])}")
+            del Aw
+            torch.cuda.empty_cache()
+        if pool is not None:
+            pool.close()
+            pool.join()
+        extra["laplacian64"] = laplacian_leg(cb, dev, not args.no_check)
+        log(f"laplacian 64x64: {json.dumps(extra['laplacian64'])}")
         if not args.no_solves:
             # the metric's other half: solves/s of FP64 CG against the mixed-precision solver, and of the
             # serving loop's batches against one request at a time, with p50/p99 latency
@@ -711,7 +904,6 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
-
 
 if __name__ == "__main__":
     sys.exit(main())

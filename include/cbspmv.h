@@ -93,7 +93,10 @@ typedef struct {
     double th0;             /* super-sparse share that turns aggregation on (default 0.15) */
     int64_t wave_nnz;       /* target non-zeros per wavefront work range; 0 = automatic (about 5120
                                ranges, each of at least 256 non-zeros and at most about 18 KB of codes
-                               and values: 2048 FP64 entries, 3686 FP32, 4096 BF16) */
+                               and values: 2048 FP64 entries, 3686 FP32, 4096 BF16).  An explicit
+                               value so large that one range's packed tiles would span 2 GiB or
+                               more is refused by cb_create with CB_ERROR_INVALID_VALUE (the
+                               streaming kernel addresses a range with 32-bit offsets) */
     int32_t row_reduce;     /* how the streaming SpMV kernel sums a pass's products into row
                                accumulators: 0 = one LDS atomic add per entry; 1 = a DPP segmented
                                scan over lanes of the same (tile, row), then one add per run;

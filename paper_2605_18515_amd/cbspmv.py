@@ -201,11 +201,24 @@ def _stream_ptr(stream):
     return stream.cuda_stream  # torch.cuda.Stream
 
 
-def _dev_ptr(t, dtype_name: str | None = None, numel: int | None = None):
+def _require_dense(*tensors) -> None:
+    for t in tensors:
+        if t is not None and not isinstance(t, int) and not t.is_contiguous():
+            raise ValueError(f"tensor with strides {tuple(t.stride())} is not contiguous: the library "
+                             "reads and writes vectors as unit-stride arrays")
+
+
+def _dev_ptr(t, dtype_name: str | None = None, numel: int | None = None, dense: bool = True):
+    """Device address of a tensor handed to the C ABI.  dense: the library reads or writes it as
+    one unit-stride array, so views with other strides (a column of a matrix, an expanded tensor
+    whose elements share memory) are refused; the k-right-hand-side calls check their 2-D strides
+    themselves and pass dense=False."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if dense:
+        _require_dense(t)
     if not t.is_cuda:
         raise ValueError("vectors must live on the GPU")
     if dtype_name is not None and str(t.dtype) != dtype_name:
@@ -261,8 +274,8 @@ def cb_spmv(A: int, alpha: float, x, beta: float, y, stream=None) -> None:
 
 
 def cb_spmm(A: int, k: int, alpha: float, X, ldx: int, beta: float, Y, ldy: int, stream=None) -> None:
-    _check(_lib.cb_spmm(A, int(k), float(alpha), _dev_ptr(X), int(ldx), float(beta), _dev_ptr(Y), int(ldy),
-                        _stream_ptr(stream)))
+    _check(_lib.cb_spmm(A, int(k), float(alpha), _dev_ptr(X, dense=False), int(ldx), float(beta),
+                        _dev_ptr(Y, dense=False), int(ldy), _stream_ptr(stream)))
 
 
 def cb_cg_options_default(**kw) -> CbCgOptions:
@@ -381,6 +394,7 @@ class CbMatrix:
 
     def spmv(self, x, y, alpha: float = 1.0, beta: float = 0.0, stream=None):
         inf = self.info
+        _require_dense(x, y)
         _dev_ptr(x, self.vector_dtype, inf["n"]) if inf["n"] else None
         _dev_ptr(y, self.vector_dtype, inf["m"]) if inf["m"] else None
         cb_spmv(self.handle, alpha, x, beta, y, stream)
@@ -389,15 +403,22 @@ class CbMatrix:
     def spmm(self, X, Y, alpha: float = 1.0, beta: float = 0.0, stream=None):
         if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
             raise ValueError("X (n x k) and Y (m x k) must be 2-D with the same k")
-        if X.stride(1) != 1 or Y.stride(1) != 1:
-            raise ValueError("X and Y must be row-major")
+        k = X.shape[1]
+        # row-major with a leading dimension of at least k: rows must not overlap (an expanded
+        # tensor has row stride 0); a single row may have any row stride
+        for name, T in (("X", X), ("Y", Y)):
+            if T.stride(1) != 1 and k > 1:
+                raise ValueError(f"{name} must be row-major (unit column stride)")
+            if T.shape[0] > 1 and T.stride(0) < k:
+                raise ValueError(f"{name} has row stride {T.stride(0)} < k = {k}: its rows overlap")
         inf = self.info
         if X.shape[0] != inf["n"] or Y.shape[0] != inf["m"]:
             raise ValueError("shape mismatch")
-        _dev_ptr(X, self.vector_dtype)
-        _dev_ptr(Y, self.vector_dtype)
-        k = X.shape[1]
-        cb_spmm(self.handle, k, alpha, X, max(X.stride(0), k), beta, Y, max(Y.stride(0), k), stream)
+        _dev_ptr(X, self.vector_dtype, dense=False)
+        _dev_ptr(Y, self.vector_dtype, dense=False)
+        ldx = X.stride(0) if X.shape[0] > 1 else k
+        ldy = Y.stride(0) if Y.shape[0] > 1 else k
+        cb_spmm(self.handle, k, alpha, X, ldx, beta, Y, ldy, stream)
         return Y
 
     def export_csr(self):
@@ -410,6 +431,7 @@ class CbMatrix:
         """Solve A x = b by CG from the given x (device tensors of the vector type); work: a device
         uint8 tensor of at least cb_cg_workspace_bytes bytes, allocated here when None."""
         n = self.info["n"]
+        _require_dense(b, x, work)
         _dev_ptr(b, self.vector_dtype)
         _dev_ptr(x, self.vector_dtype)
         if b.numel() != n or x.numel() != n:
@@ -472,6 +494,16 @@ def cb_server_options_default(**kw) -> CbServerOptions:
     return o
 
 
+def check_host_vectors(dt, n: int, **vecs) -> None:
+    """Host vectors of a served request: numpy arrays of dtype dt with n elements each, C-contiguous
+    (the server copies them as n consecutive elements)."""
+    for name, v in vecs.items():
+        if not isinstance(v, np.ndarray) or v.dtype != dt or v.size != n:
+            raise ValueError(f"{name} must be a {np.dtype(dt).name} array of {n} elements")
+        if not v.flags.c_contiguous:
+            raise ValueError(f"{name} must be C-contiguous")
+
+
 class CbServer:
     """A serving loop on the current device (cb_server_*).  Host vectors given to submit_* are
     numpy arrays of the matrix's vector type; they are kept alive here until their request is
@@ -513,10 +545,7 @@ class CbServer:
         return self._submit(r, (X, Y))
 
     def submit_cg(self, mid: int, b: np.ndarray, x: np.ndarray, rtol: float = 0.0, max_iter: int = 0) -> int:
-        dt = self._dtype(mid)
-        n = self._mats[mid].info["n"]
-        if b.dtype != dt or x.dtype != dt or b.size != n or x.size != n or not x.flags.c_contiguous:
-            raise ValueError(f"b and x must be {np.dtype(dt).name} arrays of n elements")
+        check_host_vectors(self._dtype(mid), self._mats[mid].info["n"], b=b, x=x)
         r = CbRequest(kind=CB_REQ_CG, matrix=mid, k=1, in_=b.ctypes.data, out=x.ctypes.data, rtol=rtol,
                       max_iter=max_iter)
         return self._submit(r, (b, x))

@@ -65,8 +65,14 @@ int64_t region_bytes(int fmt, int64_t nnz, int vsize);
 uint32_t f32_bits_rne(double v);
 uint16_t bf16_bits_rne(double v);
 
+// Bytes of payload one work range of the streaming kernel may span: its batch records and the
+// kernel address the range with 32-bit offsets (plus the readable padding past the payload's end).
+constexpr int64_t kMaxRangeSpan = ((int64_t)1 << 31) - 2 * cbs::kPayloadPad;
+
+// max_range_span: the limit above (a smaller one only in the converter's own tests).
 cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
-                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err);
+                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err,
+                    int64_t max_range_span = kMaxRangeSpan);
 cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_idx, void *values, std::string &err);
 void fill_info(const HostStructure &s, cb_info_t &info);
 int64_t spmv_bytes(const HostStructure &s);

@@ -334,7 +334,8 @@ uint16_t bf16_bits_rne(double v) {
 }
 
 cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
-                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err) {
+                    const double *values, const cb_options_t &opt, HostStructure &out, std::string &err,
+                    int64_t max_range_span) {
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t kLim = (int64_t)1 << 31;
     if (m < 0 || n < 0 || nnz < 0) { err = "negative size"; return CB_ERROR_INVALID_VALUE; }
@@ -697,6 +698,18 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             if (s.payload_bytes >= ((int64_t)1 << 48)) {
                 err = "payload too large for the tile records";
                 return CB_ERROR_NOT_SUPPORTED;
+            }
+            // a range's batch ends and region starts are 32-bit offsets from its first payload byte
+            for (int64_t w = 0; w < NW; ++w) {
+                const int64_t t0 = wptr[w], t1 = wptr[w + 1];
+                if (t0 >= t1) continue;
+                const int64_t span = s.tile_vp[t1 - 1] + region_bytes(s.tile_type[t1 - 1], s.tile_nnz[t1 - 1], s.vsize) -
+                                     s.tile_vp[t0];
+                if (span > max_range_span) {
+                    err = "wave_nnz too large: work range " + std::to_string(w) + " would span " + std::to_string(span) +
+                          " payload bytes (at most " + std::to_string(max_range_span) + ")";
+                    return CB_ERROR_INVALID_VALUE;
+                }
             }
             build_stream(s);
         }

@@ -185,15 +185,23 @@ def power_law(n: int = 4_000_000, seed: int = 2, a: float = 2.1, max_len: int = 
     keys = np.unique(np.concatenate([rl * n + cl, ru * n + cu]))
     del rl, cl, ru, cu
     # rows whose distinct count fell short (duplicates) draw more: local rows that are
-    # saturated cannot gain local columns, so all refills are uniform over [0, n).
+    # saturated cannot gain local columns, so all refills are uniform over [0, n).  Each
+    # round adds the new distinct keys to the sorted set by insertion (the same set as a
+    # unique() of the union, without re-sorting all keys).
+    cnt = np.bincount(keys // n, minlength=n)
     for _ in range(1000):
-        cnt = np.bincount(keys // n, minlength=n)
         short = L - cnt
         if not (short > 0).any():
             break
         rr = np.repeat(rows, np.maximum(short, 0))
         cc = (rng.random(rr.shape[0]) * n).astype(np.int64)
-        keys = np.unique(np.concatenate([keys, rr * n + cc]))
+        new = np.unique(rr * n + cc)
+        pos = np.searchsorted(keys, new)
+        fresh = pos >= keys.shape[0]
+        fresh[~fresh] = keys[pos[~fresh]] != new[~fresh]
+        new, pos = new[fresh], pos[fresh]
+        keys = np.insert(keys, pos, new)
+        cnt += np.bincount(new // n, minlength=n)
     else:  # pragma: no cover
         raise RuntimeError("power_law: could not fill rows")
     r = keys // n
@@ -285,3 +293,12 @@ def vector(n: int, seed: int, stream: int = STREAM_X, dyadic: bool = False) -> n
 def rhs(n: int, k: int, seed: int) -> np.ndarray:
     """Row-major n x k block of right-hand sides, U[-1, 1]."""
     return _rng(seed, STREAM_RHS).uniform(-1.0, 1.0, size=(n, k))
+
+
+def rhs_columns(n: int, k: int, seed0: int) -> np.ndarray:
+    """Row-major n x k block whose column j is U[-1, 1] drawn from seed seed0 + j (so the first
+    columns of a wider block are the same vectors)."""
+    X = np.empty((n, k))
+    for j in range(k):
+        X[:, j] = _rng(seed0 + j, STREAM_RHS).uniform(-1.0, 1.0, n)
+    return X

@@ -37,3 +37,22 @@ def test_committed_traffic_applies_only_to_its_structure():
     # the bytes follow from the counters and the copy-kernel factors
     b = t["fetch_kib"] * 1024 * t["fetch_factor"] + t["write_kib"] * 1024 * t["write_factor"]
     assert abs(b - t["bytes_per_launch"]) <= 1024
+
+
+def test_sampled_rows_give_exactly_those_rows_of_the_product():
+    """The bench checks SpMM legs on sampled rows: the oracle's product of the row sub-matrix must be
+    exactly the sampled rows of the full product (same summation per row)."""
+    import numpy as np
+
+    import oracle
+    from paper_2605_18515_amd import matgen
+
+    A = matgen.power_law(3000, seed=5, max_len=200)
+    rows = bench.sample_rows(A, 300, 1)
+    assert rows[0] == 0 and rows[-1] == A.m - 1 and np.all(np.diff(rows) > 0)
+    assert np.diff(A.row_ptr)[rows].max() == np.diff(A.row_ptr).max()
+    sub = bench.rows_of(A, rows)
+    X = matgen.rhs_columns(A.n, 3, 3)
+    assert np.array_equal(oracle.spmm(sub, X), oracle.spmm(A, X)[rows])
+    # column j of the block is the vector of seed 3 + j
+    assert np.array_equal(matgen.rhs_columns(A.n, 5, 3)[:, :3], X)

@@ -82,10 +82,14 @@ def test_block3d_dyadic_bitwise(cb, block):
 
 
 @pytest.mark.timeout(300)
+@pytest.mark.parametrize("vtype", ["f32", "bf16"])
 @pytest.mark.parametrize("k", [8, 32])
-def test_block3d_spmm_sampled_rows(cb, block, k):
-    X = matgen.rhs(block.n, k, 3)
-    M = cb.CbMatrix.from_csr(block, value_type="f32")
+def test_block3d_spmm_sampled_rows(cb, block, k, vtype):
+    """The k-right-hand-side product on the FP32 and BF16 copies of the block matrix, X column j
+    drawn from seed 3 + j and rounded to FP32, sampled rows against the FP64 oracle on the original
+    values and X, within the storage precision's tolerance."""
+    X = matgen.rhs_columns(block.n, k, 3)
+    M = cb.CbMatrix.from_csr(block, value_type=vtype)
     Xd = torch.from_numpy(X).to("cuda", torch.float32)
     Yd = torch.full((block.m, k), float("nan"), dtype=torch.float32, device="cuda")
     M.spmm(Xd, Yd)
@@ -97,9 +101,9 @@ def test_block3d_spmm_sampled_rows(cb, block, k):
     Y = Yd.cpu().double().numpy()[rows]
     ref = oracle.spmm(sub, X)
     scl = oracle.spmm(matgen.Csr(sub.m, sub.n, sub.row_ptr, sub.col_idx, np.abs(sub.values)), np.abs(X))
-    e, viol, worst = oracle.scaled_error(Y.ravel(), ref.ravel(), scl.ravel(), TOL["f32"])
-    print(f"[block3d spmm k={k}] max scaled error {e:.3e} over {rows.size} rows")
-    assert viol == 0
+    e, viol, worst = oracle.scaled_error(Y.ravel(), ref.ravel(), scl.ravel(), TOL[vtype])
+    print(f"[block3d spmm {vtype} k={k}] max scaled error {e:.3e} over {rows.size} rows")
+    assert viol == 0, (e, worst)
 
 
 @pytest.mark.timeout(300)
