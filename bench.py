@@ -119,6 +119,8 @@ def kernel_name(info: dict, lb: str) -> str:
     agg = "aggregated" if info["col_agg"] else "plain columns"
     if info["spmv_kernel"] == 1:
         return f"spmv_rows_kernel<FP64, {agg}>"
+    if info["spmv_kernel"] == 2:
+        return f"spmv_quad_kernel<FP64, {agg}, row sums {info['row_reduce']}>"
     return f"spmv_stream_kernel<FP64, {agg}, row sums {info['row_reduce']}>"
 
 
@@ -199,7 +201,7 @@ def sample_rows(A, count: int, seed: int):
     return np.unique(np.concatenate([pick, np.argsort(lens)[-16:], [0, A.m - 1]]))
 
 
-def spmv_leg(cb, A, dev, steps: int, settle_s: float, check: bool, workload: str) -> dict:
+def spmv_leg(cb, A, dev, steps: int, settle_s: float, check: bool, workload: str, **opts) -> dict:
     """FP64 SpMV of A (default options: the paper's rules, contiguous ranges), x from seed 1: kernel
     time from HIP events over `steps` launches after an untimed settle, algorithmic bytes and their
     fraction of the HBM peak, and the max scaled error of every row against the oracle."""
@@ -209,7 +211,7 @@ def spmv_leg(cb, A, dev, steps: int, settle_s: float, check: bool, workload: str
     from paper_2605_18515_amd import matgen
 
     x = matgen.vector(A.n, 1)
-    M = cb.CbMatrix.from_csr(A)
+    M = cb.CbMatrix.from_csr(A, **opts)
     info = M.info
     xd = torch.from_numpy(x).to(dev)
     yd = torch.empty(A.m, dtype=torch.float64, device=dev)
@@ -604,6 +606,9 @@ def main() -> int:
     ap.add_argument("--lb", default="contiguous", choices=["contiguous", "paper", "none"])
     ap.add_argument("--col-agg", type=int, default=-1)
     ap.add_argument("--wave-nnz", type=int, default=0)
+    ap.add_argument("--spmv-kernel", type=int, default=-1,
+                    help="natural-order SpMV kernel of the handles (cb_options_t.spmv_kernel; -1 the library's "
+                         "default)")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32/BF16, SpMM and copy legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle check of the result")
@@ -684,7 +689,8 @@ def main() -> int:
     log(f"generated {args.workload} matrix n={A.n} nnz={A.nnz} in {time.perf_counter() - t:.1f}s")
 
     t = time.perf_counter()
-    M = cb.CbMatrix.from_csr(A, lb_mode=args.lb, col_agg=args.col_agg, wave_nnz=args.wave_nnz)
+    M = cb.CbMatrix.from_csr(A, lb_mode=args.lb, col_agg=args.col_agg, wave_nnz=args.wave_nnz,
+                             spmv_kernel=args.spmv_kernel)
     create_s = time.perf_counter() - t
     info = M.info
     log(f"converted+uploaded in {create_s:.2f}s (convert {info['convert_seconds']:.2f}s): {info['ntiles']} tiles "
@@ -759,7 +765,7 @@ def main() -> int:
         sub = rows_of(A, srows)
         for vt in ("f32", "bf16"):
             Mv = cb.CbMatrix.from_csr(A, value_type=vt, lb_mode=args.lb, col_agg=args.col_agg,
-                                      wave_nnz=args.wave_nnz)
+                                      wave_nnz=args.wave_nnz, spmv_kernel=args.spmv_kernel)
             iv = Mv.info
             x32 = torch.from_numpy(x).to(dev, torch.float32)
             y32 = torch.empty(A.m, dtype=torch.float32, device=dev)
@@ -810,7 +816,7 @@ def main() -> int:
         for wl in ("poisson", "powerlaw"):
             Aw = pending[wl].get() if wl in pending else make_matrix(wl, 0)
             extra[f"spmv_{wl}"] = spmv_leg(cb, Aw, dev, lsteps, args.leg_settle_seconds, not args.no_check,
-                                           WORKLOADS[wl])
+                                           WORKLOADS[wl], spmv_kernel=args.spmv_kernel)
             log(f"{wl}: {json.dumps(extra[f'spmv_{wl}'])}")
             del Aw
             torch.cuda.empty_cache()

@@ -113,7 +113,10 @@ typedef struct {
                                0 (default) = x and y are float.  FP64 storage: always double. */
     int32_t spmv_kernel;    /* natural-order SpMV kernel: 0 = entries per lane across a batch's tiles
                                (the streaming kernel); 1 = rows per lane, four 16-lane groups each
-                               walking its panels' tiles; -1 (default) = 0 */
+                               walking its panels' tiles; 2 = quads per lane (four consecutive
+                               entries of one tile per lane, codes and values loaded straight into
+                               registers; row_reduce 1 then means 0, each lane summing its own row
+                               runs); -1 (default) = 0 */
     int32_t reserved32;
     int64_t reserved[4];
 } cb_options_t;
@@ -155,7 +158,7 @@ typedef struct {
     double flat_run_mean;   /* COO/CSR entries per (tile, row) run: the lanes one scan step merges */
     int32_t row_reduce;     /* the resolved row_reduce option (0 .. 4) */
     int32_t vector_f64;     /* 1 when x and y are double (FP64 storage, or vector_f64 set) */
-    int32_t spmv_kernel;    /* the resolved spmv_kernel option (0 or 1) */
+    int32_t spmv_kernel;    /* the resolved spmv_kernel option (0, 1 or 2) */
     int32_t reserved2;
     int64_t reserved[3];
 } cb_info_t;

@@ -67,7 +67,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.prepass_list = put(4 * (size_t)s.nprepass);
     // the streaming kernel reads 17 records from the start of every batch
     const bool stream = s.lb_mode != CB_LB_PAPER;
-    L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kRecordPad) : 0);
+    L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kStreamRecordPad) : 0);
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)cbh::kBlk * NT : 0);
     L.tile_rec = put(stream ? 16 * NT : 0);
@@ -172,6 +172,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "structure upload");
     }
+    const bool natural = s.lb_mode != CB_LB_PAPER;
     cbd::DevView &v = A->view;
     v.tile_row = dptr<int32_t>(A, L.tile_row);
     v.tile_col = dptr<int32_t>(A, L.tile_col);
@@ -198,7 +199,9 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.col_agg = s.col_agg;
     v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
     v.row_reduce = s.row_reduce;
-    v.rows_kernel = s.spmv_kernel;
+    v.spmv_kernel = s.spmv_kernel;
+    v.payload_alloc = (int64_t)s.payload_bytes + cbs::kPayloadPad;
+    v.stream_alloc = natural ? 16 * ((int64_t)s.nrecords + cbs::kStreamRecordPad) : 0;
     // the device copy is the structure from now on
     std::vector<int32_t>().swap(s.tile_row);
     std::vector<int32_t>().swap(s.tile_col);

@@ -31,8 +31,11 @@ struct DevView {
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan,
                                   // 2 FP64 LDS atomics, 3 and 4 = 0 and 2 with two accumulator copies
-    int32_t rows_kernel;          // natural order: 1 = the rows-per-lane kernel instead of the streaming one
+    int32_t spmv_kernel;          // natural order: 0 the streaming kernel, 1 rows per lane, 2 the quad kernel
+                                  // (batch_stream then holds quad batches)
     const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
+    int64_t payload_alloc;        // readable bytes from payload (the structure's bytes and the padding after them)
+    int64_t stream_alloc;         // readable bytes from batch_stream
 };
 
 // One product of a batched launch: y = alpha A x + beta y for the natural-order structure d, its
@@ -47,10 +50,11 @@ struct BatchJob {
 };
 
 // Products of several natural-order structures in one launch.  wave_job[b] (total entries, device
-// memory) is the job of workgroup b; every job has kernel value code vtype, aggregation agg and
-// row-sum mode rr; y rows of shared panels must be prepared as for one product.
+// memory) is the job of workgroup b; every job has kernel value code vtype, aggregation agg,
+// row-sum mode rr and batch format (quad: 1 for spmv_kernel 2 structures, else 0); y rows of
+// shared panels must be prepared as for one product.
 hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
-                             hipStream_t stream);
+                             int quad, hipStream_t stream);
 
 // vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float);
 // 3 = FP32 values, 4 = BF16 values with x, y double and FP64 arithmetic

@@ -56,4 +56,37 @@ constexpr int kBatchPanels = 4;   // consecutive panels a batch may touch (accum
 constexpr int kRecordPad = kBatchTiles + 1;  // records readable past the end of the stream
 constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes readable past their ends
 
+// ---- quad stream (the quad kernel, spmv_kernel = 2) --------------------------
+//
+// The same work ranges cut into batches of at most kQTiles tiles, kBatchPanels consecutive panels
+// and kQPasses * 64 quads.  A quad is four consecutive entries of one tile: a COO or CSR tile of nz
+// entries holds ceil(nz / 4) quads (its last one partly empty), a Dense tile 64 (entries e = 4q ..
+// 4q + 3 of its row-major 256, occupancy bits honoured).  The quads of a batch are numbered Q = 0 ..
+// qtot - 1 in tile order; in pass p of the kernel lane l takes quad 64 p + l.
+//
+//   header  {pb, nt | np << 8 | done << 16, qtot, 0}
+//     pb     first panel of the batch; nt tiles; np = ceil(qtot / 64) passes
+//     done   bit k: panel pb + k has its last tile of this range in the batch
+//   record of tile i of the batch (i = 0 .. nt - 1, kernel order)  {cb, vb, lim, meta}
+//     meta   slot | qs << 2 | dense << 15, with slot = panel & (kBatchPanels - 1) and qs the
+//            tile's first quad
+//     COO / CSR:  the four codes of quad Q are the dword at payload byte cb + 4 Q, its four values
+//                 start at vb + 4 * size(Val) * Q (bytes relative to the range's first payload
+//                 byte), and entry 4 Q + j exists iff 4 Q + j < lim (= 4 qs + nz)
+//     Dense:      cb = the tile's occupancy bitmap, vb as above; the four bits of quad Q are
+//                 nibble Q - qs of the bitmap
+// The x area of the kernel holds the batch's tiles' 16 x values each, tile i at 16 i.
+#ifndef CB_TUNE_QTILES
+#define CB_TUNE_QTILES 16
+#endif
+#ifndef CB_TUNE_QPASSES
+#define CB_TUNE_QPASSES 4
+#endif
+constexpr int kQTiles = CB_TUNE_QTILES;    // tiles per quad batch (x-area slots)
+constexpr int kQPasses = CB_TUNE_QPASSES;  // passes of 64 quads per batch (the kernel's payload registers)
+static_assert(kQTiles % 4 == 0 && kQTiles <= 32, "x gathers take four tiles; tile positions fit the x-area index");
+constexpr int kQRecordPad = kQTiles + 1;  // records readable past the end of the quad stream
+static_assert(kQPasses * 64 <= 1023, "first quads take 10 bits of the record word");
+constexpr int kStreamRecordPad = kQRecordPad > kRecordPad ? kQRecordPad : kRecordPad;  // both batch formats
+
 }  // namespace cbs

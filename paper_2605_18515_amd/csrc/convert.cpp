@@ -287,6 +287,68 @@ void build_stream(HostStructure &s) {
     }
 }
 
+// Quad batches of the quad kernel (format in cb_stream.h), written to batch_stream / batch_ptr in
+// place of build_stream's batches.
+void build_qstream(HostStructure &s) {
+    using namespace cbs;
+    const int vs = s.vsize;
+    const int64_t NW = s.nwaves;
+    s.batch_ptr.assign((size_t)NW + 1, 0);
+    std::vector<int32_t> &bs = s.batch_stream;
+    bs.clear();
+    int64_t nb = 0;
+    auto quads = [&](int64_t t) -> int64_t {
+        return s.tile_type[t] == CB_FMT_DENSE ? 64 : (s.tile_nnz[t] + 3) / 4;
+    };
+    auto push = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
+        bs.push_back(a);
+        bs.push_back(b);
+        bs.push_back(c);
+        bs.push_back(d);
+    };
+    for (int64_t w = 0; w < NW; ++w) {
+        s.batch_ptr[w] = (int32_t)(bs.size() / 4);
+        const int64_t t0 = s.wave_ptr[w], t1 = s.wave_ptr[w + 1];
+        if (t0 >= t1) continue;
+        const int64_t B0 = s.tile_vp[t0];
+        int64_t b = t0;
+        while (b < t1) {
+            int64_t e = b + 1, qtot = quads(b);
+            while (e < t1 && e - b < kQTiles && s.tile_row[e] - s.tile_row[b] < kBatchPanels &&
+                   qtot + quads(e) <= (int64_t)kQPasses * 64) {
+                qtot += quads(e);
+                ++e;
+            }
+            const int32_t pb = s.tile_row[b];
+            uint32_t done = 0;
+            for (int64_t t = b; t < e; ++t) done |= 1u << (s.tile_row[t] - pb);
+            if (e < t1 && s.tile_row[e] == s.tile_row[e - 1]) done &= ~(1u << (s.tile_row[e - 1] - pb));
+            const int64_t np = (qtot + 63) / 64;
+            push(pb, (int32_t)((e - b) | (np << 8) | (done << 16)), (int32_t)qtot, 0);
+            int64_t qs = 0;
+            for (int64_t t = b; t < e; ++t) {
+                const int fmt = s.tile_type[t];
+                const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
+                const uint32_t meta = (uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) | ((uint32_t)qs << 2) |
+                                      ((fmt == CB_FMT_DENSE ? 1u : 0u) << 15);
+                if (fmt == CB_FMT_DENSE) {
+                    push((int32_t)(rel + (int64_t)kBlk * kBlk * vs), (int32_t)(rel - 4 * vs * qs), 0, (int32_t)meta);
+                } else {
+                    const int64_t hb = fmt == CB_FMT_CSR ? kBlk : 0;
+                    const int64_t crel = rel + hb, vrel = rel + hb + nz + padding(hb + nz, vs);
+                    push((int32_t)(crel - 4 * qs), (int32_t)(vrel - 4 * vs * qs), (int32_t)(4 * qs + nz), (int32_t)meta);
+                }
+                qs += quads(t);
+            }
+            ++nb;
+            b = e;
+        }
+    }
+    s.batch_ptr[NW] = (int32_t)(bs.size() / 4);
+    s.nbatches = nb;
+    s.nrecords = (int64_t)(bs.size() / 4);
+}
+
 }  // namespace
 
 int padding(int64_t index_bytes, int vsize) {
@@ -350,7 +412,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.row_reduce < -1 || opt.row_reduce > 4) { err = "row_reduce must be -1 .. 4"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
-    if (opt.spmv_kernel < -1 || opt.spmv_kernel > 1) { err = "spmv_kernel must be -1, 0 or 1"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
     if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
     const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
 
@@ -391,7 +453,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     s.nnz = nnz;
     s.vtype = opt.value_type;
     s.vector_f64 = opt.value_type == CB_VALUE_F64 || opt.vector_f64 ? 1 : 0;
-    s.spmv_kernel = opt.spmv_kernel > 0 ? 1 : 0;
+    s.spmv_kernel = opt.spmv_kernel > 0 ? opt.spmv_kernel : 0;
     s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
     s.lb_mode = opt.lb_mode;
     s.quantum_tiles = opt.quantum_tiles;
@@ -470,6 +532,8 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // (stencils, scattered rows) the copies only cost LDS
         if (opt.row_reduce >= 0) {
             s.row_reduce = opt.row_reduce;
+            // the quad kernel sums each lane's row runs in registers instead of a segmented scan
+            if (s.spmv_kernel == 2 && s.row_reduce == 1) s.row_reduce = 0;
         } else {
             const bool runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
             if (s.vector_f64) s.row_reduce = runs ? 3 : 0;
@@ -712,6 +776,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                 }
             }
             build_stream(s);
+            if (s.spmv_kernel == 2) build_qstream(s);
         }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed during conversion";

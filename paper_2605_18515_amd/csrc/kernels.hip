@@ -684,6 +684,363 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJo
     stream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
+// ---- quad kernel (natural order, spmv_kernel = 2) ---------------------------
+//
+// The batches are quad batches (cb_stream.h): a lane takes a quad -- four
+// consecutive entries of one tile -- per pass, so the per-entry work of
+// Algorithm 3 (unpack the code, multiply by the staged x, add into the row)
+// runs four entries at a time.  The four codes arrive as one dword and the
+// four values as one or two 16-byte loads, straight from HBM into registers
+// (buffer loads on a resource covering the range's payload: an address past
+// the resource reads zero instead of faulting); the LDS holds only the x
+// area, the row sums, the batch's records and its tile-start marks.  A lane's
+// entries that share a row are summed in a register first, so a row run costs
+// one LDS add.  Pipeline per step b (one wait, at the top):
+//   top       x of batch b into the x area; the panels batch b-1 finished to
+//             y; batch b+2's records and tile starts into LDS
+//   issue     x of batch b+1, x columns of batch b+2, records of batch b+3,
+//             y of the panels batch b finishes
+//   multiply  batch b from its registers
+//   issue     codes and values of batch b+1 into the registers batch b freed
+// A lane finds its quad's tile by one ballot of the pass's tile-start marks:
+// tile = (tiles started before the pass) + (marks at or below the lane) - 1.
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 buffer resource: 32-bit data format, no swizzle
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes) {
+    const uint32_t nr = bytes <= 0 ? 0u : bytes >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nr, kRsrcWord3);
+}
+
+// raw words of one quad's four values: FP64 two 16-byte loads, FP32 one, BF16 the three aligned
+// dwords around its eight bytes (BF16 values are 2-byte aligned)
+template <int VS>
+struct QRaw;
+template <>
+struct QRaw<8> {
+    static constexpr int kWords = 8;
+    __device__ static void load(rsrc_t r, int off, uint32_t *w) {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w, w[4] = b.x, w[5] = b.y, w[6] = b.z, w[7] = b.w;
+    }
+};
+template <>
+struct QRaw<4> {
+    static constexpr int kWords = 4;
+    __device__ static void load(rsrc_t r, int off, uint32_t *w) {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w;
+    }
+};
+template <>
+struct QRaw<2> {
+    static constexpr int kWords = 3;
+    __device__ static void load(rsrc_t r, int off, uint32_t *w) {
+        using u32x3 = unsigned int __attribute__((ext_vector_type(3)));
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, off & ~3, 0, 0);
+        w[0] = a.x, w[1] = a.y, w[2] = a.z;
+    }
+};
+// value j of a quad from its raw words; half: the BF16 values start 2 bytes into the first word
+template <int VT>
+__device__ __forceinline__ typename Val<VT>::A quad_value(const uint32_t *w, int j, bool half) {
+    using A = typename Val<VT>::A;
+    constexpr int VS = Val<VT>::kSize;
+    if constexpr (VS == 8) {
+        return __hiloint2double((int)w[2 * j + 1], (int)w[2 * j]);
+    } else if constexpr (VS == 4) {
+        return (A)__uint_as_float(w[j]);
+    } else {
+        const uint32_t lo = __builtin_amdgcn_alignbit(w[1], w[0], half ? 16 : 0);
+        const uint32_t hi = __builtin_amdgcn_alignbit(w[2], w[1], half ? 16 : 0);
+        const uint32_t word = j < 2 ? lo : hi;
+        return (A)__uint_as_float((j & 1) ? (word & 0xFFFF0000u) : (word << 16));
+    }
+}
+
+template <int VT, bool AGG, int RR>
+__device__ __forceinline__ void qstream_range(const DevView &d, int w, typename Val<VT>::A alpha,
+                                              typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
+                                              typename Val<VT>::A *__restrict__ y) {
+    static_assert(kWavesPerBlock == 1, "one work range per workgroup");
+    static_assert(RR != 1, "the quad kernel sums a lane's row runs itself");
+    using A = typename Val<VT>::A;
+    using AC = typename std::conditional<RR == 2 || RR == 4, double, A>::type;  // accumulator type
+    constexpr int NACC = RR >= 3 ? 2 : 1;
+    constexpr int VS = Val<VT>::kSize;
+    constexpr int NWD = QRaw<VS>::kWords;
+    constexpr int QT = cbs::kQTiles, QP = cbs::kQPasses;
+    constexpr int NG = QT / 4;
+    static_assert(QT % 4 == 0 && QT <= 32 && QT + 1 <= kWave, "x gathers take four tiles; records fit one load");
+    __shared__ __align__(16) A xarea[QT * 16];
+    __shared__ __align__(16) AC acc[kMaxPanels * 16 * NACC];
+    __shared__ __align__(16) i32x4 rtab[2][QT];
+    __shared__ __align__(16) uint32_t marks[2][kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    if (w >= d.nwaves) return;
+    const int o_begin = d.batch_ptr[w], o_end = d.batch_ptr[w + 1];
+    if (o_begin >= o_end) return;
+    const int oend = o_end - o_begin;
+    const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    const int64_t pbase = d.tile_vp[t0];
+    const rsrc_t prs = make_rsrc(d.payload + pbase, d.payload_alloc - pbase);
+    const rsrc_t rrs = make_rsrc(d.batch_stream + 4 * (int64_t)o_begin, d.stream_alloc - 16 * (int64_t)o_begin);
+    const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
+    const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
+    const int gj = lane >> 4, glc = lane & 15;
+
+    // header and records of the batch at record o (relative to the range's first): lane 63 the
+    // header, lane i < QT record i (lanes QT .. 62 record QT - 1 again)
+    i32x4 Q;
+    auto qload = [&](int o) {
+        const int r = lane == kWave - 1 ? o : o + 1 + min(lane, QT - 1);
+        Q = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rrs, 16 * r, 0, 0));
+    };
+    struct Hdr {
+        int pb, nt, np, done, qtot;
+    };
+    auto header = [&]() {
+        const int hz = __builtin_amdgcn_readlane(Q.y, kWave - 1);
+        return Hdr{__builtin_amdgcn_readlane(Q.x, kWave - 1), hz & 0xFF, (hz >> 8) & 0xFF, (hz >> 16) & 0xF,
+                   __builtin_amdgcn_readlane(Q.z, kWave - 1)};
+    };
+    // the records in Q (header h) into record table `par`, and the tiles' first quads as marks: byte
+    // (p, l) of the mark table is set where tile starts at quad 64 p + l
+    auto stage = [&](const Hdr &h, int par) {
+        marks[par][lane] = 0u;
+        if (lane < h.nt) {
+            rtab[par][lane] = Q;
+            const int qs = (Q.w >> 2) & 0x3FF;
+            reinterpret_cast<uint8_t *>(marks[par])[4 * (qs & 63) + ((qs >> 6) & 3)] = 1;
+        }
+    };
+
+    // x of a batch whose first tile is tb (nt tiles), as in the streaming kernel
+    int RG[NG];
+    auto issue_cols = [&](int tb, int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (4 * g < nt) {
+                const int t = min(tb + 4 * g + gj, t1 - 1);
+                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + (glc & 3) * 4 + (glc >> 2)] : d.tile_col[t];
+            }
+        }
+    };
+    A XG[NG];
+    auto issue_x = [&](int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (4 * g < nt) {
+                int col = RG[g];
+                if (!AGG) {
+                    const int64_t c = 16 * (int64_t)RG[g] + glc;
+                    col = c < d.n ? (int)c : 0;
+                }
+                XG[g] = x[col];
+            }
+        }
+    };
+    auto put_x = [&](int nt) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            if (4 * g < nt) xarea[64 * g + lane] = XG[g];
+    };
+
+    // the quads of a batch in flight: codes, value words and a word of what the multiply needs
+    //   bits 0-8 x-area index of the tile, 9-15 accumulator offset (slot, copy), 16 Dense,
+    //   17-20 the entries present (COO/CSR) or 17-24 the first code and 25-27 the bitmap nibble
+    //   (Dense), 31 BF16 values start 2 bytes into their first word
+    uint32_t C[QP], M[QP], W[QP][NWD];
+    auto issue_payload = [&](const Hdr &h, int par) {
+        const uint32_t mk = marks[par][lane];
+        int jb = 0;
+#pragma unroll
+        for (int p = 0; p < QP; ++p) {
+            if (p < h.np) {
+                const uint64_t bal = __builtin_amdgcn_ballot_w64(((mk >> (8 * p)) & 0xFFu) != 0u);
+                const int below =
+                    (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                const int ti = jb + below + (int)((bal >> lane) & 1u) - 1;
+                jb += __builtin_popcountll(bal);
+                const i32x4 r = rtab[par][max(ti, 0)];
+                const int q = 64 * p + lane;
+                const bool live = q < h.qtot;
+                const bool dense = live && ((r.w >> 15) & 1);
+                const int slot = r.w & (kMaxPanels - 1);
+                uint32_t m = (uint32_t)(ti << 4) |
+                             ((uint32_t)(slot * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0)) << 9);
+                int caddr;
+                if (dense) {
+                    const int dq = q - ((r.w >> 2) & 0x3FF);
+                    caddr = r.x + 4 * (dq >> 3);
+                    m |= (1u << 16) | ((uint32_t)(((dq & 3) << 6) | (dq >> 2)) << 17) | ((uint32_t)(dq & 7) << 25);
+                } else {
+                    const int nv = live ? min(max(r.z - 4 * q, 0), 4) : 0;
+                    caddr = r.x + 4 * q;
+                    m |= (uint32_t)((1 << nv) - 1) << 17;
+                }
+                const int vaddr = r.y + 4 * VS * q;
+                if (VS == 2) m |= (uint32_t)(vaddr & 2) << 30;
+                M[p] = m;
+                C[p] = __builtin_amdgcn_raw_buffer_load_b32(prs, caddr, 0, 0);
+                QRaw<VS>::load(prs, vaddr, W[p]);
+            }
+        }
+    };
+    auto multiply = [&](int np) {
+#pragma unroll
+        for (int p = 0; p < QP; ++p) {
+            if (p < np) {
+                const uint32_t m = M[p];
+                uint32_t codes, vm;
+                if ((m >> 16) & 1u) {
+                    vm = (C[p] >> (4 * ((m >> 25) & 7u))) & 0xFu;
+                    codes = ((m >> 17) & 0xFFu) * 0x01010101u + 0x30201000u;
+                } else {
+                    vm = (m >> 17) & 0xFu;
+                    codes = C[p];
+                }
+                const int xo = (int)(m & 0x1FFu), ao = (int)((m >> 9) & 0x7Fu);
+                const bool half = (m >> 31) != 0u;
+                AC s = AC(0);
+                int run = (int)(codes & 15u);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t code = (codes >> (8 * j)) & 0xFFu;
+                    const A xv = xarea[xo + (int)(code >> 4)];
+                    const bool ok = (vm >> j) & 1u;
+                    const A prod = ok ? quad_value<VT>(W[p], j, half) * xv : A(0);
+                    const int row = ok ? (int)(code & 15u) : run;
+                    if (row != run) {
+                        lds_add(&acc[ao + run], s);
+                        s = AC(0);
+                        run = row;
+                    }
+                    s += (AC)prod;
+                }
+                if (vm) lds_add(&acc[ao + run], s);
+            }
+        }
+    };
+
+    // panels finished by a batch, as in the streaming kernel
+    const int fk = lane >> 4, fr = lane & 15;
+    A YP = A(0);
+    int done_pb = 0, done_mask = 0;
+    auto is_shared = [&](int p) { return (p == p_first && sh_first) || (p == p_last && sh_last); };
+    auto issue_y = [&]() {
+        if (beta == A(0)) return;
+        const int64_t row = 16 * (int64_t)(done_pb + fk) + fr;
+        if (((done_mask >> fk) & 1) && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
+    };
+    auto flush = [&]() {
+        if ((done_mask >> fk) & 1) {
+            const int p = done_pb + fk;
+            AC *a = &acc[(p & (kMaxPanels - 1)) * 16 * NACC + fr];
+            AC sv = *a;
+            *a = AC(0);
+            if constexpr (NACC == 2) {
+                sv += a[16];
+                a[16] = AC(0);
+            }
+            const A v = (A)sv;
+            const int64_t row = 16 * (int64_t)p + fr;
+            if (row < d.m) {
+                if (is_shared(p)) {
+                    global_add(&y[row], alpha * v);
+                } else {
+                    A r = alpha * v;
+                    if (beta != A(0)) r += beta * YP;
+                    y[row] = r;
+                }
+            }
+        }
+        done_mask = 0;
+    };
+
+    if (lane < kMaxPanels * 16) acc[lane] = AC(0);
+    if constexpr (NACC == 2) acc[lane + 64] = AC(0);
+    // prologue: batch 0's records, x columns, payload and x; batch 1's records and x columns; batch
+    // 2's records in flight.  At the top of step b the registers hold the payload and x of batch b,
+    // the x columns of batch b+1 and Q the records of batch b+2; the tables hold batches b and b+1.
+    qload(0);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    Hdr h0 = header(), h1{}, h2{};
+    stage(h0, 0);
+    issue_cols(t0, h0.nt);
+    int o1 = 1 + h0.nt;
+    const int tb1 = t0 + h0.nt;
+    if (o1 < oend) qload(o1);
+    __builtin_amdgcn_wave_barrier();
+    issue_payload(h0, 0);
+    issue_x(h0.nt);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    int o2 = o1, tb2 = tb1;
+    if (o1 < oend) {
+        h1 = header();
+        stage(h1, 1);
+        issue_cols(tb1, h1.nt);
+        o2 = o1 + 1 + h1.nt;
+        tb2 = tb1 + h1.nt;
+        if (o2 < oend) qload(o2);
+    }
+    int par = 0;  // record table of batch b
+    int ob = 0;
+    while (ob < oend) {
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        put_x(h0.nt);
+        flush();
+        const bool have1 = o1 < oend, have2 = o2 < oend;
+        int o3 = o2;
+        if (have2) {
+            h2 = header();
+            stage(h2, par);  // batch b+2 takes batch b's table (batch b's payload was issued a step ago)
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (have1) issue_x(h1.nt);
+        if (have2) {
+            issue_cols(tb2, h2.nt);
+            o3 = o2 + 1 + h2.nt;
+            if (o3 < oend) qload(o3);
+        }
+        done_pb = h0.pb;
+        done_mask = h0.done;
+        issue_y();
+        multiply(h0.np);
+        __builtin_amdgcn_wave_barrier();
+        if (have1) issue_payload(h1, par ^ 1);
+        ob = o1;
+        h0 = h1;
+        o1 = o2;
+        h1 = h2;
+        o2 = o3;
+        tb2 += have2 ? h2.nt : 0;
+        par ^= 1;
+    }
+    flush();
+}
+
+// The serving loop's batched launch for quad-batch structures (as spmv_batch_kernel)
+template <int VT, bool AGG, int RR>
+__global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJob *__restrict__ jobs,
+                                                                     const int32_t *__restrict__ wave_job, int total) {
+    using A = typename Val<VT>::A;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    if (b >= total) return;
+    const BatchJob &J = jobs[wave_job[b]];
+    qstream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
+}
+
+template <int VT, bool AGG, int RR>
+__global__ __launch_bounds__(kBlockThreads) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
+                                                                   typename Val<VT>::A beta,
+                                                                   const typename Val<VT>::A *__restrict__ x,
+                                                                   typename Val<VT>::A *__restrict__ y) {
+    qstream_range<VT, AGG, RR>(d, xcd_block(blockIdx.x, gridDim.x), alpha, beta, x, y);
+}
+
 // ---- rows per lane (natural order) -----------------------------------------
 //
 // Each 16-lane group of the wavefront takes every fourth panel of the work range and walks the
@@ -1095,7 +1452,25 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     // row sums: FP32 LDS atomics are slow where many lanes of a pass hit one row (long runs),
     // the segmented scan costs the same whatever the runs; the handle holds the choice
     const A a = (A)alpha, b = (A)beta;
-    if (d.natural_order && d.rows_kernel) {
+    if (d.natural_order && d.spmv_kernel == 2) {
+        constexpr bool kWide = std::is_same<A, double>::value;
+        constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
+        const int rr = d.row_reduce;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
+        };
+        if (d.col_agg) {
+            if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2>);
+            else if (rr == 3) go(spmv_quad_kernel<VT, true, 3>);
+            else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4>);
+            else go(spmv_quad_kernel<VT, true, 0>);
+        } else {
+            if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2>);
+            else if (rr == 3) go(spmv_quad_kernel<VT, false, 3>);
+            else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4>);
+            else go(spmv_quad_kernel<VT, false, 0>);
+        }
+    } else if (d.natural_order && d.spmv_kernel == 1) {
         if (d.col_agg)
             hipLaunchKernelGGL((spmv_rows_kernel<VT, true>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
                                (const A *)x, (A *)y);
@@ -1461,9 +1836,20 @@ hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const v
 
 namespace {
 template <int VT, bool AGG>
-hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, hipStream_t s) {
+hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, int quad, hipStream_t s) {
     constexpr bool kWide = std::is_same<typename Val<VT>::A, double>::value;
     const dim3 grid((unsigned)total), block(kBlockThreads);
+    if (quad) {
+        if (rr == 2)
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 0 : 2>), grid, block, 0, s, jobs, wave_job, total);
+        else if (rr == 3)
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 3>), grid, block, 0, s, jobs, wave_job, total);
+        else if (rr == 4)
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 3 : 4>), grid, block, 0, s, jobs, wave_job, total);
+        else
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 0>), grid, block, 0, s, jobs, wave_job, total);
+        return hipGetLastError();
+    }
     if (rr == 1)
         hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 2)
@@ -1477,20 +1863,22 @@ hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, in
     return hipGetLastError();
 }
 template <int VT>
-hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, hipStream_t s) {
-    return agg ? batch_rr<VT, true>(jobs, wave_job, total, rr, s) : batch_rr<VT, false>(jobs, wave_job, total, rr, s);
+hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, int quad,
+                    hipStream_t s) {
+    return agg ? batch_rr<VT, true>(jobs, wave_job, total, rr, quad, s)
+               : batch_rr<VT, false>(jobs, wave_job, total, rr, quad, s);
 }
 }  // namespace
 
 hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
-                             hipStream_t stream) {
+                             int quad, hipStream_t stream) {
     if (total <= 0) return hipSuccess;
     switch (vtype) {
-        case 0: return batch_vt<0>(jobs, wave_job, total, agg, rr, stream);
-        case 1: return batch_vt<1>(jobs, wave_job, total, agg, rr, stream);
-        case 2: return batch_vt<2>(jobs, wave_job, total, agg, rr, stream);
-        case 3: return batch_vt<3>(jobs, wave_job, total, agg, rr, stream);
-        case 4: return batch_vt<4>(jobs, wave_job, total, agg, rr, stream);
+        case 0: return batch_vt<0>(jobs, wave_job, total, agg, rr, quad, stream);
+        case 1: return batch_vt<1>(jobs, wave_job, total, agg, rr, quad, stream);
+        case 2: return batch_vt<2>(jobs, wave_job, total, agg, rr, quad, stream);
+        case 3: return batch_vt<3>(jobs, wave_job, total, agg, rr, quad, stream);
+        case 4: return batch_vt<4>(jobs, wave_job, total, agg, rr, quad, stream);
         default: return hipErrorInvalidValue;
     }
 }
