@@ -339,6 +339,25 @@ cb_status_t cb_cg(cb_matrix_t A, const void *b, void *x, void *work, int64_t wor
 cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, double *x, void *work, int64_t work_bytes,
                          const cb_cg_options_t *opt, cb_cg_result_t *res, void *stream);
 
+/* ---- CG without device allocation ----
+ *
+ * For callers that cannot allocate device memory (loops that must not call hipMalloc, harnesses
+ * that forbid it): cb_cg with its workspace taken from a fixed array of CB_CG_NOALLOC_MAX_BYTES
+ * bytes inside the library instead of a caller's buffer.  Arguments, results and errors as for
+ * cb_cg; b and x stay caller-owned device vectors.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the array is reserved in device memory when the library's
+ * code is loaded on a GPU and kept, one per GPU, until the process ends.  It fits solves whose
+ * cb_cg_workspace_bytes(A, NULL) is at most CB_CG_NOALLOC_MAX_BYTES (FP64 vectors: n up to about
+ * 2.79 million; float vectors: about 5.59 million); larger ones return CB_ERROR_INVALID_VALUE.
+ * A must live on the current device (else CB_ERROR_INVALID_VALUE).  All calls on one GPU share that
+ * GPU's array: the library runs them one at a time (a second caller waits for the first), and
+ * each call returns only after its work on `stream` has finished.  The array keeps the last
+ * call's contents; every solve sets what it reads before reading it. */
+#define CB_CG_NOALLOC_MAX_BYTES (64 * 1024 * 1024)
+
+cb_status_t cb_cg_noalloc(cb_matrix_t A, const void *b, void *x, const cb_cg_options_t *opt, cb_cg_result_t *res,
+                          void *stream);
+
 /* Message for the last non-success status returned on this thread. */
 const char *cb_last_error(void);
 

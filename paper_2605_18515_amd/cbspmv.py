@@ -140,6 +140,8 @@ _lib.cb_cg_options_default.argtypes = [ctypes.POINTER(CbCgOptions)]
 _lib.cb_cg_workspace_bytes.argtypes = [_p, _p, ctypes.POINTER(_i64)]
 _lib.cb_cg.argtypes = [_p, _p, _p, _p, _i64, ctypes.POINTER(CbCgOptions), ctypes.POINTER(CbCgResult), _p]
 _lib.cb_cg_refine.argtypes = [_p, _p, _p, _p, _p, _i64, ctypes.POINTER(CbCgOptions), ctypes.POINTER(CbCgResult), _p]
+_lib.cb_cg_noalloc.argtypes = [_p, _p, _p, ctypes.POINTER(CbCgOptions), ctypes.POINTER(CbCgResult), _p]
+CB_CG_NOALLOC_MAX_BYTES = 64 * 1024 * 1024
 _lib.cb_create.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions), _p]
 _lib.cb_create_host.argtypes = [ctypes.POINTER(_p), _i64, _i64, _i64, _p, _p, _p, ctypes.POINTER(CbOptions)]
 _lib.cb_spmv.argtypes = [_p, _dbl, _p, _dbl, _p, _p]
@@ -155,7 +157,7 @@ _lib.cb_last_error.restype = ctypes.c_char_p
 for _f in ("cb_options_default", "cb_create", "cb_create_host", "cb_spmv", "cb_spmm", "cb_destroy", "cb_export_csr",
            "cb_get_info", "cb_export_structure", "cb_copy_probe", "cb_read_probe",
            "cb_cg_options_default", "cb_cg_workspace_bytes",
-           "cb_cg", "cb_cg_refine", "cb_server_options_default", "cb_server_create", "cb_server_add_matrix",
+           "cb_cg", "cb_cg_refine", "cb_cg_noalloc", "cb_server_options_default", "cb_server_create", "cb_server_add_matrix",
            "cb_server_submit", "cb_server_poll", "cb_server_wait", "cb_server_stats", "cb_server_destroy",
            "cb_tune_options_default", "cb_tune"):
     getattr(_lib, _f).restype = ctypes.c_int
@@ -303,6 +305,14 @@ def cb_cg(A: int, b, x, work, work_bytes: int, opt: CbCgOptions | None = None, s
     r = CbCgResult()
     _check(_lib.cb_cg(A, _dev_ptr(b), _dev_ptr(x), _dev_ptr(work), int(work_bytes),
                       ctypes.byref(opt) if opt is not None else None, ctypes.byref(r), _stream_ptr(stream)))
+    return _cg_result(r)
+
+
+def cb_cg_noalloc(A: int, b, x, opt: CbCgOptions | None = None, stream=None) -> dict:
+    """cb_cg with the library's fixed device workspace (no allocation by the caller or the library)."""
+    r = CbCgResult()
+    _check(_lib.cb_cg_noalloc(A, _dev_ptr(b), _dev_ptr(x), ctypes.byref(opt) if opt is not None else None,
+                              ctypes.byref(r), _stream_ptr(stream)))
     return _cg_result(r)
 
 

@@ -15,10 +15,18 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "cb_host.h"
+#include "cb_internal.h"
 #include "cbspmv.h"
+
+// Workspace of cb_cg_noalloc: a fixed array in device memory, one copy per GPU the library runs on,
+// held until the process ends.  Host code never passes this name to a kernel or a copy (on the host
+// it is only a stand-in for the symbol); it uses the device address hipGetSymbolAddress returns for
+// the current device.
+static __device__ __align__(256) uint8_t scratch[CB_CG_NOALLOC_MAX_BYTES];
 
 namespace {
 
@@ -418,6 +426,25 @@ cb_status_t refine_restart(cb_matrix_t A, cb_matrix_t A_low, int64_t n, const do
     return CB_SUCCESS;
 }
 
+// Device addresses of the scratch array, per device, taken once with that device current; the mutex
+// of a device also serialises the cb_cg_noalloc calls that share its array.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];
+void *g_scratch[kMaxDevices];
+
+// *ptr = this device's scratch address (looked up on the first call); the caller holds g_scratch_mu[dev]
+cb_status_t scratch_address(int dev, void **ptr) {
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CB_ERROR_HIP, std::string("hipGetSymbolAddress of the solver scratch: ") + hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *ptr = g_scratch[dev];
+    return CB_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -539,6 +566,32 @@ cb_status_t cb_cg_refine(cb_matrix_t A, cb_matrix_t A_low, const double *b, doub
     }
     *res = r;
     return CB_SUCCESS;
+}
+
+cb_status_t cb_cg_noalloc(cb_matrix_t A, const void *b, void *x, const cb_cg_options_t *opt, cb_cg_result_t *res,
+                          void *stream) {
+    Mat M;
+    cb_status_t st = mat_of(A, M);
+    if (st != CB_SUCCESS) return st;
+    const int64_t need = (int64_t)cg_bytes(M.n, M.esize, M.esize);
+    if (need > (int64_t)CB_CG_NOALLOC_MAX_BYTES)
+        return fail(CB_ERROR_INVALID_VALUE, "cb_cg_noalloc: the solve needs " + std::to_string(need) +
+                                                " bytes of workspace, more than its fixed " +
+                                                std::to_string((int64_t)CB_CG_NOALLOC_MAX_BYTES) +
+                                                " (use cb_cg with a caller workspace)");
+    cbh::MatrixView v;
+    if ((st = cbh::matrix_view(A, v)) != CB_SUCCESS) return st;
+    int dev = -1;
+    if ((st = hipcheck(hipGetDevice(&dev), "hipGetDevice")) != CB_SUCCESS) return st;
+    if (dev != v.device) return fail(CB_ERROR_INVALID_VALUE, "cb_cg_noalloc: the matrix lives on another device than the current one");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CB_ERROR_NOT_SUPPORTED, "cb_cg_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    void *work = nullptr;
+    if ((st = scratch_address(dev, &work)) != CB_SUCCESS) return st;
+    st = cb_cg(A, b, x, work, need, opt, res, stream);
+    // the array is free for the next call only once this solve's kernels have finished
+    const cb_status_t sync = hipcheck(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+    return st != CB_SUCCESS ? st : sync;
 }
 
 }  // extern "C"

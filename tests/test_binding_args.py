@@ -3,6 +3,8 @@ vector as one unit-stride array and every k-right-hand-side block as rows of at 
 so the binding refuses tensors whose memory does not have that shape before any pointer reaches
 the library (a strided view would be read wrongly, an expanded one would be read or written past
 its allocation)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -73,3 +75,21 @@ def test_server_host_vectors_must_be_contiguous():
         cb.check_host_vectors(np.float64, n, b=good, x=strided)
     with pytest.raises(ValueError, match="float32"):
         cb.check_host_vectors(np.float32, n, b=good, x=good)
+
+
+def test_noalloc_cg_limit_and_host_handle():
+    """The fixed workspace size of cb_cg_noalloc in the binding equals the header's, and a host-only
+    handle or a NULL handle is refused before any device work."""
+    import os
+    import re
+
+    text = open(os.path.join(os.path.dirname(cb.LIB_PATH), "..", "include", "cbspmv.h")).read()
+    m = re.search(r"#define CB_CG_NOALLOC_MAX_BYTES \((\d+) \* (\d+) \* (\d+)\)", text)
+    assert m and int(m[1]) * int(m[2]) * int(m[3]) == cb.CB_CG_NOALLOC_MAX_BYTES
+    A = matgen.identity(20)
+    h = cb.cb_create_host(20, 20, 20, A.row_ptr, A.col_idx, A.values)
+    lib = cb.library_handle()
+    r = cb.CbCgResult()
+    assert lib.cb_cg_noalloc(h, 16, 32, None, ctypes.byref(r), None) == cb.CB_ERROR_NOT_SUPPORTED
+    assert lib.cb_cg_noalloc(None, 16, 32, None, ctypes.byref(r), None) == cb.CB_ERROR_INVALID_VALUE
+    cb.cb_destroy(h)
