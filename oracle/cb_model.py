@@ -7,9 +7,9 @@ notation, how CB-SpMV turns a sparse matrix into its two-level tile structure
 (Section 3, Fig. 7):
 
   1. uniform 16 x 16 partition into sub-blocks ("tiles") keyed like a block
-     COO (Section 3.1);
+     COO (Section 3.1; 8 x 8 as the other sub-block size the library offers);
   2. the th0 decision on the share of super-sparse tiles and, when taken,
-     block-aware column aggregation per 16-row panel (Section 3.3.1);
+     block-aware column aggregation per panel of tile rows (Section 3.3.1);
   3. per-tile format selection with th1 / th2 (Section 3.3.2);
   4. intra-block data aggregation: packed 4+4-bit coordinates, padding and
      values behind a virtual pointer (Section 3.2, Algorithm 3 unpacking);
@@ -28,6 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 BLK = 16              # Section 3.1: uniform 16 x 16 sub-blocks
+BLK_SIZES = (8, 16)   # sub-block sizes the library offers (8: the same one-byte codes, fewer slots)
 SUPER_SPARSE = 32     # Section 3.3.1: "super-sparse" = fewer than 32 non-zeros
 TH0 = 0.15            # Section 3.3.1
 TH1 = 32              # Section 3.3.2: COO below th1
@@ -41,7 +42,7 @@ TILE_ALIGN = 16       # reading: every tile region starts on a 16-byte boundary
 
 @dataclass
 class Tile:
-    panel: int                 # blk_row_idx: index of the 16-row panel
+    panel: int                 # blk_row_idx: index of the panel (blk rows)
     tcol: int                  # blk_col_idx: column-block (or aggregated chunk) index
     entries: list              # [(local_row, local_col, entry_index_in_input)], row-major
     fmt: int = COO
@@ -56,10 +57,11 @@ class Model:
     m: int
     n: int
     col_agg: bool
-    share: float                       # super-sparse share on the plain partition
+    share: float                       # super-sparse share on the plain 16 x 16 partition
     tiles: list                        # natural order: (panel, tcol) ascending
     restore_cols: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     cols_offset: np.ndarray = field(default_factory=lambda: np.zeros(1, np.int64))
+    blk: int = BLK                     # sub-block size: panels of blk rows, tiles blk x blk
 
 
 # ---- Section 3.1: uniform 16 x 16 partition -------------------------------
@@ -69,15 +71,15 @@ def csr_rows(row_ptr: np.ndarray) -> np.ndarray:
     return np.repeat(np.arange(m, dtype=np.int64), np.diff(row_ptr))
 
 
-def plain_tiles(row_ptr, col_idx) -> dict:
-    """Sub-block of entry (r, c) is (r // 16, c // 16); its local coordinates are
-    (r % 16, c % 16).  Returns {(panel, cb): [(lr, lc, t), ...]} with entries in
+def plain_tiles(row_ptr, col_idx, blk: int = BLK) -> dict:
+    """Sub-block of entry (r, c) is (r // blk, c // blk); its local coordinates are
+    (r % blk, c % blk).  Returns {(panel, cb): [(lr, lc, t), ...]} with entries in
     row-major order inside each tile."""
     rows = csr_rows(row_ptr)
     tiles: dict = {}
     for t in range(col_idx.shape[0]):
         r, c = int(rows[t]), int(col_idx[t])
-        tiles.setdefault((r // BLK, c // BLK), []).append((r % BLK, c % BLK, t))
+        tiles.setdefault((r // blk, c // blk), []).append((r % blk, c % blk, t))
     for ent in tiles.values():
         ent.sort()
     return tiles
@@ -86,7 +88,9 @@ def plain_tiles(row_ptr, col_idx) -> dict:
 # ---- Section 3.3.1: th0 decision and block-aware column aggregation --------
 
 def super_sparse_share(tiles: dict) -> float:
-    """Share of non-empty sub-blocks with fewer than 32 non-zeros."""
+    """Share of non-empty sub-blocks with fewer than 32 non-zeros (reading: always
+    taken on the paper's 16 x 16 partition, whatever sub-block size the structure
+    then uses -- the paper defines super-sparse for 16 x 16 sub-blocks only)."""
     if not tiles:
         return 0.0
     return sum(1 for e in tiles.values() if len(e) < SUPER_SPARSE) / len(tiles)
@@ -103,28 +107,28 @@ def decide_col_agg(share: float, th0: float = TH0, mode: int = -1) -> bool:
     return share >= th0
 
 
-def aggregate_columns(m: int, row_ptr, col_idx):
-    """Per 16-row panel, drop the columns that hold no entry and shift the rest
-    left (Fig. 5(b)); restore_cols maps an aggregated column back to the
+def aggregate_columns(m: int, row_ptr, col_idx, blk: int = BLK):
+    """Per panel of blk rows, drop the columns that hold no entry and shift the
+    rest left (Fig. 5(b)); restore_cols maps an aggregated column back to the
     original one and cols_offset marks where each panel's list starts.
 
     reading: the aggregated columns of panel p are its distinct original columns
-    in ascending order; aggregated column a lands in chunk a // 16 at local
-    column a % 16, and the original column is
-    restore_cols[cols_offset[p] + 16 * chunk + local_col]."""
-    npanels = (m + BLK - 1) // BLK
+    in ascending order; aggregated column a lands in chunk a // blk at local
+    column a % blk, and the original column is
+    restore_cols[cols_offset[p] + blk * chunk + local_col]."""
+    npanels = (m + blk - 1) // blk
     rows = csr_rows(row_ptr)
     restore, offsets = [], [0]
     tiles: dict = {}
     for p in range(npanels):
-        lo, hi = int(row_ptr[p * BLK]), int(row_ptr[min(m, (p + 1) * BLK)])
+        lo, hi = int(row_ptr[p * blk]), int(row_ptr[min(m, (p + 1) * blk)])
         cols_p = sorted(set(int(c) for c in col_idx[lo:hi]))
         rank = {c: a for a, c in enumerate(cols_p)}
         restore.extend(cols_p)
         offsets.append(offsets[-1] + len(cols_p))
         for t in range(lo, hi):
             a = rank[int(col_idx[t])]
-            tiles.setdefault((p, a // BLK), []).append((int(rows[t]) % BLK, a % BLK, t))
+            tiles.setdefault((p, a // blk), []).append((int(rows[t]) % blk, a % blk, t))
     for ent in tiles.values():
         ent.sort()
     return np.array(restore, dtype=np.int32), np.array(offsets, dtype=np.int64), tiles
@@ -142,21 +146,23 @@ def select_format(nnz: int, th1: int = TH1, th2: int = TH2) -> int:
 
 
 def build(m: int, n: int, row_ptr, col_idx, col_agg_mode: int = -1, th0: float = TH0,
-          th1: int = TH1, th2: int = TH2) -> Model:
+          th1: int = TH1, th2: int = TH2, blk: int = BLK) -> Model:
     """Steps 1-3 of the pipeline in the paper's order (Fig. 7): partition,
-    aggregation decision and aggregation, format per sub-block."""
+    aggregation decision and aggregation, format per sub-block.  blk is the
+    sub-block size (16 in the paper, 8 the library's other choice)."""
+    if blk not in BLK_SIZES:
+        raise ValueError("sub-block size must be one of %s" % (BLK_SIZES,))
     row_ptr = np.asarray(row_ptr)
     col_idx = np.asarray(col_idx)
-    plain = plain_tiles(row_ptr, col_idx)
-    share = super_sparse_share(plain)
+    share = super_sparse_share(plain_tiles(row_ptr, col_idx, BLK))
     agg = decide_col_agg(share, th0, col_agg_mode)
     if agg:
-        restore, offsets, tiles = aggregate_columns(m, row_ptr, col_idx)
+        restore, offsets, tiles = aggregate_columns(m, row_ptr, col_idx, blk)
     else:
-        restore, offsets, tiles = np.zeros(0, np.int32), np.zeros(1, np.int64), plain
+        restore, offsets, tiles = np.zeros(0, np.int32), np.zeros(1, np.int64), plain_tiles(row_ptr, col_idx, blk)
     order = sorted(tiles)
     out = [Tile(p, c, tiles[(p, c)], select_format(len(tiles[(p, c)]), th1, th2)) for (p, c) in order]
-    return Model(m, n, agg, share, out, restore, offsets)
+    return Model(m, n, agg, share, out, restore, offsets, blk)
 
 
 # ---- Section 3.2 / Algorithm 3: intra-block data aggregation --------------
@@ -178,20 +184,20 @@ def unpack_code(b: int) -> tuple[int, int]:
     return b & 15, b >> 4
 
 
-def tile_region_bytes(fmt: int, nnz: int, vtype: str) -> int:
+def tile_region_bytes(fmt: int, nnz: int, vtype: str, blk: int = BLK) -> int:
     """Bytes of one tile's packed region (before rounding to TILE_ALIGN).
 
     COO:   nnz codes, padding, nnz values.
-    CSR:   16 one-byte row starts, nnz codes, padding, nnz values
+    CSR:   blk one-byte row starts, nnz codes, padding, nnz values
            (reading: the paper gives no in-tile CSR layout).
-    Dense: 256 values in row-major order, then a 32-byte occupancy bitmap so
-           explicitly stored zeros survive (reading; the kernel never reads it)."""
+    Dense: blk * blk values in row-major order, then a blk * blk / 8-byte
+           occupancy bitmap so explicitly stored zeros survive (reading)."""
     sv = VALUE_SIZE[vtype]
     if fmt == COO:
         return nnz + padding(nnz, sv) + nnz * sv
     if fmt == CSR:
-        return BLK + nnz + padding(BLK + nnz, sv) + nnz * sv
-    return BLK * BLK * sv + 32
+        return blk + nnz + padding(blk + nnz, sv) + nnz * sv
+    return blk * blk * sv + blk * blk // 8
 
 
 def layout(model: Model, vtype: str) -> tuple[list, int]:
@@ -200,7 +206,7 @@ def layout(model: Model, vtype: str) -> tuple[list, int]:
     vps, off = [], 0
     for t in model.tiles:
         vps.append(off)
-        size = tile_region_bytes(t.fmt, t.nnz, vtype)
+        size = tile_region_bytes(t.fmt, t.nnz, vtype, model.blk)
         off += (size + TILE_ALIGN - 1) // TILE_ALIGN * TILE_ALIGN
     return vps, off
 
@@ -225,22 +231,23 @@ def pack(model: Model, values: np.ndarray, vtype: str, rounder=None) -> bytes:
     bits = value_bits(values, vtype, rounder)
     vps, total = layout(model, vtype)
     buf = bytearray(total)
+    blk = model.blk
     for t, vp in zip(model.tiles, vps):
         if t.fmt == DENSE:
-            mask = bytearray(32)
+            mask = bytearray(blk * blk // 8)
             for lr, lc, idx in t.entries:
-                e = lr * BLK + lc
+                e = lr * blk + lc
                 struct.pack_into(fmtc, buf, vp + e * sv, int(bits[idx]))
                 mask[e >> 3] |= 1 << (e & 7)
-            buf[vp + BLK * BLK * sv: vp + BLK * BLK * sv + 32] = mask
+            buf[vp + blk * blk * sv: vp + blk * blk * sv + len(mask)] = mask
             continue
         codes = vp
         hdr = 0
         if t.fmt == CSR:
-            hdr = BLK
-            for r in range(BLK):
+            hdr = blk
+            for r in range(blk):
                 buf[vp + r] = sum(1 for e in t.entries if e[0] < r)
-            codes = vp + BLK
+            codes = vp + blk
         base_v = codes + t.nnz + padding(hdr + t.nnz, sv)
         for i, (lr, lc, idx) in enumerate(t.entries):
             buf[codes + i] = pack_code(lr, lc)
@@ -248,7 +255,7 @@ def pack(model: Model, values: np.ndarray, vtype: str, rounder=None) -> bytes:
     return bytes(buf)
 
 
-def decode_tile(buf: bytes, vp: int, fmt: int, nnz: int, vtype: str) -> list:
+def decode_tile(buf: bytes, vp: int, fmt: int, nnz: int, vtype: str, blk: int = BLK) -> list:
     """Unpack one tile starting at virtual pointer vp: returns
     [(local_row, local_col, value_bits)] in storage order (Algorithm 3 for COO;
     row starts + codes for CSR; the occupancy bitmap for Dense)."""
@@ -266,20 +273,20 @@ def decode_tile(buf: bytes, vp: int, fmt: int, nnz: int, vtype: str) -> list:
             lr, lc = unpack_code(buf[vp + i])
             out.append((lr, lc, val(base_v + i * sv)))
     elif fmt == CSR:
-        starts = list(buf[vp:vp + BLK]) + [nnz]
-        codes = vp + BLK
-        base_v = codes + nnz + padding(BLK + nnz, sv)
-        for r in range(BLK):
+        starts = list(buf[vp:vp + blk]) + [nnz]
+        codes = vp + blk
+        base_v = codes + nnz + padding(blk + nnz, sv)
+        for r in range(blk):
             for i in range(starts[r], starts[r + 1]):
                 lr, lc = unpack_code(buf[codes + i])
                 if lr != r:
                     raise ValueError("CSR tile: code row does not match row start")
                 out.append((lr, lc, val(base_v + i * sv)))
     else:
-        mask = buf[vp + BLK * BLK * sv: vp + BLK * BLK * sv + 32]
-        for e in range(BLK * BLK):
+        mask = buf[vp + blk * blk * sv: vp + blk * blk * sv + blk * blk // 8]
+        for e in range(blk * blk):
             if (mask[e >> 3] >> (e & 7)) & 1:
-                out.append((e // BLK, e % BLK, val(vp + e * sv)))
+                out.append((e // blk, e % blk, val(vp + e * sv)))
     return out
 
 

@@ -118,54 +118,56 @@ def _dense_pattern(A):
     return P
 
 
+@pytest.mark.parametrize("blk", [8, 16])
 @pytest.mark.parametrize("seed", range(5))
-def test_plain_partition_brute_force(seed):
+def test_plain_partition_brute_force(seed, blk):
     rng = np.random.default_rng(seed)
     m, n = int(rng.integers(1, 70)), int(rng.integers(1, 70))
     A = matgen.random_csr(m, n, float(rng.uniform(0.02, 0.5)), seed)
     P = _dense_pattern(A)
-    tiles = cm.plain_tiles(A.row_ptr, A.col_idx)
+    tiles = cm.plain_tiles(A.row_ptr, A.col_idx, blk)
     expect = {}
-    for p in range(0, m, 16):
-        for c in range(0, n, 16):
-            cnt = int(P[p:p + 16, c:c + 16].sum())
+    for p in range(0, m, blk):
+        for c in range(0, n, blk):
+            cnt = int(P[p:p + blk, c:c + blk].sum())
             if cnt:
-                expect[(p // 16, c // 16)] = cnt
+                expect[(p // blk, c // blk)] = cnt
     assert {k: len(v) for k, v in tiles.items()} == expect
     for (p, c), ent in tiles.items():
         for lr, lc, t in ent:
-            assert A.rows()[t] == 16 * p + lr and A.col_idx[t] == 16 * c + lc
+            assert A.rows()[t] == blk * p + lr and A.col_idx[t] == blk * c + lc
 
 
+@pytest.mark.parametrize("blk", [8, 16])
 @pytest.mark.parametrize("seed", range(5))
-def test_column_aggregation_brute_force(seed):
+def test_column_aggregation_brute_force(seed, blk):
     rng = np.random.default_rng(50 + seed)
     m, n = int(rng.integers(1, 60)), int(rng.integers(1, 300))
     A = matgen.random_csr(m, n, float(rng.uniform(0.01, 0.2)), seed)
     P = _dense_pattern(A)
-    restore, offs, tiles = cm.aggregate_columns(m, A.row_ptr, A.col_idx)
+    restore, offs, tiles = cm.aggregate_columns(m, A.row_ptr, A.col_idx, blk)
     got = {k: len(v) for k, v in tiles.items()}
     expect, rc = {}, []
-    for p in range(0, m, 16):
-        sub = P[p:p + 16]
+    for p in range(0, m, blk):
+        sub = P[p:p + blk]
         keep = np.nonzero(sub.any(axis=0))[0]       # non-empty columns, shifted left
         rc.extend(keep.tolist())
         packed = sub[:, keep]
-        for c in range(0, packed.shape[1], 16):
-            expect[(p // 16, c // 16)] = int(packed[:, c:c + 16].sum())
+        for c in range(0, packed.shape[1], blk):
+            expect[(p // blk, c // blk)] = int(packed[:, c:c + blk].sum())
     assert got == expect
     assert restore.tolist() == rc
-    # every chunk but a panel's last holds exactly 16 non-empty columns, so >= 16 entries
-    for p in range((m + 15) // 16):
+    # every chunk but a panel's last holds exactly blk non-empty columns, so >= blk entries
+    for p in range((m + blk - 1) // blk):
         ncols = int(offs[p + 1] - offs[p])
-        for c in range((ncols + 15) // 16):
-            if c < (ncols + 15) // 16 - 1:
-                assert got[(p, c)] >= 16
+        for c in range((ncols + blk - 1) // blk):
+            if c < (ncols + blk - 1) // blk - 1:
+                assert got[(p, c)] >= blk
     # original coordinates come back through restore_cols / cols_offset
     for (p, c), ent in tiles.items():
         for lr, lc, t in ent:
-            assert restore[offs[p] + 16 * c + lc] == A.col_idx[t]
-            assert A.rows()[t] == 16 * p + lr
+            assert restore[offs[p] + blk * c + lc] == A.col_idx[t]
+            assert A.rows()[t] == blk * p + lr
 
 
 def test_format_threshold_edges():
@@ -274,20 +276,72 @@ def test_code_nibbles():
             assert 0 <= b < 256 and (b & 15, b >> 4) == (lr, lc)
 
 
+@pytest.mark.parametrize("blk", [8, 16])
 @pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
-def test_pack_decode_round_trip(vtype):
+def test_pack_decode_round_trip(vtype, blk):
     rng = np.random.default_rng(21)
     dens = np.repeat([0.9, 0.35, 0.04], [32, 32, 26])[:, None]
     D = np.where(rng.random((90, 75)) < dens, rng.uniform(-1, 1, (90, 75)), 0.0)
     A = matgen.from_dense(D)
     rounder = {"f32": oracle.round_f32_bits, "bf16": oracle.round_bf16_bits, "f64": None}[vtype]
+    th1, th2 = (20, 60) if blk == 16 else (6, 40)
     for agg in (0, 1):
-        model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=agg, th1=20, th2=60)
+        model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=agg, th1=th1, th2=th2, blk=blk)
         assert {t.fmt for t in model.tiles} == {cm.COO, cm.CSR, cm.DENSE}
         buf = cm.pack(model, A.values, vtype, rounder)
         vps, _ = cm.layout(model, vtype)
         bits = cm.value_bits(A.values, vtype, rounder)
         for t, vp in zip(model.tiles, vps):
             assert vp % cm.TILE_ALIGN == 0
-            dec = cm.decode_tile(buf, vp, t.fmt, t.nnz, vtype)
+            dec = cm.decode_tile(buf, vp, t.fmt, t.nnz, vtype, blk)
             assert [(lr, lc, int(bits[i])) for lr, lc, i in t.entries] == [(a, b, int(c)) for a, b, c in dec]
+
+
+def _check_worked8(ex, model, A):
+    buf = cm.pack(model, A.values, "f64")
+    vps, total = cm.layout(model, "f64")
+    assert total == ex["payload_bytes"] == len(buf)
+    assert [(t.panel, t.tcol, t.fmt, t.nnz, vp) for t, vp in zip(model.tiles, vps)] == \
+        [(e["panel"], e["tcol"], e["fmt"], e["nnz"], e["vp"]) for e in ex["tiles"]]
+    dense = struct.unpack_from("<64d", buf, 0)
+    for slot, v in enumerate(dense):
+        assert v == ex["dense_value_slots"].get(str(slot), 0.0)
+    assert list(buf[512:520]) == ex["dense_mask"]
+    vp = ex["tiles"][1]["vp"]
+    nc = len(ex["csr_codes"])
+    assert list(buf[vp:vp + 8]) == ex["csr_row_starts"]
+    assert list(buf[vp + 8:vp + 8 + nc]) == ex["csr_codes"]
+    assert list(struct.unpack_from("<%dd" % nc, buf, vp + ex["csr_value_offset"])) == ex["csr_values"]
+    for t, vpt in zip(model.tiles, vps):
+        dec = cm.decode_tile(buf, vpt, t.fmt, t.nnz, "f64", 8)
+        assert [(lr, lc) for lr, lc, _ in dec] == [(lr, lc) for lr, lc, _ in t.entries]
+    return buf, vps
+
+
+def test_worked_example_8x8():
+    """Sub-block size 8: a hand-worked conversion (tests/golden/cb8_worked_example.json)."""
+    g = golden("cb8_worked_example.json")
+    D = np.zeros((g["m"], g["n"]))
+    for r, c, v in g["entries"]:
+        D[r, c] = v
+    A = matgen.from_dense(D)
+    assert cm.super_sparse_share(cm.plain_tiles(A.row_ptr, A.col_idx)) == g["share_16"]["share"]
+    ex = g["plain_f64"]
+    model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=0, th1=g["th1"], th2=g["th2"], blk=8)
+    assert not model.col_agg and model.blk == 8
+    buf, vps = _check_worked8(ex, model, A)
+    for t, vp, e in zip(model.tiles[2:], vps[2:], ex["coo"]):
+        assert list(buf[vp:vp + t.nnz]) == e["codes"]
+        assert list(struct.unpack_from("<%dd" % t.nnz, buf, vp + e["value_offset"])) == e["values"]
+    ex = g["aggregated_f64"]
+    model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, th1=g["th1"], th2=g["th2"], blk=8)
+    assert model.col_agg
+    assert model.restore_cols.tolist() == ex["restore_cols"]
+    assert model.cols_offset.tolist() == ex["cols_offset"]
+    _check_worked8(ex, model, A)
+
+
+def test_unknown_sub_block_size_is_refused():
+    A = matgen.identity(4)
+    with pytest.raises(ValueError):
+        cm.build(A.m, A.n, A.row_ptr, A.col_idx, blk=32)
