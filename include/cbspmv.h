@@ -4,16 +4,16 @@
  * The library converts a CSR matrix into the two-level tile structure of
  * CB-SpMV (Cong et al., ICS '25) and multiplies it with dense vectors on the
  * GPU:
- *   - uniform 16 x 16 sub-blocks ("tiles") located by a high-level COO of
- *     tiles: blk_row_idx, blk_col_idx, nnz_per_blk, vp_per_blk, type_per_blk
- *     (Section 3.1);
+ *   - uniform 16 x 16 sub-blocks ("tiles"; 8 x 8 on request) located by a
+ *     high-level COO of tiles: blk_row_idx, blk_col_idx, nnz_per_blk,
+ *     vp_per_blk, type_per_blk (Section 3.1);
  *   - every tile's packed 4+4-bit coordinates, padding and values stored side
  *     by side in one byte buffer and found through its virtual pointer
  *     (Section 3.2);
  *   - block-aware column aggregation, chosen by the th0 rule, and per-tile
  *     COO / CSR / Dense format selection by th1 / th2 (Section 3.3);
  *   - inter-thread-block load balance (Section 3.4, Algorithm 2), plus a
- *     panel-contiguous nnz-balanced split that keeps every 16-row panel in
+ *     panel-contiguous nnz-balanced split that keeps every panel of tile rows in
  *     one work unit where it can;
  *   - y = alpha * A * x + beta * y (Section 3.5 kernels, Algorithms 3 and 4)
  *     and the k-right-hand-side form Y = alpha * A * X + beta * Y.
@@ -117,7 +117,14 @@ typedef struct {
                                entries of one tile per lane, codes and values loaded straight into
                                registers; row_reduce 1 then means 0, each lane summing its own row
                                runs); -1 (default) = 0 */
-    int32_t reserved32;
+    int32_t tile_dim;       /* sub-block size S (Section 3.1 fixes 16): 0 (default) or 16 = 16 x 16
+                               tiles, 8 = 8 x 8 tiles (panels of 8 rows, the same one-byte (row,
+                               column) codes, 8 one-byte row starts per CSR tile, 64 values and an
+                               8-byte bitmap per Dense tile; th1 / th2 apply as given, so th2 >= 64
+                               means no Dense tile).  The super-sparse share behind the th0 rule is
+                               always taken on the 16 x 16 partition.  8 with spmv_kernel 1 is
+                               refused with CB_ERROR_NOT_SUPPORTED; any other value with
+                               CB_ERROR_INVALID_VALUE. */
     int64_t reserved[4];
 } cb_options_t;
 
@@ -159,7 +166,7 @@ typedef struct {
     int32_t row_reduce;     /* the resolved row_reduce option (0 .. 4) */
     int32_t vector_f64;     /* 1 when x and y are double (FP64 storage, or vector_f64 set) */
     int32_t spmv_kernel;    /* the resolved spmv_kernel option (0, 1 or 2) */
-    int32_t reserved2;
+    int32_t tile_dim;       /* sub-block size S of the structure (16 or 8) */
     int64_t reserved[3];
 } cb_info_t;
 
@@ -170,8 +177,8 @@ typedef struct {
  * when aggregation is applied, prepass_panels, ntiles for tile_xoff (aggregation
  * only). */
 typedef struct {
-    int32_t *tile_row;       /* blk_row_idx: 16-row panel of each tile */
-    int32_t *tile_col;       /* blk_col_idx: 16-column block, or aggregated chunk */
+    int32_t *tile_row;       /* blk_row_idx: panel (tile_dim rows) of each tile */
+    int32_t *tile_col;       /* blk_col_idx: tile_dim-column block, or aggregated chunk */
     int32_t *tile_nnz;       /* nnz_per_blk */
     int64_t *tile_vp;        /* vp_per_blk: byte offset of the tile in payload */
     uint8_t *tile_type;      /* type_per_blk: cb_format_t */
@@ -183,12 +190,12 @@ typedef struct {
     int32_t *wave_ptr;       /* tile range of each wavefront work range, nwaves + 1 */
     uint8_t *panel_shared;   /* 1 if the panel's tiles span more than one work range */
     int32_t *prepass_list;   /* panels written by the pre-pass */
-    int32_t *tile_xoff;      /* aggregation only: cols_offset[tile_row] + 16 * tile_col, kernel order */
+    int32_t *tile_xoff;      /* aggregation only: cols_offset[tile_row] + tile_dim * tile_col, kernel order */
     int32_t *batch_stream;   /* streaming kernel: stream_bytes / 4 ints, a 16-byte header per batch
                                 followed by a 16-byte record per tile (CB_LB_PAPER: none) */
     int32_t *batch_ptr;      /* first record of each work range, nwaves + 1 (CB_LB_PAPER: none) */
-    int32_t *tile_cols;      /* aggregation with the streaming kernel: 16 original columns per tile in
-                                kernel order, 16 * ntiles (else none) */
+    int32_t *tile_cols;      /* aggregation with the streaming kernel: tile_dim original columns per
+                                tile in kernel order, tile_dim * ntiles (else none) */
 } cb_structure_t;
 
 /* Fill *opt with the defaults above (the paper's thresholds). */
@@ -228,9 +235,9 @@ cb_status_t cb_spmv(cb_matrix_t A, double alpha, const void *x, double beta, voi
  * m x k, both row-major device arrays with leading dimensions ldx >= k and
  * ldy >= k (elements).  Element type as for cb_spmv.  k == 1 with unit
  * leading dimensions is cb_spmv.  With the contiguous or no load balance
- * every tile is multiplied on the matrix cores (MFMA) as a 16 x 16 block times
- * its 16 rows of X, 16 or 32 columns of X per launch slice; with Algorithm 2's
- * order only Dense tiles are.  Errors as for cb_spmv, plus
+ * every tile is multiplied on the matrix cores (MFMA) as a 16 x 16 block (an
+ * 8 x 8 tile in its top-left corner) times its rows of X, 16 or 32 columns of
+ * X per launch slice; with Algorithm 2's order only Dense tiles are.  Errors as for cb_spmv, plus
  * CB_ERROR_INVALID_VALUE for k < 1 or ld < k. */
 cb_status_t cb_spmm(cb_matrix_t A, int32_t k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                     int64_t ldy, void *stream);
@@ -363,21 +370,24 @@ const char *cb_last_error(void);
 
 /* ---- Autotuner (NEXT: per-matrix layout choices by measurement) ----
  *
- * cb_tune converts the matrix under a short list of candidate options and times cb_spmv on each
- * (HIP events on `stream`, median of reps launches with x = 1 and beta = 0), by coordinate
- * descent from `base` over: column aggregation on/off, the format thresholds th1/th2 (the
- * paper's (32, 128), COO for everything below Dense at 200, COO only), the row-sum mode, and the
- * work per wavefront (half and twice the automatic size).  A choice is kept when it is at least
+ * cb_tune converts the matrix under a short list of candidate options and times the product on
+ * each (cb_spmv, or cb_spmm with spmm_k right-hand sides; HIP events on `stream`, median of reps
+ * launches with x = 1 and beta = 0), by coordinate descent from `base` over: column aggregation
+ * on/off, the sub-block size (16 x 16 or 8 x 8 tiles, th1/th2 scaled with the tile's area), the
+ * natural-order kernel (entries or quads per lane), the format thresholds th1/th2 (the base
+ * ones, COO below Dense at 200/256 of the tile's slots, COO only), the row-sum mode, the
+ * load-balance split (nnz-balanced at panel boundaries or equal tile counts) and the work per
+ * wavefront (half and twice the current ranges' mean).  A choice is kept when it is at least
  * 1 % faster.  Every candidate computes the same product within the storage precision's
- * tolerance; the tile size stays 16 (the one-byte (row, column) codes).  The tuner allocates:
- * candidate structures, x and y. */
+ * tolerance.  The tuner allocates: candidate structures, X and Y. */
 #define CB_TUNE_MAX_CANDIDATES 16
 
 typedef struct {
     uint32_t struct_size;   /* sizeof(cb_tune_options_t) */
     int32_t reps;           /* timed launches per candidate (after 3 untimed); 20 */
     int32_t max_candidates; /* 1 .. CB_TUNE_MAX_CANDIDATES; CB_TUNE_MAX_CANDIDATES */
-    int32_t reserved32;
+    int32_t spmm_k;         /* 0 or 1 (default 0): time cb_spmv; 2 .. 4096: time cb_spmm with that
+                               many right-hand sides (X n x k, Y m x k, leading dimension k) */
     int64_t reserved[4];
 } cb_tune_options_t;
 
@@ -387,6 +397,8 @@ typedef struct {
     int64_t spmv_bytes;     /* its algorithmic bytes per launch */
     int32_t col_agg;        /* resolved aggregation */
     int32_t row_reduce;     /* resolved row-sum mode */
+    int32_t tile_dim;       /* resolved sub-block size (16 or 8) */
+    int32_t spmv_kernel;    /* resolved natural-order kernel */
 } cb_tune_candidate_t;
 
 typedef struct {

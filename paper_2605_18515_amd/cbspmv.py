@@ -49,7 +49,7 @@ class CbOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
                 ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
                 ("wave_nnz", _i64), ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32),
-                ("reserved32", _i32), ("reserved", _i64 * 4)]
+                ("tile_dim", _i32), ("reserved", _i64 * 4)]
 
 
 class CbInfo(ctypes.Structure):
@@ -62,7 +62,7 @@ class CbInfo(ctypes.Structure):
                 ("quantum_nnz_std", _dbl), ("wave_nnz_max", _i64), ("wave_nnz_mean", _dbl), ("wave_nnz_std", _dbl),
                 ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
                 ("reserved0", _i32), ("nbatches", _i64), ("stream_bytes", _i64), ("flat_run_mean", _dbl),
-                ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32), ("reserved2", _i32),
+                ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32), ("tile_dim", _i32),
                 ("reserved", _i64 * 3)]
 
 
@@ -111,12 +111,13 @@ CB_TUNE_MAX_CANDIDATES = 16
 
 
 class CbTuneOptions(ctypes.Structure):
-    _fields_ = [("struct_size", _u32), ("reps", _i32), ("max_candidates", _i32), ("reserved32", _i32),
+    _fields_ = [("struct_size", _u32), ("reps", _i32), ("max_candidates", _i32), ("spmm_k", _i32),
                 ("reserved", _i64 * 4)]
 
 
 class CbTuneCandidate(ctypes.Structure):
-    _fields_ = [("opt", CbOptions), ("us", _dbl), ("spmv_bytes", _i64), ("col_agg", _i32), ("row_reduce", _i32)]
+    _fields_ = [("opt", CbOptions), ("us", _dbl), ("spmv_bytes", _i64), ("col_agg", _i32), ("row_reduce", _i32),
+                ("tile_dim", _i32), ("spmv_kernel", _i32)]
 
 
 class CbTuneReport(ctypes.Structure):
@@ -360,7 +361,7 @@ def cb_export_structure(A: int) -> dict:
         "tile_xoff": np.empty(NT if info["col_agg"] else 0, np.int32),
         "batch_stream": np.empty(info["stream_bytes"] // 4, np.int32),
         "batch_ptr": np.empty(info["nwaves"] + 1 if info["lb_mode"] != CB_LB_PAPER else 0, np.int32),
-        "tile_cols": np.empty(16 * NT if info["lb_mode"] != CB_LB_PAPER and info["col_agg"] else 0, np.int32),
+        "tile_cols": np.empty(info["tile_dim"] * NT if info["lb_mode"] != CB_LB_PAPER and info["col_agg"] else 0, np.int32),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
     _check(_lib.cb_export_structure(A, ctypes.byref(s)))
@@ -602,21 +603,24 @@ def cb_tune_options_default(**kw) -> CbTuneOptions:
 _OPT_NAMES = [n for n, _ in CbOptions._fields_ if not n.startswith("reserved") and n != "struct_size"]
 
 
-def cb_tune(csr, stream=None, keep: bool = True, reps: int = 20, **base):
-    """Tunes the options for csr (cb_tune).  Returns (CbMatrix or None, best options as a dict,
-    candidates: list of dicts with the options, us, spmv_bytes, col_agg, row_reduce, best)."""
+def cb_tune(csr, stream=None, keep: bool = True, reps: int = 20, spmm_k: int = 0, **base):
+    """Tunes the options for csr (cb_tune; spmm_k > 1 times cb_spmm with that many right-hand sides).
+    Returns (CbMatrix or None, best options as a dict, candidates: list of dicts with the options,
+    us, spmv_bytes, col_agg, row_reduce, tile_dim, spmv_kernel, best)."""
     rp, ci, va = _csr_args(csr.row_ptr, csr.col_idx, csr.values)
     b = cb_options_default(**base)
     best = CbOptions()
     rep = CbTuneReport()
     h = _p()
     _check(_lib.cb_tune(ctypes.byref(h) if keep else None, csr.m, csr.n, csr.nnz, rp.ctypes.data, ci.ctypes.data,
-                        va.ctypes.data, ctypes.byref(b), ctypes.byref(cb_tune_options_default(reps=reps)),
+                        va.ctypes.data, ctypes.byref(b),
+                        ctypes.byref(cb_tune_options_default(reps=reps, spmm_k=spmm_k)),
                         ctypes.byref(best), ctypes.byref(rep), _stream_ptr(stream)))
     cands = []
     for i in range(rep.ncandidates):
         c = rep.cand[i]
         cands.append({"opt": {n: getattr(c.opt, n) for n in _OPT_NAMES}, "us": c.us, "spmv_bytes": c.spmv_bytes,
-                      "col_agg": c.col_agg, "row_reduce": c.row_reduce, "best": i == rep.best})
+                      "col_agg": c.col_agg, "row_reduce": c.row_reduce, "tile_dim": c.tile_dim,
+                      "spmv_kernel": c.spmv_kernel, "best": i == rep.best})
     M = CbMatrix(h.value, best.value_type) if keep else None
     return M, {n: getattr(best, n) for n in _OPT_NAMES}, cands

@@ -69,7 +69,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     const bool stream = s.lb_mode != CB_LB_PAPER;
     L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kStreamRecordPad) : 0);
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
-    L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)cbh::kBlk * NT : 0);
+    L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)s.blk * NT : 0);
     L.tile_rec = put(stream ? 16 * NT : 0);
     L.panel_tile = put(stream ? 4 * ((size_t)s.npanels + 1) : 0);
     L.total = off;
@@ -200,6 +200,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
     v.row_reduce = s.row_reduce;
     v.spmv_kernel = s.spmv_kernel;
+    v.tile_lt = s.lt;
     v.payload_alloc = (int64_t)s.payload_bytes + cbs::kPayloadPad;
     v.stream_alloc = natural ? 16 * ((int64_t)s.nrecords + cbs::kStreamRecordPad) : 0;
     // the device copy is the structure from now on
@@ -264,7 +265,7 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.batch_ptr, A->h.lb_mode != CB_LB_PAPER ? (size_t)A->h.nwaves + 1 : 0, tmp.batch_ptr)) !=
         CB_SUCCESS)
         return st;
-    if ((st = fetch(A, L.tile_cols, A->h.lb_mode != CB_LB_PAPER && A->h.col_agg ? (size_t)cbh::kBlk * NT : 0,
+    if ((st = fetch(A, L.tile_cols, A->h.lb_mode != CB_LB_PAPER && A->h.col_agg ? (size_t)A->h.blk * NT : 0,
                     tmp.tile_cols)) != CB_SUCCESS)
         return st;
     s = &tmp;

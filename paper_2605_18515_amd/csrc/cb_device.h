@@ -10,8 +10,8 @@ namespace cbd {
 // Pointers into the handle's single device allocation.  The tile arrays are in
 // kernel order: wavefront w processes tiles [wave_ptr[w], wave_ptr[w+1]).
 struct DevView {
-    const int32_t *tile_row;      // 16-row panel of the tile
-    const int32_t *tile_col;      // column block, or aggregated chunk
+    const int32_t *tile_row;      // panel (S = 1 << tile_lt rows) of the tile
+    const int32_t *tile_col;      // column block (S columns), or aggregated chunk
     const int32_t *tile_nnz;
     const int64_t *tile_vp;       // byte offset of the tile's packed region
     const uint8_t *tile_type;     // 0 COO, 1 CSR, 2 Dense
@@ -24,7 +24,7 @@ struct DevView {
     const int32_t *prepass_list;  // nprepass
     const int32_t *batch_stream;  // natural order only: batch headers and tile records (cb_stream.h), 4 ints each
     const int32_t *batch_ptr;     // natural order only: first record of each work range, nwaves + 1
-    const int32_t *tile_cols;     // natural order with col_agg: 16 original columns per tile
+    const int32_t *tile_cols;     // natural order with col_agg: S original columns per tile
     const int32_t *tile_rec;      // natural order: {vp low, vp high | type << 16 | (nnz - 1) << 18, panel, column block}
     int64_t m, n;
     int32_t nwaves, npanels, nprepass, col_agg;
@@ -34,6 +34,8 @@ struct DevView {
     int32_t spmv_kernel;          // natural order: 0 the streaming kernel, 1 rows per lane, 2 the quad kernel
                                   // (batch_stream then holds quad batches)
     const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
+    int32_t tile_lt;              // log2 of the tile size S: 4 (16 x 16 tiles) or 3 (8 x 8)
+    int32_t pad0;
     int64_t payload_alloc;        // readable bytes from payload (the structure's bytes and the padding after them)
     int64_t stream_alloc;         // readable bytes from batch_stream
 };
@@ -51,10 +53,10 @@ struct BatchJob {
 
 // Products of several natural-order structures in one launch.  wave_job[b] (total entries, device
 // memory) is the job of workgroup b; every job has kernel value code vtype, aggregation agg,
-// row-sum mode rr and batch format (quad: 1 for spmv_kernel 2 structures, else 0); y rows of
-// shared panels must be prepared as for one product.
+// row-sum mode rr, batch format (quad: 1 for spmv_kernel 2 structures, else 0) and tile size
+// 1 << lt; y rows of shared panels must be prepared as for one product.
 hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
-                             int quad, hipStream_t stream);
+                             int quad, int lt, hipStream_t stream);
 
 // vtype: 0 = FP64 values, x, y double; 1 = FP32 values; 2 = BF16 values (x, y float);
 // 3 = FP32 values, 4 = BF16 values with x, y double and FP64 arithmetic

@@ -10,10 +10,11 @@
 
 namespace cbh {
 
-constexpr int kBlk = 16;          // Section 3.1: 16 x 16 sub-blocks
-constexpr int kSuperSparse = 32;  // Section 3.3.1: fewer than 32 non-zeros
+constexpr int kBlk = 16;          // Section 3.1: 16 x 16 sub-blocks (the default; 8 x 8 on request)
+constexpr int kSuperSparse = 32;  // Section 3.3.1: fewer than 32 non-zeros (on the 16 x 16 partition)
 constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte boundary
-constexpr int kDenseMaskBytes = 32;
+// occupancy bitmap of a Dense S x S tile: one bit per element
+constexpr int dense_mask_bytes(int blk) { return blk * blk / 8; }
 constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
 
 struct HostStructure {
@@ -25,10 +26,12 @@ struct HostStructure {
     int64_t plain_tiles = 0;
     int lb_mode = CB_LB_CONTIGUOUS;
     int quantum_tiles = 8;
+    int blk = kBlk;  // tile size S: panels of S rows, S x S tiles (16 or 8)
+    int lt = 4;      // log2(S)
     int64_t npanels = 0, ntiles = 0;
     // kernel order (after load balance)
     std::vector<int32_t> tile_row, tile_col, tile_nnz, tile_ori;
-    std::vector<int32_t> tile_xoff;  // aggregation only: cols_offset[row] + 16 * col (restore_cols index of the tile)
+    std::vector<int32_t> tile_xoff;  // aggregation only: cols_offset[row] + S * col (restore_cols index of the tile)
     std::vector<int64_t> tile_vp;
     std::vector<uint8_t> tile_type;
     std::vector<uint8_t> payload;
@@ -39,7 +42,7 @@ struct HostStructure {
     // batch records of the streaming kernel (natural-order modes only): 4 ints per record,
     // batch_ptr[w] = first record of work range w
     std::vector<int32_t> batch_stream, batch_ptr;
-    // column aggregation with the streaming kernel: 16 original columns per tile, kernel order
+    // column aggregation with the streaming kernel: S original columns per tile, kernel order
     std::vector<int32_t> tile_cols;
     // natural-order modes: one 16-byte record per tile for the k-right-hand-side kernel
     // {vp low word, vp high 16 bits | type << 16 | (nnz - 1) << 18, panel, column block}
@@ -61,7 +64,7 @@ struct HostStructure {
 };
 
 int padding(int64_t index_bytes, int vsize);
-int64_t region_bytes(int fmt, int64_t nnz, int vsize);
+int64_t region_bytes(int fmt, int64_t nnz, int vsize, int blk);
 uint32_t f32_bits_rne(double v);
 uint16_t bf16_bits_rne(double v);
 

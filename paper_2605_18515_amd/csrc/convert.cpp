@@ -110,16 +110,17 @@ struct PanelCounts {
     int64_t flat = 0, runs = 0;  // COO/CSR entries and (tile, row) runs
 };
 
-// Groups the entries of one 16-row panel into tiles.  With aggregation the
-// panel's distinct columns (ascending) are its aggregated columns and chunk c
-// holds aggregated columns [16c, 16c + 16) (Section 3.3.1); without it chunk
-// = column / 16.  Entries end up row-major inside each tile.
+// Groups the entries of one panel (S = blk rows) into S x S tiles.  With
+// aggregation the panel's distinct columns (ascending) are its aggregated
+// columns and chunk c holds aggregated columns [S c, S c + S) (Section 3.3.1);
+// without it chunk = column / S.  Entries end up row-major inside each tile.
 class PanelBuilder {
   public:
-    PanelBuilder(const int64_t *rp, const int32_t *ci, int64_t m) : rp_(rp), ci_(ci), m_(m) {}
+    PanelBuilder(const int64_t *rp, const int32_t *ci, int64_t m, int lt) : rp_(rp), ci_(ci), m_(m), lt_(lt) {}
 
     void build(int64_t p, bool agg) {
-        const int64_t r0 = p * kBlk, r1 = std::min(m_, r0 + kBlk);
+        const int64_t S = (int64_t)1 << lt_;
+        const int64_t r0 = p * S, r1 = std::min(m_, r0 + S);
         const int64_t e0 = rp_[r0], e1 = rp_[r1];
         cols_.clear();
         ent_.clear();
@@ -137,7 +138,7 @@ class PanelBuilder {
                     a = (uint64_t)(std::lower_bound(cols_.begin(), cols_.end(), ci_[t]) - cols_.begin());
                 else
                     a = (uint64_t)ci_[t];
-                ent_.push_back({((a >> 4) << 8) | (lr << 4) | (a & 15u), t});
+                ent_.push_back({((a >> lt_) << 8) | (lr << 4) | (a & (uint64_t)(S - 1)), t});
             }
         }
         std::sort(ent_.begin(), ent_.end(), [](const Entry &x, const Entry &y) { return x.key < y.key; });
@@ -150,6 +151,7 @@ class PanelBuilder {
     const int64_t *rp_;
     const int32_t *ci_;
     int64_t m_;
+    int lt_;  // log2 of the tile size
     std::vector<int32_t> cols_;
     std::vector<Entry> ent_;
 };
@@ -186,13 +188,13 @@ void moments(const std::vector<int64_t> &v, int64_t &mx, double &mean, double &s
 // kBatchPanels consecutive ones.
 void build_stream(HostStructure &s) {
     using namespace cbs;
-    const int vs = s.vsize;
+    const int vs = s.vsize, S = s.blk;
     const int64_t NW = s.nwaves;
     s.batch_ptr.assign((size_t)NW + 1, 0);
     std::vector<int32_t> &bs = s.batch_stream;
     bs.clear();
     int64_t nb = 0;
-    auto region = [&](int64_t t) { return region_bytes(s.tile_type[t], s.tile_nnz[t], vs); };
+    auto region = [&](int64_t t) { return region_bytes(s.tile_type[t], s.tile_nnz[t], vs, S); };
     auto push = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
         bs.push_back(a);
         bs.push_back(b);
@@ -231,11 +233,11 @@ void build_stream(HostStructure &s) {
                     if ((fmt == CB_FMT_DENSE) != (pass == 1)) continue;
                     const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
                     const uint32_t tag = ((uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) << 24) | ((uint32_t)(t - b) << 27);
-                    const int32_t xo = s.col_agg ? s.cols_offset[s.tile_row[t]] + 16 * s.tile_col[t] : s.tile_col[t];
+                    const int32_t xo = s.col_agg ? s.cols_offset[s.tile_row[t]] + S * s.tile_col[t] : s.tile_col[t];
                     if (fmt == CB_FMT_DENSE) {
                         push((int32_t)tag, 0, (int32_t)rel, xo);
                     } else {
-                        const int64_t hb = fmt == CB_FMT_CSR ? kBlk : 0;
+                        const int64_t hb = fmt == CB_FMT_CSR ? S : 0;
                         const int64_t voff = rel + hb + nz + padding(hb + nz, vs);
                         const uint32_t pmask = (1u << kRingBits) - 1;
                         const uint32_t cpos = (uint32_t)(rel + hb - es) & pmask, vpos = (uint32_t)(voff - vs * es) & pmask;
@@ -274,14 +276,14 @@ void build_stream(HostStructure &s) {
     }
     s.tile_cols.clear();
     if (s.col_agg) {
-        s.tile_cols.resize((size_t)s.ntiles * kBlk);
+        s.tile_cols.resize((size_t)s.ntiles * S);
         for (int64_t t = 0; t < s.ntiles; ++t) {
-            const int64_t p = s.tile_row[t], base = s.cols_offset[p] + (int64_t)kBlk * s.tile_col[t];
-            const int64_t width = std::min<int64_t>(kBlk, s.cols_offset[p + 1] - base);
-            // column c at position (c mod 4) * 4 + c / 4: a lane of a matrix-core operand that needs
-            // columns q, q + 4, q + 8, q + 12 reads them as one 16-byte load
-            for (int c = 0; c < kBlk; ++c)
-                s.tile_cols[(size_t)(t * kBlk + (c & 3) * 4 + (c >> 2))] =
+            const int64_t p = s.tile_row[t], base = s.cols_offset[p] + (int64_t)S * s.tile_col[t];
+            const int64_t width = std::min<int64_t>(S, s.cols_offset[p + 1] - base);
+            // column c at position (c mod 4) * (S / 4) + c / 4: a lane of a matrix-core operand that
+            // needs columns q, q + 4, ... reads them as one 16-byte (S = 16) or 8-byte (S = 8) load
+            for (int c = 0; c < S; ++c)
+                s.tile_cols[(size_t)(t * S + (c & 3) * (S / 4) + (c >> 2))] =
                     s.restore_cols[(size_t)(c < width ? base + c : s.cols_offset[p])];
         }
     }
@@ -291,14 +293,14 @@ void build_stream(HostStructure &s) {
 // place of build_stream's batches.
 void build_qstream(HostStructure &s) {
     using namespace cbs;
-    const int vs = s.vsize;
+    const int vs = s.vsize, S = s.blk;
     const int64_t NW = s.nwaves;
     s.batch_ptr.assign((size_t)NW + 1, 0);
     std::vector<int32_t> &bs = s.batch_stream;
     bs.clear();
     int64_t nb = 0;
     auto quads = [&](int64_t t) -> int64_t {
-        return s.tile_type[t] == CB_FMT_DENSE ? 64 : (s.tile_nnz[t] + 3) / 4;
+        return s.tile_type[t] == CB_FMT_DENSE ? S * S / 4 : (s.tile_nnz[t] + 3) / 4;
     };
     auto push = [&](int32_t a, int32_t b, int32_t c, int32_t d) {
         bs.push_back(a);
@@ -332,9 +334,9 @@ void build_qstream(HostStructure &s) {
                 const uint32_t meta = (uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) | ((uint32_t)qs << 2) |
                                       ((fmt == CB_FMT_DENSE ? 1u : 0u) << 15);
                 if (fmt == CB_FMT_DENSE) {
-                    push((int32_t)(rel + (int64_t)kBlk * kBlk * vs), (int32_t)(rel - 4 * vs * qs), 0, (int32_t)meta);
+                    push((int32_t)(rel + (int64_t)S * S * vs), (int32_t)(rel - 4 * vs * qs), 0, (int32_t)meta);
                 } else {
-                    const int64_t hb = fmt == CB_FMT_CSR ? kBlk : 0;
+                    const int64_t hb = fmt == CB_FMT_CSR ? S : 0;
                     const int64_t crel = rel + hb, vrel = rel + hb + nz + padding(hb + nz, vs);
                     push((int32_t)(crel - 4 * qs), (int32_t)(vrel - 4 * vs * qs), (int32_t)(4 * qs + nz), (int32_t)meta);
                 }
@@ -357,14 +359,14 @@ int padding(int64_t index_bytes, int vsize) {
     return r ? vsize - r : 0;
 }
 
-int64_t region_bytes(int fmt, int64_t nnz, int vsize) {
+int64_t region_bytes(int fmt, int64_t nnz, int vsize, int blk) {
     int64_t b;
     if (fmt == CB_FMT_COO)
         b = nnz + padding(nnz, vsize) + nnz * vsize;
     else if (fmt == CB_FMT_CSR)
-        b = kBlk + nnz + padding(kBlk + nnz, vsize) + nnz * vsize;
+        b = blk + nnz + padding(blk + nnz, vsize) + nnz * vsize;
     else
-        b = (int64_t)kBlk * kBlk * vsize + kDenseMaskBytes;
+        b = (int64_t)blk * blk * vsize + dense_mask_bytes(blk);
     return (b + kTileAlign - 1) / kTileAlign * kTileAlign;
 }
 
@@ -413,6 +415,11 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.row_reduce < -1 || opt.row_reduce > 4) { err = "row_reduce must be -1 .. 4"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.tile_dim != 0 && opt.tile_dim != 8 && opt.tile_dim != 16) { err = "tile_dim must be 0, 8 or 16"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.tile_dim == 8 && opt.spmv_kernel == 1) {
+        err = "the rows-per-lane kernel (spmv_kernel 1) takes 16 x 16 tiles only";
+        return CB_ERROR_NOT_SUPPORTED;
+    }
     if (std::isnan(opt.th0)) { err = "th0 is NaN"; return CB_ERROR_INVALID_VALUE; }
     const int nth = opt.host_threads > 0 ? opt.host_threads : default_threads();
 
@@ -457,13 +464,18 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
     s.lb_mode = opt.lb_mode;
     s.quantum_tiles = opt.quantum_tiles;
-    const int64_t P = (m + kBlk - 1) / kBlk;
+    s.blk = opt.tile_dim == 8 ? 8 : kBlk;
+    s.lt = s.blk == 8 ? 3 : 4;
+    const int S = s.blk, LT = s.lt;
+    const int64_t P = (m + S - 1) / S;
     s.npanels = P;
 
     try {
         // ---- Section 3.1 + 3.3.1: plain partition census, th0 decision ------
-        std::vector<int64_t> plain_cnt(P, 0), super_cnt(P, 0);
-        if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
+        // (always on the 16 x 16 partition: the paper defines super-sparse sub-blocks there)
+        const int64_t P16 = (m + kBlk - 1) / kBlk;
+        std::vector<int64_t> plain_cnt(P16, 0), super_cnt(P16, 0);
+        if (!parallel_dynamic(nth, P16, 64, [&](int64_t b, int64_t e) {
                 std::vector<int32_t> cb;
                 for (int64_t p = b; p < e; ++p) {
                     const int64_t r0 = p * kBlk, r1 = std::min(m, r0 + kBlk);
@@ -493,7 +505,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // ---- pass A: tiles, bytes and aggregated columns per panel ----------
         std::vector<PanelCounts> pc(P);
         if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
-                PanelBuilder pb(row_ptr, col_idx, m);
+                PanelBuilder pb(row_ptr, col_idx, m, LT);
                 for (int64_t p = b; p < e; ++p) {
                     pb.build(p, agg);
                     PanelCounts c;
@@ -503,7 +515,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                         const int fmt = select_format((int64_t)(hi - lo), opt.th1, opt.th2);
                         c.tiles += 1;
                         c.fmt[fmt] += 1;
-                        c.bytes += region_bytes(fmt, (int64_t)(hi - lo), s.vsize);
+                        c.bytes += region_bytes(fmt, (int64_t)(hi - lo), s.vsize, S);
                         if (fmt != CB_FMT_DENSE) {
                             c.flat += (int64_t)(hi - lo);
                             for (size_t i = lo; i < hi; ++i) c.runs += (i == lo || (ent[i].key >> 4) != (ent[i - 1].key >> 4));
@@ -555,7 +567,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // ---- pass B: write tiles --------------------------------------------
         const int vs = s.vsize, vt = s.vtype;
         if (!parallel_dynamic(nth, P, 64, [&](int64_t b, int64_t e) {
-                PanelBuilder pb(row_ptr, col_idx, m);
+                PanelBuilder pb(row_ptr, col_idx, m, LT);
                 for (int64_t p = b; p < e; ++p) {
                     pb.build(p, agg);
                     if (agg) std::copy(pb.cols().begin(), pb.cols().end(), s.restore_cols.begin() + col_base[p]);
@@ -571,9 +583,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                         ntype[ti] = (uint8_t)fmt;
                         uint8_t *base = s.payload.data() + off;
                         if (fmt == CB_FMT_DENSE) {
-                            uint8_t *mask = base + (int64_t)kBlk * kBlk * vs;
+                            uint8_t *mask = base + (int64_t)S * S * vs;
                             for (size_t q = lo; q < hi; ++q) {
-                                const int slot = (int)(ent[q].key & 0xFFu);  // (lr << 4 | lc) = lr*16 + lc
+                                // element (lr, lc) of the S x S tile, row-major
+                                const int slot = (int)(((ent[q].key >> 4) & 15u) * (uint64_t)S + (ent[q].key & 15u));
                                 store_value(base + (int64_t)slot * vs, values[ent[q].idx], vt);
                                 mask[slot >> 3] |= (uint8_t)(1u << (slot & 7));
                             }
@@ -581,12 +594,12 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                             uint8_t *codes = base;
                             int64_t hdr = 0;
                             if (fmt == CB_FMT_CSR) {
-                                hdr = kBlk;
-                                codes = base + kBlk;
+                                hdr = S;
+                                codes = base + S;
                                 // one-byte row starts: entries before row r
                                 int cnt[kBlk + 1] = {0};
                                 for (size_t q = lo; q < hi; ++q) cnt[((ent[q].key >> 4) & 15u) + 1] += 1;
-                                for (int r = 0; r < kBlk; ++r) {
+                                for (int r = 0; r < S; ++r) {
                                     cnt[r + 1] += cnt[r];
                                     base[r] = (uint8_t)cnt[r];
                                 }
@@ -598,7 +611,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                                 store_value(vals + (int64_t)(q - lo) * vs, values[ent[q].idx], vt);
                             }
                         }
-                        off += region_bytes(fmt, nz, vs);
+                        off += region_bytes(fmt, nz, vs, S);
                         ++ti;
                     });
                 }
@@ -715,7 +728,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         }
         if (agg) {
             s.tile_xoff.resize(NT);
-            for (int64_t i = 0; i < NT; ++i) s.tile_xoff[i] = s.cols_offset[s.tile_row[i]] + 16 * s.tile_col[i];
+            for (int64_t i = 0; i < NT; ++i) s.tile_xoff[i] = s.cols_offset[s.tile_row[i]] + S * s.tile_col[i];
         }
         s.quantum_ptr = qptr;
         s.wave_ptr = wptr;
@@ -767,7 +780,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             for (int64_t w = 0; w < NW; ++w) {
                 const int64_t t0 = wptr[w], t1 = wptr[w + 1];
                 if (t0 >= t1) continue;
-                const int64_t span = s.tile_vp[t1 - 1] + region_bytes(s.tile_type[t1 - 1], s.tile_nnz[t1 - 1], s.vsize) -
+                const int64_t span = s.tile_vp[t1 - 1] + region_bytes(s.tile_type[t1 - 1], s.tile_nnz[t1 - 1], s.vsize, S) -
                                      s.tile_vp[t0];
                 if (span > max_range_span) {
                     err = "wave_nnz too large: work range " + std::to_string(w) + " would span " + std::to_string(span) +
@@ -792,7 +805,7 @@ cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_id
         err = "NULL output buffer";
         return CB_ERROR_INVALID_VALUE;
     }
-    const int vs = s.vsize;
+    const int vs = s.vsize, S = s.blk;
     try {
         // decode every tile into (row, col, value bits); tiles may come in any order
         std::vector<int64_t> cnt((size_t)s.m + 1, 0);
@@ -802,19 +815,19 @@ cb_status_t export_csr(const HostStructure &s, int64_t *row_ptr, int32_t *col_id
                 const int fmt = s.tile_type[i];
                 const uint8_t *base = s.payload.data() + s.tile_vp[i];
                 auto orig_col = [&](int lc) -> int64_t {
-                    if (s.col_agg) return s.restore_cols[(size_t)(s.cols_offset[p] + 16 * c + lc)];
-                    return 16 * c + lc;
+                    if (s.col_agg) return s.restore_cols[(size_t)(s.cols_offset[p] + S * c + lc)];
+                    return S * c + lc;
                 };
                 if (fmt == CB_FMT_DENSE) {
-                    const uint8_t *mask = base + (int64_t)kBlk * kBlk * vs;
-                    for (int e = 0; e < kBlk * kBlk; ++e)
-                        if ((mask[e >> 3] >> (e & 7)) & 1) emit(16 * p + (e >> 4), orig_col(e & 15), base + (int64_t)e * vs);
+                    const uint8_t *mask = base + (int64_t)S * S * vs;
+                    for (int e = 0; e < S * S; ++e)
+                        if ((mask[e >> 3] >> (e & 7)) & 1) emit(S * p + e / S, orig_col(e % S), base + (int64_t)e * vs);
                 } else {
-                    const int64_t hdr = fmt == CB_FMT_CSR ? kBlk : 0;
+                    const int64_t hdr = fmt == CB_FMT_CSR ? S : 0;
                     const uint8_t *codes = base + hdr;
                     const uint8_t *vals = codes + nz + padding(hdr + nz, vs);
                     for (int64_t q = 0; q < nz; ++q)
-                        emit(16 * p + (codes[q] & 15), orig_col(codes[q] >> 4), vals + q * vs);
+                        emit(S * p + (codes[q] & 15), orig_col(codes[q] >> 4), vals + q * vs);
                 }
             }
         };
@@ -869,7 +882,7 @@ int64_t spmv_bytes(const HostStructure &s) {
         // column block per tile), two range pointers per range and the first tile's offset and the end
         // panels' flags, pre-pass list
         b += 16 * s.nrecords;
-        b += s.col_agg ? 4 * kBlk * s.ntiles : 4 * s.ntiles;
+        b += s.col_agg ? 4 * (int64_t)s.blk * s.ntiles : 4 * s.ntiles;
         b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
     }
     return b;
@@ -911,6 +924,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.row_reduce = s.row_reduce;
     info.vector_f64 = s.vector_f64;
     info.spmv_kernel = s.spmv_kernel;
+    info.tile_dim = s.blk;
 }
 
 }  // namespace cbh

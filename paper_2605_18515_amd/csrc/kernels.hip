@@ -231,12 +231,15 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
     A *xs = xs_all[wid];
     A *acc = acc_all[wid];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    // tile size S = 16 or 8: rows of a panel, columns of a tile; CSR and Dense tiles take four lanes
+    // per row (lanes of rows past S idle), S / 4 values per lane of a Dense row
+    const int LT = d.tile_lt, S = 1 << LT, vpl = S >> 2;
     if (lane < 16) acc[lane] = A(0);
     const int r4 = lane >> 2, q4 = lane & 3;
 
     auto flush = [&](int p) {
-        if (lane < 16) {
-            const int64_t row = 16 * (int64_t)p + lane;
+        if (lane < S) {
+            const int64_t row = ((int64_t)p << LT) + lane;
             const A v = acc[lane];
             acc[lane] = A(0);
             if (row < d.m) {
@@ -262,13 +265,13 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
             if (cur >= 0) flush(cur);
             cur = p;
         }
-        if (lane < 16) {
+        if (lane < S) {
             A xv = A(0);
             if (d.col_agg) {
-                const int a = d.cols_offset[p] + 16 * c + lane;
+                const int a = d.cols_offset[p] + (c << LT) + lane;
                 if (a < d.cols_offset[p + 1]) xv = x[d.restore_cols[a]];
             } else {
-                const int64_t col = 16 * (int64_t)c + lane;
+                const int64_t col = ((int64_t)c << LT) + lane;
                 if (col < d.n) xv = x[col];
             }
             xs[lane] = xv;
@@ -280,23 +283,26 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(DevView d, typename
                 lds_add(&acc[code & 15], Val<VT>::load(vals, e) * xs[code >> 4]);
             }
         } else if (ty == 1) {
-            const uint8_t *codes = base + 16;
-            const uint8_t *vals = codes + nz + pad_bytes(16 + nz, VS);
-            const int s = base[r4];
-            const int e_end = r4 < 15 ? (int)base[r4 + 1] : nz;
+            const uint8_t *codes = base + S;
+            const uint8_t *vals = codes + nz + pad_bytes(S + nz, VS);
             A sum = A(0);
-            for (int e = s + q4; e < e_end; e += 4) sum += Val<VT>::load(vals, e) * xs[codes[e] >> 4];
+            if (r4 < S) {
+                const int s = base[r4];
+                const int e_end = r4 < S - 1 ? (int)base[r4 + 1] : nz;
+                for (int e = s + q4; e < e_end; e += 4) sum += Val<VT>::load(vals, e) * xs[codes[e] >> 4];
+            }
             sum = quad_sum(sum);
-            if (q4 == 0) acc[r4] += sum;
+            if (q4 == 0 && r4 < S) acc[r4] += sum;
         } else {
-            const uint8_t *mask = base + 256 * VS;
-            const uint32_t bits = (mask[2 * r4 + (q4 >> 1)] >> ((q4 & 1) * 4)) & 0xFu;
+            // Dense: lane (r4, q4) takes elements e0 .. e0 + S/4 - 1 of row r4, e0 = r4 S + q4 S / 4
+            const uint8_t *mask = base + (S * S) * VS;
+            const int e0 = (r4 << LT) + q4 * vpl;
+            const uint32_t bits = r4 < S ? (mask[e0 >> 3] >> (e0 & 7)) & ((1u << vpl) - 1u) : 0u;
             A sum = A(0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if ((bits >> j) & 1u) sum += Val<VT>::load(base, r4 * 16 + 4 * q4 + j) * xs[4 * q4 + j];
+            for (int j = 0; j < vpl; ++j)
+                if ((bits >> j) & 1u) sum += Val<VT>::load(base, e0 + j) * xs[q4 * vpl + j];
             sum = quad_sum(sum);
-            if (q4 == 0) acc[r4] += sum;
+            if (q4 == 0 && r4 < S) acc[r4] += sum;
         }
     }
     if (cur >= 0) flush(cur);
@@ -350,18 +356,21 @@ constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left
 // adding into the second (entries of a row sit in neighbouring lanes, so long rows collide half as
 // often on one LDS address; the copies are added when the panel is written)
 // One work range w of the structure d (the body of the streaming kernel, shared by the one-matrix
-// and the batched launch).
-template <int VT, bool AGG, int RR>
+// and the batched launch).  LT: log2 of the tile size S (4: 16 x 16 tiles, 3: 8 x 8).
+template <int VT, bool AGG, int RR, int LT>
 __device__ __forceinline__ void stream_range(const DevView &d, int w, typename Val<VT>::A alpha,
                                              typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                              typename Val<VT>::A *__restrict__ y) {
     using A = typename Val<VT>::A;
+    constexpr int S = 1 << LT;  // rows of a panel, columns of a tile
+    constexpr int TPG = kWave / S;  // tiles per x gather
+    static_assert(LT == 3 || LT == 4, "16 x 16 or 8 x 8 tiles");
     using AC = typename std::conditional<RR == 2 || RR == 4, double, A>::type;  // accumulator type
     constexpr bool DPPRED = RR == 1;
     constexpr int NACC = RR >= 3 ? 2 : 1;  // accumulator copies
     constexpr int VS = Val<VT>::kSize;
     __shared__ __align__(16) uint8_t pring_all[kWavesPerBlock][kPRing];
-    __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * 16];
+    __shared__ __align__(16) A xarea_all[kWavesPerBlock][kBatchTiles * S];
     __shared__ __align__(16) AC acc_all[kWavesPerBlock][kMaxPanels * 16 * NACC];
     const int lane = threadIdx.x & (kWave - 1);
     // with one wavefront per workgroup its LDS arrays sit at fixed addresses
@@ -378,7 +387,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     // only the first and the last panel of a natural-order range can be shared with another range
     const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
     const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
-    const int gj = lane >> 4, glc = lane & 15;
+    const int gj = lane >> LT, glc = lane & (S - 1);
 
     // header and records of the batch at record o: lane i < 16 record i (lanes 16 .. 62 record 15
     // again), lane 63 the header.  Three batches' records stay in registers, one tile per lane:
@@ -411,18 +420,18 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
             if (i < pcnt) ring4[((pfirst + i) & (kRC - 1)) * kWave + lane] = P[i];
     };
     // x of a batch whose first tile is tb (nt tiles): in gather g, lane (gj, glc) takes column glc of
-    // tile tb + 4g + gj (clamped to the range), so x lands at x area entry 16 * (tile in batch) + glc.
-    // The column indices are loaded one step before the x values: under aggregation the tiles'
+    // tile tb + TPG g + gj (clamped to the range), so x lands at x area entry S * (tile in batch) +
+    // glc.  The column indices are loaded one step before the x values: under aggregation the tiles'
     // original columns (tile_cols, 256 contiguous bytes per gather), else the tiles' column blocks.
     // Columns past a tile's last one read a valid column of the matrix and are never multiplied.
-    constexpr int NG = kBatchTiles / 4;
+    constexpr int NG = (kBatchTiles + TPG - 1) / TPG;
     int RG[NG];
     auto issue_cols = [&](int tb, int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            if (4 * g < nt) {
-                const int t = min(tb + 4 * g + gj, t1 - 1);
-                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + (glc & 3) * 4 + (glc >> 2)] : d.tile_col[t];
+            if (TPG * g < nt) {
+                const int t = min(tb + TPG * g + gj, t1 - 1);
+                RG[g] = AGG ? d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)] : d.tile_col[t];
             }
         }
     };
@@ -430,10 +439,10 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     auto issue_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            if (4 * g < nt) {
+            if (TPG * g < nt) {
                 int col = RG[g];
                 if (!AGG) {
-                    const int64_t c = 16 * (int64_t)RG[g] + glc;
+                    const int64_t c = S * (int64_t)RG[g] + glc;
                     col = c < d.n ? (int)c : 0;
                 }
                 XG[g] = x[col];
@@ -443,18 +452,18 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     auto put_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (4 * g < nt) xarea[64 * g + lane] = XG[g];
+            if (TPG * g < nt) xarea[64 * g + lane] = XG[g];
     };
 
-    // panels finished by a batch: lane (k, r) holds row r of panel pb + k
+    // panels finished by a batch: lane (k, r) holds row r of panel pb + k (rows r < S)
     const int fk = lane >> 4, fr = lane & 15;
     A YP = A(0);
     int done_pb = 0, done_mask = 0;
     auto is_shared = [&](int p) { return (p == p_first && sh_first) || (p == p_last && sh_last); };
     auto issue_y = [&]() {
         if (beta == A(0)) return;
-        const int64_t row = 16 * (int64_t)(done_pb + fk) + fr;
-        if (((done_mask >> fk) & 1) && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
+        const int64_t row = S * (int64_t)(done_pb + fk) + fr;
+        if (((done_mask >> fk) & 1) && fr < S && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
     };
     auto flush = [&]() {
         if ((done_mask >> fk) & 1) {
@@ -467,8 +476,8 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
                 a[16] = AC(0);
             }
             const A v = (A)sv;
-            const int64_t row = 16 * (int64_t)p + fr;
-            if (row < d.m) {
+            const int64_t row = S * (int64_t)p + fr;
+            if (fr < S && row < d.m) {
                 if (is_shared(p)) {
                     global_add(&y[row], alpha * v);
                 } else {
@@ -518,7 +527,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         auto entry = [&](uint32_t pk, int E, uint32_t &code) {
             code = pring[(pk + E) & kPMask];
             return Val<VT>::load(pring + (((pk >> cbs::kRingBits) + VS * E) & kPMask), 0) *
-                   xarea[((pk >> 27) << 4) + (code >> 4)];
+                   xarea[((pk >> 27) << LT) + (code >> 4)];
         };
         auto accumulate = [&](A prod, int ti, uint32_t code, uint32_t pk, bool valid) {
             const int slot = (pk >> 24) & (kMaxPanels - 1);
@@ -563,20 +572,24 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
             const A prod = entry(pk, E, code);
             accumulate(prod, ti, code, pk, E < etot);
         }
-        // dense tiles, four lanes per row
+        // dense tiles, four lanes per row: lane (r4, q4) takes elements ed .. ed + S/4 - 1 of row r4,
+        // ed = r4 S + q4 S / 4, under its bits of the occupancy bitmap (rows past S idle)
+        constexpr int VPL = S / 4;
         const int r4 = lane >> 2, q4 = lane & 3;
+        const int ed = (r4 << LT) + q4 * VPL;
         for (int k = 0; k < ndense; ++k) {
             const uint32_t pk = (uint32_t)__builtin_amdgcn_readlane(rl.x, nflat + k);
             const int rel = __builtin_amdgcn_readlane(rl.y, nflat + k);
-            const uint32_t bits = (pring[(rel + 256 * VS + 2 * r4 + (q4 >> 1)) & kPMask] >> ((q4 & 1) * 4)) & 0xFu;
-            const int vo = rel + (r4 * 16 + 4 * q4) * VS;
-            const A *xs = xarea + ((pk >> 27) << 4) + 4 * q4;
+            const uint32_t bits =
+                r4 < S ? (pring[(rel + S * S * VS + (ed >> 3)) & kPMask] >> (ed & 7)) & ((1u << VPL) - 1u) : 0u;
+            const int vo = rel + ed * VS;
+            const A *xs = xarea + ((pk >> 27) << LT) + VPL * q4;
             A sum = A(0);
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
+            for (int jj = 0; jj < VPL; ++jj)
                 if ((bits >> jj) & 1u) sum += Val<VT>::load(pring + ((vo + jj * VS) & kPMask), 0) * xs[jj];
             sum = quad_sum(sum);
-            if (q4 == 0) lds_add(&acc[((pk >> 24) & (kMaxPanels - 1)) * 16 * NACC + r4], (AC)sum);
+            if (q4 == 0 && r4 < S) lds_add(&acc[((pk >> 24) & (kMaxPanels - 1)) * 16 * NACC + r4], (AC)sum);
         }
     };
 
@@ -661,19 +674,19 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     flush();
 }
 
-template <int VT, bool AGG, int RR>
+template <int VT, bool AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
                                                                      typename Val<VT>::A beta,
                                                                      const typename Val<VT>::A *__restrict__ x,
                                                                      typename Val<VT>::A *__restrict__ y) {
     const int wid = kWavesPerBlock == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    stream_range<VT, AGG, RR>(d, xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid, alpha, beta, x, y);
+    stream_range<VT, AGG, RR, LT>(d, xcd_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wid, alpha, beta, x, y);
 }
 
 // Products of several matrices in one launch (the serving loop's batches): workgroup b, after the
 // XCD remap, runs work range b - jobs[j].wave_base of job j = wave_job[b]; every job of a launch has
-// the same value type, aggregation and row-sum mode.
-template <int VT, bool AGG, int RR>
+// the same value type, aggregation, row-sum mode and tile size.
+template <int VT, bool AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJob *__restrict__ jobs,
                                                                     const int32_t *__restrict__ wave_job, int total) {
     static_assert(kWavesPerBlock == 1, "one work range per workgroup");
@@ -681,7 +694,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJo
     const int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= total) return;
     const BatchJob &J = jobs[wave_job[b]];
-    stream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
+    stream_range<VT, AGG, RR, LT>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
 // ---- quad kernel (natural order, spmv_kernel = 2) ---------------------------
@@ -760,21 +773,25 @@ __device__ __forceinline__ typename Val<VT>::A quad_value(const uint32_t *w, int
     }
 }
 
-template <int VT, bool AGG, int RR>
+template <int VT, bool AGG, int RR, int LT>
 __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename Val<VT>::A alpha,
                                               typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                               typename Val<VT>::A *__restrict__ y) {
     static_assert(kWavesPerBlock == 1, "one work range per workgroup");
     static_assert(RR != 1, "the quad kernel sums a lane's row runs itself");
+    static_assert(LT == 3 || LT == 4, "16 x 16 or 8 x 8 tiles");
+    constexpr int S = 1 << LT;      // rows of a panel, columns of a tile
+    constexpr int TPG = kWave / S;  // tiles per x gather
+    constexpr int QPR = S / 4;      // quads per row of a Dense tile
     using A = typename Val<VT>::A;
     using AC = typename std::conditional<RR == 2 || RR == 4, double, A>::type;  // accumulator type
     constexpr int NACC = RR >= 3 ? 2 : 1;
     constexpr int VS = Val<VT>::kSize;
     constexpr int NWD = QRaw<VS>::kWords;
     constexpr int QT = cbs::kQTiles, QP = cbs::kQPasses;
-    constexpr int NG = QT / 4;
+    constexpr int NG = (QT + TPG - 1) / TPG;
     static_assert(QT % 4 == 0 && QT <= 32 && QT + 1 <= kWave, "x gathers take four tiles; records fit one load");
-    __shared__ __align__(16) A xarea[QT * 16];
+    __shared__ __align__(16) A xarea[NG * kWave];
     __shared__ __align__(16) AC acc[kMaxPanels * 16 * NACC];
     __shared__ __align__(16) i32x4 rtab[2][QT];
     __shared__ __align__(16) uint32_t marks[2][kWave];
@@ -789,7 +806,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     const rsrc_t rrs = make_rsrc(d.batch_stream + 4 * (int64_t)o_begin, d.stream_alloc - 16 * (int64_t)o_begin);
     const int p_first = d.tile_row[t0], p_last = d.tile_row[t1 - 1];
     const bool sh_first = d.panel_shared[p_first] != 0, sh_last = d.panel_shared[p_last] != 0;
-    const int gj = lane >> 4, glc = lane & 15;
+    const int gj = lane >> LT, glc = lane & (S - 1);
 
     // header and records of the batch at record o (relative to the range's first): lane 63 the
     // header, lane i < QT record i (lanes QT .. 62 record QT - 1 again)
@@ -822,9 +839,9 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     auto issue_cols = [&](int tb, int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            if (4 * g < nt) {
-                const int t = min(tb + 4 * g + gj, t1 - 1);
-                RG[g] = AGG ? d.tile_cols[16 * (size_t)t + (glc & 3) * 4 + (glc >> 2)] : d.tile_col[t];
+            if (TPG * g < nt) {
+                const int t = min(tb + TPG * g + gj, t1 - 1);
+                RG[g] = AGG ? d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)] : d.tile_col[t];
             }
         }
     };
@@ -832,10 +849,10 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     auto issue_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            if (4 * g < nt) {
+            if (TPG * g < nt) {
                 int col = RG[g];
                 if (!AGG) {
-                    const int64_t c = 16 * (int64_t)RG[g] + glc;
+                    const int64_t c = S * (int64_t)RG[g] + glc;
                     col = c < d.n ? (int)c : 0;
                 }
                 XG[g] = x[col];
@@ -845,7 +862,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     auto put_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (4 * g < nt) xarea[64 * g + lane] = XG[g];
+            if (TPG * g < nt) xarea[64 * g + lane] = XG[g];
     };
 
     // the quads of a batch in flight: codes, value words and a word of what the multiply needs
@@ -869,13 +886,15 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                 const bool live = q < h.qtot;
                 const bool dense = live && ((r.w >> 15) & 1);
                 const int slot = r.w & (kMaxPanels - 1);
-                uint32_t m = (uint32_t)(ti << 4) |
+                uint32_t m = (uint32_t)(ti << LT) |
                              ((uint32_t)(slot * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0)) << 9);
                 int caddr;
                 if (dense) {
+                    // quad dq of a Dense tile: row dq / QPR, columns 4 (dq mod QPR) .. + 3, i.e. elements
+                    // 4 dq .. 4 dq + 3 of the row-major tile and bits 4 dq .. of its bitmap
                     const int dq = q - ((r.w >> 2) & 0x3FF);
                     caddr = r.x + 4 * (dq >> 3);
-                    m |= (1u << 16) | ((uint32_t)(((dq & 3) << 6) | (dq >> 2)) << 17) | ((uint32_t)(dq & 7) << 25);
+                    m |= (1u << 16) | ((uint32_t)(((dq % QPR) << 6) | (dq / QPR)) << 17) | ((uint32_t)(dq & 7) << 25);
                 } else {
                     const int nv = live ? min(max(r.z - 4 * q, 0), 4) : 0;
                     caddr = r.x + 4 * q;
@@ -932,8 +951,8 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     auto is_shared = [&](int p) { return (p == p_first && sh_first) || (p == p_last && sh_last); };
     auto issue_y = [&]() {
         if (beta == A(0)) return;
-        const int64_t row = 16 * (int64_t)(done_pb + fk) + fr;
-        if (((done_mask >> fk) & 1) && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
+        const int64_t row = S * (int64_t)(done_pb + fk) + fr;
+        if (((done_mask >> fk) & 1) && fr < S && row < d.m && !is_shared(done_pb + fk)) YP = y[row];
     };
     auto flush = [&]() {
         if ((done_mask >> fk) & 1) {
@@ -946,8 +965,8 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                 a[16] = AC(0);
             }
             const A v = (A)sv;
-            const int64_t row = 16 * (int64_t)p + fr;
-            if (row < d.m) {
+            const int64_t row = S * (int64_t)p + fr;
+            if (fr < S && row < d.m) {
                 if (is_shared(p)) {
                     global_add(&y[row], alpha * v);
                 } else {
@@ -1023,22 +1042,22 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
 }
 
 // The serving loop's batched launch for quad-batch structures (as spmv_batch_kernel)
-template <int VT, bool AGG, int RR>
+template <int VT, bool AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJob *__restrict__ jobs,
                                                                      const int32_t *__restrict__ wave_job, int total) {
     using A = typename Val<VT>::A;
     const int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= total) return;
     const BatchJob &J = jobs[wave_job[b]];
-    qstream_range<VT, AGG, RR>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
+    qstream_range<VT, AGG, RR, LT>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
-template <int VT, bool AGG, int RR>
+template <int VT, bool AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
                                                                    typename Val<VT>::A *__restrict__ y) {
-    qstream_range<VT, AGG, RR>(d, xcd_block(blockIdx.x, gridDim.x), alpha, beta, x, y);
+    qstream_range<VT, AGG, RR, LT>(d, xcd_block(blockIdx.x, gridDim.x), alpha, beta, x, y);
 }
 
 // ---- rows per lane (natural order) -----------------------------------------
@@ -1162,15 +1181,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_rows_kernel(DevView d, typ
 // tile would contribute 0*Inf; those tiles take the entry-by-entry path.
 
 // packed region size of a tile (16-byte aligned), as laid out by the converter
+// bytes of a tile's packed region (S = 1 << lt), rounded to the 16-byte tile alignment
 template <int VS>
-__device__ __forceinline__ int region_dev(int ty, int nz) {
+__device__ __forceinline__ int region_dev(int ty, int nz, int lt) {
+    const int S = 1 << lt;
     int b;
     if (ty == 0)
         b = nz + pad_bytes(nz, VS) + nz * VS;
     else if (ty == 1)
-        b = 16 + nz + pad_bytes(16 + nz, VS) + nz * VS;
+        b = S + nz + pad_bytes(S + nz, VS) + nz * VS;
     else
-        b = 256 * VS + 32;
+        b = S * S * VS + S * S / 8;
     return (b + 15) & ~15;
 }
 
@@ -1218,14 +1239,16 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
     A *xs = xs_all[wid];
     A *cs = cs_all[wid];
     const int t0 = d.wave_ptr[w], t1 = d.wave_ptr[w + 1];
+    // lane (r4, q4) owns row r4 of the panel (rows past the tile size S idle) and KC/4 columns of Y
     const int r4 = lane >> 2, q4 = lane & 3, jb = q4 * NJ;
+    const int LT = d.tile_lt, TS = 1 << LT;
     A acc[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) acc[i] = A(0);
 
     auto flush = [&](int p, bool shared) {
-        const int64_t row = 16 * (int64_t)p + r4;
-        if (row < d.m) {
+        const int64_t row = ((int64_t)p << LT) + r4;
+        if (r4 < TS && row < d.m) {
             A *yp = Y + row * ldy + j0 + jb;
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
@@ -1262,23 +1285,24 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
     // original column of local column r4 of a tile (restore entry read one tile ahead)
     auto restore_entry = [&](const TM &m) {
         if (!d.col_agg) return 0;
-        const int a = d.cols_offset[m.row] + 16 * m.col + r4;
+        const int a = d.cols_offset[m.row] + (m.col << LT) + r4;
         return d.restore_cols[min(a, d.cols_offset[m.row + 1] - 1)];
     };
     auto colvalid = [&](const TM &m) {
-        if (d.col_agg) return d.cols_offset[m.row] + 16 * m.col + r4 < d.cols_offset[m.row + 1];
-        return 16 * (int64_t)m.col + r4 < d.n;
+        if (r4 >= TS) return false;
+        if (d.col_agg) return d.cols_offset[m.row] + (m.col << LT) + r4 < d.cols_offset[m.row + 1];
+        return ((int64_t)m.col << LT) + r4 < d.n;
     };
     // loads of one tile: its packed region (chunks past the region end re-read the last one) and
     // its X rows (lane (r4, q4): column r4, KC/4 entries; columns outside the tile read row 0)
     u32x4 P[3];
     A XR[NJ];
     auto issue_tile = [&](const TM &m, int rcol, bool cv) {
-        const int last = (region_dev<VS>((m.nts >> 16) & 0xFF, m.nts & 0xFFFF) - 1) >> 10;
+        const int last = (region_dev<VS>((m.nts >> 16) & 0xFF, m.nts & 0xFFFF, LT) - 1) >> 10;
         const u32x4 *src = reinterpret_cast<const u32x4 *>(d.payload + m.vp) + lane;
 #pragma unroll
         for (int i = 0; i < 3; ++i) P[i] = src[min(i, last) * kWave];
-        const int64_t col = d.col_agg ? rcol : 16 * (int64_t)m.col + r4;
+        const int64_t col = d.col_agg ? rcol : ((int64_t)m.col << LT) + r4;
         const int64_t rowoff = cv ? col * ldx : 0;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) XR[i] = X[rowoff + j0 + min(jb + i, kc - 1)];
@@ -1317,7 +1341,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
             cur_sh = m.nts >> 24;
         }
         const int nz = m.nts & 0xFFFF, ty = (m.nts >> 16) & 0xFF;
-        if (ty == 2 && KC >= 16 && __ballot(!finite) == 0) {
+        if (ty == 2 && KC >= 16 && TS == 16 && __ballot(!finite) == 0) {
             // dense tile on the matrix cores: C(16 x 16 block ob) = sum_kb D[:, 4kb:4kb+4] X[4kb:4kb+4, block]
             const int li = lane & 15, lk = lane >> 4;
             A a[4];
@@ -1336,25 +1360,27 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
             continue;
         }
         if (ty == 2) {
-            // entry by entry over the occupancy bitmap of row r4
-            const uint8_t *mask = tbuf + 256 * VS;
-            const uint32_t bits = (uint32_t)mask[2 * r4] | ((uint32_t)mask[2 * r4 + 1] << 8);
-            for (int cc = 0; cc < 16; ++cc) {
+            // entry by entry over the occupancy bitmap of row r4 (bits r4 S .. r4 S + S - 1)
+            const uint8_t *mask = tbuf + TS * TS * VS;
+            const int eb = (r4 * TS) >> 3;
+            const uint32_t bits =
+                r4 < TS ? ((uint32_t)mask[eb] | ((uint32_t)mask[eb + 1] << 8)) & ((1u << TS) - 1u) : 0u;
+            for (int cc = 0; cc < TS; ++cc) {
                 if ((bits >> cc) & 1u) {
-                    const A v = Val<VT>::load(tbuf, r4 * 16 + cc);
+                    const A v = Val<VT>::load(tbuf, r4 * TS + cc);
 #pragma unroll
                     for (int i = 0; i < NJ; ++i) acc[i] += v * xs[cc * KC + jb + i];
                 }
             }
             continue;
         }
-        const int hdr = ty == 1 ? 16 : 0;
+        const int hdr = ty == 1 ? TS : 0;
         const uint8_t *codes = tbuf + hdr;
         const uint8_t *vals = codes + nz + pad_bytes(hdr + nz, VS);
         int rs, re;
         if (ty == 1) {
-            rs = tbuf[r4];
-            re = r4 < 15 ? (int)tbuf[r4 + 1] : nz;
+            rs = r4 < TS ? (int)tbuf[r4] : 0;
+            re = r4 < TS - 1 ? (int)tbuf[r4 + 1] : r4 == TS - 1 ? nz : 0;
         } else {
             // COO: entries are row-major; row r4 spans the entries with row < r4 + 1 minus those with row < r4
             rs = 0;
@@ -1380,15 +1406,15 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_kernel(DevView d, typename
     if (cur >= 0) flush(cur, cur_sh != 0);
 }
 
-// y <- beta * y (0 when beta == 0) on the rows of shared and empty panels
+// y <- beta * y (0 when beta == 0) on the rows of shared and empty panels (panels of 1 << lt rows)
 template <class A>
 __global__ void prepass_kernel(const int32_t *__restrict__ list, int32_t np, int64_t m, A beta, A *__restrict__ y,
-                               int k, int64_t ldy) {
+                               int k, int64_t ldy, int lt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = 16 * (int64_t)k;
+    const int64_t per = ((int64_t)k) << lt;
     if (i >= (int64_t)np * per) return;
     const int64_t pi = i / per, rem = i - pi * per;
-    const int64_t row = 16 * (int64_t)list[pi] + rem / k;
+    const int64_t row = ((int64_t)list[pi] << lt) + rem / k;
     const int j = (int)(rem % k);
     if (row >= m) return;
     A *yp = y + row * ldy + j;
@@ -1435,10 +1461,62 @@ __global__ __launch_bounds__(256) void read_kernel(const uint4 *__restrict__ src
 template <class A>
 hipError_t prepass(const DevView &d, double beta, void *y, int k, int64_t ldy, hipStream_t s) {
     if (d.nprepass <= 0) return hipSuccess;
-    const int64_t total = (int64_t)d.nprepass * 16 * k;
+    const int64_t total = ((int64_t)d.nprepass * k) << d.tile_lt;
     const int64_t nb = (total + 255) / 256;
     hipLaunchKernelGGL(prepass_kernel<A>, dim3((unsigned)nb), dim3(256), 0, s, d.prepass_list, d.nprepass, d.m,
-                       (A)beta, (A *)y, k, ldy);
+                       (A)beta, (A *)y, k, ldy, (int)d.tile_lt);
+    return hipGetLastError();
+}
+
+// the natural-order kernels of one value type and tile size, chosen by aggregation and row-sum mode
+// (FP64 accumulators already: modes 2 and 4 are modes 0 and 3)
+template <int VT, int LT>
+hipError_t spmv_stream_launch(const DevView &d, typename Val<VT>::A a, typename Val<VT>::A b, const void *x, void *y,
+                              int nb, hipStream_t s) {
+    using A = typename Val<VT>::A;
+    constexpr bool kWide = std::is_same<A, double>::value;
+    constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
+    const int rr = d.row_reduce;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
+    };
+    if (d.col_agg) {
+        if (rr == 1) go(spmv_stream_kernel<VT, true, 1, LT>);
+        else if (rr == 2) go(spmv_stream_kernel<VT, true, kRR2, LT>);
+        else if (rr == 3) go(spmv_stream_kernel<VT, true, 3, LT>);
+        else if (rr == 4) go(spmv_stream_kernel<VT, true, kRR4, LT>);
+        else go(spmv_stream_kernel<VT, true, 0, LT>);
+    } else {
+        if (rr == 1) go(spmv_stream_kernel<VT, false, 1, LT>);
+        else if (rr == 2) go(spmv_stream_kernel<VT, false, kRR2, LT>);
+        else if (rr == 3) go(spmv_stream_kernel<VT, false, 3, LT>);
+        else if (rr == 4) go(spmv_stream_kernel<VT, false, kRR4, LT>);
+        else go(spmv_stream_kernel<VT, false, 0, LT>);
+    }
+    return hipGetLastError();
+}
+
+template <int VT, int LT>
+hipError_t spmv_quad_launch(const DevView &d, typename Val<VT>::A a, typename Val<VT>::A b, const void *x, void *y,
+                            int nb, hipStream_t s) {
+    using A = typename Val<VT>::A;
+    constexpr bool kWide = std::is_same<A, double>::value;
+    constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
+    const int rr = d.row_reduce;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
+    };
+    if (d.col_agg) {
+        if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2, LT>);
+        else if (rr == 3) go(spmv_quad_kernel<VT, true, 3, LT>);
+        else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4, LT>);
+        else go(spmv_quad_kernel<VT, true, 0, LT>);
+    } else {
+        if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2, LT>);
+        else if (rr == 3) go(spmv_quad_kernel<VT, false, 3, LT>);
+        else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4, LT>);
+        else go(spmv_quad_kernel<VT, false, 0, LT>);
+    }
     return hipGetLastError();
 }
 
@@ -1453,23 +1531,8 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     // the segmented scan costs the same whatever the runs; the handle holds the choice
     const A a = (A)alpha, b = (A)beta;
     if (d.natural_order && d.spmv_kernel == 2) {
-        constexpr bool kWide = std::is_same<A, double>::value;
-        constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
-        const int rr = d.row_reduce;
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
-        };
-        if (d.col_agg) {
-            if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2>);
-            else if (rr == 3) go(spmv_quad_kernel<VT, true, 3>);
-            else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4>);
-            else go(spmv_quad_kernel<VT, true, 0>);
-        } else {
-            if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2>);
-            else if (rr == 3) go(spmv_quad_kernel<VT, false, 3>);
-            else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4>);
-            else go(spmv_quad_kernel<VT, false, 0>);
-        }
+        if (d.tile_lt == 3) return spmv_quad_launch<VT, 3>(d, a, b, x, y, nb, s);
+        return spmv_quad_launch<VT, 4>(d, a, b, x, y, nb, s);
     } else if (d.natural_order && d.spmv_kernel == 1) {
         if (d.col_agg)
             hipLaunchKernelGGL((spmv_rows_kernel<VT, true>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
@@ -1478,26 +1541,8 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
             hipLaunchKernelGGL((spmv_rows_kernel<VT, false>), dim3(nb), dim3(kBlockThreads), 0, s, d, a, b,
                                (const A *)x, (A *)y);
     } else if (d.natural_order) {
-        // double accumulators already: modes 2 and 4 are modes 0 and 3
-        constexpr bool kWide = std::is_same<A, double>::value;
-        constexpr int kRR2 = kWide ? 0 : 2, kRR4 = kWide ? 3 : 4;
-        const int rr = d.row_reduce;
-        auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
-        };
-        if (d.col_agg) {
-            if (rr == 1) go(spmv_stream_kernel<VT, true, 1>);
-            else if (rr == 2) go(spmv_stream_kernel<VT, true, kRR2>);
-            else if (rr == 3) go(spmv_stream_kernel<VT, true, 3>);
-            else if (rr == 4) go(spmv_stream_kernel<VT, true, kRR4>);
-            else go(spmv_stream_kernel<VT, true, 0>);
-        } else {
-            if (rr == 1) go(spmv_stream_kernel<VT, false, 1>);
-            else if (rr == 2) go(spmv_stream_kernel<VT, false, kRR2>);
-            else if (rr == 3) go(spmv_stream_kernel<VT, false, 3>);
-            else if (rr == 4) go(spmv_stream_kernel<VT, false, kRR4>);
-            else go(spmv_stream_kernel<VT, false, 0>);
-        }
+        if (d.tile_lt == 3) return spmv_stream_launch<VT, 3>(d, a, b, x, y, nb, s);
+        return spmv_stream_launch<VT, 4>(d, a, b, x, y, nb, s);
     } else
         hipLaunchKernelGGL(spmv_kernel<VT>, dim3(nb), dim3(kBlockThreads), 0, s, d, (A)alpha, (A)beta,
                            (const A *)x, (A *)y);
@@ -1526,7 +1571,9 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
 // operand and accumulator layouts (see Mfma): lane l holds A[l % 16][4kb + l / 16]
 // and B[4kb + l / 16][l % 16] in step kb
 // X32: every element of X lies within 4 GiB of X, so its address is X plus a 32-bit byte offset
-template <int VT, int KC, bool AGG, int NS, bool X32>
+// LT = 3 (8 x 8 tiles): the tile sits in the top-left corner of the 16 x 16 operand, only its
+// columns' two 4-wide MFMA steps run and only the accumulator rows of its 8 panel rows are written.
+template <int VT, int KC, bool AGG, int NS, bool X32, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typename Val<VT>::A alpha,
                                                                   typename Val<VT>::A beta,
                                                                   const typename Val<VT>::A *__restrict__ X,
@@ -1536,7 +1583,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
     using C = typename Mfma<A>::C;
     constexpr int VS = Val<VT>::kSize;
     constexpr int NB = KC / 16;  // 16-column output blocks
+    constexpr int TS = 1 << LT;  // tile size
+    constexpr int KB = TS / 4;   // 4-column MFMA steps per tile
+    constexpr int MW = TS * TS / 32;  // bitmap words of a Dense tile
+    using CI = typename std::conditional<LT == 4, u32x4, i32x2>::type;  // a lane's KB original columns
     static_assert(KC == 16 || KC == 32, "16 or 32 columns per slice");
+    static_assert(LT == 3 || LT == 4, "16 x 16 or 8 x 8 tiles");
     __shared__ __align__(16) A dense_all[kWavesPerBlock][256];
     __shared__ A cs_all[kWavesPerBlock][16 * KC];
     __shared__ A xs_all[kWavesPerBlock][16 * KC];
@@ -1561,15 +1613,15 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
     // four stages stay within the 63 vector loads a wavefront can have in flight.
     struct Stage {
         i32x4 rec;      // {vp low, vp high | type << 16 | (nnz - 1) << 18, panel, column block}
-        u32x4 ci;       // aggregation: original columns lg, lg + 4, lg + 8, lg + 12 of the tile
+        CI ci;          // aggregation: original columns lg, lg + 4, ... of the tile
         A ev[4];        // values of entries (elements) 4l .. 4l+3
-        uint32_t ec;    // COO/CSR: codes of entries 4l .. 4l+3; Dense: occupancy bitmap word l % 8
-        A xb[NB][4];    // B operands: X[column 4kb + lg][j0 + 16ob + lr]
+        uint32_t ec;    // COO/CSR: codes of entries 4l .. 4l+3; Dense: occupancy bitmap word l % MW
+        A xb[NB][4];    // B operands: X[column 4kb + lg][j0 + 16ob + lr] (kb < KB)
     };
     auto issue_idx = [&](Stage &S, int t) __attribute__((always_inline)) {
         const int tc = min(t, t1 - 1);
         S.rec = reinterpret_cast<const i32x4 *>(d.tile_rec)[tc];
-        if constexpr (AGG) S.ci = reinterpret_cast<const u32x4 *>(d.tile_cols)[4 * (size_t)tc + lg];
+        if constexpr (AGG) S.ci = reinterpret_cast<const CI *>(d.tile_cols)[4 * (size_t)tc + lg];
     };
     auto rec_ty = [](int y) { return (y >> 16) & 3; };
     auto rec_nz = [](int y) { return ((y >> 18) & 0xFF) + 1; };
@@ -1578,22 +1630,22 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
         const int nz = rec_nz(y), ty = rec_ty(y);
         const int64_t vp = ((int64_t)(y & 0xFFFF) << 32) | (uint32_t)__builtin_amdgcn_readfirstlane(S.rec.x);
         const uint8_t *base = d.payload + vp;
-        const int hb = ty == 1 ? 16 : 0;
+        const int hb = ty == 1 ? TS : 0;
         const int e = 4 * lane < nz ? 4 * lane : 0;  // lanes past the tile re-read its first entries
         const uint8_t *vals = ty == 2 ? base : base + hb + nz + pad_bytes(hb + nz, VS);
-        const int vi = ty == 2 ? 4 * lane : e;
-        S.ec = ty == 2 ? reinterpret_cast<const uint32_t *>(base + 256 * VS)[lane & 7]
+        const int vi = ty == 2 ? (4 * lane < TS * TS ? 4 * lane : 0) : e;
+        S.ec = ty == 2 ? reinterpret_cast<const uint32_t *>(base + TS * TS * VS)[lane & (MW - 1)]
                        : *reinterpret_cast<const uint32_t *>(base + hb + e);
         Val<VT>::load4(vals, vi, S.ev);
     };
     auto issue_x = [&](Stage &S) __attribute__((always_inline)) {
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
+        for (int kb = 0; kb < KB; ++kb) {
             int col;
             if constexpr (AGG) {
                 col = (int)S.ci[kb];
             } else {
-                const int64_t c = 16 * (int64_t)__builtin_amdgcn_readfirstlane(S.rec.w) + 4 * kb + lg;
+                const int64_t c = ((int64_t)__builtin_amdgcn_readfirstlane(S.rec.w) << LT) + 4 * kb + lg;
                 col = c < d.n ? (int)c : 0;
             }
             if constexpr (X32) {
@@ -1621,8 +1673,8 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
             const int col = 16 * ob + lr;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int64_t row = 16 * (int64_t)p + Mfma<A>::row(lane, v);
-                if (row < d.m && col < kc) {
+                const int64_t row = ((int64_t)p << LT) + Mfma<A>::row(lane, v);
+                if (Mfma<A>::row(lane, v) < TS && row < d.m && col < kc) {
                     A *yp = Y + row * ldy + j0 + col;
                     if (shared) {
                         global_add(yp, alpha * acc[ob][v]);
@@ -1650,20 +1702,20 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
 #pragma unroll
             for (int v = 0; v < 4; ++v) cs[Mfma<A>::row(lane, v) * KC + 16 * ob + lr] = acc[ob][v];
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) xs[(4 * kb + lg) * KC + 16 * ob + lr] = S.xb[ob][kb];
+            for (int kb = 0; kb < KB; ++kb) xs[(4 * kb + lg) * KC + 16 * ob + lr] = S.xb[ob][kb];
         }
         __builtin_amdgcn_wave_barrier();
-        // Dense: ec of lane i holds word i % 8 of the occupancy bitmap and element (r, c) is value
-        // c % 4 of lane 4r + c / 4; COO/CSR: entry e is byte e % 4 of ec and value e % 4 of lane e / 4
-        const int n = ty == 2 ? 256 : nz;
+        // Dense: ec of lane i holds word i % MW of the occupancy bitmap and element e = TS r + c is
+        // value e % 4 of lane e / 4; COO/CSR: entry e is byte e % 4 of ec and value e % 4 of lane e / 4
+        const int n = ty == 2 ? TS * TS : nz;
         for (int e = 0; e < n; ++e) {
             int r, c, src, j;
             if (ty == 2) {
                 if (!((__shfl(ec, e >> 5) >> (e & 31)) & 1)) continue;
-                r = e >> 4;
-                c = e & 15;
-                src = 4 * r + (c >> 2);
-                j = c & 3;
+                r = e >> LT;
+                c = e & (TS - 1);
+                src = e >> 2;
+                j = e & 3;
             } else {
                 const int code = (__shfl(ec, e >> 2) >> (8 * (e & 3))) & 0xFF;
                 r = code & 15;
@@ -1694,7 +1746,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) finite = finite && __builtin_isfinite(S.xb[ob][kb]);
+            for (int kb = 0; kb < KB; ++kb) finite = finite && __builtin_isfinite(S.xb[ob][kb]);
         if (__ballot(!finite) != 0) {
             exact_tile(S);
             return;
@@ -1702,8 +1754,9 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
         const int y = __builtin_amdgcn_readfirstlane(S.rec.y);
         const int nz = rec_nz(y), ty = rec_ty(y);
         // the 16 x 16 operand in LDS, element (r, c) at r*16 + (c%4)*4 + c/4, so lane l reads its four
-        // values A[lr][4kb + lg] as one contiguous group; COO/CSR tiles are zero-filled first
-        if (ty != 2) {
+        // values A[lr][4kb + lg] as one contiguous group; COO/CSR tiles (and 8 x 8 Dense tiles, which
+        // fill its top-left corner) are zero-filled first
+        if (ty != 2 || TS != 16) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) dense[4 * lane + i] = A(0);
             __builtin_amdgcn_wave_barrier();
@@ -1712,24 +1765,24 @@ __global__ __launch_bounds__(kBlockThreads) void spmm_mfma_kernel(DevView d, typ
         for (int i = 0; i < 4; ++i) {
             int r, c;
             if (ty == 2) {
-                r = lane >> 2;
-                c = 4 * (lane & 3) + i;
+                r = (4 * lane + i) >> LT;
+                c = (4 * lane + i) & (TS - 1);
             } else {
                 const int code = (S.ec >> (8 * i)) & 0xFF;
                 r = code & 15;
                 c = code >> 4;
             }
-            if (ty == 2 || 4 * lane + i < nz) dense[r * 16 + (c & 3) * 4 + (c >> 2)] = S.ev[i];
+            if (ty == 2 ? 4 * lane + i < TS * TS : 4 * lane + i < nz) dense[r * 16 + (c & 3) * 4 + (c >> 2)] = S.ev[i];
         }
         __builtin_amdgcn_wave_barrier();
         A a[4];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) a[kb] = dense[lr * 16 + lg * 4 + kb];
+        for (int kb = 0; kb < KB; ++kb) a[kb] = dense[lr * 16 + lg * 4 + kb];
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc[ob] = Mfma<A>::step(a[kb], S.xb[ob][kb], acc[ob]);
+            for (int kb = 0; kb < KB; ++kb) acc[ob] = Mfma<A>::step(a[kb], S.xb[ob][kb], acc[ob]);
     };
 
     // prologue: tiles t0 .. t0+NS-2 in flight, metadata and column indices of tile t0+NS-1
@@ -1770,7 +1823,7 @@ hipError_t spmm_kc(const DevView &d, int k, double alpha, const void *X, int64_t
     return hipGetLastError();
 }
 
-template <int VT, int KC, bool AGG>
+template <int VT, int KC, bool AGG, int LT>
 hipError_t spmm_mfma(const DevView &d, int k, double alpha, const void *X, int64_t ldx, double beta, void *Y,
                      int64_t ldy, hipStream_t s) {
     using A = typename Val<VT>::A;
@@ -1783,10 +1836,10 @@ hipError_t spmm_mfma(const DevView &d, int k, double alpha, const void *X, int64
     constexpr int NS = kWide && CB_TUNE_SPMM_STAGES > 2 ? CB_TUNE_SPMM_STAGES - 1 : CB_TUNE_SPMM_STAGES;  // FP64 stages are twice the registers
     const bool x32 = ((uint64_t)d.n * (uint64_t)ldx + (uint64_t)k) * sizeof(A) < ((uint64_t)1 << 32);
     if (x32)
-        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, true>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
+        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, true, LT>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
                            (A)alpha, (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
     else
-        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, false>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
+        hipLaunchKernelGGL((spmm_mfma_kernel<VT, KC, AGG, NS, false, LT>), dim3(nb, ny), dim3(kBlockThreads), 0, s, d,
                            (A)alpha, (A)beta, (const A *)X, ldx, (A *)Y, ldy, k);
     return hipGetLastError();
 }
@@ -1796,11 +1849,18 @@ hipError_t spmm_vt(const DevView &d, int k, double alpha, const void *X, int64_t
                    int64_t ldy, hipStream_t s) {
     if (d.natural_order && CB_TUNE_SPMM_MFMA) {
         const bool wide = k > 16 && CB_TUNE_SPMM_KC_MAX >= 32;
+        if (d.tile_lt == 3) {
+            if (d.col_agg)
+                return wide ? spmm_mfma<VT, 32, true, 3>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                            : spmm_mfma<VT, 16, true, 3>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+            return wide ? spmm_mfma<VT, 32, false, 3>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                        : spmm_mfma<VT, 16, false, 3>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+        }
         if (d.col_agg)
-            return wide ? spmm_mfma<VT, 32, true>(d, k, alpha, X, ldx, beta, Y, ldy, s)
-                        : spmm_mfma<VT, 16, true>(d, k, alpha, X, ldx, beta, Y, ldy, s);
-        return wide ? spmm_mfma<VT, 32, false>(d, k, alpha, X, ldx, beta, Y, ldy, s)
-                    : spmm_mfma<VT, 16, false>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+            return wide ? spmm_mfma<VT, 32, true, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                        : spmm_mfma<VT, 16, true, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
+        return wide ? spmm_mfma<VT, 32, false, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s)
+                    : spmm_mfma<VT, 16, false, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     }
     if (k <= 4) return spmm_kc<VT, 4>(d, k, alpha, X, ldx, beta, Y, ldy, s);
     if (k <= 8) return spmm_kc<VT, 8>(d, k, alpha, X, ldx, beta, Y, ldy, s);
@@ -1835,50 +1895,55 @@ hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const v
 }
 
 namespace {
-template <int VT, bool AGG>
+template <int VT, bool AGG, int LT>
 hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, int quad, hipStream_t s) {
     constexpr bool kWide = std::is_same<typename Val<VT>::A, double>::value;
     const dim3 grid((unsigned)total), block(kBlockThreads);
     if (quad) {
         if (rr == 2)
-            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 0 : 2>), grid, block, 0, s, jobs, wave_job, total);
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 0 : 2, LT>), grid, block, 0, s, jobs, wave_job,
+                               total);
         else if (rr == 3)
-            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 3>), grid, block, 0, s, jobs, wave_job, total);
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 3, LT>), grid, block, 0, s, jobs, wave_job, total);
         else if (rr == 4)
-            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 3 : 4>), grid, block, 0, s, jobs, wave_job, total);
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 3 : 4, LT>), grid, block, 0, s, jobs, wave_job,
+                               total);
         else
-            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 0>), grid, block, 0, s, jobs, wave_job, total);
+            hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 0, LT>), grid, block, 0, s, jobs, wave_job, total);
         return hipGetLastError();
     }
     if (rr == 1)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 2)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 0 : 2>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 0 : 2, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 3)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 3>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 3, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 4)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 3 : 4>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 3 : 4, LT>), grid, block, 0, s, jobs, wave_job, total);
     else
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 0>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 0, LT>), grid, block, 0, s, jobs, wave_job, total);
     return hipGetLastError();
 }
 template <int VT>
-hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, int quad,
+hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, int quad, int lt,
                     hipStream_t s) {
-    return agg ? batch_rr<VT, true>(jobs, wave_job, total, rr, quad, s)
-               : batch_rr<VT, false>(jobs, wave_job, total, rr, quad, s);
+    if (lt == 3)
+        return agg ? batch_rr<VT, true, 3>(jobs, wave_job, total, rr, quad, s)
+                   : batch_rr<VT, false, 3>(jobs, wave_job, total, rr, quad, s);
+    return agg ? batch_rr<VT, true, 4>(jobs, wave_job, total, rr, quad, s)
+               : batch_rr<VT, false, 4>(jobs, wave_job, total, rr, quad, s);
 }
 }  // namespace
 
 hipError_t launch_spmv_batch(const BatchJob *jobs, const int32_t *wave_job, int total, int vtype, int agg, int rr,
-                             int quad, hipStream_t stream) {
+                             int quad, int lt, hipStream_t stream) {
     if (total <= 0) return hipSuccess;
     switch (vtype) {
-        case 0: return batch_vt<0>(jobs, wave_job, total, agg, rr, quad, stream);
-        case 1: return batch_vt<1>(jobs, wave_job, total, agg, rr, quad, stream);
-        case 2: return batch_vt<2>(jobs, wave_job, total, agg, rr, quad, stream);
-        case 3: return batch_vt<3>(jobs, wave_job, total, agg, rr, quad, stream);
-        case 4: return batch_vt<4>(jobs, wave_job, total, agg, rr, quad, stream);
+        case 0: return batch_vt<0>(jobs, wave_job, total, agg, rr, quad, lt, stream);
+        case 1: return batch_vt<1>(jobs, wave_job, total, agg, rr, quad, lt, stream);
+        case 2: return batch_vt<2>(jobs, wave_job, total, agg, rr, quad, lt, stream);
+        case 3: return batch_vt<3>(jobs, wave_job, total, agg, rr, quad, lt, stream);
+        case 4: return batch_vt<4>(jobs, wave_job, total, agg, rr, quad, lt, stream);
         default: return hipErrorInvalidValue;
     }
 }

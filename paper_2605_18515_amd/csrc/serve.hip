@@ -273,7 +273,7 @@ struct Group {
     int top = 0;  // slots [0, top) hold every active solve
     // batched products: per (kernel value code, aggregation, row-sum mode)
     struct Launch {
-        int kvt, agg, rr, quad, first, count, total;
+        int kvt, agg, rr, quad, lt, first, count, total;
     };
     std::vector<Launch> launches;
     cbd::BatchJob *d_bjobs = nullptr;
@@ -534,13 +534,14 @@ template <class T>
 hipError_t cb_server_s::build_launches(Group<T> &g) {
     g.launches.clear();
     if (!g.active) return hipSuccess;
-    // order the active solves by (kernel value code, batch format, aggregation, row-sum mode)
+    // order the active solves by (kernel value code, tile size, batch format, aggregation, row-sum mode)
     std::vector<int> order;
     for (int i = 0; i < g.top; ++i)
         if (g.req[i]) order.push_back(i);
     auto key = [&](int i) {
         const cbh::MatrixView &v = mats[g.req[i]->r.matrix].v;
-        return v.kernel_vt * 32 + (v.view.spmv_kernel == 2 ? 16 : 0) + v.col_agg * 8 + v.row_reduce;  // row_reduce < 8
+        return v.kernel_vt * 64 + (v.view.tile_lt == 3 ? 32 : 0) + (v.view.spmv_kernel == 2 ? 16 : 0) + v.col_agg * 8 +
+               v.row_reduce;  // row_reduce < 8
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     std::vector<cbd::BatchJob> bj;
@@ -554,6 +555,7 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
         L.agg = v0.col_agg;
         L.rr = v0.row_reduce;
         L.quad = v0.view.spmv_kernel == 2 ? 1 : 0;
+        L.lt = v0.view.tile_lt;
         L.first = (int)bj.size();
         L.total = 0;
         for (; i < order.size() && key(order[i]) == k0; ++i) {
@@ -599,7 +601,7 @@ hipError_t cb_server_s::enqueue_steps(Group<T> &g, int nsteps) {
         size_t wofs = 0;
         for (const auto &L : g.launches) {
             hipError_t e = cbd::launch_spmv_batch(g.d_bjobs + L.first, g.d_wave_job + wofs, L.total, L.kvt, L.agg, L.rr,
-                                                   L.quad, s);
+                                                   L.quad, L.lt, s);
             if (e != hipSuccess) return e;
             wofs += (size_t)L.total;
         }

@@ -31,18 +31,24 @@ struct Bench {
     void *x = nullptr, *y = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int reps = 20;
+    int k = 1;  // right-hand sides: 1 = cb_spmv, more = cb_spmm with X n x k, Y m x k
 };
 
-// median kernel time of one cb_spmv (microseconds) over reps single-launch measurements
+cb_status_t product(cb_matrix_t A, Bench &B) {
+    if (B.k <= 1) return cb_spmv(A, 1.0, B.x, 0.0, B.y, B.s);
+    return cb_spmm(A, B.k, 1.0, B.x, B.k, 0.0, B.y, B.k, B.s);
+}
+
+// median kernel time of one product (microseconds) over reps single-launch measurements
 cb_status_t time_spmv(cb_matrix_t A, Bench &B, double &us) {
     std::vector<float> t;
     for (int i = 0; i < 3; ++i) {
-        const cb_status_t st = cb_spmv(A, 1.0, B.x, 0.0, B.y, B.s);
+        const cb_status_t st = product(A, B);
         if (st != CB_SUCCESS) return st;
     }
     for (int i = 0; i < B.reps; ++i) {
         hipEventRecord(B.e0, B.s);
-        const cb_status_t st = cb_spmv(A, 1.0, B.x, 0.0, B.y, B.s);
+        const cb_status_t st = product(A, B);
         if (st != CB_SUCCESS) return st;
         hipEventRecord(B.e1, B.s);
         hipError_t e = hipEventSynchronize(B.e1);
@@ -85,6 +91,8 @@ struct Tuner {
         c.spmv_bytes = info.spmv_bytes;
         c.col_agg = info.col_agg;
         c.row_reduce = info.row_reduce;
+        c.tile_dim = info.tile_dim;
+        c.spmv_kernel = info.spmv_kernel;
         idx = (int)cand.size();
         cand.push_back(c);
         handles.push_back(A);
@@ -127,7 +135,8 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             return fail(CB_ERROR_INVALID_VALUE, "cb_tune_options_t.struct_size mismatch");
         to = *topt;
     }
-    if (to.reps < 1 || to.reps > 10000 || to.max_candidates < 1 || to.max_candidates > CB_TUNE_MAX_CANDIDATES)
+    if (to.reps < 1 || to.reps > 10000 || to.max_candidates < 1 || to.max_candidates > CB_TUNE_MAX_CANDIDATES ||
+        to.spmm_k < 0 || to.spmm_k > 4096)
         return fail(CB_ERROR_INVALID_VALUE, "invalid tuner options");
     cb_options_t b0;
     cb_options_default(&b0);
@@ -147,16 +156,17 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
     T.max_cand = to.max_candidates;
     T.B.s = (hipStream_t)stream;
     T.B.reps = to.reps;
+    T.B.k = std::max(1, to.spmm_k);
     const int wide = b0.value_type == CB_VALUE_F64 || b0.vector_f64;
-    const size_t es = wide ? 8 : 4;
-    hipError_t e = hipMalloc(&T.B.x, std::max<size_t>(es * (size_t)std::max<int64_t>(n, 1), 256));
-    if (e == hipSuccess) e = hipMalloc(&T.B.y, std::max<size_t>(es * (size_t)std::max<int64_t>(m, 1), 256));
+    const size_t es = wide ? 8 : 4, kk = (size_t)T.B.k;
+    hipError_t e = hipMalloc(&T.B.x, std::max<size_t>(es * kk * (size_t)std::max<int64_t>(n, 1), 256));
+    if (e == hipSuccess) e = hipMalloc(&T.B.y, std::max<size_t>(es * kk * (size_t)std::max<int64_t>(m, 1), 256));
     if (e == hipSuccess) e = hipEventCreate(&T.B.e0);
     if (e == hipSuccess) e = hipEventCreate(&T.B.e1);
     cb_status_t st = CB_SUCCESS;
     if (e != hipSuccess) st = hipfail(e, "tuner buffers");
     if (st == CB_SUCCESS && n > 0) {
-        hipLaunchKernelGGL(fill_one, dim3(256), dim3(256), 0, T.B.s, T.B.x, n, wide);
+        hipLaunchKernelGGL(fill_one, dim3(256), dim3(256), 0, T.B.s, T.B.x, n * (int64_t)kk, wide);
         if ((e = hipGetLastError()) != hipSuccess) st = hipfail(e, "tuner fill");
     }
     // coordinate descent: every knob tried against the best options so far
@@ -170,14 +180,39 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             o.col_agg = T.cand[T.best].col_agg ? 0 : 1;
             if (st == CB_SUCCESS) st = T.eval(o, idx);
         }
-        // format thresholds: COO below Dense at 200, COO only (the streaming kernel reads COO and
-        // CSR entries alike, so a CSR tile's row header is extra bytes there)
-        for (const auto th : {std::pair<int, int>{257, 200}, std::pair<int, int>{257, 257}}) {
+        // sub-block size: the other of 16 and 8, the format thresholds scaled with the tile's area
+        // (the paper's 32 and 128 of 256 slots become 8 and 32 of 64)
+        {
             cb_options_t o = cur();
-            if (o.th1 == th.first && o.th2 == th.second) continue;
-            o.th1 = th.first;
-            o.th2 = th.second;
+            if (T.cand[T.best].tile_dim == 8) {
+                o.tile_dim = 16;
+                o.th1 = std::min(o.th1, 64) * 4;
+                o.th2 = std::min(o.th2, 64) * 4;
+            } else {
+                o.tile_dim = 8;
+                o.th1 = (o.th1 + 3) / 4;
+                o.th2 = o.th2 / 4;
+            }
             if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
+        // the natural-order kernel: entries per lane (0) or quads per lane (2)
+        {
+            cb_options_t o = cur();
+            o.spmv_kernel = T.cand[T.best].spmv_kernel == 2 ? 0 : 2;
+            if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
+        // format thresholds: COO below Dense at 200 of 256 slots, COO only (the streaming kernel reads
+        // COO and CSR entries alike, so a CSR tile's row header is extra bytes there)
+        {
+            const int slots = T.cand[T.best].tile_dim * T.cand[T.best].tile_dim;
+            for (const auto th : {std::pair<int, int>{slots + 1, slots * 200 / 256},
+                                  std::pair<int, int>{slots + 1, slots + 1}}) {
+                cb_options_t o = cur();
+                if (o.th1 == th.first && o.th2 == th.second) continue;
+                o.th1 = th.first;
+                o.th2 = th.second;
+                if (st == CB_SUCCESS) st = T.eval(o, idx);
+            }
         }
         // row sums: the modes other than the resolved one (FP32/BF16 values: the FP64-accumulator
         // modes and the segmented scan; FP32 LDS atomics lose everywhere)

@@ -42,10 +42,12 @@ def host_matrix(A, **opts):
     return cb.CbMatrix.from_csr(A, device=False, **opts)
 
 
-def check_against_model(A, vtype="f64", col_agg=-1, th1=32, th2=128, lb="contiguous", W=8, th0=0.15):
-    M = host_matrix(A, value_type=vtype, col_agg=col_agg, th1=th1, th2=th2, lb_mode=lb, quantum_tiles=W, th0=th0)
+def check_against_model(A, vtype="f64", col_agg=-1, th1=32, th2=128, lb="contiguous", W=8, th0=0.15, tile_dim=16):
+    M = host_matrix(A, value_type=vtype, col_agg=col_agg, th1=th1, th2=th2, lb_mode=lb, quantum_tiles=W, th0=th0,
+                    tile_dim=tile_dim)
     info, s = M.info, M.structure()
-    model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=col_agg, th0=th0, th1=th1, th2=th2)
+    assert info["tile_dim"] == tile_dim
+    model = cm.build(A.m, A.n, A.row_ptr, A.col_idx, col_agg_mode=col_agg, th0=th0, th1=th1, th2=th2, blk=tile_dim)
     NT = len(model.tiles)
     assert info["ntiles"] == NT
     assert info["col_agg"] == int(model.col_agg)
@@ -68,7 +70,7 @@ def check_against_model(A, vtype="f64", col_agg=-1, th1=32, th2=128, lb="contigu
     if model.col_agg:
         assert np.array_equal(s["restore_cols"], model.restore_cols)
         assert np.array_equal(s["cols_offset"], model.cols_offset)
-        assert np.array_equal(s["tile_xoff"], s["cols_offset"][s["tile_row"]] + 16 * s["tile_col"])
+        assert np.array_equal(s["tile_xoff"], s["cols_offset"][s["tile_row"]] + tile_dim * s["tile_col"])
     else:
         assert s["tile_xoff"].size == 0
     # grouping
@@ -115,6 +117,34 @@ MATS = {
 @pytest.mark.parametrize("col_agg", [-1, 0, 1])
 def test_converter_matches_model(name, col_agg):
     check_against_model(MATS[name](), col_agg=col_agg)
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+@pytest.mark.parametrize("col_agg", [-1, 0, 1])
+def test_converter_matches_model_8x8(name, col_agg):
+    check_against_model(MATS[name](), col_agg=col_agg, tile_dim=8, th1=8, th2=40)
+
+
+@pytest.mark.parametrize("lb", ["paper", "none"])
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
+def test_converter_matches_model_8x8_every_mode(vtype, lb):
+    info, _, _ = check_against_model(MATS["dense_mix"](), vtype=vtype, col_agg=0, tile_dim=8, th1=8, th2=40, lb=lb,
+                                     W=3)
+    assert info["tiles_coo"] and info["tiles_csr"] and info["tiles_dense"]
+
+
+def test_tile_dim_is_checked():
+    A = matgen.laplacian_2d(8)
+    for bad in (4, 32, -1, 17):
+        with pytest.raises(cb.CbError) as e:
+            host_matrix(A, tile_dim=bad)
+        assert e.value.status == cb.CB_ERROR_INVALID_VALUE
+    with pytest.raises(cb.CbError) as e:
+        host_matrix(A, tile_dim=8, spmv_kernel=1)
+    assert e.value.status == cb.CB_ERROR_NOT_SUPPORTED
+    M = host_matrix(A, tile_dim=0)
+    assert M.info["tile_dim"] == 16
+    M.close()
 
 
 @pytest.mark.parametrize("vtype", ["f32", "bf16"])
@@ -166,6 +196,7 @@ def test_round_trip(name, vtype):
     for agg in (0, 1):
         for lb in ("contiguous", "paper"):
             roundtrip(MATS[name](), vtype, col_agg=agg, th1=20, th2=60, lb_mode=lb)
+            roundtrip(MATS[name](), vtype, col_agg=agg, th1=8, th2=40, lb_mode=lb, tile_dim=8)
 
 
 def test_round_trip_special_values():
@@ -177,8 +208,9 @@ def test_round_trip_special_values():
     assert A.nnz == keep.sum()
     for vt in ("f64", "f32", "bf16"):
         for th2 in (128, 5):  # th2 = 5 forces Dense tiles, whose zero fill must not swallow stored zeros
-            roundtrip(A, vt, col_agg=0, th1=2, th2=th2)
-            roundtrip(A, vt, col_agg=1, th1=2, th2=th2)
+            for td in (16, 8):
+                roundtrip(A, vt, col_agg=0, th1=2, th2=th2, tile_dim=td)
+                roundtrip(A, vt, col_agg=1, th1=2, th2=th2, tile_dim=td)
 
 
 def test_empty_shapes():
@@ -358,16 +390,18 @@ def test_read_probe_validates_arguments():
 @settings(max_examples=40, deadline=None)
 @given(m=st.integers(0, 60), n=st.integers(0, 60), dens=st.floats(0, 1), seed=st.integers(0, 10 ** 6),
        vtype=st.sampled_from(["f64", "f32", "bf16"]), agg=st.sampled_from([-1, 0, 1]),
-       th=st.sampled_from([(32, 128), (4, 40), (1, 1)]), lb=st.sampled_from(["contiguous", "paper", "none"]))
-def test_random_round_trip(m, n, dens, seed, vtype, agg, th, lb):
+       th=st.sampled_from([(32, 128), (4, 40), (1, 1)]), lb=st.sampled_from(["contiguous", "paper", "none"]),
+       tile_dim=st.sampled_from([16, 8]))
+def test_random_round_trip(m, n, dens, seed, vtype, agg, th, lb, tile_dim):
     rng = np.random.default_rng(seed)
     D = np.where(rng.random((m, n)) < dens,
                  rng.choice([0.0, -0.0, np.nan, np.inf, 1.0, -2.5, 1e-40, 7e38], (m, n)) * 1.0, 0.0)
     keep = rng.random((m, n)) < dens
     A = matgen.from_dense(D, keep_zeros_mask=keep)
-    roundtrip(A, vtype, col_agg=agg, th1=th[0], th2=th[1], lb_mode=lb, wave_nnz=int(rng.integers(0, 300)))
+    roundtrip(A, vtype, col_agg=agg, th1=th[0], th2=th[1], lb_mode=lb, wave_nnz=int(rng.integers(0, 300)),
+              tile_dim=tile_dim)
     if m * n <= 900 and vtype == "f64":
-        check_against_model(A, col_agg=agg, th1=th[0], th2=th[1], lb=lb)
+        check_against_model(A, col_agg=agg, th1=th[0], th2=th[1], lb=lb, tile_dim=tile_dim)
 
 
 def test_automatic_range_size():

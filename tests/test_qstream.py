@@ -40,6 +40,9 @@ def emulate(A, X, vtype="f64", **opts):
     M.close()
     assert info["spmv_kernel"] == 2
     vs = VSIZE[vtype]
+    S = info["tile_dim"]  # tile size
+    assert S == opts.get("tile_dim", 16)
+    QPR = S // 4  # quads per Dense row
     agg = bool(info["col_agg"])
     pay = np.concatenate([s["payload"], np.zeros(PAD, np.uint8)])  # the readable padding reads zeros
     bs = s["batch_stream"].reshape(-1, 4)
@@ -79,7 +82,7 @@ def emulate(A, X, vtype="f64", **opts):
             # limits
             assert 1 <= nt <= QT and 1 <= npass <= QP and npass == (qtot + 63) // 64 and qtot <= 64 * QP
             assert row[tiles[0]] == pb and all(0 <= row[i] - pb < PANELS for i in tiles)
-            quads = [64 if ty[i] == cm.DENSE else (int(nnz[i]) + 3) // 4 for i in tiles]
+            quads = [S * S // 4 if ty[i] == cm.DENSE else (int(nnz[i]) + 3) // 4 for i in tiles]
             assert qtot == sum(quads)
             # marks and the ballot: the tile of every lane
             marks = np.zeros((QP, 64), bool)
@@ -103,10 +106,10 @@ def emulate(A, X, vtype="f64", **opts):
                         assert slot == row[i] % PANELS
                     if dense:
                         dq = q - ((meta >> 2) & 0x3FF)
-                        assert 0 <= dq < 64
+                        assert 0 <= dq < S * S // 4
                         word = int.from_bytes(load(cbase + 4 * (dq >> 3), 4), "little")
                         vm = (word >> (4 * (dq & 7))) & 0xF
-                        codes = [(((dq & 3) << 6) | (dq >> 2)) + 16 * j for j in range(4)]
+                        codes = [(((dq % QPR) << 6) | (dq // QPR)) + 16 * j for j in range(4)]
                     else:
                         nv = min(max(lim - 4 * q, 0), 4) if live else 0
                         vm = (1 << nv) - 1
@@ -118,12 +121,13 @@ def emulate(A, X, vtype="f64", **opts):
                             continue
                         c = codes[j]
                         lc = c >> 4
+                        assert lc < S and (c & 15) < S
                         if agg:
-                            tc = s["tile_cols"][16 * i:16 * i + 16].reshape(4, 4).T.ravel()
+                            tc = s["tile_cols"][S * i:S * i + S].reshape(4, S // 4).T.ravel()
                             oc = int(tc[lc])
                         else:
-                            oc = 16 * int(col[i]) + lc
-                        y[16 * panel + (c & 15)] += vals[j] * X[oc]
+                            oc = S * int(col[i]) + lc
+                        y[S * panel + (c & 15)] += vals[j] * X[oc]
                         seen[i] += 1
                 jb += int(bal.sum())
             for k in range(PANELS):
@@ -160,6 +164,14 @@ MATS = {
 def test_quad_batches_decode_to_the_product(name, col_agg, vtype):
     A, X = dyadic_case(MATS[name]())
     assert np.array_equal(emulate(A, X, vtype, col_agg=col_agg), oracle.spmv(A, X))
+
+
+@pytest.mark.parametrize("vtype", ["f64", "bf16"])
+@pytest.mark.parametrize("col_agg", [0, 1])
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_quad_batches_decode_to_the_product_8x8(name, col_agg, vtype):
+    A, X = dyadic_case(MATS[name]())
+    assert np.array_equal(emulate(A, X, vtype, col_agg=col_agg, tile_dim=8, th1=8, th2=40), oracle.spmv(A, X))
 
 
 @pytest.mark.parametrize("th", [(32, 128), (1, 1), (300, 300), (4, 40)])

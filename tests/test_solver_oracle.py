@@ -162,12 +162,13 @@ def test_server_rejects_bad_options_and_null_arguments(cb):
 def test_tune_option_defaults_and_argument_errors(cb):
     o = cb.cb_tune_options_default()
     assert (o.reps, o.max_candidates) == (20, cb.CB_TUNE_MAX_CANDIDATES)
-    assert ctypes.sizeof(cb.CbTuneCandidate) == ctypes.sizeof(cb.CbOptions) + 24
+    assert ctypes.sizeof(cb.CbTuneCandidate) == ctypes.sizeof(cb.CbOptions) + 32
     A = matgen.laplacian_2d(8)
     lib = cb.library_handle()
     rp, ci, va = (np.ascontiguousarray(A.row_ptr), np.ascontiguousarray(A.col_idx), np.ascontiguousarray(A.values))
     best = cb.CbOptions()
-    for bad in ({"reps": 0}, {"max_candidates": 0}, {"max_candidates": cb.CB_TUNE_MAX_CANDIDATES + 1}):
+    for bad in ({"reps": 0}, {"max_candidates": 0}, {"max_candidates": cb.CB_TUNE_MAX_CANDIDATES + 1},
+                {"spmm_k": -1}, {"spmm_k": 4097}):
         st = lib.cb_tune(None, A.m, A.n, A.nnz, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, None,
                          ctypes.byref(cb.cb_tune_options_default(**bad)), ctypes.byref(best), None, None)
         assert st == cb.CB_ERROR_INVALID_VALUE, bad

@@ -22,8 +22,8 @@ RINGB = CHUNK * RING
 VSIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 
-def region(fmt, nz, vtype):
-    b = cm.tile_region_bytes(int(fmt), int(nz), vtype)
+def region(fmt, nz, vtype, blk=16):
+    b = cm.tile_region_bytes(int(fmt), int(nz), vtype, blk)
     return (b + 15) // 16 * 16
 
 
@@ -57,8 +57,10 @@ def check_stream(A, X, vtype="f64", **opts):
     info, s = M.info, M.structure()
     M.close()
     vs = VSIZE[vtype]
+    S = info["tile_dim"]  # tile size
+    assert S == opts.get("tile_dim", 16)
     assert info["stream_bytes"] == 16 * (info["ntiles"] + info["nbatches"])
-    assert s["tile_cols"].size == (16 * info["ntiles"] if info["col_agg"] else 0)
+    assert s["tile_cols"].size == (S * info["ntiles"] if info["col_agg"] else 0)
     assert s["batch_stream"].size == info["stream_bytes"] // 4
     bp = s["batch_ptr"]
     assert bp[0] == 0 and bp[-1] == info["ntiles"] + info["nbatches"] and np.all(np.diff(bp) >= 0)
@@ -86,7 +88,7 @@ def check_stream(A, X, vtype="f64", **opts):
             assert 1 <= nt <= TILES and nflat + ndense == nt
             assert row[tiles[0]] == pb and all(0 <= row[i] - pb < PANELS for i in tiles)
             rs = int(vp[tiles[0]]) - B0
-            assert re_ == int(vp[tiles[-1]]) - B0 + region(ty[tiles[-1]], nnz[tiles[-1]], vtype)
+            assert re_ == int(vp[tiles[-1]]) - B0 + region(ty[tiles[-1]], nnz[tiles[-1]], vtype, S)
             assert (re_ - 1) // CHUNK - rs // CHUNK + 1 <= RING
             # records: flat tiles in order, then dense tiles in order
             flat = [i for i in tiles if ty[i] != cm.DENSE]
@@ -100,11 +102,11 @@ def check_stream(A, X, vtype="f64", **opts):
                 slot, ti = (pk >> 24) & 7, pk >> 27
                 assert slot == row[i] % PANELS and ti == i - tiles[0]
                 xo = int(r[3])
-                assert xo == (s["cols_offset"][row[i]] + 16 * col[i] if agg else col[i])
+                assert xo == (s["cols_offset"][row[i]] + S * col[i] if agg else col[i])
                 if ty[i] == cm.DENSE:
                     assert pk & 0xFFFFFF == 0 and int(r[1]) == 0 and int(r[2]) == rel
                     continue
-                hb = 16 if ty[i] == cm.CSR else 0
+                hb = S if ty[i] == cm.CSR else 0
                 nz = int(nnz[i])
                 assert int(r[2]) == 0
                 # positions are kept modulo the 4 KB ring the kernel addresses
@@ -125,25 +127,26 @@ def check_stream(A, X, vtype="f64", **opts):
                 assert panel == row[i]
                 xo = int(r[3])
                 if agg:
-                    # the tile's 16 columns the kernel gathers x through
-                    tc = s["tile_cols"][16 * i:16 * i + 16].reshape(4, 4).T.ravel()  # stored (c % 4) * 4 + c // 4
-                    width = min(16, s["cols_offset"][row[i] + 1] - xo)
+                    # the tile's S columns the kernel gathers x through, stored (c % 4) * (S / 4) + c // 4
+                    tc = s["tile_cols"][S * i:S * i + S].reshape(4, S // 4).T.ravel()
+                    width = min(S, s["cols_offset"][row[i] + 1] - xo)
                     assert np.array_equal(tc[:width], s["restore_cols"][xo:xo + width])
                     assert np.all(tc[width:] == s["restore_cols"][s["cols_offset"][row[i]]])
                     orig = lambda c: tc[c]
                 else:
-                    orig = lambda c: 16 * xo + c
+                    orig = lambda c: S * xo + c
                 if ty[i] == cm.DENSE:
                     base = B0 + int(r[2])
-                    for e in range(256):
-                        if (pay[base + 256 * vs + (e >> 3)] >> (e & 7)) & 1:
-                            y[16 * panel + (e >> 4)] += value_at(pay, base + e * vs, vtype) * X[orig(e & 15)]
+                    for e in range(S * S):
+                        if (pay[base + S * S * vs + (e >> 3)] >> (e & 7)) & 1:
+                            y[S * panel + e // S] += value_at(pay, base + e * vs, vtype) * X[orig(e % S)]
                     continue
                 end = int(r[1])
                 for E in range(es, end + 1):
                     code = int(pay[at((pk & 0xFFF) + E)])
+                    assert (code & 15) < S and (code >> 4) < S
                     v = value_at(pay, at(((pk >> 12) & 0xFFF) + vs * E), vtype)
-                    y[16 * panel + (code & 15)] += v * X[orig(code >> 4)]
+                    y[S * panel + (code & 15)] += v * X[orig(code >> 4)]
                 es = end + 1
             # done panels: every panel of the range once, in the batch holding its last tile
             for k in range(PANELS):
@@ -193,6 +196,16 @@ def test_batches_decode_to_the_product(name, col_agg, vtype):
     y = check_stream(A, X, vtype, col_agg=col_agg)
     ref = oracle.spmv(A, X)
     assert np.array_equal(y, ref)
+
+
+@pytest.mark.parametrize("vtype", ["f64", "bf16"])
+@pytest.mark.parametrize("col_agg", [0, 1])
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_batches_decode_to_the_product_8x8(name, col_agg, vtype):
+    """8 x 8 tiles (th2 = 40 so that Dense tiles appear where rows are full)."""
+    A, X = dyadic_case(MATS[name]())
+    y = check_stream(A, X, vtype, col_agg=col_agg, tile_dim=8, th1=8, th2=40)
+    assert np.array_equal(y, oracle.spmv(A, X))
 
 
 @pytest.mark.parametrize("wave_nnz", [64, 300, 5000])
