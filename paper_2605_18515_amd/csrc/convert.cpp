@@ -542,6 +542,14 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // runs of two or more (dense blocks) the two accumulator copies halve the collisions on one
         // address (3D block matrix: 3.5 % faster in FP64, 12 % in FP32), where they come one by one
         // (stencils, scattered rows) the copies only cost LDS
+        // natural-order kernel (measured on gfx950): the quad kernel wins where tiles are well filled
+        // and their rows hold runs of entries (3D block matrix: FP64 147 against 153 us, BF16 77 against
+        // 105), the streaming kernel where tiles are sparse or rows come one entry per tile row
+        // (stencils, power-law rows), whose quads are part empty and sum no runs
+        if (opt.spmv_kernel < 0 && s.lb_mode != CB_LB_PAPER) {
+            const bool long_runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
+            s.spmv_kernel = long_runs && nnz >= 32 * NT ? 2 : 0;
+        }
         if (opt.row_reduce >= 0) {
             s.row_reduce = opt.row_reduce;
             // the quad kernel sums each lane's row runs in registers instead of a segmented scan

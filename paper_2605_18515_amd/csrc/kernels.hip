@@ -48,6 +48,16 @@ namespace {
 #ifndef CB_TUNE_NT_LOADS
 #define CB_TUNE_NT_LOADS 0  // payload chunk loads with the nontemporal hint
 #endif
+#ifndef CB_TUNE_QCPOL
+#define CB_TUNE_QCPOL 0  // cache-policy bits of the quad kernel's payload and record loads (2: nontemporal)
+#endif
+
+// a load of streamed (read-once) data, with the nontemporal hint when NT
+template <bool NT, class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = CB_TUNE_WAVES_PER_BLOCK;
@@ -393,7 +403,9 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     // again), lane 63 the header.  Three batches' records stay in registers, one tile per lane:
     // {record word, last flat entry (COO/CSR) or region start (Dense)}, never both set
     i32x4 Q;
-    auto qload = [&](int o) { Q = rstream[o + (lane == kWave - 1 ? 0 : 1 + min(lane, kBatchTiles - 1))]; };
+    auto qload = [&](int o) {
+        Q = ld_stream<CB_TUNE_NT_LOADS != 0>(&rstream[o + (lane == kWave - 1 ? 0 : 1 + min(lane, kBatchTiles - 1))]);
+    };
     auto recv = [&]() { return i32x2{Q.x, Q.y | Q.z}; };
 
     // payload chunks of a batch not loaded yet (chi: chunks whose loads were issued); re is the
@@ -431,7 +443,8 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         for (int g = 0; g < NG; ++g) {
             if (TPG * g < nt) {
                 const int t = min(tb + TPG * g + gj, t1 - 1);
-                RG[g] = AGG ? d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)] : d.tile_col[t];
+                RG[g] = AGG ? ld_stream<CB_TUNE_NT_LOADS != 0>(&d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)])
+                            : d.tile_col[t];
             }
         }
     };
@@ -734,8 +747,8 @@ template <>
 struct QRaw<8> {
     static constexpr int kWords = 8;
     __device__ static void load(rsrc_t r, int off, uint32_t *w) {
-        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0);
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CB_TUNE_QCPOL);
+        const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, CB_TUNE_QCPOL);
         w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w, w[4] = b.x, w[5] = b.y, w[6] = b.z, w[7] = b.w;
     }
 };
@@ -743,7 +756,7 @@ template <>
 struct QRaw<4> {
     static constexpr int kWords = 4;
     __device__ static void load(rsrc_t r, int off, uint32_t *w) {
-        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CB_TUNE_QCPOL);
         w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w;
     }
 };
@@ -752,7 +765,7 @@ struct QRaw<2> {
     static constexpr int kWords = 3;
     __device__ static void load(rsrc_t r, int off, uint32_t *w) {
         using u32x3 = unsigned int __attribute__((ext_vector_type(3)));
-        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, off & ~3, 0, 0);
+        const u32x3 a = __builtin_amdgcn_raw_buffer_load_b96(r, off & ~3, 0, CB_TUNE_QCPOL);
         w[0] = a.x, w[1] = a.y, w[2] = a.z;
     }
 };
@@ -813,7 +826,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     i32x4 Q;
     auto qload = [&](int o) {
         const int r = lane == kWave - 1 ? o : o + 1 + min(lane, QT - 1);
-        Q = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rrs, 16 * r, 0, 0));
+        Q = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rrs, 16 * r, 0, CB_TUNE_QCPOL));
     };
     struct Hdr {
         int pb, nt, np, done, qtot;
@@ -841,7 +854,8 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         for (int g = 0; g < NG; ++g) {
             if (TPG * g < nt) {
                 const int t = min(tb + TPG * g + gj, t1 - 1);
-                RG[g] = AGG ? d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)] : d.tile_col[t];
+                RG[g] = AGG ? ld_stream<CB_TUNE_QCPOL != 0>(&d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)])
+                            : d.tile_col[t];
             }
         }
     };
@@ -903,7 +917,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                 const int vaddr = r.y + 4 * VS * q;
                 if (VS == 2) m |= (uint32_t)(vaddr & 2) << 30;
                 M[p] = m;
-                C[p] = __builtin_amdgcn_raw_buffer_load_b32(prs, caddr, 0, 0);
+                C[p] = __builtin_amdgcn_raw_buffer_load_b32(prs, caddr, 0, CB_TUNE_QCPOL);
                 QRaw<VS>::load(prs, vaddr, W[p]);
             }
         }

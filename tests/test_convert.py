@@ -347,7 +347,7 @@ def test_row_reduce_resolution_and_run_statistic():
         assert M.info["row_reduce"] == want and M.info["flat_run_mean"] == 1.0
         M.close()
     for rr in (0, 1, 2, 3, 4):
-        M = cb.CbMatrix.from_csr(A, device=False, row_reduce=rr)
+        M = cb.CbMatrix.from_csr(A, device=False, row_reduce=rr, spmv_kernel=0)
         assert M.info["row_reduce"] == rr
         M.close()
     # double vectors: always with FP64 storage, on request with FP32/BF16 (then FP64 atomics suffice)
@@ -428,3 +428,24 @@ def test_automatic_range_size():
     M = cb.CbMatrix.from_csr(big, device=False, wave_nnz=500)
     assert M.info["wave_nnz_mean"] <= 600
     M.close()
+
+
+def test_automatic_kernel_choice():
+    """spmv_kernel = -1: the quad kernel (2) where tiles hold >= 32 entries on average in row runs of
+    two or more, else the streaming kernel (0); Algorithm 2 structures have no natural-order kernel."""
+    n = 16
+    cols = np.stack([np.arange(n), (np.arange(n) + 1) % n], 1)
+    cols.sort(axis=1)
+    A = matgen.Csr(n, n, np.arange(0, 2 * n + 1, 2, dtype=np.int64), cols.ravel().astype(np.int32), np.ones(2 * n))
+    # the same pattern without its last entry: 31 entries in the one tile
+    B = matgen.Csr(n, n, np.minimum(np.arange(0, 2 * n + 1, 2, dtype=np.int64), 2 * n - 1),
+                   cols.ravel()[:-1].astype(np.int32), np.ones(2 * n - 1))
+    P = matgen.Csr(n, n, np.arange(n + 1, dtype=np.int64), ((np.arange(n) * 5) % n).astype(np.int32), np.ones(n))
+    cases = [(A, {}, 2), (A, {"value_type": "bf16"}, 2), (A, {"spmv_kernel": 0}, 0), (A, {"lb_mode": "paper"}, 0),
+             (A, {"lb_mode": "none"}, 2), (B, {}, 0), (P, {}, 0), (A, {"tile_dim": 8}, 0)]
+    for M_, kw, want in cases:
+        M = cb.CbMatrix.from_csr(M_, device=False, **kw)
+        assert M.info["spmv_kernel"] == want, (kw, M.info["spmv_kernel"])
+        if want == 2:
+            assert M.info["row_reduce"] in (3, 4)
+        M.close()

@@ -53,6 +53,7 @@ def decode(s, info, vtype):
 
 
 def check_stream(A, X, vtype="f64", **opts):
+    opts.setdefault("spmv_kernel", 0)  # the streaming kernel's batch format
     M = cb.CbMatrix.from_csr(A, device=False, value_type=vtype, **opts)
     info, s = M.info, M.structure()
     M.close()
@@ -228,7 +229,7 @@ def test_paper_mode_has_no_records():
 def test_limits_cut_batches():
     # a single 16-row panel of 40 dense-ish tiles: the 16-tile limit and the 4-chunk limit both cut
     A, X = dyadic_case(matgen.from_dense(np.random.default_rng(3).uniform(-1, 1, (16, 640))))
-    M = cb.CbMatrix.from_csr(A, device=False, col_agg=0)
+    M = cb.CbMatrix.from_csr(A, device=False, col_agg=0, spmv_kernel=0)
     info = M.info
     M.close()
     assert info["tiles_dense"] == 40
@@ -237,7 +238,7 @@ def test_limits_cut_batches():
     assert np.array_equal(check_stream(A, X, "f64", col_agg=0), oracle.spmv(A, X))
     # one tile per panel over many panels: the 4-panel limit cuts
     A2, X2 = dyadic_case(matgen.identity(16 * 40))
-    M = cb.CbMatrix.from_csr(A2, device=False)
+    M = cb.CbMatrix.from_csr(A2, device=False, spmv_kernel=0)
     info2 = M.info
     M.close()
     assert info2["nbatches"] >= 5
