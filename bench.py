@@ -364,13 +364,15 @@ def _serve_matrix(spec):
 def serve_legs(args, cb, matgen, nreq: int) -> dict:
     """Serving workload: 256 resident matrices from the three families (3D block, power-law, 3D
     Poisson) with n log-uniform in [1e3, 1e6], every other one stored in FP32; requests are SpMM
-    with k uniform in 1..16 on any matrix, or a CG solve (cap 500 iterations, rtol 1e-8 for FP64,
-    1e-5 for FP32) on a Poisson matrix, half each.  Three runs of the same request list: the
-    server with every request submitted at once (throughput), the server under Poisson arrivals at
-    half that rate (p50/p99 latency), and the plain path, one request at a time through cb_spmm
-    and cb_cg.  Returns the measurements."""
+    with k uniform in 1..16 on any matrix, or a CG solve (cap 500 iterations) on a Poisson matrix to
+    a relative residual of 1e-10, half each: on a FP64 matrix plain CG, on a FP32 one the refined
+    kind (the FP32 copy's products, FP64 residual replacement with a FP64 twin of the matrix; only
+    a true residual ends it).  Three runs of the same request list: the server with every request
+    submitted at once (throughput), the server under Poisson arrivals at half that rate (p50/p99
+    latency), and the plain path, one request at a time through cb_spmm, cb_cg and cb_cg_refine.
+    Then the precision comparison on the Poisson matrices alone (serve_precision).  Returns the
+    measurements."""
     import multiprocessing as mp
-    import threading
 
     import numpy as np
     import torch
@@ -384,12 +386,16 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     log(f"generated 256 matrices ({sum(A.nnz for A in csrs) / 1e6:.0f} M non-zeros) in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32") for i, A in enumerate(csrs)]
-    log(f"converted and uploaded in {time.perf_counter() - t:.1f}s, "
-        f"{sum(M.info['device_bytes'] for M in mats) / 2 ** 30:.2f} GiB on the device")
     dts = [np.float64 if i % 2 == 0 else np.float32 for i in range(256)]
     spd = [i for i, s in enumerate(specs) if s[0] == "poisson"]
-    # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix
+    # FP64 twins of the FP32 Poisson matrices: the refined solves' residual replacement
+    twin = {i: cb.CbMatrix.from_csr(csrs[i]) for i in spd if dts[i] == np.float32}
+    log(f"converted and uploaded in {time.perf_counter() - t:.1f}s, "
+        f"{sum(M.info['device_bytes'] for M in list(mats) + list(twin.values())) / 2 ** 30:.2f} GiB on the device")
+    # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix (double
+    # for the refined solves)
     xin = [np.random.default_rng(i).uniform(-1, 1, A.n * 16).astype(dts[i]) for i, A in enumerate(csrs)]
+    b64 = {i: xin[i][:csrs[i].n].astype(np.float64) for i in twin}
     reqs = []
     for r in range(nreq):
         if rng.random() < 0.5:
@@ -397,20 +403,21 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
             reqs.append(("cg", i, 1))
         else:
             reqs.append(("spmm", int(rng.integers(0, 256)), int(rng.integers(1, 17))))
-
-    def rtol(i):
-        return 1e-8 if dts[i] == np.float64 else 1e-5
+    rtol, cap = 1e-10, 500
 
     def outputs():
-        return [np.zeros(csrs[i].n * k if kind == "spmm" else csrs[i].n, dts[i]) for kind, i, k in reqs]
+        return [np.zeros(csrs[i].n * k, dts[i]) if kind == "spmm" else
+                np.zeros(csrs[i].n, np.float64 if i in twin else dts[i]) for kind, i, k in reqs]
 
-    def submit_all(S, outs, gaps=None, count=None):
+    def submit_all(S, ids, outs, gaps=None, count=None):
         tickets = []
         for j, (kind, i, k) in enumerate(reqs[:count]):
             if gaps is not None:
                 time.sleep(gaps[j])
-            if kind == "cg":
-                tickets.append(S.submit_cg(i, xin[i][:csrs[i].n], outs[j], rtol=rtol(i), max_iter=500))
+            if kind == "cg" and i in twin:
+                tickets.append(S.submit_cg_refine(ids[("hi", i)], i, b64[i], outs[j], rtol=rtol, max_iter=cap))
+            elif kind == "cg":
+                tickets.append(S.submit_cg(i, xin[i][:csrs[i].n], outs[j], rtol=rtol, max_iter=cap))
             else:
                 tickets.append(S.submit_spmm(i, xin[i][:csrs[i].n * k].reshape(csrs[i].n, k),
                                              outs[j].reshape(csrs[i].m, k)))
@@ -421,9 +428,9 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     def serve(gaps=None, count=None):
         outs = outputs()
         S = cb.CbServer(max_active=max_active, arena_bytes=arena << 30)
-        for M in mats:
-            S.add_matrix(M)
-        tickets = submit_all(S, outs, gaps, count)
+        ids = {i: S.add_matrix(M) for i, M in enumerate(mats)}
+        ids.update({("hi", i): S.add_matrix(M) for i, M in twin.items()})
+        tickets = submit_all(S, ids, outs, gaps, count)
         resp = [S.wait(t) for t in tickets]
         st = S.stats()
         S.close()
@@ -447,10 +454,14 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     for j, (kind, i, k) in enumerate(reqs):
         ts = time.perf_counter()
         M, A, tdt = mats[i], csrs[i], torch.float64 if dts[i] == np.float64 else torch.float32
-        if kind == "cg":
+        if kind == "cg" and i in twin:
+            x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+            twin[i].cg_refine(M, torch.from_numpy(b64[i]).to(dev), x, rtol=rtol, max_iter=cap, check_every=8)
+            outs_s[j][:] = x.cpu().numpy()
+        elif kind == "cg":
             b = torch.from_numpy(xin[i][:A.n]).to(dev)
             x = torch.zeros(A.n, dtype=tdt, device=dev)
-            M.cg(b, x, rtol=rtol(i), max_iter=500, check_every=8)
+            M.cg(b, x, rtol=rtol, max_iter=cap, check_every=8)
             outs_s[j][:] = x.cpu().numpy()
         else:
             X = torch.from_numpy(xin[i][:A.n * k]).to(dev).reshape(A.n, k)
@@ -469,18 +480,71 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
         a, b_ = outs_b[j].astype(np.float64), outs_s[j].astype(np.float64)
         worst = max(worst, float(np.abs(a - b_).max() / max(1e-300, np.abs(b_).max())))
     conv = sum(1 for (kind, _, _), r in zip(reqs, resp_b) if kind == "cg" and r["converged"])
-    for M in mats:
+    nref = sum(1 for kind, i, _ in reqs if kind == "cg" and i in twin)
+    for M in mats + list(twin.values()):
         M.close()
-    del mats
+    del mats, twin
     torch.cuda.empty_cache()
-    return {"requests": len(reqs), "cg_requests": ncg, "all_at_once": st_b,
+    prec = serve_precision(args, cb, [csrs[i] for i in spd], [xin[i] for i in spd])
+    return {"requests": len(reqs), "cg_requests": ncg, "refined_requests": nref, "rtol": rtol, "all_at_once": st_b,
             "poisson_arrivals": dict(st_p, rate_per_s=lam), "one_at_a_time": seq,
             "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
-            "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst}
+            "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst, "precision": prec}
+
+
+def serve_precision(args, cb, csrs, xin, nsolves: int = 256) -> dict:
+    """FP64 serving against mixed-precision serving at the same accuracy: the serving workload's
+    Poisson matrices, each resident as FP64, FP32 and BF16 handles; the same nsolves CG requests
+    (random matrix, b from the matrix's input block, x0 = 0, cap 500 iterations) served all at once
+    three ways -- plain FP64 CG (recurrence residual <= 1e-10), and the refined kind on the BF16 and
+    on the FP32 copy (FP64 residual replacement, true residual <= 1e-10).  Every solve's true
+    residual is then measured with the CPU oracle on a sample."""
+    import numpy as np
+
+    import oracle  # noqa: F401  (the oracle's true residual)
+    from oracle import solvers
+
+    rng = np.random.default_rng(77)
+    pick = [int(rng.integers(0, len(csrs))) for _ in range(nsolves)]
+    H = {}
+    for vt in ("f64", "f32", "bf16"):
+        H[vt] = [cb.CbMatrix.from_csr(A, value_type=vt) for A in csrs]
+    bs = [xin[i][:csrs[i].n].astype(np.float64) for i in range(len(csrs))]
+    out = {"workload": f"{len(csrs)} resident 3D Poisson matrices (n log-uniform in [1e3, 1e6]), {nsolves} CG "
+                       "solves to 1e-10, x0 = 0, cap 500 iterations, all submitted at once", "solves": nsolves}
+    check = sorted(set(int(j) for j in rng.choice(nsolves, min(24, nsolves), replace=False)))
+    for mode in ("fp64_cg", "refine_bf16", "refine_f32"):
+        S = cb.CbServer(max_active=args.serve_active, arena_bytes=args.serve_arena_gib << 30)
+        ids = {vt: [S.add_matrix(M) for M in H[vt]] for vt in H}
+        xs = [np.zeros(csrs[i].n) for i in pick]
+        tickets = []
+        for j, i in enumerate(pick):
+            if mode == "fp64_cg":
+                tickets.append(S.submit_cg(ids["f64"][i], bs[i], xs[j], rtol=1e-10, max_iter=500))
+            else:
+                low = "bf16" if mode == "refine_bf16" else "f32"
+                tickets.append(S.submit_cg_refine(ids["f64"][i], ids[low][i], bs[i], xs[j], rtol=1e-10, max_iter=500))
+        resp = [S.wait(t) for t in tickets]
+        st = S.stats()
+        S.close()
+        true_res = [solvers.residual(csrs[pick[j]], bs[pick[j]], xs[j]) for j in check]
+        out[mode] = {"solves_per_s": st["solves_per_s"], "p50_ms": st["p50_us"] / 1e3, "p99_ms": st["p99_us"] / 1e3,
+                     "converged": sum(1 for r in resp if r["converged"]),
+                     "mean_iterations": float(np.mean([r["iterations"] for r in resp])),
+                     "replacements": int(sum(r["replacements"] for r in resp)),
+                     "max_true_residual_oracle": float(max(true_res)), "oracle_checked": len(check)}
+        log(f"serving precision, {mode}: {json.dumps(out[mode])}")
+    for vt in H:
+        for M in H[vt]:
+            M.close()
+    base = out["fp64_cg"]["solves_per_s"]
+    out["speedup_vs_fp64"] = {m: out[m]["solves_per_s"] / base for m in ("fp64_cg", "refine_bf16", "refine_f32")}
+    return out
 
 
 SERVE_WORKLOAD = ("serving: 256 resident matrices (3D block, power-law, 3D Poisson; n log-uniform in [1e3, 1e6]; "
-                  "FP64 and FP32), SpMM k in 1..16 or CG (cap 500) requests")
+                  "FP64 and FP32), SpMM k in 1..16 or CG requests to 1e-10 (cap 500; FP32 matrices: FP64 "
+                  "residual replacement)")
 
 
 def run_serve(args, cb, matgen) -> int:
@@ -845,7 +909,9 @@ def main() -> int:
                 "speedup_solves": srv["speedup_solves_vs_one_at_a_time"],
                 "poisson_arrivals_per_s": srv["poisson_arrivals"]["rate_per_s"],
                 "p50_ms": srv["poisson_arrivals"]["p50_us"] / 1e3, "p99_ms": srv["poisson_arrivals"]["p99_us"] / 1e3,
-                "cg_converged": srv["cg_converged"], "max_rel_diff_vs_one_at_a_time": srv["max_rel_diff_vs_one_at_a_time"]}
+                "cg_converged": srv["cg_converged"], "refined_requests": srv["refined_requests"], "rtol": srv["rtol"],
+                "max_rel_diff_vs_one_at_a_time": srv["max_rel_diff_vs_one_at_a_time"],
+                "precision": srv["precision"]}
     else:
         M.close()
 

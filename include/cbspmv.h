@@ -447,7 +447,14 @@ typedef struct {
     int64_t reserved[4];
 } cb_server_options_t;
 
-typedef enum { CB_REQ_SPMM = 0, CB_REQ_CG = 1 } cb_request_kind_t;
+/* CB_REQ_CG: CG in the matrix's own vector type, stopped on the recurrence residual.
+ * CB_REQ_CG_REFINE: CG with FP64 residual replacement (as cb_cg_refine with CB_REFINE_REPLACE and
+ * replace_factor 1e-2): matrix is a FP64 handle, matrix_low a FP32 or BF16 handle of the same
+ * matrix with float vectors; the steps multiply by matrix_low (p and q float), x, r, the dot
+ * products and the scalar recurrences stay FP64, r is replaced by the true residual b - A x of
+ * the FP64 matrix between periods, and only a true residual <= rtol |b| ends the solve as
+ * converged.  b and x are double. */
+typedef enum { CB_REQ_SPMM = 0, CB_REQ_CG = 1, CB_REQ_CG_REFINE = 2 } cb_request_kind_t;
 
 typedef struct {
     uint32_t struct_size;   /* sizeof(cb_request_t) */
@@ -458,9 +465,10 @@ typedef struct {
     const void *in;         /* host, the matrix's vector type: SpMM X (n x k row-major); CG b (n) */
     void *out;              /* host: SpMM Y (m x k, read when beta != 0, written); CG x (n: the start,
                                overwritten with the solution) */
-    double rtol;            /* CG: stop when the recurrence residual is <= rtol |b|; 0 = 1e-10 */
+    double rtol;            /* CG: stop when the recurrence residual (CB_REQ_CG_REFINE: the true
+                               residual) is <= rtol |b|; 0 = 1e-10 */
     int32_t max_iter;       /* CG: iteration cap (rounded up to a multiple of check_every); 0 = 500 */
-    int32_t reserved32;
+    int32_t matrix_low;     /* CB_REQ_CG_REFINE: id of the FP32/BF16 copy the steps multiply by */
     int64_t reserved[4];
 } cb_request_t;
 
@@ -469,10 +477,13 @@ typedef struct {
     int32_t status;         /* cb_status_t of the request */
     int32_t iterations;     /* CG iterations */
     int32_t converged;      /* CG: 1 when the residual test was met */
-    double rel_residual;    /* CG: recurrence |r| / |b| at the end */
+    double rel_residual;    /* CG: |r| / |b| at the end (recurrence; CB_REQ_CG_REFINE: the true
+                               residual of the last replacement) */
     double latency_us;      /* submission to completion */
     double queue_us;        /* submission to admission */
-    int64_t reserved[2];
+    int32_t replacements;   /* CB_REQ_CG_REFINE: residual replacements (the last one decides) */
+    int32_t restarts;       /* CB_REQ_CG_REFINE: replacements that restarted the direction */
+    int64_t reserved[1];
 } cb_response_t;
 
 typedef struct {

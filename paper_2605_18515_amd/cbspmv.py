@@ -91,12 +91,13 @@ class CbServerOptions(ctypes.Structure):
 class CbRequest(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("kind", _i32), ("matrix", _i32), ("k", _i32), ("alpha", _dbl),
                 ("beta", _dbl), ("in_", _p), ("out", _p), ("rtol", _dbl), ("max_iter", _i32),
-                ("reserved32", _i32), ("reserved", _i64 * 4)]
+                ("matrix_low", _i32), ("reserved", _i64 * 4)]
 
 
 class CbResponse(ctypes.Structure):
     _fields_ = [("done", _i32), ("status", _i32), ("iterations", _i32), ("converged", _i32),
-                ("rel_residual", _dbl), ("latency_us", _dbl), ("queue_us", _dbl), ("reserved", _i64 * 2)]
+                ("rel_residual", _dbl), ("latency_us", _dbl), ("queue_us", _dbl), ("replacements", _i32),
+                ("restarts", _i32), ("reserved", _i64 * 1)]
 
 
 class CbServerStats(ctypes.Structure):
@@ -106,7 +107,7 @@ class CbServerStats(ctypes.Structure):
                 ("active_peak", _i32), ("graph_builds", _i32), ("steps", _i64), ("reserved", _i64 * 4)]
 
 
-CB_REQ_SPMM, CB_REQ_CG = range(2)
+CB_REQ_SPMM, CB_REQ_CG, CB_REQ_CG_REFINE = range(3)
 CB_TUNE_MAX_CANDIDATES = 16
 
 
@@ -559,6 +560,15 @@ class CbServer:
         check_host_vectors(self._dtype(mid), self._mats[mid].info["n"], b=b, x=x)
         r = CbRequest(kind=CB_REQ_CG, matrix=mid, k=1, in_=b.ctypes.data, out=x.ctypes.data, rtol=rtol,
                       max_iter=max_iter)
+        return self._submit(r, (b, x))
+
+    def submit_cg_refine(self, mid: int, mid_low: int, b: np.ndarray, x: np.ndarray, rtol: float = 0.0,
+                         max_iter: int = 0) -> int:
+        """CG with FP64 residual replacement: mid is the FP64 handle, mid_low its FP32/BF16 copy
+        (float vectors) that the steps multiply by; b and x are float64."""
+        check_host_vectors(np.float64, self._mats[mid].info["n"], b=b, x=x)
+        r = CbRequest(kind=CB_REQ_CG_REFINE, matrix=mid, matrix_low=mid_low, k=1, in_=b.ctypes.data,
+                      out=x.ctypes.data, rtol=rtol, max_iter=max_iter)
         return self._submit(r, (b, x))
 
     def poll(self, ticket: int) -> dict:

@@ -40,13 +40,18 @@ using Clock = std::chrono::steady_clock;
 
 struct SolveScal {
     double rr, pq, rrn, bb;
+    double rr0;  // r.r at the solve's start (or its last residual replacement)
     int32_t bad, pad;
 };
 
-template <class T>
+// one active solve: x, r, b in TX; the direction p and the product q = A p in TP, the vector type
+// of the matrix the steps multiply by (TP = TX for plain CG; float with TX = double for a refined
+// solve, whose products run on a FP32/BF16 copy)
+template <class TX, class TP>
 struct SolveJob {
-    T *x, *r, *p, *q;
-    const T *b;
+    TX *x, *r;
+    TP *p, *q;
+    const TX *b;
     int64_t n;
     int32_t active;
     int32_t zero_q;  // the product's shared or empty panels need q cleared before it
@@ -65,9 +70,9 @@ __device__ double block_sum(double v) {
 }
 
 // grid (kGB, solves): block sums of p.q per solve
-template <class T>
-__global__ __launch_bounds__(kT) void sb_dot_pq(const SolveJob<T> *__restrict__ jobs, double *__restrict__ partial) {
-    const SolveJob<T> &J = jobs[blockIdx.y];
+template <class TX, class TP>
+__global__ __launch_bounds__(kT) void sb_dot_pq(const SolveJob<TX, TP> *__restrict__ jobs, double *__restrict__ partial) {
+    const SolveJob<TX, TP> &J = jobs[blockIdx.y];
     if (!J.active) return;
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT)
@@ -94,8 +99,8 @@ __device__ double solve_total(const double *__restrict__ part) {
 // grid (solves), 64 threads: the kGB block sums of a solve in block order; mode 2 (one solve, its
 // start): rr = rrn = sum; mode 3 (one solve): bb = sum, pq = 0, bad = 0.  (The steps add their block
 // sums inside the kernels that use them, solve_total.)
-template <class T>
-__global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ jobs, const double *__restrict__ partial,
+template <class TX, class TP>
+__global__ __launch_bounds__(64) void sb_reduce(const SolveJob<TX, TP> *__restrict__ jobs, const double *__restrict__ partial,
                                                 SolveScal *__restrict__ scal, int mode, int one) {
     const int j = one >= 0 ? one : (int)blockIdx.x;
     if (!jobs[j].active) return;
@@ -106,6 +111,7 @@ __global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ 
         if (mode == 2) {
             s.rr = v;
             s.rrn = v;
+            s.rr0 = v;
         } else {
             s.bb = v;
             s.pq = 0.0;
@@ -117,10 +123,10 @@ __global__ __launch_bounds__(64) void sb_reduce(const SolveJob<T> *__restrict__ 
 // grid (kGB, solves): x += alpha p, r -= alpha q with alpha = rr / pq, where pq adds the block sums
 // of p.q (pq_part) and rr is the previous step's new r.r (rrn); block sums of the new r.r (rr_part).
 // Block 0 records rr and pq for sb_update_p and the host; no other block reads them here.
-template <class T>
-__global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict__ jobs, SolveScal *__restrict__ scal,
+template <class TX, class TP>
+__global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<TX, TP> *__restrict__ jobs, SolveScal *__restrict__ scal,
                                                    const double *__restrict__ pq_part, double *__restrict__ rr_part) {
-    const SolveJob<T> &J = jobs[blockIdx.y];
+    const SolveJob<TX, TP> &J = jobs[blockIdx.y];
     if (!J.active) return;
     SolveScal &s = scal[blockIdx.y];
     const double pq = solve_total(pq_part + blockIdx.y * kGB);
@@ -134,8 +140,8 @@ __global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict
     const double alpha = ok ? rr / pq : 0.0;
     double v = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
-        J.x[i] = (T)((double)J.x[i] + alpha * (double)J.p[i]);
-        const T ri = (T)((double)J.r[i] - alpha * (double)J.q[i]);
+        J.x[i] = (TX)((double)J.x[i] + alpha * (double)J.p[i]);
+        const TX ri = (TX)((double)J.r[i] - alpha * (double)J.q[i]);
         J.r[i] = ri;
         v += (double)ri * (double)ri;
     }
@@ -146,10 +152,10 @@ __global__ __launch_bounds__(kT) void sb_update_xr(const SolveJob<T> *__restrict
 // grid (kGB, solves): p = r + beta p with beta = rrn / rr, where rrn adds the block sums of the new
 // r.r (rr_part); q cleared where the product needs it.  Block 0 records rrn for the next step and
 // the host; no other block reads it here.
-template <class T>
-__global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<T> *__restrict__ jobs, SolveScal *__restrict__ scal,
+template <class TX, class TP>
+__global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<TX, TP> *__restrict__ jobs, SolveScal *__restrict__ scal,
                                                   const double *__restrict__ rr_part) {
-    const SolveJob<T> &J = jobs[blockIdx.y];
+    const SolveJob<TX, TP> &J = jobs[blockIdx.y];
     if (!J.active) return;
     SolveScal &s = scal[blockIdx.y];
     const double rrn = solve_total(rr_part + blockIdx.y * kGB);
@@ -157,8 +163,8 @@ __global__ __launch_bounds__(kT) void sb_update_p(const SolveJob<T> *__restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) s.rrn = rrn;
     const double beta = rr > 0.0 ? rrn / rr : 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < J.n; i += (int64_t)kGB * kT) {
-        J.p[i] = (T)((double)J.r[i] + beta * (double)J.p[i]);
-        if (J.zero_q) J.q[i] = T(0);
+        J.p[i] = (TP)((double)J.r[i] + beta * (double)J.p[i]);
+        if (J.zero_q) J.q[i] = TP(0);
     }
 }
 
@@ -167,12 +173,24 @@ template <class T>
 __global__ __launch_bounds__(kT) void sb_copy(T *__restrict__ dst, const T *__restrict__ src, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) dst[i] = src[i];
 }
-template <class T>
-__global__ __launch_bounds__(kT) void sb_start(T *__restrict__ p, T *__restrict__ q, const T *__restrict__ r,
+template <class TX, class TP>
+__global__ __launch_bounds__(kT) void sb_start(TP *__restrict__ p, TP *__restrict__ q, const TX *__restrict__ r,
                                                int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        p[i] = r[i];
-        q[i] = T(0);
+        p[i] = (TP)r[i];
+        q[i] = TP(0);
+    }
+}
+// a refined solve's residual replacement, second half: t holds the true residual b - A x (FP64
+// matrix); r takes its place, and the direction either restarts (p = t) or keeps its Krylov
+// history with the residual part corrected (p += t - r, so p = t + beta p_old as if the step's p
+// update had used the true residual)
+__global__ __launch_bounds__(kT) void sb_replace(float *__restrict__ p, double *__restrict__ r,
+                                                 const double *__restrict__ t, int64_t n, int restart) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        const double ti = t[i];
+        p[i] = restart ? (float)ti : (float)((double)p[i] + (ti - r[i]));
+        r[i] = ti;
     }
 }
 template <class T>
@@ -251,6 +269,13 @@ struct Req {
     int conv = 0;      // outcome of a finished solve, reported once its x has landed
     double rel = 0.0;
     bool failed = false;
+    int pm = -1;       // the matrix the solve's steps multiply by (matrix_low for a refined solve)
+    // refined solves: the true residual's device vector and the replacement state (as cb_cg_refine)
+    double *t = nullptr;
+    const double *b64 = nullptr;
+    double *x64 = nullptr;
+    double anchor = 0.0, best = 0.0, low = 0.0;
+    int low_it = 0, stalls = 0, repl = 0, restarts = 0;
 };
 
 struct Mat {
@@ -259,13 +284,14 @@ struct Mat {
     int esize;  // vector element bytes
 };
 
-// solve slots and device tables of one vector type
-template <class T>
+// solve slots and device tables of one pair of vector types (solution and residual TX, direction
+// and product TP)
+template <class TX, class TP>
 struct Group {
     int S = 0;
-    std::vector<SolveJob<T>> jobs;  // host copy of the table
-    std::vector<Req *> req;         // slot -> request
-    SolveJob<T> *d_jobs = nullptr;
+    std::vector<SolveJob<TX, TP>> jobs;  // host copy of the table
+    std::vector<Req *> req;              // slot -> request
+    SolveJob<TX, TP> *d_jobs = nullptr;
     SolveScal *d_scal = nullptr;
     double *d_partial = nullptr;
     SolveScal *h_scal = nullptr;  // pinned
@@ -289,8 +315,9 @@ struct cb_server_s {
     void *arena_base = nullptr;
     Arena arena;
     std::vector<Mat> mats;
-    Group<double> g64;
-    Group<float> g32;
+    Group<double, double> g64;
+    Group<float, float> g32;
+    Group<double, float> gmx;  // refined solves: FP64 x and r, float p and q on a FP32/BF16 copy
     hipStream_t cg_stream = nullptr;
     std::vector<hipStream_t> spmm_streams;
     hipEvent_t period_ev = nullptr;
@@ -319,14 +346,15 @@ struct cb_server_s {
 
     void run();
     bool admit_one(Req *q, bool &blocked_by_memory);
-    template <class T>
-    int start_solve(Group<T> &g, Req *q, const Mat &M);
-    template <class T>
-    void retire_solves(Group<T> &g, std::vector<Req *> &done);
-    template <class T>
-    hipError_t build_launches(Group<T> &g);
-    template <class T>
-    hipError_t enqueue_steps(Group<T> &g, int nsteps);
+    template <class TX, class TP>
+    int start_solve(Group<TX, TP> &g, Req *q, const Mat &Mh, const Mat &Ml);
+    template <class TX, class TP>
+    void retire_solves(Group<TX, TP> &g, std::vector<Req *> &done);
+    void retire_refined(std::vector<Req *> &done);
+    template <class TX, class TP>
+    hipError_t build_launches(Group<TX, TP> &g);
+    template <class TX, class TP>
+    hipError_t enqueue_steps(Group<TX, TP> &g, int nsteps);
     hipError_t enqueue_period();
     void complete(Req *q, cb_status_t st, int iters, int conv, double rel);
 };
@@ -342,24 +370,24 @@ cb_status_t hipfail(hipError_t e, const char *what) {
     return fail(CB_ERROR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <class T>
-hipError_t group_alloc(Group<T> &g, int S) {
+template <class TX, class TP>
+hipError_t group_alloc(Group<TX, TP> &g, int S) {
     g.S = S;
-    g.jobs.assign(S, SolveJob<T>{});
+    g.jobs.assign(S, SolveJob<TX, TP>{});
     g.req.assign(S, nullptr);
     hipError_t e;
-    if ((e = hipMalloc(&g.d_jobs, sizeof(SolveJob<T>) * S)) != hipSuccess) return e;
+    if ((e = hipMalloc(&g.d_jobs, sizeof(SolveJob<TX, TP>) * S)) != hipSuccess) return e;
     if ((e = hipMalloc(&g.d_scal, sizeof(SolveScal) * S)) != hipSuccess) return e;
     // two sets of block sums: p.q (written by sb_dot_pq, read by sb_update_xr) and r.r (written by
     // sb_update_xr, read by sb_update_p), so no kernel reads the set it writes
     if ((e = hipMalloc(&g.d_partial, sizeof(double) * kGB * 2 * S)) != hipSuccess) return e;
     if ((e = hipMalloc(&g.d_bjobs, sizeof(cbd::BatchJob) * S)) != hipSuccess) return e;
     if ((e = hipHostMalloc(&g.h_scal, sizeof(SolveScal) * S, hipHostMallocDefault)) != hipSuccess) return e;
-    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<T>) * S, hipMemcpyHostToDevice);
+    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<TX, TP>) * S, hipMemcpyHostToDevice);
 }
 
-template <class T>
-void group_free(Group<T> &g) {
+template <class TX, class TP>
+void group_free(Group<TX, TP> &g) {
     hipFree(g.d_jobs);
     hipFree(g.d_scal);
     hipFree(g.d_partial);
@@ -379,6 +407,8 @@ static size_t footprint(const cb_request_t &r, const Mat &M) {
     const size_t es = (size_t)M.esize;
     if (r.kind == CB_REQ_SPMM)
         return align_up((size_t)M.v.n * r.k * es) + align_up((size_t)M.v.m * r.k * es);
+    if (r.kind == CB_REQ_CG_REFINE)  // b, x, r, t in FP64, p, q in float
+        return 4 * align_up((size_t)M.v.n * sizeof(double)) + 2 * align_up((size_t)M.v.n * sizeof(float));
     return 5 * align_up((size_t)M.v.n * es);  // b, x, r, p, q
 }
 
@@ -392,6 +422,8 @@ void cb_server_s::complete(Req *q, cb_status_t st, int iters, int conv, double r
     rs.rel_residual = rel;
     rs.latency_us = us_between(q->t_submit, now);
     rs.queue_us = us_between(q->t_submit, q->t_admit);
+    rs.replacements = q->repl;
+    rs.restarts = q->restarts;
     {
         std::lock_guard<std::mutex> lk(mu);
         resp[q->ticket] = rs;
@@ -406,9 +438,11 @@ void cb_server_s::complete(Req *q, cb_status_t st, int iters, int conv, double r
     delete q;
 }
 
-// 1: the solve started; 0: no free slot; -1: a HIP call failed (nothing is left in the slot)
-template <class T>
-int cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
+// 1: the solve started; 0: no free slot; -1: a HIP call failed (nothing is left in the slot).
+// Mh: the system's matrix (r = b - Mh x at the start); Ml: the matrix the steps multiply by (Mh
+// itself for plain CG, its FP32/BF16 copy for a refined solve)
+template <class TX, class TP>
+int cb_server_s::start_solve(Group<TX, TP> &g, Req *q, const Mat &Mh, const Mat &Ml) {
     int slot = -1;
     for (int i = 0; i < g.S; ++i)
         if (!g.req[i]) {
@@ -416,29 +450,34 @@ int cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
             break;
         }
     if (slot < 0) return 0;
-    const int64_t n = M.v.n;
-    const size_t vb = align_up((size_t)n * sizeof(T));
+    const int64_t n = Mh.v.n;
+    const size_t vb = align_up((size_t)n * sizeof(TX)), vp = align_up((size_t)n * sizeof(TP));
     uint8_t *base = static_cast<uint8_t *>(arena_base) + q->off;
-    T *b = reinterpret_cast<T *>(base), *x = reinterpret_cast<T *>(base + vb), *r = reinterpret_cast<T *>(base + 2 * vb),
-      *p = reinterpret_cast<T *>(base + 3 * vb), *qq = reinterpret_cast<T *>(base + 4 * vb);
+    TX *b = reinterpret_cast<TX *>(base), *x = reinterpret_cast<TX *>(base + vb), *r = reinterpret_cast<TX *>(base + 2 * vb);
+    TP *p = reinterpret_cast<TP *>(base + 3 * vb), *qq = reinterpret_cast<TP *>(base + 3 * vb + vp);
+    if (q->r.kind == CB_REQ_CG_REFINE) {
+        q->t = reinterpret_cast<double *>(base + 3 * vb + 2 * vp);
+        q->b64 = reinterpret_cast<const double *>(b);
+        q->x64 = reinterpret_cast<double *>(x);
+    }
     hipStream_t s = cg_stream;
     hipError_t e = hipSuccess;
     if (n > 0) {
-        e = hipMemcpyAsync(b, q->r.in, n * sizeof(T), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(x, q->r.out, n * sizeof(T), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(b, q->r.in, n * sizeof(TX), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(x, q->r.out, n * sizeof(TX), hipMemcpyHostToDevice, s);
         const int gb = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(sb_copy<T>, dim3(gb), dim3(kT), 0, s, r, b, n);
+            hipLaunchKernelGGL(sb_copy<TX>, dim3(gb), dim3(kT), 0, s, r, b, n);
             e = hipGetLastError();
         }
-        if (e == hipSuccess && cb_spmv(M.A, -1.0, x, 1.0, r, s) != CB_SUCCESS) e = hipErrorLaunchFailure;  // r = b - A x
+        if (e == hipSuccess && cb_spmv(Mh.A, -1.0, x, 1.0, r, s) != CB_SUCCESS) e = hipErrorLaunchFailure;  // r = b - A x
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(sb_start<T>, dim3(gb), dim3(kT), 0, s, p, qq, r, n);
+            hipLaunchKernelGGL((sb_start<TX, TP>), dim3(gb), dim3(kT), 0, s, p, qq, r, n);
             e = hipGetLastError();
         }
     }
     if (e != hipSuccess) return -1;
-    SolveJob<T> J{};
+    SolveJob<TX, TP> J{};
     J.x = x;
     J.r = r;
     J.p = p;
@@ -446,17 +485,17 @@ int cb_server_s::start_solve(Group<T> &g, Req *q, const Mat &M) {
     J.b = b;
     J.n = n;
     J.active = 1;
-    J.zero_q = M.v.nprepass > 0;
+    J.zero_q = Ml.v.nprepass > 0;
     g.jobs[slot] = J;
     g.req[slot] = q;
     q->slot = slot;
-    e = hipMemcpyAsync(g.d_jobs + slot, &g.jobs[slot], sizeof(SolveJob<T>), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(g.d_jobs + slot, &g.jobs[slot], sizeof(SolveJob<TX, TP>), hipMemcpyHostToDevice, s);
     double *part = g.d_partial + (size_t)slot * kGB;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, r, r, n, part);
-        hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 2, slot);
-        hipLaunchKernelGGL(sb_dot_one<T>, dim3(kGB), dim3(kT), 0, s, b, b, n, part);
-        hipLaunchKernelGGL(sb_reduce<T>, dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 3, slot);
+        hipLaunchKernelGGL(sb_dot_one<TX>, dim3(kGB), dim3(kT), 0, s, r, r, n, part);
+        hipLaunchKernelGGL((sb_reduce<TX, TP>), dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 2, slot);
+        hipLaunchKernelGGL(sb_dot_one<TX>, dim3(kGB), dim3(kT), 0, s, b, b, n, part);
+        hipLaunchKernelGGL((sb_reduce<TX, TP>), dim3(1), dim3(64), 0, s, g.d_jobs, g.d_partial, g.d_scal, 3, slot);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
@@ -477,9 +516,9 @@ bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
     const Mat &M = mats[q->r.matrix];
     if (q->r.kind == CB_REQ_CG) {
         if (period_inflight) return false;
-        Group<double> *gd = M.esize == 8 ? &g64 : nullptr;
-        Group<float> *gf = M.esize == 4 ? &g32 : nullptr;
-        if ((gd && gd->active >= gd->S) || (gf && gf->active >= gf->S)) return false;
+        if ((M.esize == 8 && g64.active >= g64.S) || (M.esize == 4 && g32.active >= g32.S)) return false;
+    } else if (q->r.kind == CB_REQ_CG_REFINE) {
+        if (period_inflight || gmx.active >= gmx.S) return false;
     }
     size_t off = 0;
     const size_t bytes = footprint(q->r, M);
@@ -490,8 +529,10 @@ bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
     q->off = off;
     q->bytes = bytes;
     q->t_admit = Clock::now();
-    if (q->r.kind == CB_REQ_CG) {
-        const int ok = M.esize == 8 ? start_solve(g64, q, M) : start_solve(g32, q, M);
+    if (q->r.kind == CB_REQ_CG || q->r.kind == CB_REQ_CG_REFINE) {
+        const int ok = q->r.kind == CB_REQ_CG_REFINE ? start_solve(gmx, q, M, mats[q->pm])
+                       : M.esize == 8                ? start_solve(g64, q, M, M)
+                                                     : start_solve(g32, q, M, M);
         if (ok == 0) {
             arena.release(off, bytes);
             q->bytes = 0;
@@ -530,8 +571,8 @@ bool cb_server_s::admit_one(Req *q, bool &blocked_by_memory) {
     return true;
 }
 
-template <class T>
-hipError_t cb_server_s::build_launches(Group<T> &g) {
+template <class TX, class TP>
+hipError_t cb_server_s::build_launches(Group<TX, TP> &g) {
     g.launches.clear();
     if (!g.active) return hipSuccess;
     // order the active solves by (kernel value code, tile size, batch format, aggregation, row-sum mode)
@@ -539,7 +580,7 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
     for (int i = 0; i < g.top; ++i)
         if (g.req[i]) order.push_back(i);
     auto key = [&](int i) {
-        const cbh::MatrixView &v = mats[g.req[i]->r.matrix].v;
+        const cbh::MatrixView &v = mats[g.req[i]->pm].v;
         return v.kernel_vt * 64 + (v.view.tile_lt == 3 ? 32 : 0) + (v.view.spmv_kernel == 2 ? 16 : 0) + v.col_agg * 8 +
                v.row_reduce;  // row_reduce < 8
     };
@@ -549,8 +590,8 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
     size_t i = 0;
     while (i < order.size()) {
         const int k0 = key(order[i]);
-        typename Group<T>::Launch L{};
-        const cbh::MatrixView &v0 = mats[g.req[order[i]]->r.matrix].v;
+        typename Group<TX, TP>::Launch L{};
+        const cbh::MatrixView &v0 = mats[g.req[order[i]]->pm].v;
         L.kvt = v0.kernel_vt;
         L.agg = v0.col_agg;
         L.rr = v0.row_reduce;
@@ -560,7 +601,7 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
         L.total = 0;
         for (; i < order.size() && key(order[i]) == k0; ++i) {
             const int slot = order[i];
-            const cbh::MatrixView &v = mats[g.req[slot]->r.matrix].v;
+            const cbh::MatrixView &v = mats[g.req[slot]->pm].v;
             cbd::BatchJob J{};
             J.d = v.view;
             J.x = g.jobs[slot].p;
@@ -589,11 +630,11 @@ hipError_t cb_server_s::build_launches(Group<T> &g) {
         if ((e = hipMemcpy(g.d_wave_job, wave_job.data(), sizeof(int32_t) * wave_job.size(), hipMemcpyHostToDevice)) !=
             hipSuccess)
             return e;
-    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<T>) * g.S, hipMemcpyHostToDevice);
+    return hipMemcpy(g.d_jobs, g.jobs.data(), sizeof(SolveJob<TX, TP>) * g.S, hipMemcpyHostToDevice);
 }
 
-template <class T>
-hipError_t cb_server_s::enqueue_steps(Group<T> &g, int nsteps) {
+template <class TX, class TP>
+hipError_t cb_server_s::enqueue_steps(Group<TX, TP> &g, int nsteps) {
     if (!g.active) return hipSuccess;
     hipStream_t s = cg_stream;
     const dim3 grid(kGB, g.top);
@@ -606,9 +647,9 @@ hipError_t cb_server_s::enqueue_steps(Group<T> &g, int nsteps) {
             wofs += (size_t)L.total;
         }
         double *pq_part = g.d_partial, *rr_part = g.d_partial + (size_t)kGB * g.S;
-        hipLaunchKernelGGL(sb_dot_pq<T>, grid, dim3(kT), 0, s, g.d_jobs, pq_part);
-        hipLaunchKernelGGL(sb_update_xr<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, pq_part, rr_part);
-        hipLaunchKernelGGL(sb_update_p<T>, grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, rr_part);
+        hipLaunchKernelGGL((sb_dot_pq<TX, TP>), grid, dim3(kT), 0, s, g.d_jobs, pq_part);
+        hipLaunchKernelGGL((sb_update_xr<TX, TP>), grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, pq_part, rr_part);
+        hipLaunchKernelGGL((sb_update_p<TX, TP>), grid, dim3(kT), 0, s, g.d_jobs, g.d_scal, rr_part);
     }
     return hipGetLastError();
 }
@@ -618,6 +659,7 @@ hipError_t cb_server_s::enqueue_period() {
     if (dirty) {
         if ((e = build_launches(g64)) != hipSuccess) return e;
         if ((e = build_launches(g32)) != hipSuccess) return e;
+        if ((e = build_launches(gmx)) != hipSuccess) return e;
         if (graph) {
             hipGraphExecDestroy(graph);
             graph = nullptr;
@@ -635,9 +677,11 @@ hipError_t cb_server_s::enqueue_period() {
         if ((e = hipStreamBeginCapture(cg_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
         hipError_t e1 = enqueue_steps(g64, o.check_every);
         hipError_t e2 = enqueue_steps(g32, o.check_every);
+        hipError_t e3 = enqueue_steps(gmx, o.check_every);
         e = hipStreamEndCapture(cg_stream, &gr);
         if (e1 != hipSuccess) return e1;
         if (e2 != hipSuccess) return e2;
+        if (e3 != hipSuccess) return e3;
         if (e != hipSuccess) return e;
         e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
         hipGraphDestroy(gr);
@@ -650,16 +694,19 @@ hipError_t cb_server_s::enqueue_period() {
     } else {
         if ((e = enqueue_steps(g64, o.check_every)) != hipSuccess) return e;
         if ((e = enqueue_steps(g32, o.check_every)) != hipSuccess) return e;
+        if ((e = enqueue_steps(gmx, o.check_every)) != hipSuccess) return e;
     }
     if (g64.active)
         hipMemcpyAsync(g64.h_scal, g64.d_scal, sizeof(SolveScal) * g64.top, hipMemcpyDeviceToHost, cg_stream);
     if (g32.active)
         hipMemcpyAsync(g32.h_scal, g32.d_scal, sizeof(SolveScal) * g32.top, hipMemcpyDeviceToHost, cg_stream);
+    if (gmx.active)
+        hipMemcpyAsync(gmx.h_scal, gmx.d_scal, sizeof(SolveScal) * gmx.top, hipMemcpyDeviceToHost, cg_stream);
     return hipEventRecord(period_ev, cg_stream);
 }
 
-template <class T>
-void cb_server_s::retire_solves(Group<T> &g, std::vector<Req *> &done) {
+template <class TX, class TP>
+void cb_server_s::retire_solves(Group<TX, TP> &g, std::vector<Req *> &done) {
     for (int i = 0; i < g.top; ++i) {
         Req *q = g.req[i];
         if (!q) continue;
@@ -668,7 +715,7 @@ void cb_server_s::retire_solves(Group<T> &g, std::vector<Req *> &done) {
         const bool conv = std::sqrt(s.rrn) <= q->rtol * std::sqrt(s.bb);
         if (conv || s.bad || q->iters >= q->max_iter) {
             // x back to the caller
-            if (hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(T), hipMemcpyDeviceToHost,
+            if (hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(TX), hipMemcpyDeviceToHost,
                                cg_stream) != hipSuccess)
                 q->failed = true;
             q->slot = -1;
@@ -679,6 +726,108 @@ void cb_server_s::retire_solves(Group<T> &g, std::vector<Req *> &done) {
             q->conv = conv ? 1 : 0;
             q->rel = s.bb > 0.0 ? std::sqrt(s.rrn / s.bb) : std::sqrt(s.rrn);
             done.push_back(q);
+        }
+    }
+    while (g.top > 0 && !g.req[g.top - 1]) --g.top;
+}
+
+// End of a period for the refined solves (as cb_cg_refine's residual replacement): a solve whose
+// recurrence residual has fallen by kReplaceFactor since its last replacement, reached the
+// tolerance, made no new low (10 % below the last) for eight checks, or used its iterations has r
+// replaced by the true FP64 residual b - A x; only a true residual ends a solve as converged.  The
+// direction keeps its history unless the replacement came from a stall or the true residual has
+// not halved since the previous one (restart, p = r); three replacements without halving the best
+// true residual end the solve unconverged.  Replacements run between periods, with one wait for
+// their norms.
+constexpr double kReplaceFactor = 1e-2;
+
+void cb_server_s::retire_refined(std::vector<Req *> &done) {
+    Group<double, float> &g = gmx;
+    if (!g.active) return;
+    const int ce = o.check_every;
+    auto finish = [&](int i, int conv, double rel) {
+        Req *q = g.req[i];
+        if (g.jobs[i].n > 0 &&
+            hipMemcpyAsync(q->r.out, g.jobs[i].x, (size_t)g.jobs[i].n * sizeof(double), hipMemcpyDeviceToHost,
+                           cg_stream) != hipSuccess)
+            q->failed = true;
+        q->slot = -1;
+        g.req[i] = nullptr;
+        g.jobs[i].active = 0;
+        --g.active;
+        dirty = true;
+        q->conv = conv;
+        q->rel = rel;
+        done.push_back(q);
+    };
+    std::vector<int> repl;
+    std::vector<char> stalled(g.top, 0);
+    for (int i = 0; i < g.top; ++i) {
+        Req *q = g.req[i];
+        if (!q) continue;
+        q->iters += ce;
+        const SolveScal &s = g.h_scal[i];
+        if (q->anchor < 0.0) q->anchor = q->best = q->low = std::sqrt(s.rr0);
+        const double target = q->rtol * std::sqrt(s.bb), rn = std::sqrt(s.rrn);
+        if (s.bad || !std::isfinite(rn)) {  // not positive definite along a direction, or overflow
+            finish(i, 0, s.bb > 0.0 ? rn / std::sqrt(s.bb) : rn);
+            continue;
+        }
+        if (rn < 0.9 * q->low) {
+            q->low = rn;
+            q->low_it = q->iters;
+        }
+        const bool stall = q->iters - q->low_it >= 8 * ce;
+        if (rn <= target || rn <= kReplaceFactor * q->anchor || stall || q->iters >= q->max_iter) {
+            stalled[i] = rn > target && rn > kReplaceFactor * q->anchor;
+            repl.push_back(i);
+        }
+    }
+    if (!repl.empty()) {
+        // the true residuals t = b - A x with the FP64 matrix, their squares into rr0 (and rr, rrn)
+        hipStream_t st = cg_stream;
+        for (int i : repl) {
+            Req *q = g.req[i];
+            const int64_t n = g.jobs[i].n;
+            if (n > 0) {
+                const int gb = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
+                hipLaunchKernelGGL(sb_copy<double>, dim3(gb), dim3(kT), 0, st, q->t, q->b64, n);
+                if (cb_spmv(mats[q->r.matrix].A, -1.0, q->x64, 1.0, q->t, st) != CB_SUCCESS) q->failed = true;
+            }
+            hipLaunchKernelGGL(sb_dot_one<double>, dim3(kGB), dim3(kT), 0, st, q->t, q->t, n,
+                               g.d_partial + (size_t)i * kGB);
+            hipLaunchKernelGGL((sb_reduce<double, float>), dim3(1), dim3(64), 0, st, g.d_jobs, g.d_partial, g.d_scal, 2,
+                               i);
+        }
+        if (hipMemcpyAsync(g.h_scal, g.d_scal, sizeof(SolveScal) * g.top, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            for (int i : repl) g.req[i]->failed = true;
+        for (int i : repl) {
+            Req *q = g.req[i];
+            const SolveScal &s = g.h_scal[i];
+            const double target = q->rtol * std::sqrt(s.bb), prev = q->anchor;
+            ++q->repl;
+            q->anchor = q->low = std::sqrt(s.rr0);
+            q->low_it = q->iters;
+            const double rel = s.bb > 0.0 ? q->anchor / std::sqrt(s.bb) : q->anchor;
+            if (q->failed || q->anchor <= target || q->iters >= q->max_iter || !std::isfinite(q->anchor)) {
+                finish(i, !q->failed && q->anchor <= target ? 1 : 0, rel);
+                continue;
+            }
+            if (q->anchor < 0.5 * q->best) {
+                q->best = q->anchor;
+                q->stalls = 0;
+            } else if (++q->stalls >= 3) {
+                finish(i, 0, rel);
+                continue;
+            }
+            const int restart = stalled[i] || !(q->anchor < 0.5 * prev) ? 1 : 0;
+            q->restarts += restart;
+            const int64_t n = g.jobs[i].n;
+            if (n > 0) {
+                const int gb = (int)std::min<int64_t>(1024, (n + kT - 1) / kT);
+                hipLaunchKernelGGL(sb_replace, dim3(gb), dim3(kT), 0, st, g.jobs[i].p, g.jobs[i].r, q->t, n, restart);
+            }
         }
     }
     while (g.top > 0 && !g.req[g.top - 1]) --g.top;
@@ -709,6 +858,7 @@ void cb_server_s::run() {
             std::vector<Req *> done;
             retire_solves(g64, done);
             retire_solves(g32, done);
+            retire_refined(done);
             if (!done.empty()) hipStreamSynchronize(cg_stream);
             for (Req *q : done) complete(q, q->failed ? CB_ERROR_HIP : CB_SUCCESS, q->iters, q->conv, q->rel);
             progressed = true;
@@ -732,10 +882,10 @@ void cb_server_s::run() {
                     ++it;
                 }
             }
-            active_peak = std::max(active_peak, g64.active + g32.active);
+            active_peak = std::max(active_peak, g64.active + g32.active + gmx.active);
         }
         // next period of the active solves
-        if (!period_inflight && g64.active + g32.active > 0) {
+        if (!period_inflight && g64.active + g32.active + gmx.active > 0) {
             hipError_t e = enqueue_period();
             if (e != hipSuccess) {
                 // fail every active solve
@@ -744,8 +894,10 @@ void cb_server_s::run() {
                     if (g64.req[i]) all.push_back(g64.req[i]), g64.req[i] = nullptr, g64.jobs[i].active = 0;
                 for (int i = 0; i < g32.top; ++i)
                     if (g32.req[i]) all.push_back(g32.req[i]), g32.req[i] = nullptr, g32.jobs[i].active = 0;
+                for (int i = 0; i < gmx.top; ++i)
+                    if (gmx.req[i]) all.push_back(gmx.req[i]), gmx.req[i] = nullptr, gmx.jobs[i].active = 0;
                 hipStreamSynchronize(cg_stream);
-                g64.active = g32.active = g64.top = g32.top = 0;
+                g64.active = g32.active = gmx.active = g64.top = g32.top = gmx.top = 0;
                 for (Req *q : all) complete(q, CB_ERROR_HIP, q->iters, 0, 0.0);
                 dirty = true;
                 hipGetLastError();
@@ -756,7 +908,7 @@ void cb_server_s::run() {
         }
         std::unique_lock<std::mutex> lk(mu);
         const bool busy = period_inflight || !spmm_inflight.empty();
-        if (stop && pending.empty() && !busy && g64.active + g32.active == 0) break;
+        if (stop && pending.empty() && !busy && g64.active + g32.active + gmx.active == 0) break;
         if (!progressed) {
             if (busy || !pending.empty())
                 cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -803,6 +955,7 @@ cb_status_t cb_server_create(const cb_server_options_t *opt, cb_server_t *out) {
     }
     if (e == hipSuccess) e = group_alloc(S->g64, o.max_active);
     if (e == hipSuccess) e = group_alloc(S->g32, o.max_active);
+    if (e == hipSuccess) e = group_alloc(S->gmx, o.max_active);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cg_stream, hipStreamNonBlocking);
     for (int i = 0; e == hipSuccess && i < o.spmm_streams; ++i) {
         hipStream_t s;
@@ -843,17 +996,28 @@ cb_status_t cb_server_submit(cb_server_t S, const cb_request_t *req, int64_t *ti
     std::unique_lock<std::mutex> lk(S->mu);
     if (req->matrix < 0 || req->matrix >= (int32_t)S->mats.size()) return fail(CB_ERROR_INVALID_VALUE, "unknown matrix");
     const Mat &M = S->mats[req->matrix];
-    if (req->kind != CB_REQ_SPMM && req->kind != CB_REQ_CG) return fail(CB_ERROR_INVALID_VALUE, "unknown request kind");
+    if (req->kind != CB_REQ_SPMM && req->kind != CB_REQ_CG && req->kind != CB_REQ_CG_REFINE)
+        return fail(CB_ERROR_INVALID_VALUE, "unknown request kind");
+    const bool solve = req->kind != CB_REQ_SPMM;
     if (req->kind == CB_REQ_SPMM && req->k < 1) return fail(CB_ERROR_INVALID_VALUE, "k must be at least 1");
-    if (req->kind == CB_REQ_CG && M.v.m != M.v.n) return fail(CB_ERROR_INVALID_VALUE, "CG needs a square matrix");
-    if (req->kind == CB_REQ_CG && (req->rtol < 0.0 || req->max_iter < 0))
-        return fail(CB_ERROR_INVALID_VALUE, "invalid CG parameters");
-    const bool need_in = M.v.n > 0, need_out = req->kind == CB_REQ_CG ? M.v.n > 0 : M.v.m > 0;
+    if (solve && M.v.m != M.v.n) return fail(CB_ERROR_INVALID_VALUE, "CG needs a square matrix");
+    if (solve && (req->rtol < 0.0 || req->max_iter < 0)) return fail(CB_ERROR_INVALID_VALUE, "invalid CG parameters");
+    if (req->kind == CB_REQ_CG_REFINE) {
+        if (M.v.vtype != CB_VALUE_F64) return fail(CB_ERROR_INVALID_VALUE, "a refined solve's matrix must store FP64 values");
+        if (req->matrix_low < 0 || req->matrix_low >= (int32_t)S->mats.size())
+            return fail(CB_ERROR_INVALID_VALUE, "unknown matrix_low");
+        const Mat &L = S->mats[req->matrix_low];
+        if ((L.v.vtype != CB_VALUE_F32 && L.v.vtype != CB_VALUE_BF16) || L.v.vector_f64)
+            return fail(CB_ERROR_INVALID_VALUE, "matrix_low must store FP32 or BF16 values with float vectors");
+        if (L.v.m != M.v.m || L.v.n != M.v.n) return fail(CB_ERROR_INVALID_VALUE, "matrix_low has another shape");
+    }
+    const bool need_in = M.v.n > 0, need_out = solve ? M.v.n > 0 : M.v.m > 0;
     if ((need_in && !req->in) || (need_out && !req->out)) return fail(CB_ERROR_INVALID_VALUE, "NULL vector");
     Req *q = new (std::nothrow) Req();
     if (!q) return fail(CB_ERROR_OUT_OF_MEMORY, "request");
     q->r = *req;
-    if (req->kind == CB_REQ_SPMM) q->r.k = req->k;
+    q->pm = req->kind == CB_REQ_CG_REFINE ? req->matrix_low : req->matrix;
+    q->anchor = -1.0;  // set from the first period's scalars
     q->rtol = req->rtol > 0.0 ? req->rtol : 1e-10;
     const int cap = req->max_iter > 0 ? req->max_iter : 500;
     q->max_iter = ((cap + S->o.check_every - 1) / S->o.check_every) * S->o.check_every;
@@ -950,6 +1114,7 @@ cb_status_t cb_server_destroy(cb_server_t S) {
     if (S->cg_stream) hipStreamDestroy(S->cg_stream);
     group_free(S->g64);
     group_free(S->g32);
+    group_free(S->gmx);
     if (S->arena_base) hipFree(S->arena_base);
     delete S;
     return CB_SUCCESS;

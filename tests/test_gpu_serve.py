@@ -269,3 +269,97 @@ def test_many_requests_submitted_while_the_worker_admits(cb):
         assert S.stats()["completed"] == 400
     MA.close()
     MP.close()
+
+
+def run_refined(cb, specs, mix=False, **opts):
+    """Refined solves (CB_REQ_CG_REFINE): specs of (A, low value type, seed of b); each request
+    multiplies by the FP32/BF16 copy and replaces its residual with the FP64 matrix's.  With mix,
+    plain FP64 and FP32 solves of the same matrices and SpMM requests run beside them.  Returns
+    [(x, response)] of the refined requests in submission order."""
+    mats, out = [], []
+    with cb.CbServer(**opts) as S:
+        tickets, extra = [], []
+        for i, (A, low, seed) in enumerate(specs):
+            Mh, Ml = cb.CbMatrix.from_csr(A), cb.CbMatrix.from_csr(A, value_type=low)
+            mats += [Mh, Ml]
+            h, lo = S.add_matrix(Mh), S.add_matrix(Ml)
+            b = matgen.vector(A.n, seed)
+            x = np.zeros(A.n)
+            tickets.append((x, S.submit_cg_refine(h, lo, b, x, rtol=1e-10, max_iter=3000)))
+            if mix:
+                b2, x2 = matgen.vector(A.n, seed + 1), np.zeros(A.n)
+                extra.append(S.submit_cg(h, b2, x2, rtol=1e-9))
+                b3, x3 = matgen.vector(A.n, seed + 2).astype(np.float32), np.zeros(A.n, np.float32)
+                extra.append(S.submit_cg(lo, b3, x3, rtol=1e-5))
+                X, Y = np.random.default_rng(seed).uniform(-1, 1, (A.n, 3)), np.zeros((A.m, 3))
+                extra.append(S.submit_spmm(h, X, Y))
+        for x, t in tickets:
+            out.append((x, S.wait(t)))
+        for t in extra:
+            assert S.wait(t)["status"] == cb.CB_SUCCESS
+        stats = S.stats()
+    for M in mats:
+        M.close()
+    return out, stats
+
+
+def test_refined_solves_reach_the_true_residual_alone_and_in_a_mix(cb):
+    """CB_REQ_CG_REFINE: FP32/BF16 products, FP64 residual replacement; every solve ends with a
+    true residual <= 1e-10 (checked by the oracle on the FP64 matrix), and a solve's result is the
+    same served alone and among other solves and SpMM requests."""
+    spd = spd_matrices()
+    # BF16 copies only of the operators whose values BF16 holds exactly (the scaled Poisson's are
+    # rounded, and BF16 products then stall the replacement scheme)
+    specs = [(A, low, 90 + 4 * i + j) for i, A in enumerate(spd) for j, low in enumerate(("f32", "bf16"))
+             if low == "f32" or i < len(spd) - 1]
+    alone = [run_refined(cb, [s])[0][0] for s in specs]
+    mixed, stats = run_refined(cb, specs, mix=True, max_active=6)
+    assert stats["active_peak"] > 1
+    for (A, low, seed), (xa, ra), (xm, rm) in zip(specs, alone, mixed):
+        b = matgen.vector(A.n, seed)
+        for x, r in ((xa, ra), (xm, rm)):
+            assert r["status"] == cb.CB_SUCCESS and r["converged"], (A.name, low, r)
+            assert r["replacements"] >= 1 and r["rel_residual"] <= 1e-10
+            assert solvers.residual(A, b, x) <= 1.5e-10, (A.name, low, solvers.residual(A, b, x))
+        shared = cb.CbMatrix.from_csr(A, device=False, value_type=low).info["shared_panels"] + \
+            cb.CbMatrix.from_csr(A, device=False).info["shared_panels"]
+        if shared == 0:
+            assert ra["iterations"] == rm["iterations"] and ra["replacements"] == rm["replacements"]
+            assert np.array_equal(xa, xm), (A.name, low, np.abs(xa - xm).max())
+
+
+def test_refined_solve_matches_cb_cg_refine_iterations(cb):
+    """The served refined solve takes about the iterations of the one-matrix cb_cg_refine
+    (CB_REFINE_REPLACE) on the same system: the same method, checked at the same period."""
+    A = matgen.poisson_3d(14)
+    b = matgen.vector(A.n, 5)
+    [(x, r)], _ = run_refined(cb, [(A, "bf16", 5)], check_every=8)
+    Mh, Ml = cb.CbMatrix.from_csr(A), cb.CbMatrix.from_csr(A, value_type="bf16")
+    xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    res = Mh.cg_refine(Ml, torch.from_numpy(b).to("cuda"), xd, rtol=1e-10, max_iter=3000, check_every=8)
+    Mh.close()
+    Ml.close()
+    assert res["converged"] and r["converged"]
+    assert abs(res["iterations"] - r["iterations"]) <= 3 * 8, (res, r)
+    assert solvers.residual(A, b, x) <= 1.5e-10
+
+
+def test_refined_request_errors(cb):
+    A = matgen.laplacian_2d(12)
+    B = matgen.laplacian_2d(13)
+    Mh, Ml, M32w, Mb = (cb.CbMatrix.from_csr(A), cb.CbMatrix.from_csr(A, value_type="bf16"),
+                        cb.CbMatrix.from_csr(A, value_type="f32", vector_f64=1),
+                        cb.CbMatrix.from_csr(B, value_type="f32"))
+    with cb.CbServer() as S:
+        h, lo, w, other = (S.add_matrix(M) for M in (Mh, Ml, M32w, Mb))
+        b, x = np.ones(A.n), np.zeros(A.n)
+        for hi, low in ((lo, lo), (h, h), (h, w), (h, other), (h, 99)):
+            with pytest.raises(cb.CbError) as e:
+                S.submit_cg_refine(hi, low, b, x)
+            assert e.value.status == cb.CB_ERROR_INVALID_VALUE
+        with pytest.raises(ValueError):
+            S.submit_cg_refine(h, lo, b.astype(np.float32), x)  # b and x are double
+        t = S.submit_cg_refine(h, lo, b, x)
+        assert S.wait(t)["converged"]
+    for M in (Mh, Ml, M32w, Mb):
+        M.close()
