@@ -116,6 +116,9 @@ def kernel_name(info: dict, lb: str) -> str:
     arguments spelled out."""
     if lb == "paper":
         return "spmv_kernel<FP64> (Algorithm 2 order)"
+    if lb == "paper_stream":
+        agg = "aggregated" if info["col_agg"] else "plain columns"
+        return f"spmv_quad_kernel<FP64, {agg}, row sums {info['row_reduce']}, scatter> (Algorithm 2 order, streamed)"
     agg = "aggregated" if info["col_agg"] else "plain columns"
     if info["spmv_kernel"] == 1:
         return f"spmv_rows_kernel<FP64, {agg}>"
@@ -667,7 +670,7 @@ def main() -> int:
                     help="matrix: block3d (default, 100^3 x 3 dof), powerlaw (n = 4M, Zipf 2.1 rows, mean 16), "
                          "powerlaw_literal (the same rows unscaled, mean 4.8), "
                          "poisson (7-point, 192^3), laplacian (5-point, 64 x 64)")
-    ap.add_argument("--lb", default="contiguous", choices=["contiguous", "paper", "none"])
+    ap.add_argument("--lb", default="contiguous", choices=["contiguous", "paper", "none", "paper_stream"])
     ap.add_argument("--col-agg", type=int, default=-1)
     ap.add_argument("--wave-nnz", type=int, default=0)
     ap.add_argument("--spmv-kernel", type=int, default=-1,

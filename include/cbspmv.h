@@ -78,8 +78,15 @@ typedef enum { CB_FMT_COO = 0, CB_FMT_CSR = 1, CB_FMT_DENSE = 2 } cb_format_t;
  *   CB_LB_CONTIGUOUS: natural order cut into ranges of about wave_nnz
  *                     non-zeros at panel boundaries; only panels heavier than
  *                     twice that are split.  The default: a panel inside one
- *                     range is written to y once, with no atomics. */
-typedef enum { CB_LB_NONE = 0, CB_LB_PAPER = 1, CB_LB_CONTIGUOUS = 2 } cb_lb_t;
+ *                     range is written to y once, with no atomics.
+ *   CB_LB_PAPER_STREAM: Algorithm 2's groups as CB_LB_PAPER, with the packed
+ *                     tiles re-laid in group order so that a wavefront streams
+ *                     runs of consecutive groups (about wave_nnz non-zeros) as
+ *                     one contiguous byte range; every tile's rows are added
+ *                     into y with atomics after a y <- beta*y pre-pass (the
+ *                     quad kernel in scatter form).  16 x 16 tiles only; SpMM
+ *                     runs the tile-at-a-time kernel of Algorithm 2's order. */
+typedef enum { CB_LB_NONE = 0, CB_LB_PAPER = 1, CB_LB_CONTIGUOUS = 2, CB_LB_PAPER_STREAM = 3 } cb_lb_t;
 
 typedef struct {
     uint32_t struct_size;   /* sizeof(cb_options_t): set by cb_options_default */

@@ -37,10 +37,11 @@ CB_SUCCESS, CB_ERROR_INVALID_VALUE, CB_ERROR_OUT_OF_MEMORY, CB_ERROR_HIP, CB_ERR
     CB_ERROR_INTERNAL = range(6)
 CB_VALUE_F64, CB_VALUE_F32, CB_VALUE_BF16 = range(3)
 CB_FMT_COO, CB_FMT_CSR, CB_FMT_DENSE = range(3)
-CB_LB_NONE, CB_LB_PAPER, CB_LB_CONTIGUOUS = range(3)
+CB_LB_NONE, CB_LB_PAPER, CB_LB_CONTIGUOUS, CB_LB_PAPER_STREAM = range(4)
 CB_REFINE_RESTART, CB_REFINE_REPLACE = range(2)
 VALUE_TYPES = {"f64": CB_VALUE_F64, "f32": CB_VALUE_F32, "bf16": CB_VALUE_BF16}
-LB_MODES = {"none": CB_LB_NONE, "paper": CB_LB_PAPER, "contiguous": CB_LB_CONTIGUOUS}
+LB_MODES = {"none": CB_LB_NONE, "paper": CB_LB_PAPER, "contiguous": CB_LB_CONTIGUOUS,
+            "paper_stream": CB_LB_PAPER_STREAM}
 
 _i32, _i64, _u32, _dbl, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
 

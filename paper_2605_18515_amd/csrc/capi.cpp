@@ -66,12 +66,12 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.panel_shared = put((size_t)s.npanels);
     L.prepass_list = put(4 * (size_t)s.nprepass);
     // the streaming kernel reads 17 records from the start of every batch
-    const bool stream = s.lb_mode != CB_LB_PAPER;
+    const bool stream = cbh::streamed_lb(s.lb_mode), natural = cbh::natural_lb(s.lb_mode);
     L.batch_stream = put(stream ? 16 * ((size_t)s.nrecords + cbs::kStreamRecordPad) : 0);
     L.batch_ptr = put(stream ? 4 * ((size_t)s.nwaves + 1) : 0);
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)s.blk * NT : 0);
-    L.tile_rec = put(stream ? 16 * NT : 0);
-    L.panel_tile = put(stream ? 4 * ((size_t)s.npanels + 1) : 0);
+    L.tile_rec = put(natural ? 16 * NT : 0);
+    L.panel_tile = put(natural ? 4 * ((size_t)s.npanels + 1) : 0);
     L.total = off;
     return L;
 }
@@ -172,7 +172,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "structure upload");
     }
-    const bool natural = s.lb_mode != CB_LB_PAPER;
+    const bool streamed = cbh::streamed_lb(s.lb_mode);
     cbd::DevView &v = A->view;
     v.tile_row = dptr<int32_t>(A, L.tile_row);
     v.tile_col = dptr<int32_t>(A, L.tile_col);
@@ -197,12 +197,13 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.npanels = (int32_t)s.npanels;
     v.nprepass = (int32_t)s.nprepass;
     v.col_agg = s.col_agg;
-    v.natural_order = s.lb_mode != CB_LB_PAPER ? 1 : 0;
+    v.natural_order = cbh::natural_lb(s.lb_mode) ? 1 : 0;
+    v.scatter = s.lb_mode == CB_LB_PAPER_STREAM ? 1 : 0;
     v.row_reduce = s.row_reduce;
     v.spmv_kernel = s.spmv_kernel;
     v.tile_lt = s.lt;
     v.payload_alloc = (int64_t)s.payload_bytes + cbs::kPayloadPad;
-    v.stream_alloc = natural ? 16 * ((int64_t)s.nrecords + cbs::kStreamRecordPad) : 0;
+    v.stream_alloc = streamed ? 16 * ((int64_t)s.nrecords + cbs::kStreamRecordPad) : 0;
     // the device copy is the structure from now on
     std::vector<int32_t>().swap(s.tile_row);
     std::vector<int32_t>().swap(s.tile_col);
@@ -262,10 +263,10 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.panel_shared, (size_t)A->h.npanels, tmp.panel_shared)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.prepass_list, (size_t)A->h.nprepass, tmp.prepass_list)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.batch_stream, 4 * (size_t)A->h.nrecords, tmp.batch_stream)) != CB_SUCCESS) return st;
-    if ((st = fetch(A, L.batch_ptr, A->h.lb_mode != CB_LB_PAPER ? (size_t)A->h.nwaves + 1 : 0, tmp.batch_ptr)) !=
+    if ((st = fetch(A, L.batch_ptr, cbh::streamed_lb(A->h.lb_mode) ? (size_t)A->h.nwaves + 1 : 0, tmp.batch_ptr)) !=
         CB_SUCCESS)
         return st;
-    if ((st = fetch(A, L.tile_cols, A->h.lb_mode != CB_LB_PAPER && A->h.col_agg ? (size_t)A->h.blk * NT : 0,
+    if ((st = fetch(A, L.tile_cols, cbh::streamed_lb(A->h.lb_mode) && A->h.col_agg ? (size_t)A->h.blk * NT : 0,
                     tmp.tile_cols)) != CB_SUCCESS)
         return st;
     s = &tmp;
@@ -456,7 +457,7 @@ cb_status_t matrix_view(cb_matrix_t A, MatrixView &out) {
     out.vector_f64 = A->h.vector_f64;
     out.col_agg = A->h.col_agg;
     out.row_reduce = A->h.row_reduce;
-    out.natural = A->h.lb_mode != CB_LB_PAPER;
+    out.natural = cbh::natural_lb(A->h.lb_mode);
     out.device = A->device;
     out.m = A->h.m;
     out.n = A->h.n;

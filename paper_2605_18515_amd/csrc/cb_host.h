@@ -17,6 +17,12 @@ constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte bound
 constexpr int dense_mask_bytes(int blk) { return blk * blk / 8; }
 constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
 
+// load-balance modes whose wavefront ranges are contiguous byte ranges of the payload, cut into
+// batches (all but Algorithm 2's tile-at-a-time form), and those whose kernel order is the natural
+// (panel, column) order
+inline bool streamed_lb(int lb) { return lb != CB_LB_PAPER; }
+inline bool natural_lb(int lb) { return lb == CB_LB_NONE || lb == CB_LB_CONTIGUOUS; }
+
 struct HostStructure {
     int64_t m = 0, n = 0, nnz = 0;
     int vtype = CB_VALUE_F64;

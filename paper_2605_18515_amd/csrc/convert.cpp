@@ -182,6 +182,8 @@ void moments(const std::vector<int64_t> &v, int64_t &mx, double &mean, double &s
     sd = std::sqrt((double)(s2 / v.size()));
 }
 
+void build_tile_cols(HostStructure &s);
+
 // Batches of the streaming kernel (format in cb_stream.h): every work range
 // is cut, in order, into runs of at most kBatchTiles tiles whose payload bytes
 // touch at most kRingChunks chunks of kChunk bytes and whose panels lie within
@@ -274,6 +276,12 @@ void build_stream(HostStructure &s) {
         s.tile_rec[(size_t)(4 * t + 2)] = s.tile_row[t];
         s.tile_rec[(size_t)(4 * t + 3)] = s.tile_col[t];
     }
+    build_tile_cols(s);
+}
+
+// Under aggregation, every tile's S original columns in kernel order (tile_cols, cb_stream.h).
+void build_tile_cols(HostStructure &s) {
+    const int S = s.blk;
     s.tile_cols.clear();
     if (s.col_agg) {
         s.tile_cols.resize((size_t)s.ntiles * S);
@@ -290,8 +298,9 @@ void build_stream(HostStructure &s) {
 }
 
 // Quad batches of the quad kernel (format in cb_stream.h), written to batch_stream / batch_ptr in
-// place of build_stream's batches.
-void build_qstream(HostStructure &s) {
+// place of build_stream's batches; scatter: the batches' tiles may come from any panels (Algorithm
+// 2's order), each record carries its tile's panel.
+void build_qstream(HostStructure &s, bool scatter) {
     using namespace cbs;
     const int vs = s.vsize, S = s.blk;
     const int64_t NW = s.nwaves;
@@ -316,29 +325,37 @@ void build_qstream(HostStructure &s) {
         int64_t b = t0;
         while (b < t1) {
             int64_t e = b + 1, qtot = quads(b);
-            while (e < t1 && e - b < kQTiles && s.tile_row[e] - s.tile_row[b] < kBatchPanels &&
+            while (e < t1 && e - b < kQTiles && (scatter || s.tile_row[e] - s.tile_row[b] < kBatchPanels) &&
                    qtot + quads(e) <= (int64_t)kQPasses * 64) {
                 qtot += quads(e);
                 ++e;
             }
-            const int32_t pb = s.tile_row[b];
+            const int32_t pb = scatter ? 0 : s.tile_row[b];
             uint32_t done = 0;
-            for (int64_t t = b; t < e; ++t) done |= 1u << (s.tile_row[t] - pb);
-            if (e < t1 && s.tile_row[e] == s.tile_row[e - 1]) done &= ~(1u << (s.tile_row[e - 1] - pb));
+            if (!scatter) {
+                for (int64_t t = b; t < e; ++t) done |= 1u << (s.tile_row[t] - pb);
+                if (e < t1 && s.tile_row[e] == s.tile_row[e - 1]) done &= ~(1u << (s.tile_row[e - 1] - pb));
+            }
             const int64_t np = (qtot + 63) / 64;
             push(pb, (int32_t)((e - b) | (np << 8) | (done << 16)), (int32_t)qtot, 0);
             int64_t qs = 0;
             for (int64_t t = b; t < e; ++t) {
                 const int fmt = s.tile_type[t];
                 const int64_t rel = s.tile_vp[t] - B0, nz = s.tile_nnz[t];
-                const uint32_t meta = (uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) | ((uint32_t)qs << 2) |
-                                      ((fmt == CB_FMT_DENSE ? 1u : 0u) << 15);
+                const uint32_t dense = fmt == CB_FMT_DENSE ? 1u : 0u;
+                const int64_t lim = fmt == CB_FMT_DENSE ? 0 : 4 * qs + nz;
+                // scatter: {.., .., panel, position in batch | qs << 5 | dense << 15 | lim << 16}
+                const uint32_t meta = scatter ? (uint32_t)(t - b) | ((uint32_t)qs << 5) | (dense << 15) |
+                                                    ((uint32_t)lim << 16)
+                                              : (uint32_t)(s.tile_row[t] & (kBatchPanels - 1)) | ((uint32_t)qs << 2) |
+                                                    (dense << 15);
+                const int32_t third = scatter ? s.tile_row[t] : (int32_t)lim;
                 if (fmt == CB_FMT_DENSE) {
-                    push((int32_t)(rel + (int64_t)S * S * vs), (int32_t)(rel - 4 * vs * qs), 0, (int32_t)meta);
+                    push((int32_t)(rel + (int64_t)S * S * vs), (int32_t)(rel - 4 * vs * qs), third, (int32_t)meta);
                 } else {
                     const int64_t hb = fmt == CB_FMT_CSR ? S : 0;
                     const int64_t crel = rel + hb, vrel = rel + hb + nz + padding(hb + nz, vs);
-                    push((int32_t)(crel - 4 * qs), (int32_t)(vrel - 4 * vs * qs), (int32_t)(4 * qs + nz), (int32_t)meta);
+                    push((int32_t)(crel - 4 * qs), (int32_t)(vrel - 4 * vs * qs), third, (int32_t)meta);
                 }
                 qs += quads(t);
             }
@@ -410,12 +427,16 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.col_agg < -1 || opt.col_agg > 1) { err = "col_agg must be -1, 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.th1 < 0 || opt.th2 < 0) { err = "th1 and th2 must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.quantum_tiles < 1 || opt.quantum_tiles > (1 << 20)) { err = "quantum_tiles out of range"; return CB_ERROR_INVALID_VALUE; }
-    if (opt.lb_mode < 0 || opt.lb_mode > 2) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.lb_mode < 0 || opt.lb_mode > 3) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.row_reduce < -1 || opt.row_reduce > 4) { err = "row_reduce must be -1 .. 4"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
     if (opt.tile_dim != 0 && opt.tile_dim != 8 && opt.tile_dim != 16) { err = "tile_dim must be 0, 8 or 16"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.lb_mode == CB_LB_PAPER_STREAM && (opt.tile_dim == 8 || (opt.spmv_kernel >= 0 && opt.spmv_kernel != 2))) {
+        err = "the streamed Algorithm 2 order runs the quad kernel on 16 x 16 tiles";
+        return CB_ERROR_NOT_SUPPORTED;
+    }
     if (opt.tile_dim == 8 && opt.spmv_kernel == 1) {
         err = "the rows-per-lane kernel (spmv_kernel 1) takes 16 x 16 tiles only";
         return CB_ERROR_NOT_SUPPORTED;
@@ -546,10 +567,11 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // and their rows hold runs of entries (3D block matrix: FP64 147 against 153 us, BF16 77 against
         // 105), the streaming kernel where tiles are sparse or rows come one entry per tile row
         // (stencils, power-law rows), whose quads are part empty and sum no runs
-        if (opt.spmv_kernel < 0 && s.lb_mode != CB_LB_PAPER) {
+        if (opt.spmv_kernel < 0 && natural_lb(s.lb_mode)) {
             const bool long_runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
             s.spmv_kernel = long_runs && nnz >= 32 * NT ? 2 : 0;
         }
+        if (s.lb_mode == CB_LB_PAPER_STREAM) s.spmv_kernel = 2;  // the quad kernel's scatter form
         if (opt.row_reduce >= 0) {
             s.row_reduce = opt.row_reduce;
             // the quad kernel sums each lane's row runs in registers instead of a segmented scan
@@ -629,7 +651,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         const int W = opt.quantum_tiles;
         std::vector<int32_t> order(NT);
         std::vector<int32_t> qptr;
-        if (opt.lb_mode == CB_LB_PAPER) {
+        if (opt.lb_mode == CB_LB_PAPER || opt.lb_mode == CB_LB_PAPER_STREAM) {
             // Algorithm 2: descending nnz (stable), min-heap of (load, tb_id), W slots per block
             std::vector<int32_t> byn(NT);
             std::iota(byn.begin(), byn.end(), 0);
@@ -740,6 +762,18 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         }
         s.quantum_ptr = qptr;
         s.wave_ptr = wptr;
+        if (opt.lb_mode == CB_LB_PAPER_STREAM) {
+            // the packed tiles re-laid in kernel (group) order: a work range is one byte range
+            std::vector<uint8_t> repacked(s.payload.size());
+            int64_t at = 0;
+            for (int64_t i = 0; i < NT; ++i) {
+                const int64_t rb = region_bytes(s.tile_type[i], s.tile_nnz[i], s.vsize, S);
+                std::memcpy(repacked.data() + at, s.payload.data() + s.tile_vp[i], (size_t)rb);
+                s.tile_vp[i] = at;
+                at += rb;
+            }
+            s.payload.swap(repacked);
+        }
 
         // a panel is owned when its tiles form one run inside one work range;
         // otherwise it is shared (atomics after a y <- beta*y pre-pass); empty
@@ -751,8 +785,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                 if (i == wptr[w] || s.tile_row[i] != s.tile_row[i - 1]) runs[s.tile_row[i]] += 1;
         s.panel_shared.assign(P, 0);
         for (int64_t p = 0; p < P; ++p) {
-            if (runs[p] > 1) { s.panel_shared[p] = 1; s.nshared += 1; }
-            if (runs[p] != 1) s.prepass_list.push_back((int32_t)p);
+            // the scatter form adds every tile's rows with atomics: every panel is shared
+            const bool scatter = opt.lb_mode == CB_LB_PAPER_STREAM;
+            if (runs[p] > 1 || (scatter && runs[p] > 0)) { s.panel_shared[p] = 1; s.nshared += 1; }
+            if (runs[p] != 1 || scatter) s.prepass_list.push_back((int32_t)p);
         }
 
         // ---- statistics -------------------------------------------------------
@@ -774,7 +810,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         s.nquanta = (int64_t)qptr.size() - 1;
         s.nwaves = NW;
         s.nprepass = (int64_t)s.prepass_list.size();
-        if (opt.lb_mode != CB_LB_PAPER) {
+        if (streamed_lb(opt.lb_mode)) {
             // the records' 32-bit fields bound what one range and the whole stream may hold
             if (NT + (int64_t)NW + 1 > (int64_t)INT32_MAX / 2) {
                 err = "too many tiles for the streaming kernel's batch records";
@@ -796,8 +832,13 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                     return CB_ERROR_INVALID_VALUE;
                 }
             }
-            build_stream(s);
-            if (s.spmv_kernel == 2) build_qstream(s);
+            if (opt.lb_mode == CB_LB_PAPER_STREAM) {
+                build_tile_cols(s);
+                build_qstream(s, true);
+            } else {
+                build_stream(s);
+                if (s.spmv_kernel == 2) build_qstream(s, false);
+            }
         }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed during conversion";
@@ -892,6 +933,8 @@ int64_t spmv_bytes(const HostStructure &s) {
         b += 16 * s.nrecords;
         b += s.col_agg ? 4 * (int64_t)s.blk * s.ntiles : 4 * s.ntiles;
         b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
+        // scatter form: the pre-pass writes y, the atomics read and write it again
+        if (s.lb_mode == CB_LB_PAPER_STREAM) b += 2 * xe * s.m;
     }
     return b;
 }

@@ -786,11 +786,15 @@ __device__ __forceinline__ typename Val<VT>::A quad_value(const uint32_t *w, int
     }
 }
 
-template <int VT, bool AGG, int RR, int LT>
+// SC: the scatter form (Algorithm 2's groups streamed): a batch's tiles come from any panels, each
+// tile has accumulators of its own (slot = its position in the batch), and after the batch every
+// tile's non-zero row sums are added into y with atomics (y was scaled by beta in a pre-pass).
+template <int VT, bool AGG, int RR, int LT, bool SC = false>
 __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename Val<VT>::A alpha,
                                               typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                               typename Val<VT>::A *__restrict__ y) {
     static_assert(kWavesPerBlock == 1, "one work range per workgroup");
+    static_assert(!SC || LT == 4, "the scatter form takes 16 x 16 tiles");
     static_assert(RR != 1, "the quad kernel sums a lane's row runs itself");
     static_assert(LT == 3 || LT == 4, "16 x 16 or 8 x 8 tiles");
     constexpr int S = 1 << LT;      // rows of a panel, columns of a tile
@@ -804,9 +808,13 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     constexpr int QT = cbs::kQTiles, QP = cbs::kQPasses;
     constexpr int NG = (QT + TPG - 1) / TPG;
     static_assert(QT % 4 == 0 && QT <= 32 && QT + 1 <= kWave, "x gathers take four tiles; records fit one load");
+    constexpr int NSLOT = SC ? QT : kMaxPanels;  // accumulator slots of 16 rows
     __shared__ __align__(16) A xarea[NG * kWave];
-    __shared__ __align__(16) AC acc[kMaxPanels * 16 * NACC];
+    __shared__ __align__(16) AC acc[NSLOT * 16 * NACC];
     __shared__ __align__(16) i32x4 rtab[2][QT];
+    // record word fields: the tile's first quad, and (COO/CSR) the end of its entries
+    auto rec_qs = [](const i32x4 &r) { return SC ? (r.w >> 5) & 0x3FF : (r.w >> 2) & 0x3FF; };
+    auto rec_lim = [](const i32x4 &r) { return SC ? (r.w >> 16) & 0x1FFF : r.z; };
     __shared__ __align__(16) uint32_t marks[2][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     if (w >= d.nwaves) return;
@@ -842,7 +850,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         marks[par][lane] = 0u;
         if (lane < h.nt) {
             rtab[par][lane] = Q;
-            const int qs = (Q.w >> 2) & 0x3FF;
+            const int qs = rec_qs(Q);
             reinterpret_cast<uint8_t *>(marks[par])[4 * (qs & 63) + ((qs >> 6) & 3)] = 1;
         }
     };
@@ -899,18 +907,19 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                 const int q = 64 * p + lane;
                 const bool live = q < h.qtot;
                 const bool dense = live && ((r.w >> 15) & 1);
-                const int slot = r.w & (kMaxPanels - 1);
+                // scatter form: the slot is the tile's position, taken from the x-area index in multiply
+                const int slot = SC ? 0 : r.w & (kMaxPanels - 1);
                 uint32_t m = (uint32_t)(ti << LT) |
                              ((uint32_t)(slot * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0)) << 9);
                 int caddr;
                 if (dense) {
                     // quad dq of a Dense tile: row dq / QPR, columns 4 (dq mod QPR) .. + 3, i.e. elements
                     // 4 dq .. 4 dq + 3 of the row-major tile and bits 4 dq .. of its bitmap
-                    const int dq = q - ((r.w >> 2) & 0x3FF);
+                    const int dq = q - rec_qs(r);
                     caddr = r.x + 4 * (dq >> 3);
                     m |= (1u << 16) | ((uint32_t)(((dq % QPR) << 6) | (dq / QPR)) << 17) | ((uint32_t)(dq & 7) << 25);
                 } else {
-                    const int nv = live ? min(max(r.z - 4 * q, 0), 4) : 0;
+                    const int nv = live ? min(max(rec_lim(r) - 4 * q, 0), 4) : 0;
                     caddr = r.x + 4 * q;
                     m |= (uint32_t)((1 << nv) - 1) << 17;
                 }
@@ -935,7 +944,8 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                     vm = (m >> 17) & 0xFu;
                     codes = C[p];
                 }
-                const int xo = (int)(m & 0x1FFu), ao = (int)((m >> 9) & 0x7Fu);
+                const int xo = (int)(m & 0x1FFu);
+                const int ao = SC ? (xo >> LT) * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0) : (int)((m >> 9) & 0x7Fu);
                 const bool half = (m >> 31) != 0u;
                 AC s = AC(0);
                 int run = (int)(codes & 15u);
@@ -993,8 +1003,32 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         done_mask = 0;
     };
 
-    if (lane < kMaxPanels * 16) acc[lane] = AC(0);
-    if constexpr (NACC == 2) acc[lane + 64] = AC(0);
+    for (int i = lane; i < NSLOT * 16 * NACC; i += kWave) acc[i] = AC(0);
+    // scatter form: the panels of the batch being multiplied, lane (fk, fr) for its tiles fk + 4 j
+    int PN[4] = {0, 0, 0, 0};
+    auto scatter_panels = [&](const Hdr &h, int par) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (fk + 4 * j < h.nt) PN[j] = rtab[par][fk + 4 * j].z;
+    };
+    // scatter form: every tile's row sums of the batch just multiplied added into y
+    auto scatter_flush = [&](int nt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = fk + 4 * j;
+            if (t < nt) {
+                AC *a = &acc[t * 16 * NACC + fr];
+                AC sv = *a;
+                *a = AC(0);
+                if constexpr (NACC == 2) {
+                    sv += a[16];
+                    a[16] = AC(0);
+                }
+                const int64_t row = 16 * (int64_t)PN[j] + fr;
+                if (sv != AC(0) && row < d.m) global_add(&y[row], alpha * (A)sv);
+            }
+        }
+    };
     // prologue: batch 0's records, x columns, payload and x; batch 1's records and x columns; batch
     // 2's records in flight.  At the top of step b the registers hold the payload and x of batch b,
     // the x columns of batch b+1 and Q the records of batch b+2; the tables hold batches b and b+1.
@@ -1024,7 +1058,8 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     while (ob < oend) {
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         put_x(h0.nt);
-        flush();
+        if constexpr (SC) scatter_panels(h0, par);
+        else flush();
         const bool have1 = o1 < oend, have2 = o2 < oend;
         int o3 = o2;
         if (have2) {
@@ -1038,10 +1073,13 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
             o3 = o2 + 1 + h2.nt;
             if (o3 < oend) qload(o3);
         }
-        done_pb = h0.pb;
-        done_mask = h0.done;
-        issue_y();
+        if constexpr (!SC) {
+            done_pb = h0.pb;
+            done_mask = h0.done;
+            issue_y();
+        }
         multiply(h0.np);
+        if constexpr (SC) scatter_flush(h0.nt);
         __builtin_amdgcn_wave_barrier();
         if (have1) issue_payload(h1, par ^ 1);
         ob = o1;
@@ -1052,7 +1090,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         tb2 += have2 ? h2.nt : 0;
         par ^= 1;
     }
-    flush();
+    if constexpr (!SC) flush();
 }
 
 // The serving loop's batched launch for quad-batch structures (as spmv_batch_kernel)
@@ -1066,12 +1104,12 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJ
     qstream_range<VT, AGG, RR, LT>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
-template <int VT, bool AGG, int RR, int LT>
+template <int VT, bool AGG, int RR, int LT, bool SC>
 __global__ __launch_bounds__(kBlockThreads) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
                                                                    typename Val<VT>::A *__restrict__ y) {
-    qstream_range<VT, AGG, RR, LT>(d, xcd_block(blockIdx.x, gridDim.x), alpha, beta, x, y);
+    qstream_range<VT, AGG, RR, LT, SC>(d, xcd_block(blockIdx.x, gridDim.x), alpha, beta, x, y);
 }
 
 // ---- rows per lane (natural order) -----------------------------------------
@@ -1510,7 +1548,7 @@ hipError_t spmv_stream_launch(const DevView &d, typename Val<VT>::A a, typename 
     return hipGetLastError();
 }
 
-template <int VT, int LT>
+template <int VT, int LT, bool SC = false>
 hipError_t spmv_quad_launch(const DevView &d, typename Val<VT>::A a, typename Val<VT>::A b, const void *x, void *y,
                             int nb, hipStream_t s) {
     using A = typename Val<VT>::A;
@@ -1521,15 +1559,15 @@ hipError_t spmv_quad_launch(const DevView &d, typename Val<VT>::A a, typename Va
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
     };
     if (d.col_agg) {
-        if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2, LT>);
-        else if (rr == 3) go(spmv_quad_kernel<VT, true, 3, LT>);
-        else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4, LT>);
-        else go(spmv_quad_kernel<VT, true, 0, LT>);
+        if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2, LT, SC>);
+        else if (rr == 3) go(spmv_quad_kernel<VT, true, 3, LT, SC>);
+        else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4, LT, SC>);
+        else go(spmv_quad_kernel<VT, true, 0, LT, SC>);
     } else {
-        if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2, LT>);
-        else if (rr == 3) go(spmv_quad_kernel<VT, false, 3, LT>);
-        else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4, LT>);
-        else go(spmv_quad_kernel<VT, false, 0, LT>);
+        if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2, LT, SC>);
+        else if (rr == 3) go(spmv_quad_kernel<VT, false, 3, LT, SC>);
+        else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4, LT, SC>);
+        else go(spmv_quad_kernel<VT, false, 0, LT, SC>);
     }
     return hipGetLastError();
 }
@@ -1544,7 +1582,9 @@ hipError_t spmv_vt(const DevView &d, double alpha, const void *x, double beta, v
     // row sums: FP32 LDS atomics are slow where many lanes of a pass hit one row (long runs),
     // the segmented scan costs the same whatever the runs; the handle holds the choice
     const A a = (A)alpha, b = (A)beta;
-    if (d.natural_order && d.spmv_kernel == 2) {
+    if (d.scatter) {
+        return spmv_quad_launch<VT, 4, true>(d, a, b, x, y, nb, s);
+    } else if (d.natural_order && d.spmv_kernel == 2) {
         if (d.tile_lt == 3) return spmv_quad_launch<VT, 3>(d, a, b, x, y, nb, s);
         return spmv_quad_launch<VT, 4>(d, a, b, x, y, nb, s);
     } else if (d.natural_order && d.spmv_kernel == 1) {

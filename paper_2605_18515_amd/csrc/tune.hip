@@ -145,7 +145,8 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             return fail(CB_ERROR_INVALID_VALUE, "cb_options_t.struct_size does not match this library");
         b0 = *base;
     }
-    if (b0.lb_mode == CB_LB_PAPER) return fail(CB_ERROR_NOT_SUPPORTED, "the tuner works on natural-order structures");
+    if (b0.lb_mode == CB_LB_PAPER || b0.lb_mode == CB_LB_PAPER_STREAM)
+        return fail(CB_ERROR_NOT_SUPPORTED, "the tuner works on natural-order structures");
     Tuner T;
     T.m = m;
     T.n = n;

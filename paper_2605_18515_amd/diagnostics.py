@@ -3,8 +3,10 @@
 * ``ABLATION``: the option sets of the ablation in Section 4 (Fig. 12): CB-I keeps only the
   packing of each tile's data behind one virtual pointer (no column aggregation, one format,
   no load balance); CB-II adds column aggregation by the th0 rule and the per-tile format
-  choice; the full method adds the inter-block load balance -- Algorithm 2, and the contiguous
-  split this library defaults to.
+  choice; the full method adds the inter-block load balance -- Algorithm 2 with the
+  tile-at-a-time kernel of its scattered order, Algorithm 2's groups streamed (the packed tiles
+  re-laid in group order, every tile's rows added with atomics), and the contiguous split this
+  library defaults to.
 * ``tile_nnz_histogram``: the non-zeros-per-tile histogram of Fig. 3 for a structure, from the
   tile counts the library exports.
 * ``balance``: non-zeros per unit of work (Fig. 4's spread) as the library reports it.
@@ -19,6 +21,7 @@ ABLATION = {
     "CB-I": {"col_agg": 0, "th1": 257, "th2": 257, "lb_mode": "none"},
     "CB-II": {"col_agg": -1, "th1": 32, "th2": 128, "lb_mode": "none"},
     "CB (Alg. 2)": {"col_agg": -1, "th1": 32, "th2": 128, "lb_mode": "paper"},
+    "CB (Alg. 2, streamed)": {"col_agg": -1, "th1": 32, "th2": 128, "lb_mode": "paper_stream"},
     "CB (contiguous)": {"col_agg": -1, "th1": 32, "th2": 128, "lb_mode": "contiguous"},
 }
 

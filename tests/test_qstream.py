@@ -23,6 +23,11 @@ QT, QP, PANELS, PAD = 16, 4, 4, 2048
 VSIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 
+def aligned(b: int) -> int:
+    """A tile region's bytes rounded to the 16-byte alignment of the next region."""
+    return (b + cm.TILE_ALIGN - 1) // cm.TILE_ALIGN * cm.TILE_ALIGN
+
+
 @np.errstate(invalid="ignore", over="ignore")
 def values_of(raw: bytes, vtype):
     if vtype == "f64":
@@ -34,11 +39,14 @@ def values_of(raw: bytes, vtype):
 
 
 def emulate(A, X, vtype="f64", **opts):
-    """y = A X computed from the exported quad batches exactly as the kernel addresses them."""
+    """y = A X computed from the exported quad batches exactly as the kernel addresses them.  With
+    lb_mode paper_stream (Algorithm 2's groups streamed) the batches are in scatter form: any
+    panels, the tile's position as its accumulator slot, its panel in the record."""
     M = cb.CbMatrix.from_csr(A, device=False, value_type=vtype, spmv_kernel=2, **opts)
     info, s = M.info, M.structure()
     M.close()
     assert info["spmv_kernel"] == 2
+    scatter = info["lb_mode"] == cb.CB_LB_PAPER_STREAM
     vs = VSIZE[vtype]
     S = info["tile_dim"]  # tile size
     assert S == opts.get("tile_dim", 16)
@@ -81,13 +89,25 @@ def emulate(A, X, vtype="f64", **opts):
             o += 1 + nt
             # limits
             assert 1 <= nt <= QT and 1 <= npass <= QP and npass == (qtot + 63) // 64 and qtot <= 64 * QP
-            assert row[tiles[0]] == pb and all(0 <= row[i] - pb < PANELS for i in tiles)
+            if scatter:
+                assert pb == 0 and done == 0
+                # the tiles of a range are packed back to back in kernel order
+                for i in tiles[1:]:
+                    assert vp[i] == vp[i - 1] + aligned(cm.tile_region_bytes(int(ty[i - 1]), int(nnz[i - 1]), vtype, S))
+            else:
+                assert row[tiles[0]] == pb and all(0 <= row[i] - pb < PANELS for i in tiles)
             quads = [S * S // 4 if ty[i] == cm.DENSE else (int(nnz[i]) + 3) // 4 for i in tiles]
             assert qtot == sum(quads)
+
+            def fields(r):  # first quad, end of entries, slot
+                meta = int(r[3])
+                if scatter:
+                    return (meta >> 5) & 0x3FF, (meta >> 16) & 0x1FFF, meta & 31
+                return (meta >> 2) & 0x3FF, int(r[2]), meta & 3
             # marks and the ballot: the tile of every lane
             marks = np.zeros((QP, 64), bool)
             for r in recs:
-                qs = (int(r[3]) >> 2) & 0x3FF
+                qs = fields(r)[0]
                 marks[qs >> 6, qs & 63] = True
             jb = 0
             for p in range(npass):
@@ -96,16 +116,18 @@ def emulate(A, X, vtype="f64", **opts):
                     below = int(bal[:lane].sum())
                     ti = jb + below + int(bal[lane]) - 1
                     r = recs[max(ti, 0)]
-                    cbase, vbase, lim, meta = (int(v) for v in r)
+                    cbase, vbase, meta = int(r[0]), int(r[1]), int(r[3])
+                    qs, lim, slot = fields(r)
                     q = 64 * p + lane
                     live = q < qtot
                     dense = live and ((meta >> 15) & 1)
-                    slot = meta & 3
                     i = tiles[max(ti, 0)]
-                    if live:
+                    if live and scatter:
+                        assert slot == ti and int(r[2]) == row[i]
+                    elif live:
                         assert slot == row[i] % PANELS
                     if dense:
-                        dq = q - ((meta >> 2) & 0x3FF)
+                        dq = q - qs
                         assert 0 <= dq < S * S // 4
                         word = int.from_bytes(load(cbase + 4 * (dq >> 3), 4), "little")
                         vm = (word >> (4 * (dq & 7))) & 0xF
@@ -115,7 +137,7 @@ def emulate(A, X, vtype="f64", **opts):
                         vm = (1 << nv) - 1
                         codes = list(load(cbase + 4 * q, 4))
                     vals = values_of(load(vbase + 4 * vs * q, 4 * vs), vtype)
-                    panel = pb + (slot - pb) % PANELS
+                    panel = int(r[2]) if scatter else pb + (slot - pb) % PANELS
                     for j in range(4):
                         if not (vm >> j) & 1:
                             continue
@@ -134,7 +156,8 @@ def emulate(A, X, vtype="f64", **opts):
                 if (done >> k) & 1:
                     done_panels.append(pb + k)
         assert t == t1
-        assert sorted(done_panels) == sorted(set(row[t0:t1].tolist()))
+        if not scatter:
+            assert sorted(done_panels) == sorted(set(row[t0:t1].tolist()))
     assert nb == info["nbatches"]
     assert np.array_equal(seen, nnz)
     return y
@@ -199,3 +222,46 @@ def test_quad_limits_cut_batches():
     # one tile per panel over many panels: the 4-panel limit cuts
     A2, X2 = dyadic_case(matgen.identity(16 * 40))
     assert np.array_equal(emulate(A2, X2, "f64"), oracle.spmv(A2, X2))
+
+
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("col_agg", [0, 1])
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_streamed_algorithm2_batches_decode_to_the_product(name, col_agg, vtype):
+    """lb_mode paper_stream: Algorithm 2's groups, the packed tiles re-laid in group order, quad
+    batches in scatter form; the kernel's addressing reproduces the product, every panel is
+    pre-scaled (all shared), and the grouping is the paper mode's."""
+    A, X = dyadic_case(MATS[name]())
+    for wave_nnz in (0, 50):
+        assert np.array_equal(emulate(A, X, vtype, col_agg=col_agg, lb_mode="paper_stream", wave_nnz=wave_nnz),
+                              oracle.spmv(A, X))
+    Ms = cb.CbMatrix.from_csr(A, device=False, value_type=vtype, col_agg=col_agg, lb_mode="paper_stream")
+    Mp = cb.CbMatrix.from_csr(A, device=False, value_type=vtype, col_agg=col_agg, lb_mode="paper")
+    ss, sp = Ms.structure(), Mp.structure()
+    i_s, i_p = Ms.info, Mp.info
+    Ms.close()
+    Mp.close()
+    for k in ("tile_ori", "quantum_ptr", "tile_row", "tile_col", "tile_nnz", "tile_type"):
+        assert np.array_equal(ss[k], sp[k]), k
+    assert i_s["payload_bytes"] == i_p["payload_bytes"] and i_s["prepass_panels"] == i_s["npanels"]
+    assert i_s["quantum_nnz_std"] == i_p["quantum_nnz_std"]
+    # the same packed tile regions, moved
+    vs = VSIZE[vtype]
+    for t in range(i_s["ntiles"]):
+        rb = aligned(cm.tile_region_bytes(int(ss["tile_type"][t]), int(ss["tile_nnz"][t]), vtype, 16))
+        a, b = int(ss["tile_vp"][t]), int(sp["tile_vp"][t])
+        assert np.array_equal(ss["payload"][a:a + rb], sp["payload"][b:b + rb])
+
+
+def test_streamed_algorithm2_options():
+    A = matgen.laplacian_2d(20)
+    for kw in ({"tile_dim": 8}, {"spmv_kernel": 0}, {"spmv_kernel": 1}):
+        with pytest.raises(cb.CbError) as e:
+            cb.CbMatrix.from_csr(A, device=False, lb_mode="paper_stream", **kw)
+        assert e.value.status == cb.CB_ERROR_NOT_SUPPORTED
+    M = cb.CbMatrix.from_csr(A, device=False, lb_mode="paper_stream", spmv_kernel=2)
+    assert M.info["spmv_kernel"] == 2 and M.info["lb_mode"] == cb.CB_LB_PAPER_STREAM
+    rp, ci, va = M.export_csr()
+    M.close()
+    assert np.array_equal(rp, A.row_ptr) and np.array_equal(ci, A.col_idx)
+    assert np.array_equal(va.view(np.uint64), A.values.view(np.uint64))
