@@ -371,8 +371,8 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     a relative residual of 1e-10, half each: on a FP64 matrix plain CG, on a FP32 one the refined
     kind (the FP32 copy's products, FP64 residual replacement with a FP64 twin of the matrix; only
     a true residual ends it).  Three runs of the same request list: the server with every request
-    submitted at once (throughput), the server under Poisson arrivals at half that rate (p50/p99
-    latency), and the plain path, one request at a time through cb_spmm, cb_cg and cb_cg_refine.
+    submitted at once (throughput), the server under Poisson arrivals at a quarter, half and all of
+    that rate (p50/p99 latency against load), and the plain path, one request at a time through cb_spmm, cb_cg and cb_cg_refine.
     Then the precision comparison on the Poisson matrices alone (serve_precision).  Returns the
     measurements."""
     import multiprocessing as mp
@@ -443,11 +443,19 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     outs_b, resp_b, st_b = serve()
     log(f"server, all at once: {st_b['requests_per_s']:.0f} requests/s, {st_b['solves_per_s']:.1f} solves/s, "
         f"p50 {st_b['p50_us'] / 1e3:.2f} ms, p99 {st_b['p99_us'] / 1e3:.2f} ms, active peak {st_b['active_peak']}")
-    lam = 0.5 * st_b["requests_per_s"]
-    gaps = np.random.default_rng(7).exponential(1.0 / lam, len(reqs))
-    outs_p, resp_p, st_p = serve(gaps)
-    log(f"server, Poisson arrivals at {lam:.0f}/s: {st_p['requests_per_s']:.0f} requests/s, "
-        f"p50 {st_p['p50_us'] / 1e3:.2f} ms, p99 {st_p['p99_us'] / 1e3:.2f} ms")
+    # Poisson arrivals at fractions of the saturated request rate: latency against load
+    sweep = []
+    for frac in (0.25, 0.5, 1.0):
+        lam_f = frac * st_b["requests_per_s"]
+        gaps = np.random.default_rng(7).exponential(1.0 / lam_f, len(reqs))
+        _, _, st_f = serve(gaps)
+        sweep.append({"load": frac, "rate_per_s": lam_f, "requests_per_s": st_f["requests_per_s"],
+                      "solves_per_s": st_f["solves_per_s"], "p50_ms": st_f["p50_us"] / 1e3,
+                      "p99_ms": st_f["p99_us"] / 1e3})
+        log(f"server, Poisson arrivals at {lam_f:.0f}/s ({frac:.2f} of saturation): {st_f['requests_per_s']:.0f} "
+            f"requests/s, p50 {st_f['p50_us'] / 1e3:.2f} ms, p99 {st_f['p99_us'] / 1e3:.2f} ms")
+        if frac == 0.5:
+            lam, st_p = lam_f, st_f
 
     # the plain path: one request at a time
     dev = torch.device("cuda:0")
@@ -490,7 +498,7 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     torch.cuda.empty_cache()
     prec = serve_precision(args, cb, [csrs[i] for i in spd], [xin[i] for i in spd])
     return {"requests": len(reqs), "cg_requests": ncg, "refined_requests": nref, "rtol": rtol, "all_at_once": st_b,
-            "poisson_arrivals": dict(st_p, rate_per_s=lam), "one_at_a_time": seq,
+            "poisson_arrivals": dict(st_p, rate_per_s=lam), "arrival_sweep": sweep, "one_at_a_time": seq,
             "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
             "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst, "precision": prec}
 
@@ -912,6 +920,7 @@ def main() -> int:
                 "speedup_solves": srv["speedup_solves_vs_one_at_a_time"],
                 "poisson_arrivals_per_s": srv["poisson_arrivals"]["rate_per_s"],
                 "p50_ms": srv["poisson_arrivals"]["p50_us"] / 1e3, "p99_ms": srv["poisson_arrivals"]["p99_us"] / 1e3,
+                "arrival_sweep": srv["arrival_sweep"],
                 "cg_converged": srv["cg_converged"], "refined_requests": srv["refined_requests"], "rtol": srv["rtol"],
                 "max_rel_diff_vs_one_at_a_time": srv["max_rel_diff_vs_one_at_a_time"],
                 "precision": srv["precision"]}

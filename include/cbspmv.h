@@ -134,7 +134,13 @@ typedef struct {
                                always taken on the 16 x 16 partition.  8 with spmv_kernel 1 is
                                refused with CB_ERROR_NOT_SUPPORTED; any other value with
                                CB_ERROR_INVALID_VALUE. */
-    int64_t reserved[4];
+    int32_t xcd_chunk;      /* how the kernels' workgroups (in dispatch order, which deals them to
+                               the 8 XCDs in turn) map to work ranges: c >= 1 = each XCD takes runs of
+                               c consecutive ranges, the XCDs side by side; 0 = each XCD one
+                               contiguous eighth of the ranges; -1 (default) = automatic.  Results
+                               do not depend on it. */
+    int32_t reserved32;
+    int64_t reserved[3];
 } cb_options_t;
 
 typedef struct {
@@ -176,7 +182,9 @@ typedef struct {
     int32_t vector_f64;     /* 1 when x and y are double (FP64 storage, or vector_f64 set) */
     int32_t spmv_kernel;    /* the resolved spmv_kernel option (0, 1 or 2) */
     int32_t tile_dim;       /* sub-block size S of the structure (16 or 8) */
-    int64_t reserved[3];
+    int32_t xcd_chunk;      /* the resolved xcd_chunk option */
+    int32_t reserved32;
+    int64_t reserved[2];
 } cb_info_t;
 
 /* Host buffers receiving the structure in kernel order (ntiles entries for the
@@ -383,7 +391,8 @@ const char *cb_last_error(void);
  * each (cb_spmv, or cb_spmm with spmm_k right-hand sides; HIP events on `stream`, median of reps
  * launches with x = 1 and beta = 0), by coordinate descent from `base` over: column aggregation
  * on/off, the sub-block size (16 x 16 or 8 x 8 tiles, th1/th2 scaled with the tile's area), the
- * natural-order kernel (entries or quads per lane), the format thresholds th1/th2 (the base
+ * natural-order kernel (entries or quads per lane), the workgroup-to-range mapping (xcd_chunk
+ * 16 or 0), the format thresholds th1/th2 (the base
  * ones, COO below Dense at 200/256 of the tile's slots, COO only), the row-sum mode, the
  * load-balance split (nnz-balanced at panel boundaries or equal tile counts) and the work per
  * wavefront (half and twice the current ranges' mean).  A choice is kept when it is at least

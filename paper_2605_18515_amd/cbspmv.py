@@ -50,7 +50,7 @@ class CbOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
                 ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
                 ("wave_nnz", _i64), ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32),
-                ("tile_dim", _i32), ("reserved", _i64 * 4)]
+                ("tile_dim", _i32), ("xcd_chunk", _i32), ("reserved32", _i32), ("reserved", _i64 * 3)]
 
 
 class CbInfo(ctypes.Structure):
@@ -64,7 +64,7 @@ class CbInfo(ctypes.Structure):
                 ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
                 ("reserved0", _i32), ("nbatches", _i64), ("stream_bytes", _i64), ("flat_run_mean", _dbl),
                 ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32), ("tile_dim", _i32),
-                ("reserved", _i64 * 3)]
+                ("xcd_chunk", _i32), ("reserved32", _i32), ("reserved", _i64 * 2)]
 
 
 class CbStructure(ctypes.Structure):

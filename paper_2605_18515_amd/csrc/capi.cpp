@@ -202,6 +202,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.row_reduce = s.row_reduce;
     v.spmv_kernel = s.spmv_kernel;
     v.tile_lt = s.lt;
+    v.xcd_chunk = s.xcd_chunk;
     v.payload_alloc = (int64_t)s.payload_bytes + cbs::kPayloadPad;
     v.stream_alloc = streamed ? 16 * ((int64_t)s.nrecords + cbs::kStreamRecordPad) : 0;
     // the device copy is the structure from now on
@@ -302,6 +303,7 @@ cb_status_t cb_options_default(cb_options_t *opt) {
     opt->wave_nnz = 0;
     opt->row_reduce = -1;
     opt->spmv_kernel = -1;
+    opt->xcd_chunk = -1;
     return CB_SUCCESS;
 }
 

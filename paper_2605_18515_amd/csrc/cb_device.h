@@ -37,6 +37,8 @@ struct DevView {
     int32_t tile_lt;              // log2 of the tile size S: 4 (16 x 16 tiles) or 3 (8 x 8)
     int32_t scatter;              // Algorithm 2's groups streamed (CB_LB_PAPER_STREAM): quad batches in
                                   // scatter form, every tile's rows added into y with atomics
+    int32_t xcd_chunk;            // workgroup-to-range mapping: 0 each XCD a contiguous eighth; c runs of c
+    int32_t pad1;
     int64_t payload_alloc;        // readable bytes from payload (the structure's bytes and the padding after them)
     int64_t stream_alloc;         // readable bytes from batch_stream
 };

@@ -64,6 +64,7 @@ struct HostStructure {
     int row_reduce = 0;                       // resolved: 0 LDS atomics, 1 DPP segmented scan, 2 FP64 atomics,
                                               // 3 and 4 = 0 and 2 with two accumulator copies
     int vector_f64 = 1;                       // x and y are double
+    int xcd_chunk = 0;                        // resolved workgroup-to-range mapping (0 eighths, c runs of c)
     int spmv_kernel = 0;                      // resolved: 0 entries per lane, 1 rows per lane
     // natural order: first tile of every panel (npanels + 1)
     std::vector<int32_t> panel_tile;

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -432,6 +433,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.row_reduce < -1 || opt.row_reduce > 4) { err = "row_reduce must be -1 .. 4"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.xcd_chunk < -1 || opt.xcd_chunk > (1 << 20)) { err = "xcd_chunk must be -1 .. 2^20"; return CB_ERROR_INVALID_VALUE; }
     if (opt.tile_dim != 0 && opt.tile_dim != 8 && opt.tile_dim != 16) { err = "tile_dim must be 0, 8 or 16"; return CB_ERROR_INVALID_VALUE; }
     if (opt.lb_mode == CB_LB_PAPER_STREAM && (opt.tile_dim == 8 || (opt.spmv_kernel >= 0 && opt.spmv_kernel != 2))) {
         err = "the streamed Algorithm 2 order runs the quad kernel on 16 x 16 tiles";
@@ -482,6 +484,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     s.vtype = opt.value_type;
     s.vector_f64 = opt.value_type == CB_VALUE_F64 || opt.vector_f64 ? 1 : 0;
     s.spmv_kernel = opt.spmv_kernel > 0 ? opt.spmv_kernel : 0;
+    s.xcd_chunk = opt.xcd_chunk >= 0 ? opt.xcd_chunk : 0;
     s.vsize = opt.value_type == CB_VALUE_F64 ? 8 : (opt.value_type == CB_VALUE_F32 ? 4 : 2);
     s.lb_mode = opt.lb_mode;
     s.quantum_tiles = opt.quantum_tiles;
@@ -495,12 +498,16 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // ---- Section 3.1 + 3.3.1: plain partition census, th0 decision ------
         // (always on the 16 x 16 partition: the paper defines super-sparse sub-blocks there)
         const int64_t P16 = (m + kBlk - 1) / kBlk;
-        std::vector<int64_t> plain_cnt(P16, 0), super_cnt(P16, 0);
+        std::vector<int64_t> plain_cnt(P16, 0), super_cnt(P16, 0), far_cnt(P16, 0);
+        const int64_t far = std::max<int64_t>(1, n / 8);  // entries this far from the diagonal: "far"
         if (!parallel_dynamic(nth, P16, 64, [&](int64_t b, int64_t e) {
                 std::vector<int32_t> cb;
                 for (int64_t p = b; p < e; ++p) {
                     const int64_t r0 = p * kBlk, r1 = std::min(m, r0 + kBlk);
                     cb.clear();
+                    for (int64_t r = r0; r < r1; ++r)
+                        for (int64_t t = row_ptr[r]; t < row_ptr[r + 1]; ++t)
+                            far_cnt[p] += std::llabs((int64_t)col_idx[t] - r) > far;
                     for (int64_t t = row_ptr[r0]; t < row_ptr[r1]; ++t) cb.push_back(col_idx[t] >> 4);
                     std::sort(cb.begin(), cb.end());
                     size_t i = 0;
@@ -517,6 +524,15 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         const int64_t super = std::accumulate(super_cnt.begin(), super_cnt.end(), (int64_t)0);
         s.plain_tiles = plain;
         s.share = plain ? (double)super / (double)plain : 0.0;
+        // workgroup-to-range mapping (measured on gfx950): the XCDs side by side in runs of 16 ranges
+        // keep x lines that distant rows share (stencil and block neighbours 10^4-10^5 rows apart) in
+        // every L2 between their uses (3D block matrix 142 against 148 us, 192^3 Poisson 162 against
+        // 176); where many entries lie far from the diagonal (scattered columns) each XCD on its own
+        // eighth keeps a narrower window of near-diagonal x instead (power-law rows 584 against 637)
+        if (opt.xcd_chunk < 0) {
+            const int64_t nfar = std::accumulate(far_cnt.begin(), far_cnt.end(), (int64_t)0);
+            s.xcd_chunk = nfar * 20 >= nnz && nnz > 0 ? 0 : 16;
+        }
         bool agg;
         if (opt.col_agg == 0) agg = false;
         else if (opt.col_agg == 1) agg = true;
@@ -975,6 +991,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.row_reduce = s.row_reduce;
     info.vector_f64 = s.vector_f64;
     info.spmv_kernel = s.spmv_kernel;
+    info.xcd_chunk = s.xcd_chunk;
     info.tile_dim = s.blk;
 }
 

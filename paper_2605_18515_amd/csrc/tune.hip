@@ -202,6 +202,16 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             o.spmv_kernel = T.cand[T.best].spmv_kernel == 2 ? 0 : 2;
             if (st == CB_SUCCESS) st = T.eval(o, idx);
         }
+        // workgroup-to-range mapping: the other of the XCDs side by side in runs of 16 ranges and each
+        // XCD a contiguous eighth
+        {
+            cb_info_t info{};
+            info.struct_size = sizeof(cb_info_t);
+            if (st == CB_SUCCESS && T.handles[T.best]) st = cb_get_info(T.handles[T.best], &info);
+            cb_options_t o = cur();
+            o.xcd_chunk = info.xcd_chunk == 0 ? 16 : 0;
+            if (st == CB_SUCCESS) st = T.eval(o, idx);
+        }
         // format thresholds: COO below Dense at 200 of 256 slots, COO only (the streaming kernel reads
         // COO and CSR entries alike, so a CSR tile's row header is extra bytes there)
         {

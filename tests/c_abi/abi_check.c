@@ -17,6 +17,7 @@ int main(void) {
     FIELD(cb_options_t, row_reduce);
     FIELD(cb_options_t, vector_f64);
     FIELD(cb_options_t, spmv_kernel);
+    FIELD(cb_options_t, xcd_chunk);
     SIZE(cb_info_t);
     FIELD(cb_info_t, super_sparse_share);
     FIELD(cb_info_t, spmv_bytes);
@@ -26,6 +27,7 @@ int main(void) {
     FIELD(cb_info_t, row_reduce);
     FIELD(cb_info_t, vector_f64);
     FIELD(cb_info_t, spmv_kernel);
+    FIELD(cb_info_t, xcd_chunk);
     SIZE(cb_structure_t);
     SIZE(cb_cg_options_t);
     FIELD(cb_cg_options_t, inner_rtol);

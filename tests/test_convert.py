@@ -449,3 +449,26 @@ def test_automatic_kernel_choice():
         if want == 2:
             assert M.info["row_reduce"] in (3, 4)
         M.close()
+
+
+def test_automatic_xcd_mapping():
+    """xcd_chunk = -1: runs of 16 ranges per XCD unless 5 % or more of the entries lie farther than
+    n / 8 from the diagonal (then each XCD takes a contiguous eighth); explicit values are kept."""
+    lap = matgen.laplacian_2d(40)
+    M = cb.CbMatrix.from_csr(lap, device=False)
+    assert M.info["xcd_chunk"] == 16
+    M.close()
+    # a permutation matrix reversing the order: nearly every entry is far from the diagonal
+    n = 400
+    R = matgen.Csr(n, n, np.arange(n + 1, dtype=np.int64), (n - 1 - np.arange(n)).astype(np.int32), np.ones(n))
+    M = cb.CbMatrix.from_csr(R, device=False)
+    assert M.info["xcd_chunk"] == 0
+    M.close()
+    for c in (0, 1, 7, 1024):
+        M = cb.CbMatrix.from_csr(R, device=False, xcd_chunk=c)
+        assert M.info["xcd_chunk"] == c
+        M.close()
+    for bad in (-2, 1 << 21):
+        with pytest.raises(cb.CbError) as e:
+            cb.CbMatrix.from_csr(lap, device=False, xcd_chunk=bad)
+        assert e.value.status == cb.CB_ERROR_INVALID_VALUE

@@ -442,3 +442,26 @@ def test_spmm_dense_tiles_with_nonfinite_x(cb, vtype):
         ref = oracle.spmm(A, X, comp=True)
         e, viol, w = oracle.scaled_error(Y, ref, oracle.spmm_scale(A, X), TOL[vtype])
         assert viol == 0, (th, e, w)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 3, 16, 1000])
+def test_xcd_mapping_leaves_results_unchanged(cb, chunk):
+    """Every workgroup-to-range mapping computes the same product: bit for bit on exact inputs
+    (SpMV in both natural-order kernels and Algorithm 2's streamed order, and SpMM), within the
+    tolerance otherwise."""
+    A = matgen.random_csr(900, 1100, 0.02, 7, values="dyadic")
+    x = matgen.vector(A.n, 3, dyadic=True)
+    ref = oracle.spmv(A, x)
+    for opts in ({"spmv_kernel": 0}, {"spmv_kernel": 2}, {"lb_mode": "paper_stream"}, {"lb_mode": "paper"}):
+        y = run_spmv(cb, A, x, xcd_chunk=chunk, wave_nnz=64, **opts)
+        assert np.array_equal(y.view(np.uint64), ref.view(np.uint64)), (chunk, opts)
+    B = SMALL["block8"]()
+    xb = matgen.vector(B.n, 5)
+    check(cb, B, xb, label=f"block8 chunk={chunk}", xcd_chunk=chunk)
+    X = np.stack([matgen.vector(A.n, 10 + j, dyadic=True) for j in range(8)], 1)
+    M = cb.CbMatrix.from_csr(A, xcd_chunk=chunk, wave_nnz=64)
+    Yd = torch.empty((A.m, 8), dtype=torch.float64, device="cuda")
+    M.spmm(torch.from_numpy(X).to("cuda"), Yd)
+    torch.cuda.synchronize()
+    M.close()
+    assert np.array_equal(Yd.cpu().numpy(), oracle.spmm(A, X))
