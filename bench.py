@@ -730,8 +730,8 @@ def main() -> int:
     from paper_2605_18515_amd import cbspmv as cb
 
     # the stencil and power-law legs of the extras need their matrices; worker processes (forked
-    # before this process touches the GPU, CPU work only) generate them while the GPU runs the
-    # headline and the block-matrix legs
+    # before this process touches the GPU, CPU work only) generate them while this process
+    # generates and converts the block matrix
     pool, pending = None, {}
     if (not args.no_extras and args.workload == "block3d" and not args.copy_only and not args.cg and not args.serve
             and not args.tune and not args.ablation):
@@ -775,6 +775,14 @@ def main() -> int:
     xd = torch.from_numpy(x).to(dev)
     yd = torch.empty(A.m, dtype=torch.float64, device=dev)
     step = lambda: M.spmv(xd, yd)  # noqa: E731
+    # the background generation ends before any timed region: host processes competing with the
+    # launching thread leave the GPU idle between short kernels (the BF16 leg read 83-91 us instead
+    # of 77 while they ran)
+    ready = {wl: r.get() for wl, r in pending.items()}
+    if pool is not None:
+        pool.close()
+        pool.join()
+        pool = None
     sclk0 = gpu_sclk()
     for _ in range(args.warmup):
         step()
@@ -889,15 +897,12 @@ def main() -> int:
         # stencil family at scale (192^3 Poisson), the power-law rows, and the 64 x 64 Laplacian,
         # whose whole working set sits in cache (launch latency, not HBM)
         for wl in ("poisson", "powerlaw"):
-            Aw = pending[wl].get() if wl in pending else make_matrix(wl, 0)
+            Aw = ready.pop(wl) if wl in ready else make_matrix(wl, 0)
             extra[f"spmv_{wl}"] = spmv_leg(cb, Aw, dev, lsteps, args.leg_settle_seconds, not args.no_check,
                                            WORKLOADS[wl], spmv_kernel=args.spmv_kernel)
             log(f"{wl}: {json.dumps(extra[f'spmv_{wl}'])}")
             del Aw
             torch.cuda.empty_cache()
-        if pool is not None:
-            pool.close()
-            pool.join()
         extra["laplacian64"] = laplacian_leg(cb, dev, not args.no_check)
         log(f"laplacian 64x64: {json.dumps(extra['laplacian64'])}")
         if not args.no_solves:

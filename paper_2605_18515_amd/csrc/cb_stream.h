@@ -76,11 +76,19 @@ constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes r
 //     Dense:      cb = the tile's occupancy bitmap, vb as above; the four bits of quad Q are
 //                 nibble Q - qs of the bitmap
 // The x area of the kernel holds the batch's tiles' 16 x values each, tile i at 16 i.
+//
+// Scatter form (Algorithm 2's groups streamed, CB_LB_PAPER_STREAM): the tiles of a batch may come
+// from any panels; the batch limits are kQTiles tiles and kQPasses * 64 quads.
+//   header  {0, nt | np << 8, qtot, 0}
+//   record  {cb, vb, panel, i | qs << 5 | dense << 15 | lim << 16}
+//     i      the tile's position in the batch: its accumulator slot and x-area place
+//     panel  the tile's panel, whose rows the tile's sums are added into after the batch
+//     cb, vb, qs, dense, lim as above (lim = 4 qs + nz < 2^13)
 #ifndef CB_TUNE_QTILES
 #define CB_TUNE_QTILES 16
 #endif
 #ifndef CB_TUNE_QPASSES
-#define CB_TUNE_QPASSES 4
+#define CB_TUNE_QPASSES 3
 #endif
 constexpr int kQTiles = CB_TUNE_QTILES;    // tiles per quad batch (x-area slots)
 constexpr int kQPasses = CB_TUNE_QPASSES;  // passes of 64 quads per batch (the kernel's payload registers)

@@ -1112,8 +1112,16 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJ
     qstream_range<VT, AGG, RR, LT>(J.d, b - J.wave_base, (A)J.alpha, (A)J.beta, (const A *)J.x, (A *)J.y);
 }
 
+#ifndef CB_TUNE_QWAVES
+#define CB_TUNE_QWAVES 0  // > 0: ask for at least this many wavefronts per SIMD (register cap) in the quad kernel
+#endif
+#if CB_TUNE_QWAVES > 0
+#define CB_QWAVES_ATTR __attribute__((amdgpu_waves_per_eu(CB_TUNE_QWAVES)))
+#else
+#define CB_QWAVES_ATTR
+#endif
 template <int VT, bool AGG, int RR, int LT, bool SC>
-__global__ __launch_bounds__(kBlockThreads) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
+__global__ __launch_bounds__(kBlockThreads) CB_QWAVES_ATTR void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
                                                                    typename Val<VT>::A *__restrict__ y) {

@@ -19,7 +19,7 @@ from paper_2605_18515_amd import matgen
 
 cb = pytest.importorskip("paper_2605_18515_amd.cbspmv", reason="libcbspmv.so not built")
 
-QT, QP, PANELS, PAD = 16, 4, 4, 2048
+QT, QP, PANELS, PAD = 16, 3, 4, 2048
 VSIZE = {"f64": 8, "f32": 4, "bf16": 2}
 
 
