@@ -591,6 +591,7 @@ def run_ablation(args, cb, matgen) -> int:
         row = {"nnz": A.nnz}
         for name, opts in diagnostics.ABLATION.items():
             M = cb.CbMatrix.from_csr(A, **opts)
+            settle(lambda: M.spmv(x, y), 0.3)
             _, k = time_calls(lambda: M.spmv(x, y), 100, 10)
             inf = M.info
             row[name] = {"us": k * 1e6, "gflops": 2.0 * A.nnz / k / 1e9, "spmv_bytes": inf["spmv_bytes"],
@@ -641,21 +642,34 @@ def run_tune(args, cb, matgen) -> int:
             xd = torch.from_numpy(x).to("cuda", dt)
             yd = torch.empty(A.m, dtype=dt, device="cuda")
             M = cb.CbMatrix.from_csr(A, value_type=vt)
+            settle(lambda: M.spmv(xd, yd), 0.3)
             _, k_def = time_calls(lambda: M.spmv(xd, yd), 100, 10)
             M.close()
             t = time.perf_counter()
             Mt, best, cands = cb.cb_tune(A, value_type=vt)
             tune_s = time.perf_counter() - t
+            settle(lambda: Mt.spmv(xd, yd), 0.3)
             _, k_tun = time_calls(lambda: Mt.spmv(xd, yd), 100, 10)
+            it = Mt.info
             Mt.close()
             key = f"{wl}_{vt}"
+
+            def desc(c):
+                o = c["opt"]
+                return {"tile_dim": c["tile_dim"], "spmv_kernel": c["spmv_kernel"], "col_agg": c["col_agg"],
+                        "th1": o["th1"], "th2": o["th2"], "row_reduce": c["row_reduce"], "lb_mode": o["lb_mode"],
+                        "wave_nnz": o["wave_nnz"], "xcd_chunk": o["xcd_chunk"], "us": c["us"]}
             rows[key] = {"default_us": k_def * 1e6, "tuned_us": k_tun * 1e6, "speedup": k_def / k_tun,
-                         "tune_seconds": tune_s, "candidates": len(cands),
-                         "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "lb_mode", "wave_nnz")}}
+                         "tune_seconds": tune_s, "candidates": [desc(c) for c in cands],
+                         "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "lb_mode", "wave_nnz",
+                                                       "xcd_chunk", "tile_dim", "spmv_kernel")},
+                         "tuned_structure": {k: it[k] for k in ("tile_dim", "spmv_kernel", "col_agg", "row_reduce",
+                                                                "xcd_chunk", "ntiles")}}
             log(f"{key}: default {k_def * 1e6:.1f} us, tuned {k_tun * 1e6:.1f} us ({k_def / k_tun:.3f}x) "
-                f"in {tune_s:.1f}s, best {rows[key]['best']}; candidates: " + "; ".join(
-                    f"agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) rr={c['row_reduce']} "
-                    f"lb={c['opt']['lb_mode']} wn={c['opt']['wave_nnz']} {c['us']:.1f}" for c in cands))
+                f"in {tune_s:.1f}s, chosen {rows[key]['tuned_structure']}; candidates: " + "; ".join(
+                    f"S={c['tile_dim']} k{c['spmv_kernel']} agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) "
+                    f"rr={c['row_reduce']} lb={c['opt']['lb_mode']} wn={c['opt']['wave_nnz']} "
+                    f"xcd={c['opt']['xcd_chunk']} {c['us']:.1f}" for c in cands))
             del xd, yd
             torch.cuda.empty_cache()
     geo = float(np.exp(np.mean([np.log(r["speedup"]) for r in rows.values()])))
