@@ -40,7 +40,7 @@ namespace {
 #define CB_TUNE_SPMM_MFMA 1  // natural-order SpMM on the matrix cores (0: the tile-at-a-time kernel)
 #endif
 #ifndef CB_TUNE_SPMM_STAGES
-#define CB_TUNE_SPMM_STAGES 3  // tiles whose loads are in flight in the matrix-core SpMM (FP64: one fewer, at least 2)
+#define CB_TUNE_SPMM_STAGES 2  // tiles whose loads are in flight in the matrix-core SpMM (FP64: one fewer, at least 2)
 #endif
 #ifndef CB_TUNE_SPMM_KC_MAX
 #define CB_TUNE_SPMM_KC_MAX 32  // widest column slice of the matrix-core SpMM (16 or 32)
