@@ -794,6 +794,38 @@ __device__ __forceinline__ typename Val<VT>::A quad_value(const uint32_t *w, int
     }
 }
 
+// a + byte K of b, one SDWA add (written out: the compiler otherwise re-derives each byte with a
+// shift and a mask from the expression that produced b)
+template <int K>
+__device__ __forceinline__ uint32_t add_byte(uint32_t a, uint32_t b) {
+    static_assert(K >= 0 && K < 4, "a byte of a dword");
+    uint32_t r;
+    if constexpr (K == 0)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+            : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (K == 1)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+            : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (K == 2)
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+            : "=v"(r) : "v"(a), "v"(b));
+    else
+        asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+            : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// all ones where bit j of v is set, else zero (one signed bit-field extract)
+__device__ __forceinline__ int bit_mask(uint32_t v, int j) {
+    int r;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(v), "v"(j));
+    return r;
+}
+// v where mask is all ones, +0 where it is zero (a bitwise select, no compare)
+__device__ __forceinline__ float keep_if(float v, int mask) { return __int_as_float(__float_as_int(v) & mask); }
+__device__ __forceinline__ double keep_if(double v, int mask) {
+    return __longlong_as_double(__double_as_longlong(v) & (long long)mask);
+}
+
 // SC: the scatter form (Algorithm 2's groups streamed): a batch's tiles come from any panels, each
 // tile has accumulators of its own (slot = its position in the batch), and after the batch every
 // tile's non-zero row sums are added into y with atomics (y was scaled by beta in a pre-pass).
@@ -955,23 +987,45 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
                 const int xo = (int)(m & 0x1FFu);
                 const int ao = SC ? (xo >> LT) * 16 * NACC + (NACC == 2 ? (lane & 1) << 4 : 0) : (int)((m >> 9) & 0x7Fu);
                 const bool half = (m >> 31) != 0u;
+                // the four x reads issued together: a code's column nibble, masked to the tile's width,
+                // names one of the tile's x slots, so an absent entry's read stays inside the x area.
+                // xb: each entry's x slot as a byte offset from the tile's first, one byte per entry
+                constexpr int XSH = sizeof(A) == 8 ? 3 : 2;
+                const uint32_t xb = (codes >> (4 - XSH)) & (0x01010101u * (uint32_t)((S - 1) << XSH));
+                const uint32_t x0 = (uint32_t)xo << XSH;
+                const char *xa = reinterpret_cast<const char *>(xarea);
+                A xq[4];
+                xq[0] = *reinterpret_cast<const A *>(xa + add_byte<0>(x0, xb));
+                xq[1] = *reinterpret_cast<const A *>(xa + add_byte<1>(x0, xb));
+                xq[2] = *reinterpret_cast<const A *>(xa + add_byte<2>(x0, xb));
+                xq[3] = *reinterpret_cast<const A *>(xa + add_byte<3>(x0, xb));
+                // rb: each entry's row accumulator as a byte offset from the slot's first
+                constexpr int ASH = sizeof(AC) == 8 ? 3 : 2;
+                const uint32_t rb = (codes << ASH) & (0x01010101u * (uint32_t)(15 << ASH));
+                const uint32_t a0 = (uint32_t)ao << ASH;
+                char *aa = reinterpret_cast<char *>(acc);
                 AC s = AC(0);
-                int run = (int)(codes & 15u);
+                uint32_t run = add_byte<0>(a0, rb);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const uint32_t code = (codes >> (8 * j)) & 0xFFu;
-                    const A xv = xarea[xo + (int)(code >> 4)];
-                    const bool ok = (vm >> j) & 1u;
-                    const A prod = ok ? quad_value<VT>(W[p], j, half) * xv : A(0);
-                    const int row = ok ? (int)(code & 15u) : run;
-                    if (row != run) {
-                        lds_add(&acc[ao + run], s);
+                    const uint32_t row = j == 0 ? run : j == 1 ? add_byte<1>(a0, rb) : j == 2 ? add_byte<2>(a0, rb)
+                                                                                              : add_byte<3>(a0, rb);
+                    // an absent entry adds a zero product.  With FP32 and BF16 values it also keeps the
+                    // current run.  With FP64 values (registers at their limit) it takes whatever row
+                    // its code byte names: absent entries only follow the present ones of a COO or CSR
+                    // tile (or sit in a Dense quad, whose four entries share one row), and every row
+                    // nibble names one of the slot's accumulators, so such a switch only adds zeros
+                    const int okm = bit_mask(vm, j);
+                    const A prod = keep_if(quad_value<VT>(W[p], j, half) * xq[j], okm);
+                    const uint32_t rk = VS == 8 ? row : (row & (uint32_t)okm) | (run & ~(uint32_t)okm);
+                    if (rk != run) {
+                        lds_add(reinterpret_cast<AC *>(aa + run), s);
                         s = AC(0);
-                        run = row;
+                        run = rk;
                     }
                     s += (AC)prod;
                 }
-                if (vm) lds_add(&acc[ao + run], s);
+                if (vm) lds_add(reinterpret_cast<AC *>(aa + run), s);
             }
         }
     };
@@ -1113,15 +1167,10 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJ
 }
 
 #ifndef CB_TUNE_QWAVES
-#define CB_TUNE_QWAVES 0  // > 0: ask for at least this many wavefronts per SIMD (register cap) in the quad kernel
-#endif
-#if CB_TUNE_QWAVES > 0
-#define CB_QWAVES_ATTR __attribute__((amdgpu_waves_per_eu(CB_TUNE_QWAVES)))
-#else
-#define CB_QWAVES_ATTR
+#define CB_TUNE_QWAVES 6  // natural-order quad kernel: at least this many wavefronts per SIMD (register cap)
 #endif
 template <int VT, bool AGG, int RR, int LT, bool SC>
-__global__ __launch_bounds__(kBlockThreads) CB_QWAVES_ATTR void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SC ? 1 : CB_TUNE_QWAVES))) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
                                                                    typename Val<VT>::A *__restrict__ y) {
