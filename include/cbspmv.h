@@ -123,9 +123,11 @@ typedef struct {
                                walking its panels' tiles; 2 = quads per lane (four consecutive
                                entries of one tile per lane, codes and values loaded straight into
                                registers; row_reduce 1 then means 0, each lane summing its own row
-                               runs); -1 (default) = automatic: 2 where the tiles hold 32 or more
-                               entries on average and their rows hold runs of two or more entries,
-                               else 0 */
+                               runs; it addresses x with 32-bit byte offsets, so 2 with more than
+                               2^29 - 16 columns is refused with CB_ERROR_NOT_SUPPORTED, as is
+                               lb_mode CB_LB_PAPER_STREAM, which runs it); -1 (default) = automatic:
+                               2 where the tiles hold 32 or more entries on average, their rows
+                               hold runs of two or more entries and n allows it, else 0 */
     int32_t tile_dim;       /* sub-block size S (Section 3.1 fixes 16): 0 (default) or 16 = 16 x 16
                                tiles, 8 = 8 x 8 tiles (panels of 8 rows, the same one-byte (row,
                                column) codes, 8 one-byte row starts per CSR tile, 64 values and an

@@ -16,6 +16,7 @@ constexpr int kTileAlign = 16;    // every tile region starts on a 16-byte bound
 // occupancy bitmap of a Dense S x S tile: one bit per element
 constexpr int dense_mask_bytes(int blk) { return blk * blk / 8; }
 constexpr int kTileCost = 8;      // per-tile overhead, in non-zero equivalents, for range balancing
+constexpr int64_t kQuadMaxCols = (int64_t(1) << 29) - 16;  // the quad kernel reads x at 32-bit byte offsets
 
 // load-balance modes whose wavefront ranges are contiguous byte ranges of the payload, cut into
 // batches (all but Algorithm 2's tile-at-a-time form), and those whose kernel order is the natural

@@ -439,6 +439,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         err = "the streamed Algorithm 2 order runs the quad kernel on 16 x 16 tiles";
         return CB_ERROR_NOT_SUPPORTED;
     }
+    if ((opt.spmv_kernel == 2 || opt.lb_mode == CB_LB_PAPER_STREAM) && n > kQuadMaxCols) {
+        err = "the quad kernel (spmv_kernel 2, lb_mode paper_stream) takes at most 2^29 - 16 columns";
+        return CB_ERROR_NOT_SUPPORTED;
+    }
     if (opt.tile_dim == 8 && opt.spmv_kernel == 1) {
         err = "the rows-per-lane kernel (spmv_kernel 1) takes 16 x 16 tiles only";
         return CB_ERROR_NOT_SUPPORTED;
@@ -585,7 +589,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // (stencils, power-law rows), whose quads are part empty and sum no runs
         if (opt.spmv_kernel < 0 && natural_lb(s.lb_mode)) {
             const bool long_runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
-            s.spmv_kernel = long_runs && nnz >= 32 * NT ? 2 : 0;
+            s.spmv_kernel = long_runs && nnz >= 32 * NT && n <= kQuadMaxCols ? 2 : 0;
         }
         if (s.lb_mode == CB_LB_PAPER_STREAM) s.spmv_kernel = 2;  // the quad kernel's scatter form
         if (opt.row_reduce >= 0) {

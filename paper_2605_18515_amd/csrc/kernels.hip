@@ -747,6 +747,17 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nr, kRsrcWord3);
 }
 
+// one value at byte offset off of a buffer (0 past its end)
+template <class A>
+__device__ __forceinline__ A buffer_value(rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(A) == 8) {
+        using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(A, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    } else {
+        return __builtin_bit_cast(A, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    }
+}
+
 // raw words of one quad's four values: FP64 two 16-byte loads, FP32 one, BF16 the three aligned
 // dwords around its eight bytes (BF16 values are 2-byte aligned)
 template <int VS>
@@ -895,31 +906,29 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         }
     };
 
-    // x of a batch whose first tile is tb (nt tiles), as in the streaming kernel
+    // x of a batch whose first tile is tb (nt tiles), as in the streaming kernel.  The tile columns
+    // and x are read through buffer resources: the range's tile columns (a load past the range's
+    // last tile returns 0, a valid column) and x (n below 2^29, so every column's byte offset fits
+    // 32 bits; a load past column n - 1 returns 0).  One offset per batch, a constant per gather.
+    constexpr int CW = AGG ? 4 * S : 4;  // bytes of tile columns per tile
+    const rsrc_t crs = AGG ? make_rsrc(d.tile_cols + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
+                           : make_rsrc(d.tile_col + t0, CW * (int64_t)(t1 - t0));
+    const rsrc_t xrs = make_rsrc(x, d.n * (int64_t)sizeof(A));
+    const int cl = AGG ? 4 * (S * gj + (glc & 3) * (S / 4) + (glc >> 2)) : 4 * gj;
     int RG[NG];
     auto issue_cols = [&](int tb, int nt) {
+        const int cb0 = CW * (tb - t0) + cl;
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            if (TPG * g < nt) {
-                const int t = min(tb + TPG * g + gj, t1 - 1);
-                RG[g] = AGG ? ld_stream<CB_TUNE_QCPOL != 0>(&d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)])
-                            : d.tile_col[t];
-            }
-        }
+        for (int g = 0; g < NG; ++g)
+            if (TPG * g < nt) RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
     };
     A XG[NG];
     auto issue_x = [&](int nt) {
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            if (TPG * g < nt) {
-                int col = RG[g];
-                if (!AGG) {
-                    const int64_t c = S * (int64_t)RG[g] + glc;
-                    col = c < d.n ? (int)c : 0;
-                }
-                XG[g] = x[col];
-            }
-        }
+        for (int g = 0; g < NG; ++g)
+            if (TPG * g < nt)
+                XG[g] = buffer_value<A>(xrs, ((uint32_t)RG[g] * (AGG ? 1u : (uint32_t)S) + (AGG ? 0u : (uint32_t)glc)) *
+                                                 (uint32_t)sizeof(A));
     };
     auto put_x = [&](int nt) {
 #pragma unroll

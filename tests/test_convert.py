@@ -472,3 +472,25 @@ def test_automatic_xcd_mapping():
         with pytest.raises(cb.CbError) as e:
             cb.CbMatrix.from_csr(lap, device=False, xcd_chunk=bad)
         assert e.value.status == cb.CB_ERROR_INVALID_VALUE
+
+
+def test_quad_kernel_column_limit():
+    # the quad kernel reads x at 32-bit byte offsets: 2^29 - 16 columns at most; beyond that the
+    # explicit request and the streamed Algorithm 2 order (which runs it) are refused, and the
+    # automatic choice takes the streaming kernel
+    lim = (1 << 29) - 16
+    for n, ok in ((lim, True), (lim + 1, False)):
+        m = 64
+        cols = np.stack([np.arange(m), n - 1 - np.arange(m)], 1).ravel().astype(np.int32)
+        A = matgen.Csr(m, n, np.arange(0, 2 * m + 1, 2, dtype=np.int64), cols, np.ones(2 * m))
+        for opts in ({"spmv_kernel": 2}, {"lb_mode": "paper_stream"}):
+            if ok:
+                M = host_matrix(A, **opts)
+                assert M.info["spmv_kernel"] == 2
+                M.close()
+            else:
+                with pytest.raises(cb.CbError, match="2\\^29"):
+                    host_matrix(A, **opts)
+        M = host_matrix(A)
+        assert M.info["spmv_kernel"] == 0
+        M.close()
