@@ -100,7 +100,10 @@ typedef struct {
     double th0;             /* super-sparse share that turns aggregation on (default 0.15) */
     int64_t wave_nnz;       /* target non-zeros per wavefront work range; 0 = automatic (about 5120
                                ranges, each of at least 256 non-zeros and at most about 18 KB of codes
-                               and values: 2048 FP64 entries, 3686 FP32, 4096 BF16).  An explicit
+                               and values: 2048 FP64 entries, 3686 FP32, 4096 BF16; where that
+                               cap binds, CB_LB_CONTIGUOUS ranges shrink over the last stretch of
+                               the matrix to about the remaining work / 2560, down to a quarter of
+                               the cap, so the last wavefronts finish close together).  An explicit
                                value so large that one range's packed tiles would span 2 GiB or
                                more is refused by cb_create with CB_ERROR_INVALID_VALUE (the
                                streaming kernel addresses a range with 32-bit offsets) */

@@ -424,6 +424,23 @@ def test_automatic_range_size():
         M.close()
     # FP64 entries (9 bytes) reach the cap, and get more, shorter ranges than FP32 (5 bytes) and BF16 (3)
     assert means["f64"] < means["f32"] == means["bf16"]
+    # where the cap binds, the ranges of the last stretch shrink to the remaining work / 2560, down to
+    # a quarter of the cap; the other ranges keep the target
+    for vt, tapered in (("f64", True), ("f32", False)):
+        M = cb.CbMatrix.from_csr(big, device=False, value_type=vt)
+        st = cb.cb_export_structure(M.handle)
+        w = np.add.reduceat(st["tile_nnz"].astype(np.int64) + 8, st["wave_ptr"][:-1])
+        rem = np.cumsum(w[::-1])[::-1]  # work from each range to the end
+        head = w[rem > 2560 * caps[vt]]
+        if tapered:
+            tail = w[rem < 2560 * caps[vt] // 8]
+            assert len(tail) > 100 and tail.mean() < 0.5 * head.mean(), (tail.mean(), head.mean())
+            # cut at panel boundaries (a panel here is about 400): about a quarter of the cap, not less
+            assert 0.6 * caps[vt] / 4 <= np.median(tail) <= caps[vt] / 4, np.median(tail)
+        else:
+            last = w[-len(w) // 8:]
+            assert abs(last.mean() - w.mean()) < 0.05 * w.mean(), (last.mean(), w.mean())
+        M.close()
     # an explicit wave_nnz overrides the rule
     M = cb.CbMatrix.from_csr(big, device=False, wave_nnz=500)
     assert M.info["wave_nnz_mean"] <= 600
