@@ -101,9 +101,10 @@ typedef struct {
     int64_t wave_nnz;       /* target non-zeros per wavefront work range; 0 = automatic (about 5120
                                ranges, each of at least 256 non-zeros and at most about 18 KB of codes
                                and values: 2048 FP64 entries, 3686 FP32, 4096 BF16; where that
-                               cap binds, CB_LB_CONTIGUOUS ranges shrink over the last stretch of
-                               the matrix to about the remaining work / 2560, down to a quarter of
-                               the cap, so the last wavefronts finish close together).  An explicit
+                               cap binds and the XCDs do not take an eighth of the ranges each
+                               (xcd_chunk 0), CB_LB_CONTIGUOUS ranges shrink over the last stretch
+                               of the matrix to about the remaining work / 2560, down to a quarter
+                               of the cap, so the last wavefronts finish close together).  An explicit
                                value so large that one range's packed tiles would span 2 GiB or
                                more is refused by cb_create with CB_ERROR_INVALID_VALUE (the
                                streaming kernel addresses a range with 32-bit offsets) */
@@ -144,7 +145,18 @@ typedef struct {
                                c consecutive ranges, the XCDs side by side; 0 = each XCD one
                                contiguous eighth of the ranges; -1 (default) = automatic.  Results
                                do not depend on it. */
-    int32_t reserved32;
+    int32_t cols16;         /* under column aggregation, how the SpMV kernels that stream work
+                               ranges (spmv_kernel 0 and 2, lb_mode contiguous, none and
+                               paper_stream, and the serving loop's batched products) read a tile's
+                               original columns: as a 4-byte base per tile (its first column) and
+                               2-byte offsets from it (2 tile_dim + 4 bytes per tile instead of
+                               4 tile_dim), possible when every tile's columns span less than
+                               65,536, or as 4-byte columns.  0 (default) = automatic: the 2-byte
+                               form where possible, except for the quad kernel with double vectors
+                               (its registers are at the limit of six wavefronts per SIMD: 4-byte
+                               columns measured faster); 1 = the 2-byte form where possible; -1 =
+                               always 4-byte columns.  Other values: CB_ERROR_INVALID_VALUE.  Results
+                               do not depend on it. */
     int64_t reserved[3];
 } cb_options_t;
 
@@ -188,7 +200,7 @@ typedef struct {
     int32_t spmv_kernel;    /* the resolved spmv_kernel option (0, 1 or 2) */
     int32_t tile_dim;       /* sub-block size S of the structure (16 or 8) */
     int32_t xcd_chunk;      /* the resolved xcd_chunk option */
-    int32_t reserved32;
+    int32_t cols16;         /* 1 when the SpMV kernels read 2-byte column offsets (the cols16 option) */
     int64_t reserved[2];
 } cb_info_t;
 
@@ -217,7 +229,11 @@ typedef struct {
                                 followed by a 16-byte record per tile (CB_LB_PAPER: none) */
     int32_t *batch_ptr;      /* first record of each work range, nwaves + 1 (CB_LB_PAPER: none) */
     int32_t *tile_cols;      /* aggregation with the streaming kernel: tile_dim original columns per
-                                tile in kernel order, tile_dim * ntiles (else none) */
+                                tile in kernel order, tile_dim * ntiles (else none); column c of a
+                                tile at position (c mod 4) * tile_dim / 4 + c / 4 */
+    int32_t *tile_cbase;     /* cols16 only: each tile's first original column, ntiles (else none) */
+    uint16_t *tile_c16;      /* cols16 only: column c of each tile minus its base at position c,
+                                tile_dim * ntiles (columns past the tile's last: 0) */
 } cb_structure_t;
 
 /* Fill *opt with the defaults above (the paper's thresholds). */

@@ -50,7 +50,7 @@ class CbOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
                 ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
                 ("wave_nnz", _i64), ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32),
-                ("tile_dim", _i32), ("xcd_chunk", _i32), ("reserved32", _i32), ("reserved", _i64 * 3)]
+                ("tile_dim", _i32), ("xcd_chunk", _i32), ("cols16", _i32), ("reserved", _i64 * 3)]
 
 
 class CbInfo(ctypes.Structure):
@@ -64,13 +64,14 @@ class CbInfo(ctypes.Structure):
                 ("spmv_bytes", _i64), ("device_bytes", _i64), ("convert_seconds", _dbl), ("on_device", _i32),
                 ("reserved0", _i32), ("nbatches", _i64), ("stream_bytes", _i64), ("flat_run_mean", _dbl),
                 ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32), ("tile_dim", _i32),
-                ("xcd_chunk", _i32), ("reserved32", _i32), ("reserved", _i64 * 2)]
+                ("xcd_chunk", _i32), ("cols16", _i32), ("reserved", _i64 * 2)]
 
 
 class CbStructure(ctypes.Structure):
     _fields_ = [(n, _p) for n in ("tile_row", "tile_col", "tile_nnz", "tile_vp", "tile_type", "tile_ori", "payload",
                                   "restore_cols", "cols_offset", "quantum_ptr", "wave_ptr", "panel_shared",
-                                  "prepass_list", "tile_xoff", "batch_stream", "batch_ptr", "tile_cols")]
+                                  "prepass_list", "tile_xoff", "batch_stream", "batch_ptr", "tile_cols",
+                                  "tile_cbase", "tile_c16")]
 
 
 class CbCgOptions(ctypes.Structure):
@@ -364,6 +365,8 @@ def cb_export_structure(A: int) -> dict:
         "batch_stream": np.empty(info["stream_bytes"] // 4, np.int32),
         "batch_ptr": np.empty(info["nwaves"] + 1 if info["lb_mode"] != CB_LB_PAPER else 0, np.int32),
         "tile_cols": np.empty(info["tile_dim"] * NT if info["lb_mode"] != CB_LB_PAPER and info["col_agg"] else 0, np.int32),
+        "tile_cbase": np.empty(NT if info["cols16"] else 0, np.int32),
+        "tile_c16": np.empty(info["tile_dim"] * NT if info["cols16"] else 0, np.uint16),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})
     _check(_lib.cb_export_structure(A, ctypes.byref(s)))

@@ -36,7 +36,8 @@ cb_status_t hip_fail(hipError_t e, const char *what) {
 // byte offsets of every array inside the single device allocation
 struct Layout {
     size_t tile_row, tile_col, tile_nnz, tile_vp, tile_type, tile_ori, tile_xoff, payload, restore_cols, cols_offset, wave_ptr,
-        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, tile_rec, panel_tile, total;
+        quantum_ptr, panel_shared, prepass_list, batch_stream, batch_ptr, tile_cols, tile_rec, panel_tile,
+        tile_cbase, tile_c16, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -72,6 +73,8 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)s.blk * NT : 0);
     L.tile_rec = put(natural ? 16 * NT : 0);
     L.panel_tile = put(natural ? 4 * ((size_t)s.npanels + 1) : 0);
+    L.tile_cbase = put(s.cols16 ? 4 * NT : 0);
+    L.tile_c16 = put(s.cols16 ? 2 * (size_t)s.blk * NT : 0);
     L.total = off;
     return L;
 }
@@ -162,6 +165,8 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
         put_array(stage, L.tile_cols, s.tile_cols);
         put_array(stage, L.tile_rec, s.tile_rec);
         put_array(stage, L.panel_tile, s.panel_tile);
+        put_array(stage, L.tile_cbase, s.tile_cbase);
+        put_array(stage, L.tile_c16, s.tile_c16);
         e = hipMalloc(&A->dbuf, L.total);
         if (e != hipSuccess) {
             A->dbuf = nullptr;
@@ -191,12 +196,14 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.tile_cols = dptr<int32_t>(A, L.tile_cols);
     v.tile_rec = dptr<int32_t>(A, L.tile_rec);
     v.panel_tile = dptr<int32_t>(A, L.panel_tile);
+    v.tile_cbase = dptr<int32_t>(A, L.tile_cbase);
+    v.tile_c16 = dptr<uint16_t>(A, L.tile_c16);
     v.m = s.m;
     v.n = s.n;
     v.nwaves = (int32_t)s.nwaves;
     v.npanels = (int32_t)s.npanels;
     v.nprepass = (int32_t)s.nprepass;
-    v.col_agg = s.col_agg;
+    v.col_agg = s.col_agg ? (s.cols16 ? 2 : 1) : 0;
     v.natural_order = cbh::natural_lb(s.lb_mode) ? 1 : 0;
     v.scatter = s.lb_mode == CB_LB_PAPER_STREAM ? 1 : 0;
     v.row_reduce = s.row_reduce;
@@ -225,6 +232,8 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     std::vector<int32_t>().swap(s.tile_cols);
     std::vector<int32_t>().swap(s.tile_rec);
     std::vector<int32_t>().swap(s.panel_tile);
+    std::vector<int32_t>().swap(s.tile_cbase);
+    std::vector<uint16_t>().swap(s.tile_c16);
     A->on_device = true;
     return CB_SUCCESS;
 }
@@ -270,6 +279,8 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.tile_cols, cbh::streamed_lb(A->h.lb_mode) && A->h.col_agg ? (size_t)A->h.blk * NT : 0,
                     tmp.tile_cols)) != CB_SUCCESS)
         return st;
+    if ((st = fetch(A, L.tile_cbase, A->h.cols16 ? NT : 0, tmp.tile_cbase)) != CB_SUCCESS) return st;
+    if ((st = fetch(A, L.tile_c16, A->h.cols16 ? (size_t)A->h.blk * NT : 0, tmp.tile_c16)) != CB_SUCCESS) return st;
     s = &tmp;
     return CB_SUCCESS;
 }
@@ -418,6 +429,8 @@ cb_status_t cb_export_structure(cb_matrix_t A, const cb_structure_t *o) {
     cp(o->batch_stream, s->batch_stream);
     cp(o->batch_ptr, s->batch_ptr);
     cp(o->tile_cols, s->tile_cols);
+    cp(o->tile_cbase, s->tile_cbase);
+    cp(o->tile_c16, s->tile_c16);
     return CB_SUCCESS;
 }
 
@@ -457,7 +470,7 @@ cb_status_t matrix_view(cb_matrix_t A, MatrixView &out) {
     out.kernel_vt = kernel_vtype(A->h);
     out.vtype = A->h.vtype;
     out.vector_f64 = A->h.vector_f64;
-    out.col_agg = A->h.col_agg;
+    out.col_agg = A->view.col_agg;
     out.row_reduce = A->h.row_reduce;
     out.natural = cbh::natural_lb(A->h.lb_mode);
     out.device = A->device;

@@ -27,13 +27,18 @@ struct DevView {
     const int32_t *tile_cols;     // natural order with col_agg: S original columns per tile
     const int32_t *tile_rec;      // natural order: {vp low, vp high | type << 16 | (nnz - 1) << 18, panel, column block}
     int64_t m, n;
-    int32_t nwaves, npanels, nprepass, col_agg;
+    int32_t nwaves, npanels, nprepass;
+    int32_t col_agg;              // 0 none; 1 aggregated, S 4-byte original columns per tile (tile_cols);
+                                  // 2 aggregated, the streaming and quad kernels read tile_cbase +
+                                  // tile_c16 (the other kernels tile_cols, also present)
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan,
                                   // 2 FP64 LDS atomics, 3 and 4 = 0 and 2 with two accumulator copies
     int32_t spmv_kernel;          // natural order: 0 the streaming kernel, 1 rows per lane, 2 the quad kernel
                                   // (batch_stream then holds quad batches)
     const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
+    const int32_t *tile_cbase;    // col_agg 2: first original column of each tile
+    const uint16_t *tile_c16;     // col_agg 2: S column offsets from it per tile, natural column order
     int32_t tile_lt;              // log2 of the tile size S: 4 (16 x 16 tiles) or 3 (8 x 8)
     int32_t scatter;              // Algorithm 2's groups streamed (CB_LB_PAPER_STREAM): quad batches in
                                   // scatter form, every tile's rows added into y with atomics

@@ -51,6 +51,11 @@ struct HostStructure {
     std::vector<int32_t> batch_stream, batch_ptr;
     // column aggregation with the streaming kernel: S original columns per tile, kernel order
     std::vector<int32_t> tile_cols;
+    // cols16: every tile's first original column, and its S columns as offsets from it (natural
+    // column order; columns past the tile's last: 0), read by the SpMV kernels instead of tile_cols
+    int cols16 = 0;
+    std::vector<int32_t> tile_cbase;
+    std::vector<uint16_t> tile_c16;
     // natural-order modes: one 16-byte record per tile for the k-right-hand-side kernel
     // {vp low word, vp high 16 bits | type << 16 | (nnz - 1) << 18, panel, column block}
     std::vector<int32_t> tile_rec;

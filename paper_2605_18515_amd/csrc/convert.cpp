@@ -32,7 +32,8 @@
 #ifndef CB_TUNE_WAVE_RANGES
 #define CB_TUNE_WAVE_RANGES 5120
 #endif
-// Matrices whose automatic ranges reach the cap run several rounds of wavefronts; there the ranges
+// Matrices whose automatic ranges reach the cap run several rounds of wavefronts; there (unless each
+// XCD takes an eighth of the ranges) the ranges
 // of the last stretch shrink (guided self-scheduling: the remaining work / 2560, down to a quarter
 // of the cap), so the last wavefronts to start end soon after the others instead of a whole range
 // later.  Measured on the 3D block matrix: SpMM k = 8 and 32 7-8 % faster (FP32 and BF16 values),
@@ -197,6 +198,7 @@ void moments(const std::vector<int64_t> &v, int64_t &mx, double &mean, double &s
 }
 
 void build_tile_cols(HostStructure &s);
+void build_tile_c16(HostStructure &s, int mode);
 
 // Batches of the streaming kernel (format in cb_stream.h): every work range
 // is cut, in order, into runs of at most kBatchTiles tiles whose payload bytes
@@ -309,6 +311,40 @@ void build_tile_cols(HostStructure &s) {
                     s.restore_cols[(size_t)(c < width ? base + c : s.cols_offset[p])];
         }
     }
+}
+
+// cols16: each tile's first original column and its S columns as 16-bit offsets from it, when every
+// tile's columns span less than 65,536 (stencil and block operators: a tile holds consecutive
+// aggregated columns of one panel, which lie in one neighbourhood of the diagonal); columns past the
+// tile's last are offset 0.  Built from tile_cols, in the same kernel order.  Automatic (mode 0):
+// not for the quad kernel with double vectors, whose registers are at the limit of six wavefronts
+// per SIMD (one more register per gather: 3D block matrix FP64 155 against 129 us); elsewhere the
+// 2-byte form measured faster (192^3 Poisson, streaming kernel: FP64 148 against 159 us, FP32 108
+// against 118; 3D block matrix, quad kernel: FP32 82 against 85, BF16 70 against 73).
+void build_tile_c16(HostStructure &s, int mode) {
+    const int S = s.blk;
+    s.cols16 = 0;
+    s.tile_cbase.clear();
+    s.tile_c16.clear();
+    if (!s.col_agg || mode < 0 || s.ntiles == 0) return;
+    const bool quad = s.spmv_kernel == 2 || s.lb_mode == CB_LB_PAPER_STREAM;
+    if (mode == 0 && quad && s.vector_f64) return;
+    std::vector<int32_t> base((size_t)s.ntiles);
+    std::vector<uint16_t> off((size_t)s.ntiles * S);
+    for (int64_t t = 0; t < s.ntiles; ++t) {
+        const int64_t p = s.tile_row[t], first = s.cols_offset[p] + (int64_t)S * s.tile_col[t];
+        const int64_t width = std::min<int64_t>(S, s.cols_offset[p + 1] - first);
+        const int64_t b = s.restore_cols[(size_t)first];
+        base[(size_t)t] = (int32_t)b;
+        for (int c = 0; c < S; ++c) {
+            const int64_t o = c < width ? (int64_t)s.restore_cols[(size_t)(first + c)] - b : 0;
+            if (o < 0 || o > 0xFFFF) return;  // a tile spans 65,536 columns or more: 4-byte columns
+            off[(size_t)(t * S + c)] = (uint16_t)o;
+        }
+    }
+    s.cols16 = 1;
+    s.tile_cbase.swap(base);
+    s.tile_c16.swap(off);
 }
 
 // Quad batches of the quad kernel (format in cb_stream.h), written to batch_stream / batch_ptr in
@@ -447,6 +483,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
     if (opt.xcd_chunk < -1 || opt.xcd_chunk > (1 << 20)) { err = "xcd_chunk must be -1 .. 2^20"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.cols16 < -1 || opt.cols16 > 1) { err = "cols16 must be -1, 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.tile_dim != 0 && opt.tile_dim != 8 && opt.tile_dim != 16) { err = "tile_dim must be 0, 8 or 16"; return CB_ERROR_INVALID_VALUE; }
     if (opt.lb_mode == CB_LB_PAPER_STREAM && (opt.tile_dim == 8 || (opt.spmv_kernel >= 0 && opt.spmv_kernel != 2))) {
         err = "the streamed Algorithm 2 order runs the quad kernel on 16 x 16 tiles";
@@ -735,7 +772,9 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             const int64_t cap = std::min<int64_t>(4096, CB_TUNE_MAX_RANGE_BYTES / (1 + s.vsize));
             target = std::min<int64_t>(cap, std::max<int64_t>(CB_TUNE_MIN_WAVE_NNZ,
                                                               (total_w + CB_TUNE_WAVE_RANGES - 1) / CB_TUNE_WAVE_RANGES));
-            taper = target == cap;
+            // not under the eighths mapping: it deals the XCDs equal counts of ranges, and shorter
+            // ranges at the end would leave the last XCD less work (power-law rows 626 against 584 us)
+            taper = target == cap && s.xcd_chunk != 0;
         }
         auto tw = [&](int32_t i) { return (int64_t)nnzv[i] + kTileCost; };
 
@@ -883,6 +922,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                 build_stream(s);
                 if (s.spmv_kernel == 2) build_qstream(s, false);
             }
+            build_tile_c16(s, opt.cols16);
         }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed during conversion";
@@ -975,7 +1015,7 @@ int64_t spmv_bytes(const HostStructure &s) {
         // column block per tile), two range pointers per range and the first tile's offset and the end
         // panels' flags, pre-pass list
         b += 16 * s.nrecords;
-        b += s.col_agg ? 4 * (int64_t)s.blk * s.ntiles : 4 * s.ntiles;
+        b += s.col_agg ? (s.cols16 ? 2 * (int64_t)s.blk + 4 : 4 * (int64_t)s.blk) * s.ntiles : 4 * s.ntiles;
         b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
         // scatter form: the pre-pass writes y, the atomics read and write it again
         if (s.lb_mode == CB_LB_PAPER_STREAM) b += 2 * xe * s.m;
@@ -1020,6 +1060,7 @@ void fill_info(const HostStructure &s, cb_info_t &info) {
     info.vector_f64 = s.vector_f64;
     info.spmv_kernel = s.spmv_kernel;
     info.xcd_chunk = s.xcd_chunk;
+    info.cols16 = s.cols16;
     info.tile_dim = s.blk;
 }
 

@@ -374,7 +374,7 @@ constexpr int kWaitVm0 = 0x0F70;  // s_waitcnt vmcnt(0), expcnt and lgkmcnt left
 // often on one LDS address; the copies are added when the panel is written)
 // One work range w of the structure d (the body of the streaming kernel, shared by the one-matrix
 // and the batched launch).  LT: log2 of the tile size S (4: 16 x 16 tiles, 3: 8 x 8).
-template <int VT, bool AGG, int RR, int LT>
+template <int VT, int AGG, int RR, int LT>
 __device__ __forceinline__ void stream_range(const DevView &d, int w, typename Val<VT>::A alpha,
                                              typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                              typename Val<VT>::A *__restrict__ y) {
@@ -443,15 +443,23 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     // glc.  The column indices are loaded one step before the x values: under aggregation the tiles'
     // original columns (tile_cols, 256 contiguous bytes per gather), else the tiles' column blocks.
     // Columns past a tile's last one read a valid column of the matrix and are never multiplied.
+    // Compressed columns (AGG 2): the lane's 2-byte offset and its tile's base, both vector loads (a
+    // scalar load would make every later LDS read wait for it: the two share one counter).
     constexpr int NG = (kBatchTiles + TPG - 1) / TPG;
     int RG[NG];
+    int RB[NG];
     auto issue_cols = [&](int tb, int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (TPG * g < nt) {
                 const int t = min(tb + TPG * g + gj, t1 - 1);
-                RG[g] = AGG ? ld_stream<CB_TUNE_NT_LOADS != 0>(&d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)])
-                            : d.tile_col[t];
+                if constexpr (AGG == 2) {
+                    RG[g] = (int)ld_stream<CB_TUNE_NT_LOADS != 0>(&d.tile_c16[S * (size_t)t + glc]);
+                    RB[g] = ld_stream<CB_TUNE_NT_LOADS != 0>(&d.tile_cbase[t]);
+                } else {
+                    RG[g] = AGG ? ld_stream<CB_TUNE_NT_LOADS != 0>(&d.tile_cols[S * (size_t)t + (glc & 3) * (S / 4) + (glc >> 2)])
+                                : d.tile_col[t];
+                }
             }
         }
     };
@@ -461,7 +469,9 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
         for (int g = 0; g < NG; ++g) {
             if (TPG * g < nt) {
                 int col = RG[g];
-                if (!AGG) {
+                if constexpr (AGG == 2) {
+                    col += RB[g];
+                } else if constexpr (!AGG) {
                     const int64_t c = S * (int64_t)RG[g] + glc;
                     col = c < d.n ? (int)c : 0;
                 }
@@ -694,7 +704,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     flush();
 }
 
-template <int VT, bool AGG, int RR, int LT>
+template <int VT, int AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, typename Val<VT>::A alpha,
                                                                      typename Val<VT>::A beta,
                                                                      const typename Val<VT>::A *__restrict__ x,
@@ -707,7 +717,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_stream_kernel(DevView d, t
 // Products of several matrices in one launch (the serving loop's batches): workgroup b, after the
 // XCD remap, runs work range b - jobs[j].wave_base of job j = wave_job[b]; every job of a launch has
 // the same value type, aggregation, row-sum mode and tile size.
-template <int VT, bool AGG, int RR, int LT>
+template <int VT, int AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_batch_kernel(const BatchJob *__restrict__ jobs,
                                                                     const int32_t *__restrict__ wave_job, int total) {
     static_assert(kWavesPerBlock == 1, "one work range per workgroup");
@@ -840,7 +850,7 @@ __device__ __forceinline__ double keep_if(double v, int mask) {
 // SC: the scatter form (Algorithm 2's groups streamed): a batch's tiles come from any panels, each
 // tile has accumulators of its own (slot = its position in the batch), and after the batch every
 // tile's non-zero row sums are added into y with atomics (y was scaled by beta in a pre-pass).
-template <int VT, bool AGG, int RR, int LT, bool SC = false>
+template <int VT, int AGG, int RR, int LT, bool SC = false>
 __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename Val<VT>::A alpha,
                                               typename Val<VT>::A beta, const typename Val<VT>::A *__restrict__ x,
                                               typename Val<VT>::A *__restrict__ y) {
@@ -910,25 +920,41 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     // and x are read through buffer resources: the range's tile columns (a load past the range's
     // last tile returns 0, a valid column) and x (n below 2^29, so every column's byte offset fits
     // 32 bits; a load past column n - 1 returns 0).  One offset per batch, a constant per gather.
-    constexpr int CW = AGG ? 4 * S : 4;  // bytes of tile columns per tile
-    const rsrc_t crs = AGG ? make_rsrc(d.tile_cols + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
-                           : make_rsrc(d.tile_col + t0, CW * (int64_t)(t1 - t0));
+    // Compressed columns (AGG 2): 2-byte offsets and 4-byte bases, each through a resource over the
+    // range's tiles (past the range's last tile both read 0: column 0)
+    constexpr int CW = AGG == 2 ? 2 * S : AGG ? 4 * S : 4;  // bytes of tile columns per tile
+    const rsrc_t crs = AGG == 2 ? make_rsrc(d.tile_c16 + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
+                       : AGG    ? make_rsrc(d.tile_cols + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
+                                : make_rsrc(d.tile_col + t0, CW * (int64_t)(t1 - t0));
+    const rsrc_t brs = make_rsrc(AGG == 2 ? d.tile_cbase + t0 : d.tile_col, 4 * (int64_t)(t1 - t0));
     const rsrc_t xrs = make_rsrc(x, d.n * (int64_t)sizeof(A));
-    const int cl = AGG ? 4 * (S * gj + (glc & 3) * (S / 4) + (glc >> 2)) : 4 * gj;
+    const int cl = AGG == 2 ? 2 * (S * gj + glc) : AGG ? 4 * (S * gj + (glc & 3) * (S / 4) + (glc >> 2)) : 4 * gj;
     int RG[NG];
+    int RB[NG];
     auto issue_cols = [&](int tb, int nt) {
         const int cb0 = CW * (tb - t0) + cl;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (TPG * g < nt) RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
+            if (TPG * g < nt) {
+                if constexpr (AGG == 2) {
+                    RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b16(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
+                    RB[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(brs, 4 * (tb - t0 + TPG * g + gj), 0,
+                                                                       CB_TUNE_QCPOL);
+                } else {
+                    RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
+                }
+            }
     };
     A XG[NG];
     auto issue_x = [&](int nt) {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (TPG * g < nt)
-                XG[g] = buffer_value<A>(xrs, ((uint32_t)RG[g] * (AGG ? 1u : (uint32_t)S) + (AGG ? 0u : (uint32_t)glc)) *
-                                                 (uint32_t)sizeof(A));
+            if (TPG * g < nt) {
+                uint32_t col;
+                if constexpr (AGG == 2) col = (uint32_t)(RG[g] + RB[g]);
+                else col = (uint32_t)RG[g] * (AGG ? 1u : (uint32_t)S) + (AGG ? 0u : (uint32_t)glc);
+                XG[g] = buffer_value<A>(xrs, col * (uint32_t)sizeof(A));
+            }
     };
     auto put_x = [&](int nt) {
 #pragma unroll
@@ -1165,7 +1191,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
 }
 
 // The serving loop's batched launch for quad-batch structures (as spmv_batch_kernel)
-template <int VT, bool AGG, int RR, int LT>
+template <int VT, int AGG, int RR, int LT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJob *__restrict__ jobs,
                                                                      const int32_t *__restrict__ wave_job, int total) {
     using A = typename Val<VT>::A;
@@ -1178,7 +1204,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJ
 #ifndef CB_TUNE_QWAVES
 #define CB_TUNE_QWAVES 6  // natural-order quad kernel: at least this many wavefronts per SIMD (register cap)
 #endif
-template <int VT, bool AGG, int RR, int LT, bool SC>
+template <int VT, int AGG, int RR, int LT, bool SC>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SC ? 1 : CB_TUNE_QWAVES))) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
@@ -1609,19 +1635,17 @@ hipError_t spmv_stream_launch(const DevView &d, typename Val<VT>::A a, typename 
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
     };
-    if (d.col_agg) {
-        if (rr == 1) go(spmv_stream_kernel<VT, true, 1, LT>);
-        else if (rr == 2) go(spmv_stream_kernel<VT, true, kRR2, LT>);
-        else if (rr == 3) go(spmv_stream_kernel<VT, true, 3, LT>);
-        else if (rr == 4) go(spmv_stream_kernel<VT, true, kRR4, LT>);
-        else go(spmv_stream_kernel<VT, true, 0, LT>);
-    } else {
-        if (rr == 1) go(spmv_stream_kernel<VT, false, 1, LT>);
-        else if (rr == 2) go(spmv_stream_kernel<VT, false, kRR2, LT>);
-        else if (rr == 3) go(spmv_stream_kernel<VT, false, 3, LT>);
-        else if (rr == 4) go(spmv_stream_kernel<VT, false, kRR4, LT>);
-        else go(spmv_stream_kernel<VT, false, 0, LT>);
-    }
+    auto by_rr = [&](auto agg) {
+        constexpr int AG = decltype(agg)::value;
+        if (rr == 1) go(spmv_stream_kernel<VT, AG, 1, LT>);
+        else if (rr == 2) go(spmv_stream_kernel<VT, AG, kRR2, LT>);
+        else if (rr == 3) go(spmv_stream_kernel<VT, AG, 3, LT>);
+        else if (rr == 4) go(spmv_stream_kernel<VT, AG, kRR4, LT>);
+        else go(spmv_stream_kernel<VT, AG, 0, LT>);
+    };
+    if (d.col_agg == 2) by_rr(std::integral_constant<int, 2>());
+    else if (d.col_agg) by_rr(std::integral_constant<int, 1>());
+    else by_rr(std::integral_constant<int, 0>());
     return hipGetLastError();
 }
 
@@ -1635,17 +1659,16 @@ hipError_t spmv_quad_launch(const DevView &d, typename Val<VT>::A a, typename Va
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlockThreads), 0, s, d, a, b, (const A *)x, (A *)y);
     };
-    if (d.col_agg) {
-        if (rr == 2) go(spmv_quad_kernel<VT, true, kRR2, LT, SC>);
-        else if (rr == 3) go(spmv_quad_kernel<VT, true, 3, LT, SC>);
-        else if (rr == 4) go(spmv_quad_kernel<VT, true, kRR4, LT, SC>);
-        else go(spmv_quad_kernel<VT, true, 0, LT, SC>);
-    } else {
-        if (rr == 2) go(spmv_quad_kernel<VT, false, kRR2, LT, SC>);
-        else if (rr == 3) go(spmv_quad_kernel<VT, false, 3, LT, SC>);
-        else if (rr == 4) go(spmv_quad_kernel<VT, false, kRR4, LT, SC>);
-        else go(spmv_quad_kernel<VT, false, 0, LT, SC>);
-    }
+    auto by_rr = [&](auto agg) {
+        constexpr int AG = decltype(agg)::value;
+        if (rr == 2) go(spmv_quad_kernel<VT, AG, kRR2, LT, SC>);
+        else if (rr == 3) go(spmv_quad_kernel<VT, AG, 3, LT, SC>);
+        else if (rr == 4) go(spmv_quad_kernel<VT, AG, kRR4, LT, SC>);
+        else go(spmv_quad_kernel<VT, AG, 0, LT, SC>);
+    };
+    if (d.col_agg == 2) by_rr(std::integral_constant<int, 2>());
+    else if (d.col_agg) by_rr(std::integral_constant<int, 1>());
+    else by_rr(std::integral_constant<int, 0>());
     return hipGetLastError();
 }
 
@@ -2026,7 +2049,7 @@ hipError_t launch_spmm(const DevView &d, int vtype, int k, double alpha, const v
 }
 
 namespace {
-template <int VT, bool AGG, int LT>
+template <int VT, int AGG, int LT>
 hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, int quad, hipStream_t s) {
     constexpr bool kWide = std::is_same<typename Val<VT>::A, double>::value;
     const dim3 grid((unsigned)total), block(kBlockThreads);
@@ -2059,10 +2082,12 @@ template <int VT>
 hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, int quad, int lt,
                     hipStream_t s) {
     if (lt == 3)
-        return agg ? batch_rr<VT, true, 3>(jobs, wave_job, total, rr, quad, s)
-                   : batch_rr<VT, false, 3>(jobs, wave_job, total, rr, quad, s);
-    return agg ? batch_rr<VT, true, 4>(jobs, wave_job, total, rr, quad, s)
-               : batch_rr<VT, false, 4>(jobs, wave_job, total, rr, quad, s);
+        return agg == 2 ? batch_rr<VT, 2, 3>(jobs, wave_job, total, rr, quad, s)
+               : agg    ? batch_rr<VT, 1, 3>(jobs, wave_job, total, rr, quad, s)
+                        : batch_rr<VT, 0, 3>(jobs, wave_job, total, rr, quad, s);
+    return agg == 2 ? batch_rr<VT, 2, 4>(jobs, wave_job, total, rr, quad, s)
+           : agg    ? batch_rr<VT, 1, 4>(jobs, wave_job, total, rr, quad, s)
+                    : batch_rr<VT, 0, 4>(jobs, wave_job, total, rr, quad, s);
 }
 }  // namespace
 

@@ -425,9 +425,10 @@ def test_automatic_range_size():
     # FP64 entries (9 bytes) reach the cap, and get more, shorter ranges than FP32 (5 bytes) and BF16 (3)
     assert means["f64"] < means["f32"] == means["bf16"]
     # where the cap binds, the ranges of the last stretch shrink to the remaining work / 2560, down to
-    # a quarter of the cap; the other ranges keep the target
-    for vt, tapered in (("f64", True), ("f32", False)):
-        M = cb.CbMatrix.from_csr(big, device=False, value_type=vt)
+    # a quarter of the cap; the other ranges keep the target; not when each XCD takes an eighth of the
+    # ranges (equal counts: shorter ranges would leave the last XCD less work)
+    for vt, tapered, kw in (("f64", True, {}), ("f32", False, {}), ("f64", False, {"xcd_chunk": 0})):
+        M = cb.CbMatrix.from_csr(big, device=False, value_type=vt, **kw)
         st = cb.cb_export_structure(M.handle)
         w = np.add.reduceat(st["tile_nnz"].astype(np.int64) + 8, st["wave_ptr"][:-1])
         rem = np.cumsum(w[::-1])[::-1]  # work from each range to the end
@@ -488,6 +489,56 @@ def test_automatic_xcd_mapping():
     for bad in (-2, 1 << 21):
         with pytest.raises(cb.CbError) as e:
             cb.CbMatrix.from_csr(lap, device=False, xcd_chunk=bad)
+        assert e.value.status == cb.CB_ERROR_INVALID_VALUE
+
+
+def test_compressed_tile_columns():
+    """cols16: where every tile's original columns span less than 65,536 (stencil and block
+    operators), the SpMV kernels read a 4-byte base and 2-byte offsets per tile; decoded, they are
+    the tile's columns (tile_cols), padding columns at offset 0; the structure counts 2 S + 4 bytes
+    per tile instead of 4 S.  Scattered far columns (power-law rows), no aggregation, Algorithm 2's
+    tile-at-a-time order and cols16 = -1 keep 4-byte columns."""
+    for A, S in ((matgen.block_3d(12, seed=3), 16), (matgen.poisson_3d(24), 16), (matgen.poisson_3d(24), 8),
+                 (matgen.laplacian_2d(64), 16)):
+        kw = {"col_agg": 1, "tile_dim": S, "cols16": 1}
+        for lb in ("contiguous", "paper_stream") if S == 16 else ("contiguous",):
+            M = cb.CbMatrix.from_csr(A, device=False, lb_mode=lb, **kw)
+            i = M.info
+            assert i["cols16"] == 1, (A.n, S, lb)
+            st = cb.cb_export_structure(M.handle)
+            nt = i["ntiles"]
+            cols = st["tile_cols"].reshape(nt, 4, S // 4).transpose(0, 2, 1).reshape(nt, S)  # natural order
+            dec = st["tile_cbase"][:, None].astype(np.int64) + st["tile_c16"].reshape(nt, S)
+            p, c = st["tile_row"], st["tile_col"]
+            first = st["cols_offset"][p] + S * c
+            width = np.minimum(S, st["cols_offset"][p + 1] - first)
+            real = np.arange(S)[None, :] < width[:, None]
+            assert np.array_equal(dec[real], cols[real])
+            assert np.all(st["tile_c16"].reshape(nt, S)[~real] == 0)
+            assert np.array_equal(st["tile_cbase"], cols[:, 0])
+            M0 = cb.CbMatrix.from_csr(A, device=False, lb_mode=lb, **dict(kw, cols16=-1))
+            assert M0.info["cols16"] == 0
+            assert M0.info["spmv_bytes"] - i["spmv_bytes"] == (4 * S - (2 * S + 4)) * nt
+            M0.close()
+            M.close()
+    for A, kw in ((matgen.power_law(100_000, seed=2), {}), (matgen.poisson_3d(24), {"col_agg": 0}),
+                  (matgen.poisson_3d(24), {"col_agg": 1, "lb_mode": "paper"})):
+        M = cb.CbMatrix.from_csr(A, device=False, **kw)
+        assert M.info["cols16"] == 0, kw
+        assert cb.cb_export_structure(M.handle)["tile_c16"].size == 0
+        M.close()
+    # automatic: the 2-byte form except for the quad kernel with double vectors
+    P = matgen.poisson_3d(24)
+    for kw, want in (({"spmv_kernel": 0}, 1), ({"spmv_kernel": 2}, 0), ({"spmv_kernel": 2, "value_type": "f32"}, 1),
+                     ({"spmv_kernel": 2, "value_type": "f32", "vector_f64": 1}, 0),
+                     ({"lb_mode": "paper_stream"}, 0), ({"lb_mode": "paper_stream", "value_type": "bf16"}, 1),
+                     ({"spmv_kernel": 2, "cols16": 1}, 1)):
+        M = cb.CbMatrix.from_csr(P, device=False, col_agg=1, **kw)
+        assert M.info["cols16"] == want, kw
+        M.close()
+    for bad in (2, -2):
+        with pytest.raises(cb.CbError) as e:
+            cb.CbMatrix.from_csr(matgen.laplacian_2d(16), device=False, cols16=bad)
         assert e.value.status == cb.CB_ERROR_INVALID_VALUE
 
 

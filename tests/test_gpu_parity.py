@@ -444,6 +444,35 @@ def test_spmm_dense_tiles_with_nonfinite_x(cb, vtype):
         assert viol == 0, (th, e, w)
 
 
+@pytest.mark.parametrize("opts", [{"spmv_kernel": 0}, {"spmv_kernel": 2}, {"lb_mode": "paper_stream"},
+                                  {"spmv_kernel": 0, "tile_dim": 8}, {"spmv_kernel": 2, "tile_dim": 8},
+                                  {"spmv_kernel": 0, "lb_mode": "none"}])
+def test_compressed_columns_match_four_byte_columns(cb, opts):
+    """The 2-byte column offsets (cols16) compute what the 4-byte columns compute, in both streaming
+    kernels, Algorithm 2's streamed order and both tile sizes, FP64 and FP32 values, with short
+    ranges (many partial gathers at a range's end): bit for bit on exact inputs (dyadic values and x:
+    every order of the row sums gives the same result; on other inputs the order of the LDS atomics
+    varies from run to run), and within the tolerance of the oracle on the generators' values."""
+    B = matgen.block_3d(10, seed=2)
+    Bd = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx,
+                    np.random.default_rng(5).integers(-16, 17, B.nnz).astype(np.float64) / 16)
+    for A in (B, Bd, matgen.poisson_3d(20), matgen.laplacian_2d(64)):
+        exact = A is not B
+        x = matgen.vector(A.n, 4, dyadic=exact)
+        for vt in ("f64", "f32"):
+            kw = dict(col_agg=1, wave_nnz=64, cols16=1, **opts)
+            M = cb.CbMatrix.from_csr(A, value_type=vt, **kw)
+            assert M.info["cols16"] == 1 and M.info["col_agg"] == 1
+            M.close()
+            y16 = run_spmv(cb, A, x, vtype=vt, **kw)
+            if exact:
+                y32 = run_spmv(cb, A, x, vtype=vt, **dict(kw, cols16=-1))
+                assert np.array_equal(y16, y32), (A.n, vt, opts)
+            ref = oracle.spmv(A, x, comp=True)
+            e, viol, _ = oracle.scaled_error(y16, ref, oracle.scale(A, x), TOL[vt])
+            assert viol == 0, (A.n, vt, opts, e)
+
+
 @pytest.mark.parametrize("chunk", [0, 1, 3, 16, 1000])
 def test_xcd_mapping_leaves_results_unchanged(cb, chunk):
     """Every workgroup-to-range mapping computes the same product: bit for bit on exact inputs
