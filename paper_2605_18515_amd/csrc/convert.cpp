@@ -123,6 +123,7 @@ inline void store_value(uint8_t *dst, double v, int vtype) {
 struct PanelCounts {
     int64_t tiles = 0, bytes = 0, cols = 0, fmt[3] = {0, 0, 0};
     int64_t flat = 0, runs = 0;  // COO/CSR entries and (tile, row) runs
+    int64_t span = 0;            // aggregation: the widest tile's original columns, last minus first
 };
 
 // Groups the entries of one panel (S = blk rows) into S x S tiles.  With
@@ -601,6 +602,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
                     pb.build(p, agg);
                     PanelCounts c;
                     c.cols = agg ? (int64_t)pb.cols().size() : 0;
+                    if (agg)
+                        for (size_t i = 0; i < pb.cols().size(); i += S)
+                            c.span = std::max<int64_t>(c.span, (int64_t)pb.cols()[std::min(i + S, pb.cols().size()) - 1] -
+                                                                   pb.cols()[i]);
                     const std::vector<Entry> &ent = pb.entries();
                     for_each_tile(ent, [&](int64_t, size_t lo, size_t hi) {
                         const int fmt = select_format((int64_t)(hi - lo), opt.th1, opt.th2);
@@ -617,7 +622,9 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             }, err)) return CB_ERROR_OUT_OF_MEMORY;
 
         std::vector<int64_t> tile_base(P + 1, 0), byte_base(P + 1, 0), col_base(P + 1, 0);
+        int64_t span = 0;
         for (int64_t p = 0; p < P; ++p) {
+            span = std::max(span, pc[p].span);
             tile_base[p + 1] = tile_base[p] + pc[p].tiles;
             byte_base[p + 1] = byte_base[p] + pc[p].bytes;
             col_base[p + 1] = col_base[p] + pc[p].cols;
@@ -636,10 +643,13 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         // natural-order kernel (measured on gfx950): the quad kernel wins where tiles are well filled
         // and their rows hold runs of entries (3D block matrix: FP64 147 against 153 us, BF16 77 against
         // 105), the streaming kernel where tiles are sparse or rows come one entry per tile row
-        // (stencils, power-law rows), whose quads are part empty and sum no runs
+        // (stencils, power-law rows), whose quads are part empty and sum no runs -- except with float
+        // vectors where 2-byte column offsets apply (cols16): there the quad kernel won on the 192^3
+        // Poisson operator too (FP32 105.9 against 108.8 us, BF16 92.1 against 102.5)
         if (opt.spmv_kernel < 0 && natural_lb(s.lb_mode)) {
             const bool long_runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
-            s.spmv_kernel = long_runs && nnz >= 32 * NT && n <= kQuadMaxCols ? 2 : 0;
+            const bool float_c16 = !s.vector_f64 && agg && opt.cols16 >= 0 && span <= 0xFFFF;
+            s.spmv_kernel = ((long_runs && nnz >= 32 * NT) || float_c16) && n <= kQuadMaxCols ? 2 : 0;
         }
         if (s.lb_mode == CB_LB_PAPER_STREAM) s.spmv_kernel = 2;  // the quad kernel's scatter form
         if (opt.row_reduce >= 0) {

@@ -1165,11 +1165,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         }
         __builtin_amdgcn_wave_barrier();
         if (have1) issue_x(h1.nt);
-        if (have2) {
-            issue_cols(tb2, h2.nt);
-            o3 = o2 + 1 + h2.nt;
-            if (o3 < oend) qload(o3);
-        }
+        if (have2) o3 = o2 + 1 + h2.nt;
         if constexpr (!SC) {
             done_pb = h0.pb;
             done_mask = h0.done;
@@ -1178,7 +1174,13 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         multiply(h0.np);
         if constexpr (SC) scatter_flush(h0.nt);
         __builtin_amdgcn_wave_barrier();
+        // issued after the multiply, so their registers are free while it runs; they are waited for
+        // at the top of the next step with the payload
         if (have1) issue_payload(h1, par ^ 1);
+        if (have2) {
+            issue_cols(tb2, h2.nt);
+            if (o3 < oend) qload(o3);
+        }
         ob = o1;
         h0 = h1;
         o1 = o2;
@@ -1204,8 +1206,11 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_qbatch_kernel(const BatchJ
 #ifndef CB_TUNE_QWAVES
 #define CB_TUNE_QWAVES 6  // natural-order quad kernel: at least this many wavefronts per SIMD (register cap)
 #endif
+#ifndef CB_TUNE_QWAVES_C16
+#define CB_TUNE_QWAVES_C16 5  // the same for FP64 values with 2-byte column offsets (one more register per gather)
+#endif
 template <int VT, int AGG, int RR, int LT, bool SC>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SC ? 1 : CB_TUNE_QWAVES))) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(SC ? 1 : (AGG == 2 && VT == 0) ? CB_TUNE_QWAVES_C16 : CB_TUNE_QWAVES))) void spmv_quad_kernel(DevView d, typename Val<VT>::A alpha,
                                                                    typename Val<VT>::A beta,
                                                                    const typename Val<VT>::A *__restrict__ x,
                                                                    typename Val<VT>::A *__restrict__ y) {

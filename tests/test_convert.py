@@ -536,6 +536,15 @@ def test_compressed_tile_columns():
         M = cb.CbMatrix.from_csr(P, device=False, col_agg=1, **kw)
         assert M.info["cols16"] == want, kw
         M.close()
+    # automatic kernel: with float vectors where the 2-byte form applies, the quad kernel (stencils
+    # too); double vectors and scattered columns keep the streaming kernel on the stencil
+    for A, kw, kern in ((P, {"value_type": "f32"}, 2), (P, {"value_type": "bf16"}, 2),
+                        (P, {"value_type": "f32", "vector_f64": 1}, 0), (P, {}, 0),
+                        (P, {"value_type": "f32", "cols16": -1}, 0),
+                        (matgen.power_law(100_000, seed=2), {"value_type": "f32"}, 0)):
+        M = cb.CbMatrix.from_csr(A, device=False, **kw)
+        assert M.info["spmv_kernel"] == kern, kw
+        M.close()
     for bad in (2, -2):
         with pytest.raises(cb.CbError) as e:
             cb.CbMatrix.from_csr(matgen.laplacian_2d(16), device=False, cols16=bad)
