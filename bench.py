@@ -658,18 +658,18 @@ def run_tune(args, cb, matgen) -> int:
                 o = c["opt"]
                 return {"tile_dim": c["tile_dim"], "spmv_kernel": c["spmv_kernel"], "col_agg": c["col_agg"],
                         "th1": o["th1"], "th2": o["th2"], "row_reduce": c["row_reduce"], "lb_mode": o["lb_mode"],
-                        "wave_nnz": o["wave_nnz"], "xcd_chunk": o["xcd_chunk"], "us": c["us"]}
+                        "wave_nnz": o["wave_nnz"], "xcd_chunk": o["xcd_chunk"], "cols16": o["cols16"], "us": c["us"]}
             rows[key] = {"default_us": k_def * 1e6, "tuned_us": k_tun * 1e6, "speedup": k_def / k_tun,
                          "tune_seconds": tune_s, "candidates": [desc(c) for c in cands],
                          "best": {k: best[k] for k in ("col_agg", "th1", "th2", "row_reduce", "lb_mode", "wave_nnz",
-                                                       "xcd_chunk", "tile_dim", "spmv_kernel")},
+                                                       "xcd_chunk", "tile_dim", "spmv_kernel", "cols16")},
                          "tuned_structure": {k: it[k] for k in ("tile_dim", "spmv_kernel", "col_agg", "row_reduce",
-                                                                "xcd_chunk", "ntiles")}}
+                                                                "xcd_chunk", "cols16", "ntiles")}}
             log(f"{key}: default {k_def * 1e6:.1f} us, tuned {k_tun * 1e6:.1f} us ({k_def / k_tun:.3f}x) "
                 f"in {tune_s:.1f}s, chosen {rows[key]['tuned_structure']}; candidates: " + "; ".join(
                     f"S={c['tile_dim']} k{c['spmv_kernel']} agg={c['col_agg']} th=({c['opt']['th1']},{c['opt']['th2']}) "
                     f"rr={c['row_reduce']} lb={c['opt']['lb_mode']} wn={c['opt']['wave_nnz']} "
-                    f"xcd={c['opt']['xcd_chunk']} {c['us']:.1f}" for c in cands))
+                    f"xcd={c['opt']['xcd_chunk']} c16={c['opt']['cols16']} {c['us']:.1f}" for c in cands))
             del xd, yd
             torch.cuda.empty_cache()
     geo = float(np.exp(np.mean([np.log(r["speedup"]) for r in rows.values()])))

@@ -412,7 +412,8 @@ const char *cb_last_error(void);
  * each (cb_spmv, or cb_spmm with spmm_k right-hand sides; HIP events on `stream`, median of reps
  * launches with x = 1 and beta = 0), by coordinate descent from `base` over: column aggregation
  * on/off, the sub-block size (16 x 16 or 8 x 8 tiles, th1/th2 scaled with the tile's area), the
- * natural-order kernel (entries or quads per lane), the workgroup-to-range mapping (xcd_chunk
+ * natural-order kernel (entries or quads per lane), the form of the original columns under
+ * aggregation (cols16: 2-byte offsets or 4-byte columns), the workgroup-to-range mapping (xcd_chunk
  * 16 or 0), the format thresholds th1/th2 (the base
  * ones, COO below Dense at 200/256 of the tile's slots, COO only), the row-sum mode, the
  * load-balance split (nnz-balanced at panel boundaries or equal tile counts) and the work per

@@ -202,6 +202,19 @@ cb_status_t cb_tune(cb_matrix_t *out, int64_t m, int64_t n, int64_t nnz, const i
             o.spmv_kernel = T.cand[T.best].spmv_kernel == 2 ? 0 : 2;
             if (st == CB_SUCCESS) st = T.eval(o, idx);
         }
+        // original columns under aggregation: 2-byte offsets from a per-tile base or 4-byte columns (the
+        // other of the resolved form; the 2-byte form only where every tile's columns span less than
+        // 65,536)
+        {
+            cb_info_t info{};
+            info.struct_size = sizeof(cb_info_t);
+            if (st == CB_SUCCESS && T.handles[T.best]) st = cb_get_info(T.handles[T.best], &info);
+            if (st == CB_SUCCESS && info.col_agg) {
+                cb_options_t o = cur();
+                o.cols16 = info.cols16 ? -1 : 1;
+                st = T.eval(o, idx);
+            }
+        }
         // workgroup-to-range mapping: the other of the XCDs side by side in runs of 16 ranges and each
         // XCD a contiguous eighth
         {
