@@ -148,13 +148,16 @@ typedef struct {
     int32_t cols16;         /* under column aggregation, how the SpMV kernels that stream work
                                ranges (spmv_kernel 0 and 2, lb_mode contiguous, none and
                                paper_stream, and the serving loop's batched products) read a tile's
-                               original columns: as a 4-byte base per tile (its first column) and
-                               2-byte offsets from it (2 tile_dim + 4 bytes per tile instead of
-                               4 tile_dim), possible when every tile's columns span less than
-                               65,536, or as 4-byte columns.  0 (default) = automatic: the 2-byte
-                               form where possible, except for the quad kernel with double vectors
+                               original columns: as 2-byte offsets from a base, or as 4-byte
+                               columns.  The quad kernel takes the base from its batch's header
+                               (2 tile_dim bytes per tile instead of 4 tile_dim) where every quad
+                               batch's columns span less than 65,536; otherwise, and for the
+                               streaming kernel, a 4-byte base per tile (its first column; 2
+                               tile_dim + 4 bytes) where every tile's columns span less than
+                               65,536.  0 (default) = automatic: a 2-byte form where possible,
+                               except the per-tile form for the quad kernel with double vectors
                                (its registers are at the limit of six wavefronts per SIMD: 4-byte
-                               columns measured faster); 1 = the 2-byte form where possible; -1 =
+                               columns measured faster); 1 = a 2-byte form where possible; -1 =
                                always 4-byte columns.  Other values: CB_ERROR_INVALID_VALUE.  Results
                                do not depend on it. */
     int64_t reserved[3];
@@ -200,7 +203,10 @@ typedef struct {
     int32_t spmv_kernel;    /* the resolved spmv_kernel option (0, 1 or 2) */
     int32_t tile_dim;       /* sub-block size S of the structure (16 or 8) */
     int32_t xcd_chunk;      /* the resolved xcd_chunk option */
-    int32_t cols16;         /* 1 when the SpMV kernels read 2-byte column offsets (the cols16 option) */
+    int32_t cols16;         /* the form the SpMV kernels read the original columns in (the cols16
+                               option): 0 4-byte columns, 1 2-byte offsets from a base per tile
+                               (tile_cbase), 2 2-byte offsets from a base per quad batch (the
+                               batch header's fourth word) */
     int64_t reserved[2];
 } cb_info_t;
 
@@ -231,8 +237,9 @@ typedef struct {
     int32_t *tile_cols;      /* aggregation with the streaming kernel: tile_dim original columns per
                                 tile in kernel order, tile_dim * ntiles (else none); column c of a
                                 tile at position (c mod 4) * tile_dim / 4 + c / 4 */
-    int32_t *tile_cbase;     /* cols16 only: each tile's first original column, ntiles (else none) */
-    uint16_t *tile_c16;      /* cols16 only: column c of each tile minus its base at position c,
+    int32_t *tile_cbase;     /* cols16 1 only: each tile's first original column, ntiles (else none) */
+    uint16_t *tile_c16;      /* cols16 1 and 2: column c of each tile minus its base (cols16 1: the
+                                tile's tile_cbase; 2: its quad batch's) at position c,
                                 tile_dim * ntiles (columns past the tile's last: 0) */
 } cb_structure_t;
 

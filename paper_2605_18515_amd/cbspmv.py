@@ -365,7 +365,7 @@ def cb_export_structure(A: int) -> dict:
         "batch_stream": np.empty(info["stream_bytes"] // 4, np.int32),
         "batch_ptr": np.empty(info["nwaves"] + 1 if info["lb_mode"] != CB_LB_PAPER else 0, np.int32),
         "tile_cols": np.empty(info["tile_dim"] * NT if info["lb_mode"] != CB_LB_PAPER and info["col_agg"] else 0, np.int32),
-        "tile_cbase": np.empty(NT if info["cols16"] else 0, np.int32),
+        "tile_cbase": np.empty(NT if info["cols16"] == 1 else 0, np.int32),
         "tile_c16": np.empty(info["tile_dim"] * NT if info["cols16"] else 0, np.uint16),
     }
     s = CbStructure(**{k: (v.ctypes.data if v.size else None) for k, v in arrs.items()})

@@ -73,7 +73,7 @@ Layout make_layout(const cbh::HostStructure &s) {
     L.tile_cols = put(stream && s.col_agg ? 4 * (size_t)s.blk * NT : 0);
     L.tile_rec = put(natural ? 16 * NT : 0);
     L.panel_tile = put(natural ? 4 * ((size_t)s.npanels + 1) : 0);
-    L.tile_cbase = put(s.cols16 ? 4 * NT : 0);
+    L.tile_cbase = put(s.cols16 == 1 ? 4 * NT : 0);
     L.tile_c16 = put(s.cols16 ? 2 * (size_t)s.blk * NT : 0);
     L.total = off;
     return L;
@@ -203,7 +203,7 @@ cb_status_t upload(cb_matrix_s *A, hipStream_t stream) {
     v.nwaves = (int32_t)s.nwaves;
     v.npanels = (int32_t)s.npanels;
     v.nprepass = (int32_t)s.nprepass;
-    v.col_agg = s.col_agg ? (s.cols16 ? 2 : 1) : 0;
+    v.col_agg = !s.col_agg ? 0 : s.cols16 == 2 ? 3 : s.cols16 == 1 ? 2 : 1;
     v.natural_order = cbh::natural_lb(s.lb_mode) ? 1 : 0;
     v.scatter = s.lb_mode == CB_LB_PAPER_STREAM ? 1 : 0;
     v.row_reduce = s.row_reduce;
@@ -279,7 +279,7 @@ cb_status_t host_view(const cb_matrix_s *A, cbh::HostStructure &tmp, const cbh::
     if ((st = fetch(A, L.tile_cols, cbh::streamed_lb(A->h.lb_mode) && A->h.col_agg ? (size_t)A->h.blk * NT : 0,
                     tmp.tile_cols)) != CB_SUCCESS)
         return st;
-    if ((st = fetch(A, L.tile_cbase, A->h.cols16 ? NT : 0, tmp.tile_cbase)) != CB_SUCCESS) return st;
+    if ((st = fetch(A, L.tile_cbase, A->h.cols16 == 1 ? NT : 0, tmp.tile_cbase)) != CB_SUCCESS) return st;
     if ((st = fetch(A, L.tile_c16, A->h.cols16 ? (size_t)A->h.blk * NT : 0, tmp.tile_c16)) != CB_SUCCESS) return st;
     s = &tmp;
     return CB_SUCCESS;

@@ -30,7 +30,8 @@ struct DevView {
     int32_t nwaves, npanels, nprepass;
     int32_t col_agg;              // 0 none; 1 aggregated, S 4-byte original columns per tile (tile_cols);
                                   // 2 aggregated, the streaming and quad kernels read tile_cbase +
-                                  // tile_c16 (the other kernels tile_cols, also present)
+                                  // tile_c16; 3 aggregated, the quad kernel reads tile_c16 + the batch
+                                  // header's base (the other kernels read tile_cols, also present)
     int32_t natural_order;        // 1: kernel order = packing order, each work range one contiguous byte range
     int32_t row_reduce;           // streaming kernel row sums: 0 LDS atomics per entry, 1 DPP segmented scan,
                                   // 2 FP64 LDS atomics, 3 and 4 = 0 and 2 with two accumulator copies
@@ -38,7 +39,8 @@ struct DevView {
                                   // (batch_stream then holds quad batches)
     const int32_t *panel_tile;    // natural order: first tile of each panel, npanels + 1
     const int32_t *tile_cbase;    // col_agg 2: first original column of each tile
-    const uint16_t *tile_c16;     // col_agg 2: S column offsets from it per tile, natural column order
+    const uint16_t *tile_c16;     // col_agg 2 and 3: S column offsets per tile from its base (2) or its
+                                  // batch's (3), natural column order
     int32_t tile_lt;              // log2 of the tile size S: 4 (16 x 16 tiles) or 3 (8 x 8)
     int32_t scatter;              // Algorithm 2's groups streamed (CB_LB_PAPER_STREAM): quad batches in
                                   // scatter form, every tile's rows added into y with atomics

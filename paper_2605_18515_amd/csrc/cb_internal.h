@@ -14,7 +14,7 @@ struct MatrixView {
     int kernel_vt = 0;   // kernel value code (cb_device.h)
     int vtype = 0;       // storage precision (cb_value_t)
     int vector_f64 = 1;  // x and y are double
-    int col_agg = 0;     // the device view's: 0 none, 1 4-byte columns, 2 compressed columns
+    int col_agg = 0;     // the device view's: 0 none, 1 4-byte columns, 2 and 3 2-byte column offsets
     int row_reduce = 0;
     int natural = 1;     // natural-order structure (the streaming kernel)
     int device = -1;

@@ -64,9 +64,11 @@ constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes r
 // 4q + 3 of its row-major 256, occupancy bits honoured).  The quads of a batch are numbered Q = 0 ..
 // qtot - 1 in tile order; in pass p of the kernel lane l takes quad 64 p + l.
 //
-//   header  {pb, nt | np << 8 | done << 16, qtot, 0}
+//   header  {pb, nt | np << 8 | done << 16, qtot, cbase}
 //     pb     first panel of the batch; nt tiles; np = ceil(qtot / 64) passes
 //     done   bit k: panel pb + k has its last tile of this range in the batch
+//     cbase  with per-batch 2-byte column offsets (cols16 2): the batch's lowest original column,
+//            which its tiles' offsets are taken from; else 0
 //   record of tile i of the batch (i = 0 .. nt - 1, kernel order)  {cb, vb, lim, meta}
 //     meta   slot | qs << 2 | dense << 15, with slot = panel & (kBatchPanels - 1) and qs the
 //            tile's first quad
@@ -79,7 +81,7 @@ constexpr int kPayloadPad = 2048;            // payload and restore_cols bytes r
 //
 // Scatter form (Algorithm 2's groups streamed, CB_LB_PAPER_STREAM): the tiles of a batch may come
 // from any panels; the batch limits are kQTiles tiles and kQPasses * 64 quads.
-//   header  {0, nt | np << 8, qtot, 0}
+//   header  {0, nt | np << 8, qtot, cbase}
 //   record  {cb, vb, panel, i | qs << 5 | dense << 15 | lim << 16}
 //     i      the tile's position in the batch: its accumulator slot and x-area place
 //     panel  the tile's panel, whose rows the tile's sums are added into after the batch

@@ -314,14 +314,18 @@ void build_tile_cols(HostStructure &s) {
     }
 }
 
-// cols16: each tile's first original column and its S columns as 16-bit offsets from it, when every
-// tile's columns span less than 65,536 (stencil and block operators: a tile holds consecutive
-// aggregated columns of one panel, which lie in one neighbourhood of the diagonal); columns past the
-// tile's last are offset 0.  Built from tile_cols, in the same kernel order.  Automatic (mode 0):
-// not for the quad kernel with double vectors, whose registers are at the limit of six wavefronts
-// per SIMD (one more register per gather: 3D block matrix FP64 155 against 129 us); elsewhere the
-// 2-byte form measured faster (192^3 Poisson, streaming kernel: FP64 148 against 159 us, FP32 108
-// against 118; 3D block matrix, quad kernel: FP32 82 against 85, BF16 70 against 73).
+// cols16: the original columns as 16-bit offsets from a base, in two forms.  Quad batches (the quad
+// kernel): where every batch's columns span less than 65,536 (the block operator: a batch covers at
+// most four panels, whose columns lie within one plane of the diagonal), the base is the batch's
+// lowest column, kept in the batch header's fourth word, so the kernel adds one wave-uniform value
+// (cols16 2: no register or load per lane).  Otherwise, where every tile's columns span less than
+// 65,536 (stencils too), the base is each tile's first column, in tile_cbase (cols16 1: one more load
+// and register per lane and gather).  Columns past a tile's last are offset 0; built from tile_cols,
+// in the same kernel order.  Automatic (mode 0): the per-tile form not for the quad kernel with double
+// vectors, whose registers are at the limit of six wavefronts per SIMD (3D block matrix FP64 155
+// against 129 us; given five wavefronts, 137 against 138); elsewhere the 2-byte forms measured faster
+// (192^3 Poisson, streaming kernel: FP64 148 against 159 us, FP32 108 against 118; 3D block matrix,
+// quad kernel: FP32 82 against 85, BF16 70 against 73).
 void build_tile_c16(HostStructure &s, int mode) {
     const int S = s.blk;
     s.cols16 = 0;
@@ -329,23 +333,58 @@ void build_tile_c16(HostStructure &s, int mode) {
     s.tile_c16.clear();
     if (!s.col_agg || mode < 0 || s.ntiles == 0) return;
     const bool quad = s.spmv_kernel == 2 || s.lb_mode == CB_LB_PAPER_STREAM;
-    if (mode == 0 && quad && s.vector_f64) return;
-    std::vector<int32_t> base((size_t)s.ntiles);
-    std::vector<uint16_t> off((size_t)s.ntiles * S);
+    std::vector<int32_t> first_col((size_t)s.ntiles), last_col((size_t)s.ntiles);
     for (int64_t t = 0; t < s.ntiles; ++t) {
         const int64_t p = s.tile_row[t], first = s.cols_offset[p] + (int64_t)S * s.tile_col[t];
         const int64_t width = std::min<int64_t>(S, s.cols_offset[p + 1] - first);
-        const int64_t b = s.restore_cols[(size_t)first];
-        base[(size_t)t] = (int32_t)b;
-        for (int c = 0; c < S; ++c) {
-            const int64_t o = c < width ? (int64_t)s.restore_cols[(size_t)(first + c)] - b : 0;
-            if (o < 0 || o > 0xFFFF) return;  // a tile spans 65,536 columns or more: 4-byte columns
-            off[(size_t)(t * S + c)] = (uint16_t)o;
-        }
+        first_col[(size_t)t] = s.restore_cols[(size_t)first];
+        last_col[(size_t)t] = s.restore_cols[(size_t)(first + width - 1)];
     }
+    auto offsets = [&](std::vector<uint16_t> &off, auto &&base_of) {
+        off.assign((size_t)s.ntiles * S, 0);
+        for (int64_t t = 0; t < s.ntiles; ++t) {
+            const int64_t p = s.tile_row[t], first = s.cols_offset[p] + (int64_t)S * s.tile_col[t];
+            const int64_t width = std::min<int64_t>(S, s.cols_offset[p + 1] - first);
+            const int64_t b = base_of(t);
+            for (int c = 0; c < S; ++c)
+                off[(size_t)(t * S + c)] = (uint16_t)(c < width ? (int64_t)s.restore_cols[(size_t)(first + c)] - b : 0);
+        }
+    };
+    if (quad) {
+        // the batches' spans, from the quad batch headers (tiles consecutive from each range's first)
+        bool fits = true;
+        std::vector<int32_t> tile_base((size_t)s.ntiles, 0);
+        for (int64_t w = 0; w < s.nwaves && fits; ++w) {
+            int64_t t = s.wave_ptr[w];
+            for (int64_t o = s.batch_ptr[w]; o < s.batch_ptr[w + 1] && fits;) {
+                const int64_t nt = s.batch_stream[(size_t)(4 * o + 1)] & 0xFF;
+                int64_t lo = INT64_MAX, hi = INT64_MIN;
+                for (int64_t i = t; i < t + nt; ++i) {
+                    lo = std::min<int64_t>(lo, first_col[(size_t)i]);
+                    hi = std::max<int64_t>(hi, last_col[(size_t)i]);
+                }
+                if (hi - lo > 0xFFFF) fits = false;
+                for (int64_t i = t; i < t + nt; ++i) tile_base[(size_t)i] = (int32_t)lo;
+                s.batch_stream[(size_t)(4 * o + 3)] = (int32_t)lo;
+                t += nt;
+                o += 1 + nt;
+            }
+        }
+        if (fits) {
+            offsets(s.tile_c16, [&](int64_t t) { return (int64_t)tile_base[(size_t)t]; });
+            s.cols16 = 2;
+            return;
+        }
+        for (int64_t w = 0; w < s.nwaves; ++w)  // the headers' fourth words back to 0: no batch base
+            for (int64_t o = s.batch_ptr[w]; o < s.batch_ptr[w + 1]; o += 1 + (s.batch_stream[(size_t)(4 * o + 1)] & 0xFF))
+                s.batch_stream[(size_t)(4 * o + 3)] = 0;
+        if (mode == 0 && s.vector_f64) return;
+    }
+    for (int64_t t = 0; t < s.ntiles; ++t)
+        if (last_col[(size_t)t] - first_col[(size_t)t] > 0xFFFF) return;  // 4-byte columns
+    s.tile_cbase = first_col;
+    offsets(s.tile_c16, [&](int64_t t) { return (int64_t)first_col[(size_t)t]; });
     s.cols16 = 1;
-    s.tile_cbase.swap(base);
-    s.tile_c16.swap(off);
 }
 
 // Quad batches of the quad kernel (format in cb_stream.h), written to batch_stream / batch_ptr in
@@ -1025,7 +1064,8 @@ int64_t spmv_bytes(const HostStructure &s) {
         // column block per tile), two range pointers per range and the first tile's offset and the end
         // panels' flags, pre-pass list
         b += 16 * s.nrecords;
-        b += s.col_agg ? (s.cols16 ? 2 * (int64_t)s.blk + 4 : 4 * (int64_t)s.blk) * s.ntiles : 4 * s.ntiles;
+        b += s.col_agg ? (s.cols16 == 2 ? 2 * (int64_t)s.blk : s.cols16 ? 2 * (int64_t)s.blk + 4 : 4 * (int64_t)s.blk) * s.ntiles
+                       : 4 * s.ntiles;
         b += 8 * (s.nwaves + 1) + 18 * s.nwaves + 4 * s.nprepass;
         // scatter form: the pre-pass writes y, the atomics read and write it again
         if (s.lb_mode == CB_LB_PAPER_STREAM) b += 2 * xe * s.m;

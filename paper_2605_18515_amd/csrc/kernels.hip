@@ -382,6 +382,7 @@ __device__ __forceinline__ void stream_range(const DevView &d, int w, typename V
     constexpr int S = 1 << LT;  // rows of a panel, columns of a tile
     constexpr int TPG = kWave / S;  // tiles per x gather
     static_assert(LT == 3 || LT == 4, "16 x 16 or 8 x 8 tiles");
+    static_assert(AGG >= 0 && AGG <= 2, "per-batch column bases are a quad-batch form");
     using AC = typename std::conditional<RR == 2 || RR == 4, double, A>::type;  // accumulator type
     constexpr bool DPPRED = RR == 1;
     constexpr int NACC = RR >= 3 ? 2 : 1;  // accumulator copies
@@ -898,12 +899,12 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
         Q = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(rrs, 16 * r, 0, CB_TUNE_QCPOL));
     };
     struct Hdr {
-        int pb, nt, np, done, qtot;
+        int pb, nt, np, done, qtot, cbase;
     };
     auto header = [&]() {
         const int hz = __builtin_amdgcn_readlane(Q.y, kWave - 1);
         return Hdr{__builtin_amdgcn_readlane(Q.x, kWave - 1), hz & 0xFF, (hz >> 8) & 0xFF, (hz >> 16) & 0xF,
-                   __builtin_amdgcn_readlane(Q.z, kWave - 1)};
+                   __builtin_amdgcn_readlane(Q.z, kWave - 1), AGG == 3 ? __builtin_amdgcn_readlane(Q.w, kWave - 1) : 0};
     };
     // the records in Q (header h) into record table `par`, and the tiles' first quads as marks: byte
     // (p, l) of the mark table is set where tile starts at quad 64 p + l
@@ -920,38 +921,42 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     // and x are read through buffer resources: the range's tile columns (a load past the range's
     // last tile returns 0, a valid column) and x (n below 2^29, so every column's byte offset fits
     // 32 bits; a load past column n - 1 returns 0).  One offset per batch, a constant per gather.
-    // Compressed columns (AGG 2): 2-byte offsets and 4-byte bases, each through a resource over the
-    // range's tiles (past the range's last tile both read 0: column 0)
-    constexpr int CW = AGG == 2 ? 2 * S : AGG ? 4 * S : 4;  // bytes of tile columns per tile
-    const rsrc_t crs = AGG == 2 ? make_rsrc(d.tile_c16 + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
+    // Compressed columns: 2-byte offsets through a resource over the range's tiles, plus (AGG 2) each
+    // tile's 4-byte base through another (past the range's last tile both read 0: column 0) or
+    // (AGG 3) the batch's base from its header (past the last tile: the batch's lowest column)
+    constexpr bool C16 = AGG >= 2;
+    constexpr int CW = C16 ? 2 * S : AGG ? 4 * S : 4;  // bytes of tile columns per tile
+    const rsrc_t crs = C16 ? make_rsrc(d.tile_c16 + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
                        : AGG    ? make_rsrc(d.tile_cols + S * (int64_t)t0, CW * (int64_t)(t1 - t0))
                                 : make_rsrc(d.tile_col + t0, CW * (int64_t)(t1 - t0));
     const rsrc_t brs = make_rsrc(AGG == 2 ? d.tile_cbase + t0 : d.tile_col, 4 * (int64_t)(t1 - t0));
     const rsrc_t xrs = make_rsrc(x, d.n * (int64_t)sizeof(A));
-    const int cl = AGG == 2 ? 2 * (S * gj + glc) : AGG ? 4 * (S * gj + (glc & 3) * (S / 4) + (glc >> 2)) : 4 * gj;
+    const int cl = C16 ? 2 * (S * gj + glc) : AGG ? 4 * (S * gj + (glc & 3) * (S / 4) + (glc >> 2)) : 4 * gj;
     int RG[NG];
-    int RB[NG];
+    int RB[AGG == 2 ? NG : 1];
     auto issue_cols = [&](int tb, int nt) {
         const int cb0 = CW * (tb - t0) + cl;
 #pragma unroll
         for (int g = 0; g < NG; ++g)
             if (TPG * g < nt) {
-                if constexpr (AGG == 2) {
+                if constexpr (C16) {
                     RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b16(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
-                    RB[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(brs, 4 * (tb - t0 + TPG * g + gj), 0,
-                                                                       CB_TUNE_QCPOL);
+                    if constexpr (AGG == 2)
+                        RB[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(brs, 4 * (tb - t0 + TPG * g + gj), 0,
+                                                                           CB_TUNE_QCPOL);
                 } else {
                     RG[g] = (int)__builtin_amdgcn_raw_buffer_load_b32(crs, cb0 + CW * TPG * g, 0, CB_TUNE_QCPOL);
                 }
             }
     };
     A XG[NG];
-    auto issue_x = [&](int nt) {
+    auto issue_x = [&](const Hdr &h) {
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (TPG * g < nt) {
+            if (TPG * g < h.nt) {
                 uint32_t col;
-                if constexpr (AGG == 2) col = (uint32_t)(RG[g] + RB[g]);
+                if constexpr (AGG == 3) col = (uint32_t)(RG[g] + h.cbase);
+                else if constexpr (AGG == 2) col = (uint32_t)(RG[g] + RB[g]);
                 else col = (uint32_t)RG[g] * (AGG ? 1u : (uint32_t)S) + (AGG ? 0u : (uint32_t)glc);
                 XG[g] = buffer_value<A>(xrs, col * (uint32_t)sizeof(A));
             }
@@ -1139,7 +1144,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     if (o1 < oend) qload(o1);
     __builtin_amdgcn_wave_barrier();
     issue_payload(h0, 0);
-    issue_x(h0.nt);
+    issue_x(h0);
     __builtin_amdgcn_s_waitcnt(kWaitVm0);
     int o2 = o1, tb2 = tb1;
     if (o1 < oend) {
@@ -1164,7 +1169,7 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
             stage(h2, par);  // batch b+2 takes batch b's table (batch b's payload was issued a step ago)
         }
         __builtin_amdgcn_wave_barrier();
-        if (have1) issue_x(h1.nt);
+        if (have1) issue_x(h1);
         if (have2) o3 = o2 + 1 + h2.nt;
         if constexpr (!SC) {
             done_pb = h0.pb;
@@ -1671,7 +1676,8 @@ hipError_t spmv_quad_launch(const DevView &d, typename Val<VT>::A a, typename Va
         else if (rr == 4) go(spmv_quad_kernel<VT, AG, kRR4, LT, SC>);
         else go(spmv_quad_kernel<VT, AG, 0, LT, SC>);
     };
-    if (d.col_agg == 2) by_rr(std::integral_constant<int, 2>());
+    if (d.col_agg == 3) by_rr(std::integral_constant<int, 3>());
+    else if (d.col_agg == 2) by_rr(std::integral_constant<int, 2>());
     else if (d.col_agg) by_rr(std::integral_constant<int, 1>());
     else by_rr(std::integral_constant<int, 0>());
     return hipGetLastError();
@@ -2058,6 +2064,7 @@ template <int VT, int AGG, int LT>
 hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, int rr, int quad, hipStream_t s) {
     constexpr bool kWide = std::is_same<typename Val<VT>::A, double>::value;
     const dim3 grid((unsigned)total), block(kBlockThreads);
+    if (AGG == 3 && !quad) return hipErrorInvalidValue;  // per-batch column bases exist in quad batches only
     if (quad) {
         if (rr == 2)
             hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, kWide ? 0 : 2, LT>), grid, block, 0, s, jobs, wave_job,
@@ -2071,28 +2078,31 @@ hipError_t batch_rr(const BatchJob *jobs, const int32_t *wave_job, int total, in
             hipLaunchKernelGGL((spmv_qbatch_kernel<VT, AGG, 0, LT>), grid, block, 0, s, jobs, wave_job, total);
         return hipGetLastError();
     }
+    constexpr int SAGG = AGG == 3 ? 2 : AGG;  // (not reached with AGG 3)
     if (rr == 1)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 1, LT>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, SAGG, 1, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 2)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 0 : 2, LT>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, SAGG, kWide ? 0 : 2, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 3)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 3, LT>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, SAGG, 3, LT>), grid, block, 0, s, jobs, wave_job, total);
     else if (rr == 4)
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, kWide ? 3 : 4, LT>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, SAGG, kWide ? 3 : 4, LT>), grid, block, 0, s, jobs, wave_job, total);
     else
-        hipLaunchKernelGGL((spmv_batch_kernel<VT, AGG, 0, LT>), grid, block, 0, s, jobs, wave_job, total);
+        hipLaunchKernelGGL((spmv_batch_kernel<VT, SAGG, 0, LT>), grid, block, 0, s, jobs, wave_job, total);
     return hipGetLastError();
 }
 template <int VT>
 hipError_t batch_vt(const BatchJob *jobs, const int32_t *wave_job, int total, int agg, int rr, int quad, int lt,
                     hipStream_t s) {
     if (lt == 3)
-        return agg == 2 ? batch_rr<VT, 2, 3>(jobs, wave_job, total, rr, quad, s)
-               : agg    ? batch_rr<VT, 1, 3>(jobs, wave_job, total, rr, quad, s)
-                        : batch_rr<VT, 0, 3>(jobs, wave_job, total, rr, quad, s);
-    return agg == 2 ? batch_rr<VT, 2, 4>(jobs, wave_job, total, rr, quad, s)
-           : agg    ? batch_rr<VT, 1, 4>(jobs, wave_job, total, rr, quad, s)
-                    : batch_rr<VT, 0, 4>(jobs, wave_job, total, rr, quad, s);
+        return agg == 3 ? batch_rr<VT, 3, 3>(jobs, wave_job, total, rr, quad, s)
+               : agg == 2 ? batch_rr<VT, 2, 3>(jobs, wave_job, total, rr, quad, s)
+               : agg      ? batch_rr<VT, 1, 3>(jobs, wave_job, total, rr, quad, s)
+                          : batch_rr<VT, 0, 3>(jobs, wave_job, total, rr, quad, s);
+    return agg == 3 ? batch_rr<VT, 3, 4>(jobs, wave_job, total, rr, quad, s)
+           : agg == 2 ? batch_rr<VT, 2, 4>(jobs, wave_job, total, rr, quad, s)
+           : agg      ? batch_rr<VT, 1, 4>(jobs, wave_job, total, rr, quad, s)
+                      : batch_rr<VT, 0, 4>(jobs, wave_job, total, rr, quad, s);
 }
 }  // namespace
 

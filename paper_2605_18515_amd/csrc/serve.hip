@@ -582,7 +582,7 @@ hipError_t cb_server_s::build_launches(Group<TX, TP> &g) {
     auto key = [&](int i) {
         const cbh::MatrixView &v = mats[g.req[i]->pm].v;
         return v.kernel_vt * 128 + (v.view.tile_lt == 3 ? 64 : 0) + (v.view.spmv_kernel == 2 ? 32 : 0) +
-               v.col_agg * 8 + v.row_reduce;  // row_reduce < 8, col_agg < 3
+               v.col_agg * 8 + v.row_reduce;  // row_reduce < 8, col_agg < 4
     };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
     std::vector<cbd::BatchJob> bj;

@@ -492,33 +492,74 @@ def test_automatic_xcd_mapping():
         assert e.value.status == cb.CB_ERROR_INVALID_VALUE
 
 
+def _poisson_box(nx, ny, nz):
+    """7-point operator on an nx x ny x nz grid (x fastest): neighbours 1, nx and nx ny rows apart."""
+    import scipy.sparse as sp
+
+    def lap(k):
+        return sp.diags([-np.ones(k - 1), 2 * np.ones(k), -np.ones(k - 1)], [-1, 0, 1])
+
+    A = (sp.kron(sp.eye(nz), sp.kron(sp.eye(ny), lap(nx))) + sp.kron(sp.eye(nz), sp.kron(lap(ny), sp.eye(nx))) +
+         sp.kron(lap(nz), sp.eye(nx * ny))).tocsr()
+    A.sort_indices()
+    return matgen.Csr(A.shape[0], A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                      A.data.astype(np.float64))
+
+
+def _tile_bases(st, info):
+    """Each tile's column base: tile_cbase (cols16 1) or its quad batch header's fourth word (2)."""
+    if info["cols16"] == 1:
+        return st["tile_cbase"].astype(np.int64)
+    bs = st["batch_stream"].reshape(-1, 4)
+    base = np.empty(info["ntiles"], np.int64)
+    for w in range(info["nwaves"]):
+        t, o = st["wave_ptr"][w], st["batch_ptr"][w]
+        while o < st["batch_ptr"][w + 1]:
+            nt = bs[o, 1] & 0xFF
+            base[t:t + nt] = bs[o, 3]
+            t += nt
+            o += 1 + nt
+    return base
+
+
 def test_compressed_tile_columns():
-    """cols16: where every tile's original columns span less than 65,536 (stencil and block
-    operators), the SpMV kernels read a 4-byte base and 2-byte offsets per tile; decoded, they are
-    the tile's columns (tile_cols), padding columns at offset 0; the structure counts 2 S + 4 bytes
-    per tile instead of 4 S.  Scattered far columns (power-law rows), no aggregation, Algorithm 2's
-    tile-at-a-time order and cols16 = -1 keep 4-byte columns."""
-    for A, S in ((matgen.block_3d(12, seed=3), 16), (matgen.poisson_3d(24), 16), (matgen.poisson_3d(24), 8),
-                 (matgen.laplacian_2d(64), 16)):
-        kw = {"col_agg": 1, "tile_dim": S, "cols16": 1}
-        for lb in ("contiguous", "paper_stream") if S == 16 else ("contiguous",):
+    """cols16: where every quad batch's original columns span less than 65,536, the quad kernel reads
+    2-byte offsets from its batch's lowest column (kept in the batch header); otherwise, and for the
+    streaming kernel, where every tile's columns span less than 65,536, 2-byte offsets from a 4-byte base
+    per tile.  Decoded, they are the tile's columns (tile_cols), padding columns at offset 0; the
+    structure counts 2 S (per batch) or 2 S + 4 (per tile) bytes per tile instead of 4 S.  Scattered
+    far columns (power-law rows), no aggregation, Algorithm 2's tile-at-a-time order and cols16 = -1
+    keep 4-byte columns."""
+    box = _poisson_box(200, 200, 3)  # planes 40,000 rows apart: tiles span little, batches of 4 panels more
+    for A, S, kern, want in ((matgen.block_3d(12, seed=3), 16, 2, 2), (matgen.poisson_3d(24), 16, 0, 1),
+                             (matgen.poisson_3d(24), 8, 0, 1), (matgen.laplacian_2d(64), 16, 0, 1),
+                             (matgen.poisson_3d(24), 16, 2, 2), (box, 16, 2, 1), (box, 16, 0, 1)):
+        kw = {"col_agg": 1, "tile_dim": S, "cols16": 1, "spmv_kernel": kern}
+        for lb in ("contiguous", "paper_stream") if S == 16 and kern == 2 else ("contiguous",):
+            if lb == "paper_stream":
+                kw = dict(kw, spmv_kernel=-1)
             M = cb.CbMatrix.from_csr(A, device=False, lb_mode=lb, **kw)
             i = M.info
-            assert i["cols16"] == 1, (A.n, S, lb)
+            assert i["cols16"] == (want if lb == "contiguous" or A is not box else 1), (A.n, S, lb, i["cols16"])
             st = cb.cb_export_structure(M.handle)
             nt = i["ntiles"]
             cols = st["tile_cols"].reshape(nt, 4, S // 4).transpose(0, 2, 1).reshape(nt, S)  # natural order
-            dec = st["tile_cbase"][:, None].astype(np.int64) + st["tile_c16"].reshape(nt, S)
+            base = _tile_bases(st, i)
+            dec = base[:, None] + st["tile_c16"].reshape(nt, S)
             p, c = st["tile_row"], st["tile_col"]
             first = st["cols_offset"][p] + S * c
             width = np.minimum(S, st["cols_offset"][p + 1] - first)
             real = np.arange(S)[None, :] < width[:, None]
             assert np.array_equal(dec[real], cols[real])
             assert np.all(st["tile_c16"].reshape(nt, S)[~real] == 0)
-            assert np.array_equal(st["tile_cbase"], cols[:, 0])
+            if i["cols16"] == 1:
+                assert np.array_equal(st["tile_cbase"], cols[:, 0])
+            else:
+                assert np.all(base <= cols[:, 0])
             M0 = cb.CbMatrix.from_csr(A, device=False, lb_mode=lb, **dict(kw, cols16=-1))
             assert M0.info["cols16"] == 0
-            assert M0.info["spmv_bytes"] - i["spmv_bytes"] == (4 * S - (2 * S + 4)) * nt
+            per_tile = 4 * S - 2 * S - (4 if i["cols16"] == 1 else 0)
+            assert M0.info["spmv_bytes"] - i["spmv_bytes"] == per_tile * nt
             M0.close()
             M.close()
     for A, kw in ((matgen.power_law(100_000, seed=2), {}), (matgen.poisson_3d(24), {"col_agg": 0}),
@@ -527,14 +568,15 @@ def test_compressed_tile_columns():
         assert M.info["cols16"] == 0, kw
         assert cb.cb_export_structure(M.handle)["tile_c16"].size == 0
         M.close()
-    # automatic: the 2-byte form except for the quad kernel with double vectors
+    # automatic: a 2-byte form, except the per-tile one for the quad kernel with double vectors
     P = matgen.poisson_3d(24)
-    for kw, want in (({"spmv_kernel": 0}, 1), ({"spmv_kernel": 2}, 0), ({"spmv_kernel": 2, "value_type": "f32"}, 1),
-                     ({"spmv_kernel": 2, "value_type": "f32", "vector_f64": 1}, 0),
-                     ({"lb_mode": "paper_stream"}, 0), ({"lb_mode": "paper_stream", "value_type": "bf16"}, 1),
-                     ({"spmv_kernel": 2, "cols16": 1}, 1)):
-        M = cb.CbMatrix.from_csr(P, device=False, col_agg=1, **kw)
-        assert M.info["cols16"] == want, kw
+    for A, kw, want in ((P, {"spmv_kernel": 0}, 1), (P, {"spmv_kernel": 2}, 2), (box, {"spmv_kernel": 2}, 0),
+                        (box, {"spmv_kernel": 2, "value_type": "f32"}, 1),
+                        (box, {"spmv_kernel": 2, "value_type": "f32", "vector_f64": 1}, 0),
+                        (box, {"lb_mode": "paper_stream"}, 0), (box, {"lb_mode": "paper_stream", "value_type": "bf16"}, 1),
+                        (box, {"spmv_kernel": 2, "cols16": 1}, 1), (box, {"spmv_kernel": 0}, 1)):
+        M = cb.CbMatrix.from_csr(A, device=False, col_agg=1, **kw)
+        assert M.info["cols16"] == want, (A.n, kw, M.info["cols16"])
         M.close()
     # automatic kernel: with float vectors where the 2-byte form applies, the quad kernel (stencils
     # too); double vectors and scattered columns keep the streaming kernel on the stencil

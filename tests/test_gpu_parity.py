@@ -453,16 +453,26 @@ def test_compressed_columns_match_four_byte_columns(cb, opts):
     ranges (many partial gathers at a range's end): bit for bit on exact inputs (dyadic values and x:
     every order of the row sums gives the same result; on other inputs the order of the LDS atomics
     varies from run to run), and within the tolerance of the oracle on the generators' values."""
+    from test_convert import _poisson_box
+
     B = matgen.block_3d(10, seed=2)
     Bd = matgen.Csr(B.m, B.n, B.row_ptr, B.col_idx,
                     np.random.default_rng(5).integers(-16, 17, B.nnz).astype(np.float64) / 16)
-    for A in (B, Bd, matgen.poisson_3d(20), matgen.laplacian_2d(64)):
+    # planes 40,000 rows apart: the quad kernel's batches span more than 65,535 columns (per-tile bases)
+    box = _poisson_box(200, 200, 3)
+    for A in (B, Bd, matgen.poisson_3d(20), matgen.laplacian_2d(64), box):
         exact = A is not B
         x = matgen.vector(A.n, 4, dyadic=exact)
         for vt in ("f64", "f32"):
-            kw = dict(col_agg=1, wave_nnz=64, cols16=1, **opts)
+            # the box with the automatic ranges: several panels per range, so its quad batches span
+            # its planes
+            kw = dict(col_agg=1, wave_nnz=0 if A is box else 64, cols16=1, **opts)
             M = cb.CbMatrix.from_csr(A, value_type=vt, **kw)
-            assert M.info["cols16"] == 1 and M.info["col_agg"] == 1
+            # the quad kernel: per-batch bases where a batch's columns span less than 65,536 (all but
+            # the box), else per-tile bases, as the streaming kernel
+            quad = opts.get("spmv_kernel") == 2 or opts.get("lb_mode") == "paper_stream"
+            want = 2 if quad and A is not box else 1
+            assert M.info["col_agg"] == 1 and M.info["cols16"] == want, (M.info["cols16"], want)
             M.close()
             y16 = run_spmv(cb, A, x, vtype=vt, **kw)
             if exact:
