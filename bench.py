@@ -885,7 +885,11 @@ def main() -> int:
                 spmmk = lambda: Mv.spmm(Xd, Yd)  # noqa: E731
                 settle(spmmk, args.leg_settle_seconds)
                 wk, kk = time_calls(spmmk, 20, 0)
-                sb = iv["spmv_bytes"] - 4 * (A.n + A.m) + 4 * k * (A.n + A.m)
+                # the SpMV structure's bytes with X and Y in place of x and y; the SpMM kernel reads the
+                # tiles' 4-byte original columns, not the SpMV kernels' 2-byte offsets
+                S_ = iv["tile_dim"]
+                c16 = {0: 0, 1: 2 * S_ - 4, 2: 2 * S_}[iv["cols16"]] * iv["ntiles"]
+                sb = iv["spmv_bytes"] + c16 - 4 * (A.n + A.m) + 4 * k * (A.n + A.m)
                 leg[f"spmm_k{k}_gflops"] = 2.0 * A.nnz * k / wk / 1e9
                 leg[f"spmm_k{k}_kernel_us"] = kk * 1e6
                 leg[f"spmm_k{k}_bytes"] = sb
@@ -906,7 +910,7 @@ def main() -> int:
             log(f"{vt}: {json.dumps(leg)}")
             Mv.close()
             torch.cuda.empty_cache()
-        del ref, sub
+        ref = sub = None  # (ref is only computed when results are checked)
         # the other FP64 workloads of the metric, each checked row by row against the oracle: the
         # stencil family at scale (192^3 Poisson), the power-law rows, and the 64 x 64 Laplacian,
         # whose whole working set sits in cache (launch latency, not HBM)
