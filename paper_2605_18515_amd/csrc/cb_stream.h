@@ -97,6 +97,7 @@ constexpr int kQPasses = CB_TUNE_QPASSES;  // passes of 64 quads per batch (the 
 static_assert(kQTiles % 4 == 0 && kQTiles <= 32, "x gathers take four tiles; tile positions fit the x-area index");
 constexpr int kQRecordPad = kQTiles + 1;  // records readable past the end of the quad stream
 static_assert(kQPasses * 64 <= 1023, "first quads take 10 bits of the record word");
+static_assert(kQPasses >= 1 && kQPasses <= 4, "the quad kernel's tile-start marks take one byte per pass of a 32-bit word");
 constexpr int kStreamRecordPad = kQRecordPad > kRecordPad ? kQRecordPad : kRecordPad;  // both batch formats
 
 }  // namespace cbs

@@ -868,7 +868,6 @@ __device__ __forceinline__ void qstream_range(const DevView &d, int w, typename 
     constexpr int VS = Val<VT>::kSize;
     constexpr int NWD = QRaw<VS>::kWords;
     constexpr int QT = cbs::kQTiles, QP = cbs::kQPasses;
-    static_assert(QP >= 1 && QP <= 4, "tile-start marks take one byte per pass of a lane's 32-bit word");
     constexpr int NG = (QT + TPG - 1) / TPG;
     static_assert(QT % 4 == 0 && QT <= 32 && QT + 1 <= kWave, "x gathers take four tiles; records fit one load");
     constexpr int NSLOT = SC ? QT : kMaxPanels;  // accumulator slots of 16 rows
