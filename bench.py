@@ -388,11 +388,12 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
         csrs = pool.map(_serve_matrix, specs)
     log(f"generated 256 matrices ({sum(A.nnz for A in csrs) / 1e6:.0f} M non-zeros) in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
-    mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32") for i, A in enumerate(csrs)]
+    sw = {"min_wave_nnz": args.serve_min_wave_nnz}
+    mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32", **sw) for i, A in enumerate(csrs)]
     dts = [np.float64 if i % 2 == 0 else np.float32 for i in range(256)]
     spd = [i for i, s in enumerate(specs) if s[0] == "poisson"]
     # FP64 twins of the FP32 Poisson matrices: the refined solves' residual replacement
-    twin = {i: cb.CbMatrix.from_csr(csrs[i]) for i in spd if dts[i] == np.float32}
+    twin = {i: cb.CbMatrix.from_csr(csrs[i], **sw) for i in spd if dts[i] == np.float32}
     log(f"converted and uploaded in {time.perf_counter() - t:.1f}s, "
         f"{sum(M.info['device_bytes'] for M in list(mats) + list(twin.values())) / 2 ** 30:.2f} GiB on the device")
     # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix (double
@@ -519,7 +520,7 @@ def serve_precision(args, cb, csrs, xin, nsolves: int = 256) -> dict:
     pick = [int(rng.integers(0, len(csrs))) for _ in range(nsolves)]
     H = {}
     for vt in ("f64", "f32", "bf16"):
-        H[vt] = [cb.CbMatrix.from_csr(A, value_type=vt) for A in csrs]
+        H[vt] = [cb.CbMatrix.from_csr(A, value_type=vt, min_wave_nnz=args.serve_min_wave_nnz) for A in csrs]
     bs = [xin[i][:csrs[i].n].astype(np.float64) for i in range(len(csrs))]
     out = {"workload": f"{len(csrs)} resident 3D Poisson matrices (n log-uniform in [1e3, 1e6]), {nsolves} CG "
                        "solves to 1e-10, x0 = 0, cap 500 iterations, all submitted at once", "solves": nsolves}
@@ -705,6 +706,8 @@ def main() -> int:
                     help="skip the CG (FP64 vs mixed) and serving legs of the extra measurements")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving leg of the extras")
     ap.add_argument("--serve-active", type=int, default=128, help="solve slots per vector type of the server")
+    ap.add_argument("--serve-min-wave-nnz", type=int, default=1024,
+                    help="min_wave_nnz of the serving workload's handles (0: the library's automatic floor)")
     ap.add_argument("--serve-arena-gib", type=int, default=16, help="device arena of the server, GiB")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--settle-seconds", type=float, default=1.0,

@@ -160,7 +160,12 @@ typedef struct {
                                columns measured faster); 1 = a 2-byte form where possible; -1 =
                                always 4-byte columns.  Other values: CB_ERROR_INVALID_VALUE.  Results
                                do not depend on it. */
-    int64_t reserved[3];
+    int64_t min_wave_nnz;   /* with wave_nnz 0: the automatic work per range is at least this many
+                               non-zero equivalents (0, the default: 256).  Longer ranges on small
+                               matrices trade one product's latency for throughput when many
+                               products share a launch (the serving loop's batches).  Negative:
+                               CB_ERROR_INVALID_VALUE. */
+    int64_t reserved[2];
 } cb_options_t;
 
 typedef struct {

@@ -50,7 +50,8 @@ class CbOptions(ctypes.Structure):
     _fields_ = [("struct_size", _u32), ("value_type", _i32), ("col_agg", _i32), ("th1", _i32), ("th2", _i32),
                 ("quantum_tiles", _i32), ("lb_mode", _i32), ("host_threads", _i32), ("th0", _dbl),
                 ("wave_nnz", _i64), ("row_reduce", _i32), ("vector_f64", _i32), ("spmv_kernel", _i32),
-                ("tile_dim", _i32), ("xcd_chunk", _i32), ("cols16", _i32), ("reserved", _i64 * 3)]
+                ("tile_dim", _i32), ("xcd_chunk", _i32), ("cols16", _i32), ("min_wave_nnz", _i64),
+                ("reserved", _i64 * 2)]
 
 
 class CbInfo(ctypes.Structure):

@@ -519,6 +519,7 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
     if (opt.quantum_tiles < 1 || opt.quantum_tiles > (1 << 20)) { err = "quantum_tiles out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.lb_mode < 0 || opt.lb_mode > 3) { err = "lb_mode out of range"; return CB_ERROR_INVALID_VALUE; }
     if (opt.wave_nnz < 0) { err = "wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
+    if (opt.min_wave_nnz < 0) { err = "min_wave_nnz must be non-negative"; return CB_ERROR_INVALID_VALUE; }
     if (opt.row_reduce < -1 || opt.row_reduce > 4) { err = "row_reduce must be -1 .. 4"; return CB_ERROR_INVALID_VALUE; }
     if (opt.vector_f64 < 0 || opt.vector_f64 > 1) { err = "vector_f64 must be 0 or 1"; return CB_ERROR_INVALID_VALUE; }
     if (opt.spmv_kernel < -1 || opt.spmv_kernel > 2) { err = "spmv_kernel must be -1, 0, 1 or 2"; return CB_ERROR_INVALID_VALUE; }
@@ -819,8 +820,9 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
         bool taper = false;
         if (target == 0) {
             const int64_t cap = std::min<int64_t>(4096, CB_TUNE_MAX_RANGE_BYTES / (1 + s.vsize));
-            target = std::min<int64_t>(cap, std::max<int64_t>(CB_TUNE_MIN_WAVE_NNZ,
-                                                              (total_w + CB_TUNE_WAVE_RANGES - 1) / CB_TUNE_WAVE_RANGES));
+            const int64_t floor_w = std::max<int64_t>(CB_TUNE_MIN_WAVE_NNZ, opt.min_wave_nnz);
+            target = std::min<int64_t>(std::max(cap, floor_w),
+                                       std::max<int64_t>(floor_w, (total_w + CB_TUNE_WAVE_RANGES - 1) / CB_TUNE_WAVE_RANGES));
             // not under the eighths mapping: it deals the XCDs equal counts of ranges, and shorter
             // ranges at the end would leave the last XCD less work (power-law rows 626 against 584 us)
             taper = target == cap && s.xcd_chunk != 0;

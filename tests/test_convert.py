@@ -442,6 +442,21 @@ def test_automatic_range_size():
             last = w[-len(w) // 8:]
             assert abs(last.mean() - w.mean()) < 0.05 * w.mean(), (last.mean(), w.mean())
         M.close()
+    # min_wave_nnz raises the automatic floor (small matrices: fewer, longer ranges), the cap too when
+    # above it; an explicit wave_nnz ignores it; negative values are refused
+    M = cb.CbMatrix.from_csr(small, device=False, min_wave_nnz=1024)
+    # (non-zeros per range: the target counts 8 per tile on top)
+    assert 600 <= M.info["wave_nnz_mean"] <= 1100 and M.info["nwaves"] <= small.nnz // 600, M.info["wave_nnz_mean"]
+    M.close()
+    M = cb.CbMatrix.from_csr(big, device=False, min_wave_nnz=1024)
+    assert M.info["wave_nnz_mean"] <= caps["f64"], M.info["wave_nnz_mean"]  # the byte cap still binds above 1024
+    M.close()
+    M = cb.CbMatrix.from_csr(small, device=False, min_wave_nnz=4096, wave_nnz=300)
+    assert M.info["wave_nnz_mean"] <= 400
+    M.close()
+    with pytest.raises(cb.CbError) as e:
+        cb.CbMatrix.from_csr(small, device=False, min_wave_nnz=-1)
+    assert e.value.status == cb.CB_ERROR_INVALID_VALUE
     # an explicit wave_nnz overrides the rule
     M = cb.CbMatrix.from_csr(big, device=False, wave_nnz=500)
     assert M.info["wave_nnz_mean"] <= 600
