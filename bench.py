@@ -389,11 +389,33 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
     log(f"generated 256 matrices ({sum(A.nnz for A in csrs) / 1e6:.0f} M non-zeros) in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     sw = {"min_wave_nnz": args.serve_min_wave_nnz}
-    mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32", **sw) for i, A in enumerate(csrs)]
+    # --serve-tune: one cb_tune per (family, value type) on the family's largest matrix; its structural choices
+    # (aggregation, sub-block size, kernel, column form, thresholds, row sums, split, XCD mapping) go to every
+    # handle of that family and type, the range size stays automatic (it depends on the matrix's size)
+    tuned = {}
+    if args.serve_tune:
+        t = time.perf_counter()
+        for fam in fams:
+            idx = [i for i, sp in enumerate(specs) if sp[0] == fam]
+            for vt in ("f64", "f32"):
+                big = max((i for i in idx if (i % 2 == 0) == (vt == "f64")), key=lambda i: csrs[i].nnz)
+                _, best, _ = cb.cb_tune(csrs[big], keep=False, value_type=vt, **sw)
+                best = {k: v for k, v in best.items() if k not in ("wave_nnz", "value_type", "host_threads")}
+                tuned[(fam, vt)] = best
+        log(f"tuned the serving handles' options in {time.perf_counter() - t:.1f}s: " +
+            "; ".join(f"{f} {v}: S={o['tile_dim']} k{o['spmv_kernel']} agg={o['col_agg']} th=({o['th1']},{o['th2']}) "
+                      f"rr={o['row_reduce']} lb={o['lb_mode']} xcd={o['xcd_chunk']} c16={o['cols16']}"
+                      for (f, v), o in tuned.items()))
+
+    def hopts(i, vt):
+        return dict(sw, **tuned.get((specs[i][0], vt), {}))
+
+    mats = [cb.CbMatrix.from_csr(A, value_type="f64" if i % 2 == 0 else "f32", **hopts(i, "f64" if i % 2 == 0 else "f32"))
+            for i, A in enumerate(csrs)]
     dts = [np.float64 if i % 2 == 0 else np.float32 for i in range(256)]
     spd = [i for i, s in enumerate(specs) if s[0] == "poisson"]
     # FP64 twins of the FP32 Poisson matrices: the refined solves' residual replacement
-    twin = {i: cb.CbMatrix.from_csr(csrs[i], **sw) for i in spd if dts[i] == np.float32}
+    twin = {i: cb.CbMatrix.from_csr(csrs[i], **hopts(i, "f64")) for i in spd if dts[i] == np.float32}
     log(f"converted and uploaded in {time.perf_counter() - t:.1f}s, "
         f"{sum(M.info['device_bytes'] for M in list(mats) + list(twin.values())) / 2 ** 30:.2f} GiB on the device")
     # inputs: one random block per matrix (X = its first n * k values), b per Poisson matrix (double
@@ -497,14 +519,16 @@ def serve_legs(args, cb, matgen, nreq: int) -> dict:
         M.close()
     del mats, twin
     torch.cuda.empty_cache()
-    prec = serve_precision(args, cb, [csrs[i] for i in spd], [xin[i] for i in spd])
+    prec = serve_precision(args, cb, [csrs[i] for i in spd], [xin[i] for i in spd],
+                           {vt: tuned.get(("poisson", "f64" if vt == "f64" else "f32"), {}) for vt in ("f64", "f32", "bf16")})
     return {"requests": len(reqs), "cg_requests": ncg, "refined_requests": nref, "rtol": rtol, "all_at_once": st_b,
             "poisson_arrivals": dict(st_p, rate_per_s=lam), "arrival_sweep": sweep, "one_at_a_time": seq,
             "speedup_solves_vs_one_at_a_time": st_b["solves_per_s"] / seq["solves_per_s"],
-            "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst, "precision": prec}
+            "cg_converged": conv, "max_rel_diff_vs_one_at_a_time": worst, "precision": prec,
+            "tuned_options": {f"{f}_{v}": o for (f, v), o in tuned.items()} or None}
 
 
-def serve_precision(args, cb, csrs, xin, nsolves: int = 256) -> dict:
+def serve_precision(args, cb, csrs, xin, tuned=None, nsolves: int = 256) -> dict:
     """FP64 serving against mixed-precision serving at the same accuracy: the serving workload's
     Poisson matrices, each resident as FP64, FP32 and BF16 handles; the same nsolves CG requests
     (random matrix, b from the matrix's input block, x0 = 0, cap 500 iterations) served all at once
@@ -520,7 +544,8 @@ def serve_precision(args, cb, csrs, xin, nsolves: int = 256) -> dict:
     pick = [int(rng.integers(0, len(csrs))) for _ in range(nsolves)]
     H = {}
     for vt in ("f64", "f32", "bf16"):
-        H[vt] = [cb.CbMatrix.from_csr(A, value_type=vt, min_wave_nnz=args.serve_min_wave_nnz) for A in csrs]
+        H[vt] = [cb.CbMatrix.from_csr(A, value_type=vt, **dict((tuned or {}).get(vt, {}),
+                                                                min_wave_nnz=args.serve_min_wave_nnz)) for A in csrs]
     bs = [xin[i][:csrs[i].n].astype(np.float64) for i in range(len(csrs))]
     out = {"workload": f"{len(csrs)} resident 3D Poisson matrices (n log-uniform in [1e3, 1e6]), {nsolves} CG "
                        "solves to 1e-10, x0 = 0, cap 500 iterations, all submitted at once", "solves": nsolves}
@@ -706,6 +731,8 @@ def main() -> int:
                     help="skip the CG (FP64 vs mixed) and serving legs of the extra measurements")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests of the serving leg of the extras")
     ap.add_argument("--serve-active", type=int, default=128, help="solve slots per vector type of the server")
+    ap.add_argument("--serve-tune", action="store_true",
+                    help="serving workload: handles take cb_tune's options per matrix family and value type")
     ap.add_argument("--serve-min-wave-nnz", type=int, default=1024,
                     help="min_wave_nnz of the serving workload's handles (0: the library's automatic floor)")
     ap.add_argument("--serve-arena-gib", type=int, default=16, help="device arena of the server, GiB")
