@@ -120,6 +120,8 @@ def kernel_name(info: dict, lb: str) -> str:
         agg = "aggregated" if info["col_agg"] else "plain columns"
         return f"spmv_quad_kernel<FP64, {agg}, row sums {info['row_reduce']}, scatter> (Algorithm 2 order, streamed)"
     agg = "aggregated" if info["col_agg"] else "plain columns"
+    if info["col_agg"] and info.get("cols16"):
+        agg += ", 2-byte column offsets per " + ("batch" if info["cols16"] == 2 else "tile")
     if info["spmv_kernel"] == 1:
         return f"spmv_rows_kernel<FP64, {agg}>"
     if info["spmv_kernel"] == 2:
