@@ -331,7 +331,8 @@ void build_tile_c16(HostStructure &s, int mode) {
     s.cols16 = 0;
     s.tile_cbase.clear();
     s.tile_c16.clear();
-    if (!s.col_agg || mode < 0 || s.ntiles == 0) return;
+    // the rows-per-lane kernel (spmv_kernel 1) reads the 4-byte columns
+    if (!s.col_agg || mode < 0 || s.ntiles == 0 || s.spmv_kernel == 1) return;
     const bool quad = s.spmv_kernel == 2 || s.lb_mode == CB_LB_PAPER_STREAM;
     std::vector<int32_t> first_col((size_t)s.ntiles), last_col((size_t)s.ntiles);
     for (int64_t t = 0; t < s.ntiles; ++t) {

@@ -578,6 +578,7 @@ def test_compressed_tile_columns():
             M0.close()
             M.close()
     for A, kw in ((matgen.power_law(100_000, seed=2), {}), (matgen.poisson_3d(24), {"col_agg": 0}),
+                  (matgen.poisson_3d(24), {"col_agg": 1, "spmv_kernel": 1, "cols16": 1}),
                   (matgen.poisson_3d(24), {"col_agg": 1, "lb_mode": "paper"})):
         M = cb.CbMatrix.from_csr(A, device=False, **kw)
         assert M.info["cols16"] == 0, kw
