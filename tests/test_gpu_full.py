@@ -68,6 +68,8 @@ def test_block3d_spmv_every_row(cb, block, vtype):
     x = matgen.vector(block.n, 1)
     y, info = spmv_gpu(cb, block, x, vtype)
     assert info["col_agg"] == 1 and info["lb_mode"] == cb.CB_LB_CONTIGUOUS and info["nwaves"] > 1000
+    # the quad kernel with 2-byte column offsets from each batch's base
+    assert info["spmv_kernel"] == 2 and info["cols16"] == 2
     check_rows(y, block, x, vtype, "block3d 100^3 x 3")
 
 
@@ -106,13 +108,22 @@ def test_block3d_spmm_sampled_rows(cb, block, k, vtype):
     assert viol == 0, (e, worst)
 
 
+@pytest.fixture(scope="module")
+def poisson192():
+    return matgen.poisson_3d(192)
+
+
 @pytest.mark.timeout(300)
-def test_poisson192_every_row(cb):
-    A = matgen.poisson_3d(192)
+@pytest.mark.parametrize("vtype", ["f64", "f32", "bf16"])
+def test_poisson192_every_row(cb, poisson192, vtype):
+    """The stencil at scale: FP64 on the streaming kernel, FP32/BF16 on the quad kernel, all reading
+    2-byte column offsets from a base per tile (a quad batch spans two grid planes, 73,729 columns)."""
+    A = poisson192
     x = matgen.vector(A.n, 1)
-    y, info = spmv_gpu(cb, A, x, "f64")
-    assert info["col_agg"] == 1
-    check_rows(y, A, x, "f64", "poisson 192^3")
+    y, info = spmv_gpu(cb, A, x, vtype)
+    assert info["col_agg"] == 1 and info["cols16"] == 1
+    assert info["spmv_kernel"] == (0 if vtype == "f64" else 2)
+    check_rows(y, A, x, vtype, "poisson 192^3")
 
 
 @pytest.mark.timeout(600)
