@@ -698,7 +698,10 @@ cb_status_t convert(int64_t m, int64_t n, int64_t nnz, const int64_t *row_ptr, c
             // the quad kernel sums each lane's row runs in registers instead of a segmented scan
             if (s.spmv_kernel == 2 && s.row_reduce == 1) s.row_reduce = 0;
         } else {
-            const bool runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs;
+            // the quad kernel sums a lane's row runs in registers before its one LDS add, so one
+            // copy of the row sums serves it (3D block matrix: FP64 131.0 against 132.4 us with two,
+            // FP32 83.6 against 84.2, BF16 within noise)
+            const bool runs = s.flat_runs > 0 && s.flat_entries >= 2 * s.flat_runs && s.spmv_kernel != 2;
             if (s.vector_f64) s.row_reduce = runs ? 3 : 0;
             else s.row_reduce = runs ? 4 : 2;
         }

@@ -335,10 +335,16 @@ def test_row_reduce_resolution_and_run_statistic():
     A = matgen.Csr(n, n, np.arange(0, 2 * n + 1, 2, dtype=np.int64), cols.ravel().astype(np.int32),
                    np.ones(2 * n))
     assert rows.size == A.nnz
-    # runs of two entries per tile row: the two-copy accumulator modes
+    # runs of two entries per tile row: the two-copy accumulator modes for the streaming kernel; the
+    # quad kernel (chosen here automatically: 32 entries in runs) sums a lane's runs itself and keeps
+    # one copy
     for vt, want in (("f64", 3), ("f32", 4), ("bf16", 4)):
-        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, th1=64, th2=256)
+        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, th1=64, th2=256, spmv_kernel=0)
         assert M.info["row_reduce"] == want and M.info["flat_run_mean"] == 2.0
+        M.close()
+    for vt, want in (("f64", 0), ("f32", 2), ("bf16", 2)):
+        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, th1=64, th2=256)
+        assert M.info["spmv_kernel"] == 2 and M.info["row_reduce"] == want
         M.close()
     # one entry per tile row (a permutation matrix): one copy
     P = matgen.Csr(n, n, np.arange(n + 1, dtype=np.int64), ((np.arange(n) * 5) % n).astype(np.int32), np.ones(n))
@@ -352,7 +358,7 @@ def test_row_reduce_resolution_and_run_statistic():
         M.close()
     # double vectors: always with FP64 storage, on request with FP32/BF16 (then FP64 atomics suffice)
     for vt, wide, want in (("f64", 0, 1), ("f32", 0, 0), ("f32", 1, 1), ("bf16", 1, 1)):
-        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, vector_f64=wide)
+        M = cb.CbMatrix.from_csr(A, device=False, value_type=vt, vector_f64=wide, spmv_kernel=0)
         assert M.info["vector_f64"] == want
         assert M.info["row_reduce"] == (3 if want else 4)
         M.close()
@@ -480,7 +486,7 @@ def test_automatic_kernel_choice():
         M = cb.CbMatrix.from_csr(M_, device=False, **kw)
         assert M.info["spmv_kernel"] == want, (kw, M.info["spmv_kernel"])
         if want == 2:
-            assert M.info["row_reduce"] in (3, 4)
+            assert M.info["row_reduce"] in (0, 2)  # one copy: the quad kernel sums its runs itself
         M.close()
 
 
