@@ -710,6 +710,49 @@ def run_tune(args, cb, matgen) -> int:
     return 0
 
 
+def run_tune_spmm(args, cb, matgen) -> int:
+    """cb_tune with k right-hand sides on the FP32 and BF16 copies of the 3D block matrix: SpMM time
+    with the default options against the tuned ones (HIP events, 20 launches each after a settle)."""
+    import torch
+
+    k = args.tune_spmm
+    A = make_matrix("block3d", 100)
+    Xd = torch.from_numpy(matgen.rhs_columns(A.n, k, 3)).to("cuda", torch.float32)
+    Yd = torch.empty((A.m, k), dtype=torch.float32, device="cuda")
+    rows = {}
+    for vt in ("f32", "bf16"):
+        M = cb.CbMatrix.from_csr(A, value_type=vt)
+        settle(lambda: M.spmm(Xd, Yd), 0.3)
+        _, k_def = time_calls(lambda: M.spmm(Xd, Yd), 20, 2)
+        M.close()
+        t = time.perf_counter()
+        Mt, best, cands = cb.cb_tune(A, value_type=vt, spmm_k=k)
+        tune_s = time.perf_counter() - t
+        settle(lambda: Mt.spmm(Xd, Yd), 0.3)
+        _, k_tun = time_calls(lambda: Mt.spmm(Xd, Yd), 20, 2)
+        it = Mt.info
+        Mt.close()
+        rows[vt] = {"default_us": k_def * 1e6, "tuned_us": k_tun * 1e6, "speedup": k_def / k_tun,
+                    "tune_seconds": tune_s,
+                    "tuned_structure": {n: it[n] for n in ("tile_dim", "col_agg", "xcd_chunk", "nwaves", "ntiles")},
+                    "best": {n: best[n] for n in ("col_agg", "th1", "th2", "lb_mode", "wave_nnz", "xcd_chunk",
+                                                  "tile_dim")},
+                    "candidates": [{"us": c["us"], "tile_dim": c["tile_dim"], "col_agg": c["col_agg"],
+                                    "wave_nnz": c["opt"]["wave_nnz"], "xcd_chunk": c["opt"]["xcd_chunk"],
+                                    "lb_mode": c["opt"]["lb_mode"], "th": [c["opt"]["th1"], c["opt"]["th2"]]}
+                                   for c in cands]}
+        log(f"spmm k={k} {vt}: default {k_def * 1e6:.1f} us, tuned {k_tun * 1e6:.1f} us "
+            f"({k_def / k_tun:.3f}x) in {tune_s:.1f}s, chosen {rows[vt]['tuned_structure']} {rows[vt]['best']}")
+    out = {"metric": f"autotuned SpMM (k = {k}) speedup over default options", "value": None, "unit": "x",
+           "n_gpus": 1, "steps": 20, "warmup": 2, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "config": {"workload": f"cb_tune with {k} right-hand sides on the 3D block matrix (100^3 x 3)"},
+           "roofline": None, "cpu_baseline": None, "extra": rows}
+    out["value"] = round(min(r["speedup"] for r in rows.values()), 4)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -760,6 +803,9 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="instead of the SpMV line: the autotuner on the block, Poisson and power-law matrices in "
                          "FP64 and FP32, tuned against default options")
+    ap.add_argument("--tune-spmm", type=int, default=0, metavar="K",
+                    help="instead of the SpMV line: the autotuner timing SpMM with K right-hand sides on the "
+                         "FP32 and BF16 block matrix, tuned against default options")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy kernel over MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -780,7 +826,7 @@ def main() -> int:
     # generates and converts the block matrix
     pool, pending = None, {}
     if (not args.no_extras and args.workload == "block3d" and not args.copy_only and not args.cg and not args.serve
-            and not args.tune and not args.ablation):
+            and not args.tune and not args.tune_spmm and not args.ablation):
         import multiprocessing as mp
 
         pool = mp.get_context("fork").Pool(2)
@@ -802,6 +848,8 @@ def main() -> int:
         return run_serve(args, cb, matgen)
     if args.tune:
         return run_tune(args, cb, matgen)
+    if args.tune_spmm:
+        return run_tune_spmm(args, cb, matgen)
     if args.ablation:
         return run_ablation(args, cb, matgen)
     t = time.perf_counter()
