@@ -116,8 +116,10 @@ typedef struct {
                                with the accumulators in two copies, odd lanes adding into the
                                second (halves the collisions of a row's neighbouring entries on
                                one LDS address); -1 (default) = automatic: 0 (FP64 values) or 2
-                               (FP32/BF16), or 3 or 4 where the tiles' rows hold their entries in
-                               runs of two or more on average.  Results agree within the storage
+                               (FP32/BF16), or 3 or 4 for the streaming kernel where the tiles'
+                               rows hold their entries in runs of two or more on average (the quad
+                               kernel, which sums a lane's row runs in registers, keeps 0 or 2).
+                               Results agree within the storage
                                precision's tolerance either way. */
     int32_t vector_f64;     /* FP32/BF16 storage only: 1 = x and y are double and the products,
                                sums, alpha and beta are FP64 (the stored values widened exactly);
